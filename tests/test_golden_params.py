@@ -1,0 +1,31 @@
+"""The solver defaults match the paper's parameter table (Tab. 1)."""
+import os
+
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden():
+    out = {}
+    with open(os.path.join(HERE, "golden", "tab1_defaults.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                out[k] = v
+    return out
+
+
+def test_defaults_match_table1():
+    g = _golden()
+    p = W.DEFAULT_PARAMS
+    for k in ("n_inv", "nkv", "mu", "nu", "mr_iters", "kc_len", "kc_restarts"):
+        assert p[k] == int(g[k]), k
+    for k in ("coarse_eps", "tol", "kc_tol"):
+        assert p[k] == float(g[k]), k
+    assert p["sap_block"] == tuple(int(x) for x in g["sap_block"].split(","))
+    big = W.CONFIGS["clover16x32_3lvl"]
+    assert big["agg"][0] == tuple(int(x) for x in g["agg_level1"].split(","))
+    assert big["agg"][1] == tuple(int(x) for x in g["agg_coarser"].split(","))
+    assert big["ntv"][0] == int(g["ntv"])

@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs for the DD-alpha-AMG hot path.
+
+This module is shared by the CPU oracle and by the GPU path.  It only draws
+random numbers and builds test inputs (gauge links, right-hand sides, initial
+test vectors); it holds none of the solver's arithmetic.
+
+The paper (Sec. 3, Tab. 2) measures on real gauge ensembles (BMW-c 48^4 and
+64^4, CLS 128x64^3) that are not available here.  Synthetic links of the same
+structure stand in for them: every link is an SU(3) matrix U = exp(i eps H)
+with H a traceless Hermitian Gaussian matrix.
+
+Conventions shared by everything in this repository:
+
+* a lattice is given by ``dims = (X, Y, Z, T)``; direction mu = 0, 1, 2, 3 is
+  x, y, z, t; the canonical site index is ``x + X*(y + Y*(z + Z*t))``, so a
+  field is a C-ordered numpy array of shape ``(T, Z, Y, X, ...)``;
+* a fine spinor has 12 complex components per site, index ``spin*3 + colour``;
+* links have shape ``(T, Z, Y, X, 4, 3, 3)`` (direction, row, column).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 13076101
+
+# Gell-Mann matrices lambda_1..lambda_8 (standard normalisation tr(l_a l_b) = 2 delta_ab).
+_GELL_MANN = np.zeros((8, 3, 3), dtype=np.complex128)
+_GELL_MANN[0][0, 1] = _GELL_MANN[0][1, 0] = 1
+_GELL_MANN[1][0, 1], _GELL_MANN[1][1, 0] = -1j, 1j
+_GELL_MANN[2][0, 0], _GELL_MANN[2][1, 1] = 1, -1
+_GELL_MANN[3][0, 2] = _GELL_MANN[3][2, 0] = 1
+_GELL_MANN[4][0, 2], _GELL_MANN[4][2, 0] = -1j, 1j
+_GELL_MANN[5][1, 2] = _GELL_MANN[5][2, 1] = 1
+_GELL_MANN[6][1, 2], _GELL_MANN[6][2, 1] = -1j, 1j
+_GELL_MANN[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+
+
+def _shape(dims):
+    X, Y, Z, T = dims
+    return (T, Z, Y, X)
+
+
+def volume(dims) -> int:
+    return int(np.prod(dims))
+
+
+def su3_exp(h: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i*eps*H) for a stack of Hermitian 3x3 matrices, via eigh."""
+    w, W = np.linalg.eigh(h)
+    ph = np.exp(1j * eps * w)
+    return np.einsum("...ab,...b,...cb->...ac", W, ph, W.conj())
+
+
+def links(dims, eps: float, seed: int) -> np.ndarray:
+    """Gauge links U_mu(x) = exp(i eps H), H = sum_a h_a lambda_a / 2, h_a ~ N(0,1).
+
+    The normals are drawn in canonical site order, then direction, with 8 per
+    link.  Returns complex128 of shape (T, Z, Y, X, 4, 3, 3).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = rng.standard_normal(_shape(dims) + (4, 8))
+    H = np.einsum("...a,aij->...ij", h, _GELL_MANN) / 2.0
+    return su3_exp(H, eps)
+
+
+def random_su3(dims, seed: int, eps: float = np.pi) -> np.ndarray:
+    """One random SU(3) matrix per site (used for gauge transformations in tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = rng.standard_normal(_shape(dims) + (8,))
+    H = np.einsum("...a,aij->...ij", h, _GELL_MANN) / 2.0
+    return su3_exp(H, eps)
+
+
+def gaussian_field(dims, dof: int, seed: int, nrhs: int | None = None) -> np.ndarray:
+    """Complex Gaussian field, Re and Im ~ N(0,1), canonical order.
+
+    Shape (T, Z, Y, X, dof), or (nrhs, T, Z, Y, X, dof) when nrhs is given.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lead = () if nrhs is None else (nrhs,)
+    g = rng.standard_normal(lead + _shape(dims) + (dof, 2))
+    return g[..., 0] + 1j * g[..., 1]
+
+
+def gaussian_spinor(dims, seed: int, nrhs: int | None = None) -> np.ndarray:
+    return gaussian_field(dims, 12, seed, nrhs)
+
+
+def point_sources(dims) -> np.ndarray:
+    """The 12 spin-colour point sources b^(s,c)(x) = delta_{x,0} e_s (x) e_c."""
+    b = np.zeros((12,) + _shape(dims) + (12,), dtype=np.complex128)
+    for k in range(12):
+        b[k, 0, 0, 0, 0, k] = 1.0
+    return b
+
+
+def test_vectors(dims, dof: int, n: int, seed: int) -> np.ndarray:
+    """The n random initial test vectors of the setup, shape (n, T, Z, Y, X, dof)."""
+    return gaussian_field(dims, dof, seed, nrhs=n)
+
+
+# --------------------------------------------------------------------------
+# Workloads.  Defaults follow the paper's parameter table (Tab. 1); sizes,
+# link spread eps and bare mass m0 define the synthetic stand-ins.
+# --------------------------------------------------------------------------
+
+DEFAULT_PARAMS = dict(
+    n_inv=6,            # setup iterations (Tab. 1)
+    coarse_eps=5e-2,    # coarsest-system relative residual (Tab. 1)
+    nkv=10,             # outer FGMRES restart length (Tab. 1)
+    tol=1e-10,          # outer relative residual (Tab. 1)
+    mu=0, nu=5,         # pre/post smoothing (Tab. 1)
+    sap_block=(2, 2, 2, 2),
+    mr_iters=3,
+    kc_len=5, kc_restarts=2, kc_tol=1e-1,   # K-cycle (Tab. 1)
+    coarse_restart=30, coarse_max_restarts=10,
+)
+
+
+def _cfg(k, **kw):
+    p = dict(DEFAULT_PARAMS)
+    p.update(kw)
+    p["seed_links"] = BASE_SEED + 100 * k
+    p["seed_rhs"] = BASE_SEED + 100 * k + 1
+    p["seed_tv"] = BASE_SEED + 100 * k + 2
+    p["seed_gauge"] = BASE_SEED + 100 * k + 3
+    return p
+
+
+CONFIGS = {
+    # two-level, 8^4, Wilson only
+    "wilson8_2lvl": _cfg(0, dims=(8, 8, 8, 8), eps=0.4, m0=-0.3, csw=0.0,
+                         levels=2, agg=[(4, 4, 4, 4)], ntv=[8], nu=2),
+    # three-level, 16^3x32, clover
+    "clover16x32_3lvl": _cfg(1, dims=(16, 16, 16, 32), eps=0.5, m0=-0.4, csw=1.0,
+                             levels=3, agg=[(4, 4, 4, 4), (2, 2, 2, 2)], ntv=[20, 20]),
+    # three-level, 32^3x64, 12 point sources
+    "clover32x64_3lvl_12rhs": _cfg(2, dims=(32, 32, 32, 64), eps=0.5, m0=-0.42, csw=1.0,
+                                   levels=3, agg=[(4, 4, 4, 4), (2, 2, 2, 2)], ntv=[20, 20]),
+    # four-level, 48^3x96
+    "clover48x96_4lvl": _cfg(4, dims=(48, 48, 48, 96), eps=0.55, m0=-0.43, csw=1.0,
+                             levels=4, agg=[(4, 4, 4, 4), (2, 2, 2, 2), (2, 2, 2, 2)],
+                             ntv=[20, 20, 28]),
+}
+
+# the uneven batch of eight lattices: (dims, eps, m0)
+UNEVEN_BATCH = [
+    ((16, 16, 16, 16), 0.30, -0.45), ((16, 16, 16, 16), 0.35, -0.45),
+    ((16, 16, 16, 16), 0.50, -0.30), ((16, 16, 16, 16), 0.60, -0.45),
+    ((24, 24, 24, 48), 0.40, -0.45), ((24, 24, 24, 48), 0.55, -0.35),
+    ((32, 32, 32, 64), 0.45, -0.30), ((32, 32, 32, 64), 0.60, -0.40),
+]
+
+
+def uneven_batch_seed(j: int) -> int:
+    return BASE_SEED + 400 + 10 * j

@@ -1,0 +1,209 @@
+/*
+ * ddamg.h -- C ABI of the MI355X (gfx950) DD-alpha-AMG library.
+ *
+ * Solves the lattice Wilson(-clover) Dirac system D z = b (Frommer, Kahl,
+ * Krieg, Leder, Rottmann, arXiv:1307.6101, Sec. 1 eq. (1)) with FGMRES
+ * preconditioned by the adaptive-aggregation domain-decomposition multilevel
+ * method (Sec. 2: Alg. 1 V-cycle, Alg. 2 K-cycle, Alg. 3 / Alg. 4 setup;
+ * Sec. 3 and Tab. 1: parameters, single-precision preconditioner inside a
+ * double-precision outer FGMRES, odd-even GMRES on the coarsest level).
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * Lattice.  dims = {X, Y, Z, T}, periodic in all four directions; direction
+ *   mu = 0,1,2,3 is x,y,z,t.  Canonical site index i = x + X*(y + Y*(z + Z*t)).
+ * Operator.  (D psi)(x) = (m0+4) psi(x)
+ *     - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^H psi(x-mu)]
+ *     - c_sw/32 sum_{mu,nu} g_mu g_nu (Q_mu,nu(x) - Q_nu,mu(x)) psi(x),
+ *   chiral gamma basis with Gamma5 = diag(1,1,-1,-1) (the paper's Gamma5:
+ *   +1 on spins 1,2, -1 on spins 3,4), Q_mu,nu the four-leaf clover.
+ * Complex numbers are interleaved (re, im).
+ * Canonical layouts (DDAMG_CANONICAL, always complex128):
+ *   links        [V][4 mu][3][3] row-major (U_mu(x) couples x to x+mu)
+ *   fine spinor  [nrhs][V][4 spin][3 colour]
+ *   level-l field [nrhs][V_l][2N]: components 0..N-1 carry Gamma5 = +1,
+ *                N..2N-1 carry Gamma5 = -1 (coarse site = aggregate, in the
+ *                canonical order of the coarse lattice)
+ *   coarse operator [V_l][9][2N][2N] row-major, blocks self, +x,+y,+z,+t,
+ *                -x,-y,-z,-t: (D_l v)(x) = sum_k B_k(x) v(x + d_k)
+ * Native layouts (DDAMG_NATIVE) are the library's internal ones, at the
+ *   precision of the call (F64: complex128, F32: complex64):
+ *   fine field   [nrhs][V/16][12][16]: 2^4 blocks of sites, aggregate-major;
+ *                site (x,y,z,t) -> block, local index lx+2ly+4lz+8lt
+ *   level-l field (l >= 1) [nrhs][V_l][2N] (canonical order)
+ *   Use ddamg_to_native / ddamg_from_native to convert.
+ * Levels are numbered from 0 (the fine lattice; the paper's level 1).
+ * Memory.  Every pointer argument named in/out/b/z/links/tv is a DEVICE
+ *   pointer owned by the caller; the library never frees it.  The handles own
+ *   the library's device memory (operators, interpolations, Krylov bases) and
+ *   free it on destroy.
+ * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
+ *   on it and return without waiting, except ddamg_create,
+ *   ddamg_build_hierarchy and ddamg_solve, which return when done.
+ * Errors.  Every int-returning call returns DDAMG_OK or a negative status;
+ *   arguments are checked on the host before anything is launched, and
+ *   ddamg_last_error() then describes the failure (thread-local string).
+ */
+#ifndef DDAMG_H
+#define DDAMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DDAMG_OK = 0,
+  DDAMG_EINVAL = -1,        /* bad argument, shape or parameter */
+  DDAMG_ENOMEM = -2,        /* device allocation failed */
+  DDAMG_EHIP = -3,          /* a HIP runtime call failed */
+  DDAMG_ENOCONV = -4,       /* solve hit max_restarts before tol */
+  DDAMG_ENONFINITE = -5,    /* NaN / Inf in b or in a residual */
+  DDAMG_EUNSUPPORTED = -6   /* valid request this build does not implement */
+};
+
+enum { DDAMG_F64 = 0, DDAMG_F32 = 1 };            /* arithmetic precision */
+enum { DDAMG_CANONICAL = 0, DDAMG_NATIVE = 1 };   /* vector layout */
+enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1 };      /* Alg. 2 / Alg. 1 */
+
+typedef struct ddamg_ctx_s* ddamg_ctx;    /* one lattice operator D */
+typedef struct ddamg_hier_s* ddamg_hier;  /* a multilevel hierarchy for D */
+
+typedef struct {
+  int dims[4];     /* X, Y, Z, T; each a multiple of 4 */
+  double m0;       /* bare mass */
+  double csw;      /* clover coefficient (0 = Wilson) */
+} ddamg_lattice;
+
+/* Method parameters; ddamg_params_default() fills the paper's Tab. 1. */
+typedef struct {
+  int levels;                 /* L >= 2 */
+  int agg[3][4];              /* aggregate (lattice-block) shape, level l -> l+1 */
+  int ntv[3];                 /* test vectors N on level l (l < L-1) */
+  int sap_block[4];           /* SAP block shape on every level (2^4) */
+  int mu, nu;                 /* pre- / post-smoothing steps (0 / 5) */
+  int mr_iters;               /* MR iterations per SAP block solve (3) */
+  int n_inv;                  /* iterative setup iterations (6) */
+  double coarse_eps;          /* coarsest relative residual (5e-2) */
+  int coarse_restart;         /* coarsest GMRES restart length (30) */
+  int coarse_max_restarts;    /* coarsest GMRES restart cycles (10) */
+  int kc_len;                 /* K-cycle FGMRES length (5) */
+  int kc_restarts;            /* K-cycle FGMRES restart cycles (2) */
+  double kc_tol;              /* K-cycle relative residual (1e-1) */
+  int nkv;                    /* outer FGMRES restart length (10) */
+  double tol;                 /* outer relative residual (1e-10) */
+  int max_restarts;           /* outer restart cycles before DDAMG_ENOCONV */
+  int precond_prec;           /* DDAMG_F32 (mixed) or DDAMG_F64 (plain) */
+  int cycle;                  /* DDAMG_KCYCLE or DDAMG_VCYCLE */
+} ddamg_params;
+
+typedef struct {
+  int status;                 /* DDAMG_OK, DDAMG_ENOCONV or DDAMG_ENONFINITE */
+  int outer_iters;            /* outer FGMRES iterations (preconditioner calls) */
+  int restarts;               /* outer restart cycles */
+  long long kcycle_iters;     /* FGMRES iterations on levels 1..L-2 */
+  long long coarsest_iters;   /* GMRES iterations on the coarsest level */
+  double true_relres;         /* ||b - D z|| / ||b||, recomputed in FP64 */
+  double seconds;             /* wall time of the call */
+} ddamg_solve_stats;
+
+/* Fill p with the defaults of Tab. 1 for `levels` levels (agg 4^4 then 2^4,
+ * N = 20, SAP blocks 2^4, 3 MR steps, mu = 0, nu = 5, n_inv = 6, eps = 5e-2,
+ * K-cycle length 5 / 2 cycles / 1e-1, n_kv = 10, tol = 1e-10, FP32
+ * preconditioner, K-cycle). */
+void ddamg_params_default(ddamg_params* p, int levels);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char* ddamg_last_error(void);
+
+/* Library version string. */
+const char* ddamg_version(void);
+
+/* Create the operator D (Sec. 1 eq. (1)) on one lattice.  `links` is a device
+ * pointer to the canonical complex128 links; they are copied (the caller may
+ * free them afterwards).  The clover term is built on the device in FP64 and
+ * kept in FP64 and FP32 next to the links.  EINVAL unless every extent is a
+ * positive multiple of 4. */
+int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out);
+void ddamg_destroy(ddamg_ctx ctx);
+
+/* out = D in for nrhs fine fields (eq. (1)), computed at `prec`.  With
+ * DDAMG_CANONICAL, in/out are complex128 canonical spinors; with
+ * DDAMG_NATIVE they are native fine fields at `prec`.  in and out must not
+ * overlap. */
+int ddamg_apply_D(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, int layout,
+                  void* stream);
+
+/* Canonical complex128 <-> native (at prec) conversion of nrhs fields of
+ * level `level` (level 0 needs only ctx; level >= 1 needs hier, else pass
+ * NULL). */
+int ddamg_to_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in, void* out,
+                    int nrhs, int prec, void* stream);
+int ddamg_from_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in, void* out,
+                      int nrhs, int prec, void* stream);
+
+/* Build the multilevel hierarchy (Sec. 2.2: Alg. 3 initial phase on every
+ * level, then Alg. 4 iterative phase for i = 1..n_inv).  `tv` holds the
+ * ntv[0] random initial test vectors as canonical complex128 fine spinors
+ * ([ntv[0]][V][12], device); where a coarser level has more test vectors than
+ * the level above, the extra ones are taken from `tv_extra` (canonical
+ * complex128 fields of that level, concatenated level by level; NULL if
+ * none).  Smoothing and cycles run at params->precond_prec; orthonormalisation
+ * and the Galerkin products D_{l+1} = P_l^H D_l P_l run in FP64.  EINVAL
+ * when a level's extents are not divisible by its aggregate or SAP block
+ * shape, a SAP block count per direction is odd, or N exceeds an aggregate's
+ * dimension. */
+int ddamg_build_hierarchy(ddamg_ctx ctx, const ddamg_params* params, const void* tv,
+                          const void* tv_extra, void* stream, ddamg_hier* out);
+void ddamg_destroy_hierarchy(ddamg_hier hier);
+
+/* Number of levels, and sites / components per site of level `level`. */
+int ddamg_level_info(ddamg_hier hier, int level, int dims_out[4], int* dof_out);
+
+/* out = D_level in for nrhs level-`level` fields (level >= 1: the Galerkin
+ * operator of Sec. 1; level 0: D).  Layout as for ddamg_apply_D. */
+int ddamg_apply_Dc(ddamg_hier hier, int level, const void* in, void* out, int nrhs, int prec,
+                   int layout, void* stream);
+
+/* coarse = P_level^H fine (Alg. 1, restriction) and fine += P_level coarse
+ * (Alg. 1, interpolation), level = 0 .. L-2. */
+int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, int nrhs,
+                   int prec, int layout, void* stream);
+int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, int nrhs,
+                  int prec, int layout, void* stream);
+
+/* nsweeps SAP steps z <- z + M (b - D z) on level `level` (Sec. 2; Tab. 1:
+ * red-black lattice blocks, mr_iters MR steps per block solve, colour 0
+ * first).  z is read and overwritten. */
+int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsweeps, int nrhs,
+                     int prec, int layout, void* stream);
+
+/* One application of the level-0 cycle (the preconditioner) to b: z = C(b)
+ * (Alg. 2, or Alg. 1 with params.cycle = DDAMG_VCYCLE). */
+int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int layout,
+                       void* stream);
+
+/* Solve D z = b for nrhs canonical complex128 right-hand sides with FGMRES
+ * (restart nkv, double precision) preconditioned by the cycle, to
+ * ||b - D z|| <= tol ||b|| (checked on the recomputed residual).  z holds the
+ * initial guess on entry (zeros for none) and the solution on return.
+ * stats (host, may be NULL) receives one record per right-hand side.
+ * Returns DDAMG_ENOCONV / DDAMG_ENONFINITE if any right-hand side did. */
+int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
+                void* stream);
+
+/* Export the orthonormalised interpolation basis of level `level` as
+ * ntv[level] canonical complex128 fields of that level ([N][V_l][d_l]), and
+ * the coarse operator D_{level} (level >= 1) in the canonical coarse layout. */
+int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream);
+int ddamg_export_coarse_op(ddamg_hier hier, int level, void* out, void* stream);
+
+/* Replace the test vectors of level `level` (canonical complex128,
+ * [ntv][V_l][d_l]) and rebuild P_level and D_{level+1} from them (FP64). */
+int ddamg_import_test_vectors(ddamg_hier hier, int level, const void* tv, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDAMG_H */

@@ -1,0 +1,439 @@
+// extern "C" entry points declared in include/ddamg.h.  Each checks its
+// arguments on the host, converts canonical <-> native layouts where asked,
+// and calls into the hierarchy / kernels on the caller's stream.
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "solver.h"
+
+using namespace ddamg;
+
+struct ddamg_ctx_s {
+  std::unique_ptr<Context> c;
+};
+struct ddamg_hier_s {
+  std::unique_ptr<Hierarchy> h;
+  ddamg_ctx_s* owner;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F> int guarded(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return DDAMG_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return DDAMG_EHIP;
+  } catch (...) {
+    g_err = "unknown failure";
+    return DDAMG_EHIP;
+  }
+}
+
+void check_prec(int prec) { DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32, "prec must be DDAMG_F64 or DDAMG_F32"); }
+void check_layout(int layout) {
+  DD_REQUIRE(layout == DDAMG_CANONICAL || layout == DDAMG_NATIVE, "layout must be DDAMG_CANONICAL or DDAMG_NATIVE");
+}
+
+template <typename T> DevArray<C<T>>& ctx_scratch(Context& c, int which);
+template <> DevArray<C<double>>& ctx_scratch<double>(Context& c, int w) { return w ? c.s64b : c.s64a; }
+template <> DevArray<C<float>>& ctx_scratch<float>(Context& c, int w) { return w ? c.s32b : c.s32a; }
+template <typename T> DevArray<C<T>>& hier_scratch(Hierarchy& h, int which);
+template <> DevArray<C<double>>& hier_scratch<double>(Hierarchy& h, int w) { return w ? h.sc64b : h.sc64a; }
+template <> DevArray<C<float>>& hier_scratch<float>(Hierarchy& h, int w) { return w ? h.sc32b : h.sc32a; }
+
+template <typename E> E* ensure(DevArray<E>& a, size_t n) {
+  if (a.n < n) a.alloc(n);
+  return a.p;
+}
+
+// canonical complex128 <-> native at T for a level-l field (one field)
+template <typename T>
+void to_nat(Context& c, int l, long long n, const double2* in, C<T>* out, hipStream_t s) {
+  if (l == 0) fine_to_native<T>(c.g, in, out, 1, s);
+  else vcopy<double, T>(in, out, n, s);
+}
+template <typename T>
+void from_nat(Context& c, int l, long long n, const C<T>* in, double2* out, hipStream_t s) {
+  if (l == 0) fine_from_native<T>(c.g, in, out, 1, s);
+  else vcopy<T, double>(in, out, n, s);
+}
+
+template <typename T>
+void apply_D_impl(Context& c, const void* in, void* out, int nrhs, int layout, hipStream_t s) {
+  const long long n = c.g.V * 12;
+  const auto op = c.view<T>();
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      dslash<T>(op, static_cast<const C<T>*>(in) + r * n, static_cast<C<T>*>(out) + r * n, s);
+    } else {
+      C<T>* a = ensure(ctx_scratch<T>(c, 0), n);
+      C<T>* b = ensure(ctx_scratch<T>(c, 1), n);
+      to_nat<T>(c, 0, n, static_cast<const double2*>(in) + r * n, a, s);
+      dslash<T>(op, a, b, s);
+      from_nat<T>(c, 0, n, b, static_cast<double2*>(out) + r * n, s);
+    }
+  }
+}
+
+Hierarchy& H_(ddamg_hier h) {
+  DD_REQUIRE(h != nullptr && h->h, "null hierarchy");
+  return *h->h;
+}
+
+// Each *_impl loops over the right-hand sides; with the canonical layout it
+// converts through the hierarchy's scratch fields.
+template <typename T>
+void apply_Dc_impl(Hierarchy& H, int level, const void* in, void* out, int nrhs, int layout) {
+  const long long n = H.lv[level].n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      H.apply<T>(level, static_cast<const C<T>*>(in) + r * n, static_cast<C<T>*>(out) + r * n);
+    } else {
+      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
+      C<T>* b = ensure(hier_scratch<T>(H, 1), n);
+      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(in) + r * n, a, H.s);
+      H.apply<T>(level, a, b);
+      from_nat<T>(*H.ctx, level, n, b, static_cast<double2*>(out) + r * n, H.s);
+    }
+  }
+}
+
+template <typename T>
+void restrict_impl(Hierarchy& H, int level, const void* fine, void* coarse, int nrhs, int layout) {
+  const long long nf = H.lv[level].n, nc = H.lv[level + 1].n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      H.restrict_to<T>(level, static_cast<const C<T>*>(fine) + r * nf, static_cast<C<T>*>(coarse) + r * nc);
+    } else {
+      C<T>* a = ensure(hier_scratch<T>(H, 0), nf);
+      C<T>* b = ensure(hier_scratch<T>(H, 1), nf);
+      to_nat<T>(*H.ctx, level, nf, static_cast<const double2*>(fine) + r * nf, a, H.s);
+      H.restrict_to<T>(level, a, b);
+      from_nat<T>(*H.ctx, level + 1, nc, b, static_cast<double2*>(coarse) + r * nc, H.s);
+    }
+  }
+}
+
+template <typename T>
+void prolong_impl(Hierarchy& H, int level, const void* coarse, void* fine, int nrhs, int layout) {
+  const long long nf = H.lv[level].n, nc = H.lv[level + 1].n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      H.prolong_add<T>(level, static_cast<const C<T>*>(coarse) + r * nc, static_cast<C<T>*>(fine) + r * nf);
+    } else {
+      C<T>* a = ensure(hier_scratch<T>(H, 0), nf);
+      C<T>* b = ensure(hier_scratch<T>(H, 1), nf);
+      to_nat<T>(*H.ctx, level, nf, static_cast<const double2*>(fine) + r * nf, a, H.s);
+      to_nat<T>(*H.ctx, level + 1, nc, static_cast<const double2*>(coarse) + r * nc, b, H.s);
+      H.prolong_add<T>(level, b, a);
+      from_nat<T>(*H.ctx, level, nf, a, static_cast<double2*>(fine) + r * nf, H.s);
+    }
+  }
+}
+
+template <typename T>
+void sap_impl(Hierarchy& H, int level, const void* b, void* z, int nsweeps, int nrhs, int layout) {
+  const long long n = H.lv[level].n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      H.sap<T>(level, static_cast<const C<T>*>(b) + r * n, static_cast<C<T>*>(z) + r * n, nsweeps);
+    } else {
+      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
+      C<T>* c = ensure(hier_scratch<T>(H, 1), n);
+      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(b) + r * n, a, H.s);
+      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(z) + r * n, c, H.s);
+      H.sap<T>(level, a, c, nsweeps);
+      from_nat<T>(*H.ctx, level, n, c, static_cast<double2*>(z) + r * n, H.s);
+    }
+  }
+}
+
+template <typename T>
+void precondition_impl(Hierarchy& H, const void* b, void* z, int nrhs, int layout) {
+  const long long n = H.lv[0].n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (layout == DDAMG_NATIVE) {
+      // the cycle writes z before reading it; b must stay intact
+      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
+      vcopy<T, T>(static_cast<const C<T>*>(b) + r * n, a, n, H.s);
+      H.cycle<T>(0, a, static_cast<C<T>*>(z) + r * n);
+    } else {
+      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
+      C<T>* c = ensure(hier_scratch<T>(H, 1), n);
+      to_nat<T>(*H.ctx, 0, n, static_cast<const double2*>(b) + r * n, a, H.s);
+      H.cycle<T>(0, a, c);
+      from_nat<T>(*H.ctx, 0, n, c, static_cast<double2*>(z) + r * n, H.s);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ddamg_last_error(void) { return g_err.c_str(); }
+
+const char* ddamg_version(void) { return "ddamg-gfx950 0.1"; }
+
+void ddamg_params_default(ddamg_params* p, int levels) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->levels = levels;
+  for (int l = 0; l < 3; ++l)
+    for (int mu = 0; mu < 4; ++mu) p->agg[l][mu] = l == 0 ? 4 : 2;
+  for (int l = 0; l < 3; ++l) p->ntv[l] = 20;
+  for (int mu = 0; mu < 4; ++mu) p->sap_block[mu] = 2;
+  p->mu = 0;
+  p->nu = 5;
+  p->mr_iters = 3;
+  p->n_inv = 6;
+  p->coarse_eps = 5e-2;
+  p->coarse_restart = 30;
+  p->coarse_max_restarts = 10;
+  p->kc_len = 5;
+  p->kc_restarts = 2;
+  p->kc_tol = 1e-1;
+  p->nkv = 10;
+  p->tol = 1e-10;
+  p->max_restarts = 100;
+  p->precond_prec = DDAMG_F32;
+  p->cycle = DDAMG_KCYCLE;
+}
+
+int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {
+  return guarded([&] {
+    DD_REQUIRE(out != nullptr, "null output handle");
+    *out = nullptr;
+    std::unique_ptr<ddamg_ctx_s> h(new ddamg_ctx_s);
+    h->c.reset(create_context(lat, static_cast<const double2*>(links), as_stream(stream)));
+    *out = h.release();
+  });
+}
+
+void ddamg_destroy(ddamg_ctx ctx) { delete ctx; }
+
+int ddamg_apply_D(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, int layout,
+                  void* stream) {
+  return guarded([&] {
+    DD_REQUIRE(ctx && ctx->c, "null context");
+    DD_REQUIRE(in && out && in != out, "in/out must be distinct device pointers");
+    DD_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    check_prec(prec);
+    check_layout(layout);
+    if (prec == DDAMG_F64) apply_D_impl<double>(*ctx->c, in, out, nrhs, layout, as_stream(stream));
+    else apply_D_impl<float>(*ctx->c, in, out, nrhs, layout, as_stream(stream));
+  });
+}
+
+int ddamg_to_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in, void* out, int nrhs,
+                    int prec, void* stream) {
+  return guarded([&] {
+    DD_REQUIRE(ctx && ctx->c && in && out && nrhs >= 1, "bad argument");
+    check_prec(prec);
+    hipStream_t s = as_stream(stream);
+    Context& c = *ctx->c;
+    if (level == 0) {
+      if (prec == DDAMG_F64) fine_to_native<double>(c.g, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, s);
+      else fine_to_native<float>(c.g, static_cast<const double2*>(in), static_cast<float2*>(out), nrhs, s);
+    } else {
+      Hierarchy& H = H_(hier);
+      DD_REQUIRE(level < H.L, "level out of range");
+      const long long n = H.lv[level].n * nrhs;
+      if (prec == DDAMG_F64) vcopy<double, double>(static_cast<const double2*>(in), static_cast<double2*>(out), n, s);
+      else vcopy<double, float>(static_cast<const double2*>(in), static_cast<float2*>(out), n, s);
+    }
+  });
+}
+
+int ddamg_from_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in, void* out, int nrhs,
+                      int prec, void* stream) {
+  return guarded([&] {
+    DD_REQUIRE(ctx && ctx->c && in && out && nrhs >= 1, "bad argument");
+    check_prec(prec);
+    hipStream_t s = as_stream(stream);
+    Context& c = *ctx->c;
+    if (level == 0) {
+      if (prec == DDAMG_F64) fine_from_native<double>(c.g, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, s);
+      else fine_from_native<float>(c.g, static_cast<const float2*>(in), static_cast<double2*>(out), nrhs, s);
+    } else {
+      Hierarchy& H = H_(hier);
+      DD_REQUIRE(level < H.L, "level out of range");
+      const long long n = H.lv[level].n * nrhs;
+      if (prec == DDAMG_F64) vcopy<double, double>(static_cast<const double2*>(in), static_cast<double2*>(out), n, s);
+      else vcopy<float, double>(static_cast<const float2*>(in), static_cast<double2*>(out), n, s);
+    }
+  });
+}
+
+int ddamg_build_hierarchy(ddamg_ctx ctx, const ddamg_params* params, const void* tv,
+                          const void* tv_extra, void* stream, ddamg_hier* out) {
+  return guarded([&] {
+    DD_REQUIRE(ctx && ctx->c, "null context");
+    DD_REQUIRE(out != nullptr, "null output handle");
+    *out = nullptr;
+    std::unique_ptr<ddamg_hier_s> h(new ddamg_hier_s);
+    h->owner = ctx;
+    h->h.reset(create_hierarchy(ctx->c.get(), params, static_cast<const double2*>(tv),
+                                static_cast<const double2*>(tv_extra), as_stream(stream)));
+    *out = h.release();
+  });
+}
+
+void ddamg_destroy_hierarchy(ddamg_hier hier) { delete hier; }
+
+int ddamg_level_info(ddamg_hier hier, int level, int dims_out[4], int* dof_out) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L, "level out of range");
+    if (dims_out) for (int mu = 0; mu < 4; ++mu) dims_out[mu] = H.lv[level].dims[mu];
+    if (dof_out) *dof_out = H.lv[level].d;
+  });
+}
+
+int ddamg_apply_Dc(ddamg_hier hier, int level, const void* in, void* out, int nrhs, int prec,
+                   int layout, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L, "level out of range");
+    DD_REQUIRE(in && out && in != out && nrhs >= 1, "bad argument");
+    check_prec(prec);
+    check_layout(layout);
+    H.s = as_stream(stream);
+    if (prec == DDAMG_F64) apply_Dc_impl<double>(H, level, in, out, nrhs, layout);
+    else apply_Dc_impl<float>(H, level, in, out, nrhs, layout);
+  });
+}
+
+int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, int nrhs, int prec,
+                   int layout, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
+    DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
+    check_prec(prec);
+    check_layout(layout);
+    H.s = as_stream(stream);
+    if (prec == DDAMG_F64) restrict_impl<double>(H, level, fine, coarse, nrhs, layout);
+    else restrict_impl<float>(H, level, fine, coarse, nrhs, layout);
+  });
+}
+
+int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, int nrhs, int prec,
+                  int layout, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
+    DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
+    check_prec(prec);
+    check_layout(layout);
+    H.s = as_stream(stream);
+    if (prec == DDAMG_F64) prolong_impl<double>(H, level, coarse, fine, nrhs, layout);
+    else prolong_impl<float>(H, level, coarse, fine, nrhs, layout);
+  });
+}
+
+int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsweeps, int nrhs,
+                     int prec, int layout, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L - 1, "SAP is defined on levels 0..L-2");
+    DD_REQUIRE(b && z && b != z && nrhs >= 1 && nsweeps >= 0, "bad argument");
+    check_prec(prec);
+    check_layout(layout);
+    H.s = as_stream(stream);
+    if (prec == DDAMG_F64) sap_impl<double>(H, level, b, z, nsweeps, nrhs, layout);
+    else sap_impl<float>(H, level, b, z, nsweeps, nrhs, layout);
+  });
+}
+
+int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int layout, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
+    check_layout(layout);
+    H.s = as_stream(stream);
+    if (H.p.precond_prec == DDAMG_F64) precondition_impl<double>(H, b, z, nrhs, layout);
+    else precondition_impl<float>(H, b, z, nrhs, layout);
+  });
+}
+
+int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
+                void* stream) {
+  int worst = DDAMG_OK;
+  int rc = guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
+    H.s = as_stream(stream);
+    const long long n = H.lv[0].n;
+    for (int r = 0; r < nrhs; ++r) {
+      auto t0 = std::chrono::steady_clock::now();
+      ddamg_solve_stats st;
+      std::memset(&st, 0, sizeof(st));
+      H.kc_iters = 0;
+      H.cs_iters = 0;
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r * n, H.ob.p, 1, H.s);
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r * n, H.ox.p, 1, H.s);
+      int st_rc;
+      if (H.p.precond_prec == DDAMG_F64) st_rc = H.outer<double>(H.ob.p, H.ox.p, &st);
+      else st_rc = H.outer<float>(H.ob.p, H.ox.p, &st);
+      fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r * n, 1, H.s);
+      DD_CHECK_HIP(hipStreamSynchronize(H.s));
+      st.kcycle_iters = H.kc_iters;
+      st.coarsest_iters = H.cs_iters;
+      st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (stats) stats[r] = st;
+      if (st_rc != DDAMG_OK && worst == DDAMG_OK) worst = st_rc;
+    }
+  });
+  if (rc != DDAMG_OK) return rc;
+  if (worst == DDAMG_ENOCONV) g_err = "outer FGMRES reached max_restarts before tol";
+  if (worst == DDAMG_ENONFINITE) g_err = "non-finite value in b or in a residual";
+  return worst;
+}
+
+int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
+    DD_REQUIRE(out != nullptr, "null output");
+    hipStream_t s = as_stream(stream);
+    const LevelStore& S = H.lv[level];
+    if (level == 0) fine_from_native<double>(H.ctx->g, S.P64.p, static_cast<double2*>(out), S.N, s);
+    else vcopy<double, double>(S.P64.p, static_cast<double2*>(out), (long long)S.N * S.n, s);
+  });
+}
+
+int ddamg_export_coarse_op(ddamg_hier hier, int level, void* out, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 1 && level < H.L, "level out of range (coarse levels are 1..L-1)");
+    DD_REQUIRE(out != nullptr, "null output");
+    export_coarse(H.lv[level].cview<double>(), static_cast<double2*>(out), as_stream(stream));
+  });
+}
+
+int ddamg_import_test_vectors(ddamg_hier hier, int level, const void* tv, void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
+    DD_REQUIRE(tv != nullptr, "null test vectors");
+    H.s = as_stream(stream);
+    LevelStore& S = H.lv[level];
+    const double2* in = static_cast<const double2*>(tv);
+    if (level == 0) fine_to_native<double>(H.ctx->g, in, S.tv64.p, S.N, H.s);
+    else vcopy<double, double>(in, S.tv64.p, (long long)S.N * S.n, H.s);
+    if (H.p.precond_prec == DDAMG_F32) vcopy<double, float>(S.tv64.p, S.tv32.p, (long long)S.N * S.n, H.s);
+    H.build_level(level, false);
+  });
+}
+
+}  // extern "C"

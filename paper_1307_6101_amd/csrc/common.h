@@ -1,0 +1,92 @@
+// Shared helpers of the gfx950 DD-alpha-AMG library: complex arithmetic on
+// HIP vector types, error handling, launch helpers and wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace ddamg {
+
+// ---------------------------------------------------------------------------
+// Errors.  Internal code throws ddamg::Error; the C ABI turns it into a
+// status code and a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  int status;
+  Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define DD_CHECK_HIP(call)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::ddamg::Error(-3, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define DD_REQUIRE(cond, msg)                                   \
+  do {                                                          \
+    if (!(cond)) throw ::ddamg::Error(-1, std::string(msg));    \
+  } while (0)
+
+#define DD_LAUNCH_CHECK() DD_CHECK_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Complex numbers: double2 / float2 with (x, y) = (re, im).
+// ---------------------------------------------------------------------------
+template <typename T> struct cplx;
+template <> struct cplx<double> { using type = double2; };
+template <> struct cplx<float> { using type = float2; };
+template <typename T> using C = typename cplx<T>::type;
+
+template <typename T> __host__ __device__ inline C<T> mk(T re, T im) {
+  C<T> c; c.x = re; c.y = im; return c;
+}
+template <typename T> __host__ __device__ inline C<T> czero() { return mk<T>(T(0), T(0)); }
+template <typename V> __host__ __device__ inline V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+template <typename V> __host__ __device__ inline V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename V> __host__ __device__ inline V cmul(V a, V b) {
+  V c; c.x = a.x * b.x - a.y * b.y; c.y = a.x * b.y + a.y * b.x; return c;
+}
+// conj(a) * b
+template <typename V> __host__ __device__ inline V cjmul(V a, V b) {
+  V c; c.x = a.x * b.x + a.y * b.y; c.y = a.x * b.y - a.y * b.x; return c;
+}
+template <typename V> __host__ __device__ inline V cconj(V a) { a.y = -a.y; return a; }
+// acc += a * b
+template <typename V> __host__ __device__ inline void cfma(V& acc, V a, V b) {
+  acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+}
+// acc += conj(a) * b
+template <typename V> __host__ __device__ inline void cjfma(V& acc, V a, V b) {
+  acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+}
+template <typename V, typename S> __host__ __device__ inline V cscale(V a, S s) {
+  a.x *= s; a.y *= s; return a;
+}
+// multiply by i
+template <typename V> __host__ __device__ inline V cmuli(V a) { V c; c.x = -a.y; c.y = a.x; return c; }
+template <typename V> __host__ __device__ inline V cmulmi(V a) { V c; c.x = a.y; c.y = -a.x; return c; }
+
+// conversion between precisions
+template <typename To, typename From> __host__ __device__ inline C<To> ccast(From a) {
+  return mk<To>(static_cast<To>(a.x), static_cast<To>(a.y));
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-level reductions (64 lanes) within groups of `width` lanes.
+// ---------------------------------------------------------------------------
+template <int WIDTH, typename T> __device__ inline T group_sum(T v) {
+#pragma unroll
+  for (int off = WIDTH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WIDTH);
+  return v;
+}
+
+inline unsigned nblocks(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace ddamg

@@ -1,0 +1,465 @@
+// Fine-lattice kernels: layout conversion, clover construction, the
+// Wilson-clover stencil and the red-black SAP colour pass with block MR.
+//
+// Operator (the paper's eq. (1); definition of D as in the two-level
+// predecessor, textbook Sheikholeslami-Wohlert form):
+//   (D psi)(x) = A(x) psi(x) - 1/2 sum_mu [ (1-g_mu) U_mu(x) psi(x+mu)
+//                                         + (1+g_mu) U_mu(x-mu)^H psi(x-mu) ]
+//   A(x) = (m0+4) - c_sw/16 sum_{mu<nu} g_mu g_nu (x) (Q_mu,nu - Q_mu,nu^H),
+// chiral gamma basis, Gamma5 = diag(1,1,-1,-1): A(x) is block diagonal with
+// one Hermitian 6x6 block per chirality.
+//
+// Spin projection.  With g_mu = [[0, B_mu],[B_mu^H, 0]], (1 -+ g_mu) psi is
+// fixed by its upper half h = (psi_0 + c0 psi_j0, psi_1 + c1 psi_j1), with
+// (j0, c0, j1, c1) = (3, i, 2, i), (3, 1, 2, -1), (2, i, 3, -i), (2, -1, 3, -1)
+// for mu = 0..3 in the forward hop and c -> -c in the backward hop; the lower
+// half is rebuilt as out_j0 += conj(c0) chi_0, out_j1 += conj(c1) chi_1 with
+// chi = U h.  So each hop moves 6 instead of 12 complex numbers through the
+// SU(3) multiply.
+#include "fine.h"
+#include "fine_dev.h"
+
+#include <vector>
+
+namespace ddamg {
+
+FineGeom make_fine_geom(const int dims[4]) {
+  FineGeom g;
+  g.V = 1;
+  g.nblk = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    g.dims[mu] = dims[mu];
+    g.nb[mu] = dims[mu] / 2;
+    g.V *= dims[mu];
+    g.nblk *= g.nb[mu];
+  }
+  return g;
+}
+
+void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks) {
+  int n[2] = {0, 0};
+  const int half = g.nblk / 2;
+  for (int b = 0; b < g.nblk; ++b) {
+    int c[4], r = b;
+    for (int mu = 0; mu < 4; ++mu) { c[mu] = r % g.nb[mu]; r /= g.nb[mu]; }
+    for (int mu = 0; mu < 4; ++mu) {
+      for (int dir = 0; dir < 2; ++dir) {
+        int cc[4] = {c[0], c[1], c[2], c[3]};
+        cc[mu] = (cc[mu] + (dir == 0 ? 1 : g.nb[mu] - 1)) % g.nb[mu];
+        nbr_blk[b * 8 + 2 * mu + dir] =
+            cc[0] + g.nb[0] * (cc[1] + g.nb[1] * (cc[2] + g.nb[2] * cc[3]));
+      }
+    }
+    int col = (c[0] + c[1] + c[2] + c[3]) & 1;
+    colour_blocks[col * half + n[col]++] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+struct DevGeom {
+  int X, Y, Z, T, nb0, nb1, nb2;
+  long long V;
+};
+static DevGeom devgeom(const FineGeom& g) {
+  return DevGeom{g.dims[0], g.dims[1], g.dims[2], g.dims[3], g.nb[0], g.nb[1], g.nb[2], g.V};
+}
+
+__device__ inline void canonical_to_native(const DevGeom& g, long long i, int& blk, int& loc) {
+  int x = (int)(i % g.X);
+  long long r = i / g.X;
+  int y = (int)(r % g.Y);
+  r /= g.Y;
+  int z = (int)(r % g.Z);
+  int t = (int)(r / g.Z);
+  blk = (x >> 1) + g.nb0 * ((y >> 1) + g.nb1 * ((z >> 1) + g.nb2 * (t >> 1)));
+  loc = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((t & 1) << 3);
+}
+
+__device__ inline long long canon_index(const DevGeom& g, int x, int y, int z, int t) {
+  x = (x + g.X) % g.X;
+  y = (y + g.Y) % g.Y;
+  z = (z + g.Z) % g.Z;
+  t = (t + g.T) % g.T;
+  return x + (long long)g.X * (y + (long long)g.Y * (z + (long long)g.Z * t));
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_to_native(DevGeom g, const double2* __restrict__ in, C<T>* __restrict__ out) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const long long off = (long long)blockIdx.y * g.V * 12;
+  int blk, loc;
+  canonical_to_native(g, i, blk, loc);
+#pragma unroll
+  for (int c = 0; c < 12; ++c)
+    out[off + ((long long)blk * 12 + c) * 16 + loc] = ccast<T>(in[off + i * 12 + c]);
+}
+
+template <typename T>
+__global__ void k_from_native(DevGeom g, const C<T>* __restrict__ in, double2* __restrict__ out) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const long long off = (long long)blockIdx.y * g.V * 12;
+  int blk, loc;
+  canonical_to_native(g, i, blk, loc);
+#pragma unroll
+  for (int c = 0; c < 12; ++c)
+    out[off + i * 12 + c] = ccast<double>(in[off + ((long long)blk * 12 + c) * 16 + loc]);
+}
+
+template <typename T>
+__global__ void k_links_to_native(DevGeom g, const double2* __restrict__ in, C<T>* __restrict__ out) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int blk, loc;
+  canonical_to_native(g, i, blk, loc);
+  for (int e = 0; e < 36; ++e)
+    out[((long long)blk * 36 + e) * 16 + loc] = ccast<T>(in[i * 36 + e]);
+}
+
+template <typename T>
+void fine_to_native(const FineGeom& g, const double2* in, C<T>* out, int nrhs, hipStream_t s) {
+  dim3 grid(nblocks(g.V, 256), nrhs);
+  k_to_native<T><<<grid, 256, 0, s>>>(devgeom(g), in, out);
+  DD_LAUNCH_CHECK();
+}
+template <typename T>
+void fine_from_native(const FineGeom& g, const C<T>* in, double2* out, int nrhs, hipStream_t s) {
+  dim3 grid(nblocks(g.V, 256), nrhs);
+  k_from_native<T><<<grid, 256, 0, s>>>(devgeom(g), in, out);
+  DD_LAUNCH_CHECK();
+}
+template <typename T>
+void links_to_native(const FineGeom& g, const double2* links, C<T>* out, hipStream_t s) {
+  k_links_to_native<T><<<nblocks(g.V, 256), 256, 0, s>>>(devgeom(g), links, out);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// clover construction (FP64, canonical links in, native packed out)
+// ---------------------------------------------------------------------------
+struct M3 { double2 e[9]; };
+
+__device__ inline M3 load_link(const double2* L, long long site, int mu) {
+  M3 m;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m.e[k] = L[(site * 4 + mu) * 9 + k];
+  return m;
+}
+// a * b, a^H * b, a * b^H
+__device__ inline M3 mm(const M3& a, const M3& b) {
+  M3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = czero<double>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(s, a.e[i * 3 + k], b.e[k * 3 + j]);
+      c.e[i * 3 + j] = s;
+    }
+  return c;
+}
+__device__ inline M3 mhm(const M3& a, const M3& b) {
+  M3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = czero<double>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cjfma(s, a.e[k * 3 + i], b.e[k * 3 + j]);
+      c.e[i * 3 + j] = s;
+    }
+  return c;
+}
+__device__ inline M3 mmh(const M3& a, const M3& b) {
+  M3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = czero<double>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(s, a.e[i * 3 + k], cconj(b.e[j * 3 + k]));
+      c.e[i * 3 + j] = s;
+    }
+  return c;
+}
+
+// chiral-basis gamma matrices, entries as (re, im)
+__constant__ double c_gamma[4][4][4][2] = {
+    {{{0, 0}, {0, 0}, {0, 0}, {0, -1}}, {{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 1}, {0, 0}, {0, 0}}, {{0, 1}, {0, 0}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {0, 0}, {-1, 0}}, {{0, 0}, {0, 0}, {1, 0}, {0, 0}},
+     {{0, 0}, {1, 0}, {0, 0}, {0, 0}}, {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {0, -1}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}, {0, 1}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, -1}, {0, 0}, {0, 0}}},
+    {{{0, 0}, {0, 0}, {1, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}, {1, 0}},
+     {{1, 0}, {0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {1, 0}, {0, 0}, {0, 0}}}};
+
+__device__ inline double2 gam(int mu, int a, int b) {
+  return mk<double>(c_gamma[mu][a][b][0], c_gamma[mu][a][b][1]);
+}
+
+__global__ void k_clover(DevGeom g, const double2* __restrict__ L, double m0, double csw,
+                         double2* __restrict__ out) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int xc[4];
+  {
+    long long r = i;
+    xc[0] = (int)(r % g.X); r /= g.X;
+    xc[1] = (int)(r % g.Y); r /= g.Y;
+    xc[2] = (int)(r % g.Z); xc[3] = (int)(r / g.Z);
+  }
+  auto nbr = [&](int mu, int smu, int nu, int snu) {
+    int c[4] = {xc[0], xc[1], xc[2], xc[3]};
+    c[mu] += smu;
+    c[nu] += snu;
+    return canon_index(g, c[0], c[1], c[2], c[3]);
+  };
+  // A_chi[6][6], chi = 0 (spins 0,1), 1 (spins 2,3)
+  double2 A[2][6][6];
+  for (int h = 0; h < 2; ++h)
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) A[h][a][b] = czero<double>();
+  if (csw != 0.0) {
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        M3 Um = load_link(L, i, mu), Un = load_link(L, i, nu);
+        M3 Um_pn = load_link(L, nbr(nu, 1, mu, 0), mu);      // U_mu(x+nu)
+        M3 Un_pm = load_link(L, nbr(mu, 1, nu, 0), nu);      // U_nu(x+mu)
+        M3 Um_mm = load_link(L, nbr(mu, -1, nu, 0), mu);     // U_mu(x-mu)
+        M3 Un_mm = load_link(L, nbr(mu, -1, nu, 0), nu);     // U_nu(x-mu)
+        M3 Um_pnmm = load_link(L, nbr(mu, -1, nu, 1), mu);   // U_mu(x+nu-mu)
+        M3 Um_mmmn = load_link(L, nbr(mu, -1, nu, -1), mu);  // U_mu(x-mu-nu)
+        M3 Un_mmmn = load_link(L, nbr(mu, -1, nu, -1), nu);  // U_nu(x-mu-nu)
+        M3 Um_mn = load_link(L, nbr(nu, -1, mu, 0), mu);     // U_mu(x-nu)
+        M3 Un_mn = load_link(L, nbr(nu, -1, mu, 0), nu);     // U_nu(x-nu)
+        M3 Un_mnpm = load_link(L, nbr(mu, 1, nu, -1), nu);   // U_nu(x-nu+mu)
+        // four counter-clockwise leaves at x
+        M3 q1 = mmh(mmh(mm(Um, Un_pm), Um_pn), Un);
+        // Un(x) Um(x+nu-mu)^H Un(x-mu)^H Um(x-mu)
+        M3 q2 = mm(mmh(mmh(Un, Um_pnmm), Un_mm), Um_mm);
+        // leaf 3: Um(x-mu)^H Un(x-mu-nu)^H Um(x-mu-nu) Un(x-nu)
+        M3 t3 = mhm(Un_mmmn, mm(Um_mmmn, Un_mn));           // Un(x-mu-nu)^H Um(x-mu-nu) Un(x-nu)
+        M3 l3 = mhm(Um_mm, t3);
+        // leaf 4: Un(x-nu)^H Um(x-nu) Un(x-nu+mu) Um(x)^H
+        M3 l4 = mmh(mhm(Un_mn, mm(Um_mn, Un_mnpm)), Um);
+        M3 F;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) F.e[k] = cadd(cadd(q1.e[k], q2.e[k]), cadd(l3.e[k], l4.e[k]));
+        // F <- Q - Q^H
+        M3 Fa;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) Fa.e[a * 3 + b] = csub(F.e[a * 3 + b], cconj(F.e[b * 3 + a]));
+        // sigma = g_mu g_nu (block diagonal in chirality)
+        for (int h = 0; h < 2; ++h)
+          for (int s = 0; s < 2; ++s)
+            for (int sp = 0; sp < 2; ++sp) {
+              double2 sg = czero<double>();
+              for (int k = 0; k < 4; ++k) cfma(sg, gam(mu, 2 * h + s, k), gam(nu, k, 2 * h + sp));
+              sg = cscale(sg, -csw / 16.0);
+              for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) cfma(A[h][s * 3 + a][sp * 3 + b], sg, Fa.e[a * 3 + b]);
+            }
+      }
+  }
+  int blk, loc;
+  canonical_to_native(g, i, blk, loc);
+  double2* o = out + (long long)blk * 36 * 16 + loc;
+  for (int h = 0; h < 2; ++h) {
+    double d[6];
+    for (int a = 0; a < 6; ++a) d[a] = A[h][a][a].x + (m0 + 4.0);
+    for (int k = 0; k < 3; ++k) o[(h * 18 + k) * 16] = mk<double>(d[2 * k], d[2 * k + 1]);
+    int e = 3;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a + 1; b < 6; ++b) o[(h * 18 + e++) * 16] = A[h][a][b];
+  }
+}
+
+void clover_build(const FineGeom& g, const double2* links, double m0, double csw, double2* out,
+                  hipStream_t s) {
+  k_clover<<<nblocks(g.V, 128), 128, 0, s>>>(devgeom(g), links, m0, csw, out);
+  DD_LAUNCH_CHECK();
+}
+
+template <typename T, int MU>
+__device__ inline void hops_mu(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk, int loc,
+                               C<T> acc[12]) {
+  constexpr int bit = 1 << MU;
+  C<T> psi[12], u[9];
+  // forward: psi(x+mu), U_mu(x)
+  {
+    int nb = (loc & bit) ? op.nbr[blk * 8 + 2 * MU] : blk;
+    load_spinor<T>(in, nb, loc ^ bit, psi);
+    load_link<T>(op.U, blk, loc, MU, u);
+    hop_apply<T, MU, true>(psi, u, acc);
+  }
+  // backward: psi(x-mu), U_mu(x-mu)^H
+  {
+    int nb = (loc & bit) ? blk : op.nbr[blk * 8 + 2 * MU + 1];
+    load_spinor<T>(in, nb, loc ^ bit, psi);
+    load_link<T>(op.U, nb, loc ^ bit, MU, u);
+    hop_apply<T, MU, false>(psi, u, acc);
+  }
+}
+
+// out(x) = (D in)(x) for one site
+template <typename T>
+__device__ inline void dslash_site(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk,
+                                   int loc, C<T> out[12]) {
+  C<T> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
+  hops_mu<T, 0>(op, in, blk, loc, acc);
+  hops_mu<T, 1>(op, in, blk, loc, acc);
+  hops_mu<T, 2>(op, in, blk, loc, acc);
+  hops_mu<T, 3>(op, in, blk, loc, acc);
+  C<T> psi[12];
+  load_spinor<T>(in, blk, loc, psi);
+  clover_apply<T>(op.A, blk, loc, psi, out);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    out[c].x -= T(0.5) * acc[c].x;
+    out[c].y -= T(0.5) * acc[c].y;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dslash(FineOpView<T> op, const C<T>* __restrict__ in,
+                                                C<T>* __restrict__ out) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15;
+  if (blk >= op.nblk) return;
+  C<T> o[12];
+  dslash_site<T>(op, in, blk, loc, o);
+  C<T>* p = out + (long long)blk * 192 + loc;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
+}
+
+template <typename T>
+void dslash(const FineOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s) {
+  k_dslash<T><<<nblocks((size_t)op.nblk * 16, 256), 256, 0, s>>>(op, in, out);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// SAP colour pass.  One thread per site, 16 lanes per 2^4 block, 16 blocks
+// per workgroup.  r = b - D z with the full operator, then mr_iters minimal
+// residual steps on the Dirichlet block operator D_i (self term + the four
+// in-block hops, partner spinors exchanged through LDS), z += x.
+// ---------------------------------------------------------------------------
+template <typename T, int MU>
+__device__ inline void inblock_hop(const FineOpView<T>& op, const C<T>* __restrict__ rs, int t, int blk,
+                                   int loc, C<T> acc[12]) {
+  constexpr int bit = 1 << MU;
+  C<T> psi[12], u[9];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
+  // the link joining loc and loc^bit belongs to the lower site of the pair
+  load_link<T>(op.U, blk, loc & ~bit, MU, u);
+  if (loc & bit) hop_apply<T, MU, false>(psi, u, acc);
+  else hop_apply<T, MU, true>(psi, u, acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int* __restrict__ cblk,
+                                                    int ncb, int mr_iters, const C<T>* __restrict__ b,
+                                                    C<T>* __restrict__ z) {
+  __shared__ C<T> rs[12 * 256];
+  const int t = threadIdx.x;
+  const int jb = blockIdx.x * 16 + (t >> 4);
+  const int loc = t & 15;
+  const bool valid = jb < ncb;
+  const int blk = valid ? cblk[jb] : 0;
+  C<T> rho[12], x[12];
+  if (valid) {
+    C<T> dz[12], bb[12];
+    dslash_site<T>(op, z, blk, loc, dz);
+    load_spinor<T>(b, blk, loc, bb);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = csub(bb[c], dz[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) x[c] = czero<T>();
+
+  for (int it = 0; it < mr_iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rs[c * 256 + t] = rho[c];
+    __syncthreads();
+    C<T> q[12], acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
+    if (valid) {
+      inblock_hop<T, 0>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, 1>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, 2>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, 3>(op, rs, t, blk, loc, acc);
+      clover_apply<T>(op.A, blk, loc, rho, q);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) q[c] = czero<T>();
+    }
+    T qr_re = 0, qr_im = 0, qq = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      q[c].x -= T(0.5) * acc[c].x;
+      q[c].y -= T(0.5) * acc[c].y;
+      qr_re += q[c].x * rho[c].x + q[c].y * rho[c].y;
+      qr_im += q[c].x * rho[c].y - q[c].y * rho[c].x;
+      qq += q[c].x * q[c].x + q[c].y * q[c].y;
+    }
+    qr_re = group_sum<16>(qr_re);
+    qr_im = group_sum<16>(qr_im);
+    qq = group_sum<16>(qq);
+    C<T> alpha = qq > T(0) ? mk<T>(qr_re / qq, qr_im / qq) : czero<T>();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      cfma(x[c], alpha, rho[c]);
+      C<T> aq = cmul(alpha, q[c]);
+      rho[c] = csub(rho[c], aq);
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    C<T>* p = z + (long long)blk * 192 + loc;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
+  }
+}
+
+template <typename T>
+void sap_colour(const FineOpView<T>& op, const int* colour_blocks, int colour, int mr_iters,
+                const C<T>* b, C<T>* z, hipStream_t s) {
+  const int ncb = op.nblk / 2;
+  k_sap_colour<T><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters,
+                                                   b, z);
+  DD_LAUNCH_CHECK();
+}
+
+// explicit instantiations
+#define DD_INST(T)                                                                              \
+  template void fine_to_native<T>(const FineGeom&, const double2*, C<T>*, int, hipStream_t);   \
+  template void fine_from_native<T>(const FineGeom&, const C<T>*, double2*, int, hipStream_t); \
+  template void links_to_native<T>(const FineGeom&, const double2*, C<T>*, hipStream_t);       \
+  template void dslash<T>(const FineOpView<T>&, const C<T>*, C<T>*, hipStream_t);              \
+  template void sap_colour<T>(const FineOpView<T>&, const int*, int, int, const C<T>*, C<T>*,   \
+                              hipStream_t);
+DD_INST(double)
+DD_INST(float)
+#undef DD_INST
+
+}  // namespace ddamg

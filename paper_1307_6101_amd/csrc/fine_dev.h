@@ -1,0 +1,106 @@
+// Device building blocks of the fine-lattice stencil (shared by the
+// Wilson-clover, SAP and Galerkin kernels).  See fine.hip for the spin
+// projection scheme.
+#pragma once
+
+#include "fine.h"
+
+namespace ddamg {
+
+// ---------------------------------------------------------------------------
+// stencil building blocks
+// ---------------------------------------------------------------------------
+// multiply by k-th power of i: 0: 1, 1: i, 2: -1, 3: -i
+template <int K, typename V> __device__ inline V mul_ik(V a) {
+  if constexpr (K == 0) return a;
+  else if constexpr (K == 1) return cmuli(a);
+  else if constexpr (K == 2) { a.x = -a.x; a.y = -a.y; return a; }
+  else return cmulmi(a);
+}
+
+template <int MU> struct Proj;
+template <> struct Proj<0> { static constexpr int J0 = 3, K0 = 1, J1 = 2, K1 = 1; };
+template <> struct Proj<1> { static constexpr int J0 = 3, K0 = 0, J1 = 2, K1 = 2; };
+template <> struct Proj<2> { static constexpr int J0 = 2, K0 = 1, J1 = 3, K1 = 3; };
+template <> struct Proj<3> { static constexpr int J0 = 2, K0 = 2, J1 = 3, K1 = 2; };
+
+// project the spinor psi (12 components) for the hop in direction MU
+// (FWD: (1-g_mu), else (1+g_mu)), multiply by the link (U or U^H), and add
+// the rebuilt spinor to acc.
+template <typename T, int MU, bool FWD>
+__device__ inline void hop_apply(const C<T> psi[12], const C<T> u[9], C<T> acc[12]) {
+  using P = Proj<MU>;
+  constexpr int k0 = FWD ? P::K0 : (P::K0 + 2) & 3;
+  constexpr int k1 = FWD ? P::K1 : (P::K1 + 2) & 3;
+  C<T> h[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h[a] = cadd(psi[a], mul_ik<k0>(psi[P::J0 * 3 + a]));
+    h[3 + a] = cadd(psi[3 + a], mul_ik<k1>(psi[P::J1 * 3 + a]));
+  }
+  C<T> chi[6];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C<T> v = czero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (FWD) cfma(v, u[a * 3 + b], h[s * 3 + b]);
+        else cjfma(v, u[b * 3 + a], h[s * 3 + b]);
+      }
+      chi[s * 3 + a] = v;
+    }
+  constexpr int c0 = (4 - k0) & 3, c1 = (4 - k1) & 3;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] = cadd(acc[a], chi[a]);
+    acc[3 + a] = cadd(acc[3 + a], chi[3 + a]);
+    acc[P::J0 * 3 + a] = cadd(acc[P::J0 * 3 + a], mul_ik<c0>(chi[a]));
+    acc[P::J1 * 3 + a] = cadd(acc[P::J1 * 3 + a], mul_ik<c1>(chi[3 + a]));
+  }
+}
+
+template <typename T>
+__device__ inline void load_spinor(const C<T>* __restrict__ f, int blk, int loc, C<T> v[12]) {
+  const C<T>* p = f + (long long)blk * 192 + loc;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = p[c * 16];
+}
+template <typename T>
+__device__ inline void load_link(const C<T>* __restrict__ U, int blk, int loc, int mu, C<T> u[9]) {
+  const C<T>* p = U + (long long)blk * 576 + mu * 144 + loc;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = p[k * 16];
+}
+
+// out = A(x) v (packed clover, both chiralities)
+template <typename T>
+__device__ inline void clover_apply(const C<T>* __restrict__ A, int blk, int loc, const C<T> v[12],
+                                    C<T> out[12]) {
+  const C<T>* p = A + (long long)blk * 576 + loc;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const C<T>* q = p + h * 18 * 16;
+    const C<T>* w = v + 6 * h;
+    C<T>* o = out + 6 * h;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      C<T> d = q[k * 16];
+      o[2 * k] = cscale(w[2 * k], d.x);
+      o[2 * k + 1] = cscale(w[2 * k + 1], d.y);
+    }
+    int e = 3;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a + 1; b < 6; ++b) {
+        C<T> m = q[e * 16];
+        ++e;
+        cfma(o[a], m, w[b]);
+        cjfma(o[b], m, w[a]);
+      }
+  }
+}
+
+}  // namespace ddamg

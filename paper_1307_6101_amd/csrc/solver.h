@@ -1,0 +1,150 @@
+// Host orchestration of the DD-alpha-AMG method on one GPU: the operator
+// context, the multilevel hierarchy, the K-/V-cycle (Alg. 2 / Alg. 1), the
+// flexible GMRES solvers, the odd-even coarsest solve and the two setup
+// phases (Alg. 3, Alg. 4).  Everything numerical runs in the kernels of
+// fine/coarse/transfer/blas; this layer only sequences launches and keeps
+// the small Krylov scalars (Hessenberg matrix, Givens rotations) on the host.
+#pragma once
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "../../include/ddamg.h"
+#include "blas.h"
+#include "coarse.h"
+#include "fine.h"
+#include "transfer.h"
+
+namespace ddamg {
+
+// RAII device array
+template <typename E>
+struct DevArray {
+  E* p = nullptr;
+  size_t n = 0;
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  DevArray& operator=(const DevArray&) = delete;
+  DevArray(DevArray&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevArray& operator=(DevArray&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevArray() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    if (hipMalloc(&p, count * sizeof(E)) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(DDAMG_ENOMEM, "device allocation of " + std::to_string(count * sizeof(E)) + " bytes failed");
+    }
+    n = count;
+  }
+  void upload(const std::vector<E>& v, hipStream_t s) {
+    alloc(v.size());
+    if (!v.empty())
+      DD_CHECK_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Context {
+  FineGeom g;
+  double m0 = 0, csw = 0;
+  DevArray<double2> U64, A64;
+  DevArray<float2> U32, A32;
+  DevArray<int> nbr, cblk;
+  DevArray<double2> s64a, s64b;   // scratch for canonical-layout calls
+  DevArray<float2> s32a, s32b;
+  template <typename T> FineOpView<T> view() const;
+};
+
+template <typename T>
+struct Work {
+  DevArray<C<T>> bin, z, r, rec, x, w, t1, t2, t3, t4;
+  DevArray<C<T>> V, Z;     // Krylov bases of this level
+  int m = 0;               // basis length
+};
+
+struct LevelStore {
+  bool fine = false;
+  int dims[4] = {0, 0, 0, 0};
+  int d = 12;
+  long long V = 0, n = 0;
+  // coarse operator (level >= 1)
+  CoarseGeom cg;
+  DevArray<int> c_nbr, c_blk_sites, c_site_blk, c_site_loc, c_even, c_odd;
+  DevArray<double2> D64, Einv64;
+  DevArray<float2> D32, Einv32;
+  // interpolation to the next level
+  int N = 0;
+  AggTables at;
+  DevArray<int> a_members, a_member_agg;
+  DevArray<double2> P64;
+  DevArray<float2> P32;
+  DevArray<double2> tv64;  // test vectors (FP64 storage; setup in the preconditioner precision uses tv32)
+  DevArray<float2> tv32;
+  AggDev ad() const { return AggDev{a_members.p, a_member_agg.p}; }
+  template <typename T> CoarseOpView<T> cview() const;
+};
+
+struct Hierarchy {
+  Context* ctx = nullptr;
+  ddamg_params p{};
+  int L = 0;
+  std::vector<LevelStore> lv;
+  std::vector<Work<double>> w64;
+  std::vector<Work<float>> w32;
+  // outer FGMRES (FP64 basis, preconditioned directions at the preconditioner precision)
+  DevArray<double2> oV, oZ64, ob, ox, ow, ot;
+  DevArray<float2> oZ32;
+  DevArray<double2> sc64a, sc64b;   // scratch for canonical-layout calls
+  DevArray<float2> sc32a, sc32b;
+  std::unique_ptr<Reducer> red;
+  hipStream_t s = nullptr;
+  bool recording = false;
+  long long kc_iters = 0, cs_iters = 0;
+  const double2* tv_extra = nullptr;
+
+  template <typename T> Work<T>& work(int l);
+  template <typename T> const C<T>* P(int l) const;
+  template <typename T> const C<T>* tv(int l) const;
+  template <typename T> C<T>* tv(int l);
+
+  // level operations at precision T
+  template <typename T> void apply(int l, const C<T>* in, C<T>* out);
+  template <typename T> void sap(int l, const C<T>* b, C<T>* z, int nsweeps);
+  template <typename T> void restrict_to(int l, const C<T>* fine, C<T>* coarse);
+  template <typename T> void prolong_add(int l, const C<T>* coarse, C<T>* fine);
+  template <typename T> void cycle(int l, const C<T>* b, C<T>* z);
+  template <typename T> void coarsest_solve(const C<T>* b, C<T>* z);
+  template <typename T> void schur(const C<T>* v, C<T>* out);
+  template <typename T, typename Op, typename Pre>
+  int fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m, int max_cycles,
+             double tol);
+  template <typename T> int outer(const double2* b, double2* x, ddamg_solve_stats* st);
+
+  // setup
+  template <typename T> void setup(const double2* tv_canonical);
+  template <typename T> void initial_setup(int l);
+  template <typename T> void iterative_setup(int l, int i);
+  // construct P_l (FP64 orthonormalisation) and D_{l+1} (FP64 Galerkin);
+  // from32: the FP32 test vectors are the current ones
+  void build_level(int l, bool from32);
+  template <typename T> void alloc_work();
+
+  double norm(const double2* v, long long n);
+};
+
+Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s);
+Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* p, const double2* tv,
+                            const double2* tv_extra, hipStream_t s);
+void validate_params(const Context& ctx, const ddamg_params& p);
+
+}  // namespace ddamg

@@ -1,0 +1,65 @@
+// Aggregation-based interpolation P_l: level l -> level l+1 (Sec. 1: P groups
+// spins 1,2 and spins 3,4 separately, R = P^H; Sec. 2.2 / Alg. 3, Alg. 4:
+// P_l built from the test vectors; Tab. 1: aggregates of 4^4 on the fine
+// level and 2^4 below).
+//
+// P_l is stored as N fields in the layout of level l: column k of every
+// (aggregate, chirality) block V_{A,sigma} sits in field k on the sites of A
+// and the components of sigma.  A coarse site is an aggregate (canonical
+// order of the coarse lattice); coarse component sigma*N + k.
+#pragma once
+
+#include <vector>
+
+#include "coarse.h"
+#include "fine.h"
+
+namespace ddamg {
+
+struct AggTables {
+  int agg[4];
+  int nagg;          // aggregates = coarse sites
+  int asz;           // sites per aggregate
+  // fine level: members are 2^4 blocks (asz/16 per aggregate); coarse: sites
+  std::vector<int> members;    // [nagg][asz/16 or asz]
+  std::vector<int> member_agg; // [nblk or V] aggregate of each member
+  int cdims[4];
+};
+
+AggTables make_fine_agg(const FineGeom& g, const int agg[4]);
+AggTables make_coarse_agg(const CoarseGeom& g, const int agg[4]);
+
+struct AggDev {
+  int* members = nullptr;
+  int* member_agg = nullptr;
+};
+
+// restriction out = P^H in and prolongation out += P in
+template <typename T>
+void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const C<T>* P,
+                   const C<T>* in, C<T>* out, hipStream_t s);
+template <typename T>
+void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const C<T>* P, const C<T>* in,
+                  C<T>* out, hipStream_t s);
+template <typename T>
+void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
+                     const C<T>* P, const C<T>* in, C<T>* out, hipStream_t s);
+template <typename T>
+void prolong_coarse(const AggDev& ad, int d, int N, long long V, const C<T>* P, const C<T>* in,
+                    C<T>* out, hipStream_t s);
+
+// orthonormalise the N test-vector fields tv (FP64, layout of level l) per
+// (aggregate, chirality) in index order (Gram-Schmidt with one
+// re-orthogonalisation pass); result written to P.
+void orthonormalise_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
+                         const double2* tv, double2* P, hipStream_t s);
+void orthonormalise_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
+                           const double2* tv, double2* P, hipStream_t s);
+
+// Galerkin D_{l+1} = P^H D_l P in FP64: self and forward blocks, [nagg][5][2N][2N]
+void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
+                   const FineOpView<double>& op, const double2* P, double2* Dc, hipStream_t s);
+void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad, int N,
+                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s);
+
+}  // namespace ddamg

@@ -1,0 +1,593 @@
+// Interpolation kernels: restriction P^H, prolongation P, block
+// orthonormalisation of the test vectors and the FP64 Galerkin products.
+#include "coarse_dev.h"
+#include "fine_dev.h"
+#include "transfer.h"
+
+namespace ddamg {
+
+AggTables make_fine_agg(const FineGeom& g, const int agg[4]) {
+  AggTables a;
+  a.nagg = 1;
+  a.asz = 1;
+  int bpa[4], na[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    a.agg[mu] = agg[mu];
+    DD_REQUIRE(agg[mu] % 2 == 0 && g.dims[mu] % agg[mu] == 0,
+               "fine aggregates must be even and tile the lattice");
+    na[mu] = g.dims[mu] / agg[mu];
+    bpa[mu] = agg[mu] / 2;
+    a.cdims[mu] = na[mu];
+    a.nagg *= na[mu];
+    a.asz *= agg[mu];
+  }
+  const int nbpa = a.asz / 16;
+  a.members.resize((size_t)a.nagg * nbpa);
+  a.member_agg.resize(g.nblk);
+  for (int A = 0; A < a.nagg; ++A) {
+    int c[4], r = A;
+    for (int mu = 0; mu < 4; ++mu) { c[mu] = r % na[mu]; r /= na[mu]; }
+    for (int j = 0; j < nbpa; ++j) {
+      int l[4], rr = j;
+      for (int mu = 0; mu < 4; ++mu) { l[mu] = rr % bpa[mu]; rr /= bpa[mu]; }
+      int b[4];
+      for (int mu = 0; mu < 4; ++mu) b[mu] = c[mu] * bpa[mu] + l[mu];
+      int blk = b[0] + g.nb[0] * (b[1] + g.nb[1] * (b[2] + g.nb[2] * b[3]));
+      a.members[(size_t)A * nbpa + j] = blk;
+      a.member_agg[blk] = A;
+    }
+  }
+  return a;
+}
+
+AggTables make_coarse_agg(const CoarseGeom& g, const int agg[4]) {
+  AggTables a;
+  a.nagg = 1;
+  a.asz = 1;
+  int na[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    a.agg[mu] = agg[mu];
+    DD_REQUIRE(agg[mu] >= 1 && g.dims[mu] % agg[mu] == 0, "aggregates must tile the lattice");
+    na[mu] = g.dims[mu] / agg[mu];
+    a.cdims[mu] = na[mu];
+    a.nagg *= na[mu];
+    a.asz *= agg[mu];
+  }
+  a.members.resize((size_t)a.nagg * a.asz);
+  a.member_agg.resize(g.V);
+  for (int A = 0; A < a.nagg; ++A) {
+    int c[4], r = A;
+    for (int mu = 0; mu < 4; ++mu) { c[mu] = r % na[mu]; r /= na[mu]; }
+    for (int j = 0; j < a.asz; ++j) {
+      int l[4], rr = j;
+      for (int mu = 0; mu < 4; ++mu) { l[mu] = rr % agg[mu]; rr /= agg[mu]; }
+      int x[4];
+      for (int mu = 0; mu < 4; ++mu) x[mu] = c[mu] * agg[mu] + l[mu];
+      int s = x[0] + g.dims[0] * (x[1] + g.dims[1] * (x[2] + g.dims[2] * x[3]));
+      a.members[(size_t)A * a.asz + j] = s;
+      a.member_agg[s] = A;
+    }
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// per-(aggregate, chirality) reduction of 2N partial sums: each thread holds
+// for coarse row k the pair (sigma=0, sigma=1) of complex partials, which are
+// wave-reduced and collected in LDS as red[wave][k][4].
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void stash4(T* red, int N, int k, T a, T b, T c, T d) {
+  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
+  if ((threadIdx.x & 63) == 0) {
+    T* r = red + ((threadIdx.x >> 6) * N + k) * 4;
+    r[0] = a; r[1] = b; r[2] = c; r[3] = d;
+  }
+}
+// after a barrier: sum over waves of entry (sigma, k)
+template <typename T>
+__device__ inline C<T> collect(const T* red, int N, int sigma, int k) {
+  const int nw = (blockDim.x + 63) >> 6;
+  T re = 0, im = 0;
+  for (int w = 0; w < nw; ++w) {
+    re += red[(w * N + k) * 4 + 2 * sigma];
+    im += red[(w * N + k) * 4 + 2 * sigma + 1];
+  }
+  return mk<T>(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// restriction / prolongation, fine level
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_restrict_fine(const int* __restrict__ members, int nbpa, int N, long long fstride,
+                                const C<T>* __restrict__ P, const C<T>* __restrict__ in,
+                                C<T>* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* red = reinterpret_cast<T*>(smem_raw);
+  const int A = blockIdx.x, t = threadIdx.x;
+  const int blk = members[A * nbpa + (t >> 4)], loc = t & 15;
+  C<T> v[12];
+  load_spinor<T>(in, blk, loc, v);
+  for (int k = 0; k < N; ++k) {
+    C<T> w[12];
+    load_spinor<T>(P + k * fstride, blk, loc, w);
+    C<T> s0 = czero<T>(), s1 = czero<T>();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cjfma(s0, w[c], v[c]);
+      cjfma(s1, w[6 + c], v[6 + c]);
+    }
+    stash4<T>(red, N, k, s0.x, s0.y, s1.x, s1.y);
+  }
+  __syncthreads();
+  if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
+}
+
+template <typename T>
+void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const C<T>* P,
+                   const C<T>* in, C<T>* out, hipStream_t s) {
+  const size_t sm = (size_t)((a.asz + 63) / 64) * N * 4 * sizeof(T);
+  k_restrict_fine<T><<<a.nagg, a.asz, sm, s>>>(ad.members, a.asz / 16, N, (long long)g.nblk * 192,
+                                               P, in, out);
+  DD_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N, long long fstride,
+                               const C<T>* __restrict__ P, const C<T>* __restrict__ in,
+                               C<T>* __restrict__ out) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15;
+  if (blk >= nblk) return;
+  const int A = blk_agg[blk];
+  const C<T>* phi = in + (long long)A * 2 * N;
+  C<T> acc[12];
+  load_spinor<T>(out, blk, loc, acc);
+  for (int k = 0; k < N; ++k) {
+    C<T> w[12];
+    load_spinor<T>(P + k * fstride, blk, loc, w);
+    const C<T> p0 = phi[k], p1 = phi[N + k];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cfma(acc[c], w[c], p0);
+      cfma(acc[6 + c], w[6 + c], p1);
+    }
+  }
+  C<T>* o = out + (long long)blk * 192 + loc;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) o[c * 16] = acc[c];
+}
+
+template <typename T>
+void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const C<T>* P, const C<T>* in,
+                  C<T>* out, hipStream_t s) {
+  k_prolong_fine<T><<<nblocks((size_t)g.nblk * 16, 256), 256, 0, s>>>(
+      ad.member_agg, g.nblk, N, (long long)g.nblk * 192, P, in, out);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// restriction / prolongation, coarse level (d components per site)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_restrict_coarse(const int* __restrict__ members, int asz, int d, int N,
+                                  long long fstride, const C<T>* __restrict__ P,
+                                  const C<T>* __restrict__ in, C<T>* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* red = reinterpret_cast<T*>(smem_raw);
+  const int A = blockIdx.x, t = threadIdx.x;
+  const bool valid = t < asz * d;
+  const int sl = valid ? t / d : 0, i = valid ? t % d : 0;
+  const int site = members[A * asz + sl];
+  const long long e = (long long)site * d + i;
+  const C<T> v = valid ? in[e] : czero<T>();
+  const bool up = i < d / 2;
+  for (int k = 0; k < N; ++k) {
+    C<T> p = czero<T>();
+    if (valid) cjfma(p, P[k * fstride + e], v);
+    stash4<T>(red, N, k, up ? p.x : T(0), up ? p.y : T(0), up ? T(0) : p.x, up ? T(0) : p.y);
+  }
+  __syncthreads();
+  if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
+}
+
+template <typename T>
+void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
+                     const C<T>* P, const C<T>* in, C<T>* out, hipStream_t s) {
+  const int rows = a.asz * d;
+  DD_REQUIRE(rows <= 1024, "coarse aggregate too large for one workgroup");
+  const int wg = 64 * ((rows + 63) / 64);
+  const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(T);
+  k_restrict_coarse<T><<<a.nagg, wg, sm, s>>>(ad.members, a.asz, d, N, V * d, P, in, out);
+  DD_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_prolong_coarse(const int* __restrict__ site_agg, long long V, int d, int N,
+                                 long long fstride, const C<T>* __restrict__ P,
+                                 const C<T>* __restrict__ in, C<T>* __restrict__ out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= V * d) return;
+  const int site = (int)(e / d), i = (int)(e % d);
+  const int sigma = i < d / 2 ? 0 : 1;
+  const C<T>* phi = in + (long long)site_agg[site] * 2 * N + sigma * N;
+  C<T> acc = out[e];
+  for (int k = 0; k < N; ++k) cfma(acc, P[k * fstride + e], phi[k]);
+  out[e] = acc;
+}
+
+template <typename T>
+void prolong_coarse(const AggDev& ad, int d, int N, long long V, const C<T>* P, const C<T>* in,
+                    C<T>* out, hipStream_t s) {
+  k_prolong_coarse<T><<<nblocks((size_t)V * d, 256), 256, 0, s>>>(ad.member_agg, V, d, N, V * d, P,
+                                                                  in, out);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Block orthonormalisation (FP64).  One workgroup per (aggregate, chirality);
+// every thread owns the same element positions in all N fields, so a thread
+// only re-reads what it wrote itself.  Gram-Schmidt with one full
+// re-orthogonalisation pass, in index order.
+// ---------------------------------------------------------------------------
+constexpr int NMAX = 32;   // max test vectors per level
+constexpr int EPT = 8;     // max elements per thread
+
+struct FineMap {
+  const int* members;
+  int nbpa;
+  __device__ long long operator()(int A, int sigma, int e) const {
+    const int ts = e / 6, c = 6 * sigma + e % 6;
+    const int blk = members[A * nbpa + (ts >> 4)];
+    return ((long long)blk * 12 + c) * 16 + (ts & 15);
+  }
+};
+struct CoarseMap {
+  const int* members;
+  int asz, d;
+  __device__ long long operator()(int A, int sigma, int e) const {
+    const int h = d / 2;
+    const int sl = e / h, c = sigma * h + e % h;
+    return (long long)members[A * asz + sl] * d + c;
+  }
+};
+
+// sum over the workgroup of nv (<= 2*NMAX) doubles held in v[]; lds >= 16*2*NMAX
+__device__ inline void wg_sum_n(double (&v)[2 * NMAX], int nv, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int j = 0; j < 2 * NMAX; ++j)
+    if (j < nv) {
+      double s = wave_sum(v[j]);
+      if (lane == 0) lds[wave * 2 * NMAX + j] = s;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2 * NMAX; ++j)
+    if (j < nv) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += lds[w * 2 * NMAX + j];
+      v[j] = s;
+    }
+  __syncthreads();
+}
+
+template <class Map>
+__global__ void __launch_bounds__(256) k_orth(Map map, int m, int N, long long fstride,
+                                              const double2* __restrict__ tv, double2* __restrict__ P) {
+  __shared__ double lds[16 * 2 * NMAX];
+  const int A = blockIdx.x >> 1, sigma = blockIdx.x & 1;
+  long long off[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * blockDim.x;
+    off[q] = e < m ? map(A, sigma, e) : -1;
+  }
+  for (int k = 0; k < N; ++k) {
+    double2 w[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) w[q] = off[q] >= 0 ? tv[k * fstride + off[q]] : czero<double>();
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+      double h[2 * NMAX];
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) {
+        h[2 * j] = 0;
+        h[2 * j + 1] = 0;
+        if (j < k) {
+#pragma unroll
+          for (int q = 0; q < EPT; ++q)
+            if (off[q] >= 0) {
+              const double2 p = P[j * fstride + off[q]];
+              h[2 * j] += p.x * w[q].x + p.y * w[q].y;
+              h[2 * j + 1] += p.x * w[q].y - p.y * w[q].x;
+            }
+        }
+      }
+      wg_sum_n(h, 2 * k, lds);
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < k) {
+          const double2 hj = mk<double>(h[2 * j], h[2 * j + 1]);
+#pragma unroll
+          for (int q = 0; q < EPT; ++q)
+            if (off[q] >= 0) w[q] = csub(w[q], cmul(hj, P[j * fstride + off[q]]));
+        }
+    }
+    double nn[2 * NMAX];
+    nn[0] = 0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) nn[0] += w[q].x * w[q].x + w[q].y * w[q].y;
+    wg_sum_n(nn, 1, lds);
+    const double inv = nn[0] > 0 ? 1.0 / sqrt(nn[0]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+      if (off[q] >= 0) P[k * fstride + off[q]] = cscale(w[q], inv);
+  }
+}
+
+void orthonormalise_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
+                         const double2* tv, double2* P, hipStream_t s) {
+  const int m = a.asz * 6;
+  DD_REQUIRE(N <= NMAX, "too many test vectors");
+  DD_REQUIRE(N <= m, "more test vectors than the aggregate dimension");
+  DD_REQUIRE(m <= 256 * EPT, "aggregate too large");
+  k_orth<FineMap><<<2 * a.nagg, 256, 0, s>>>(FineMap{ad.members, a.asz / 16}, m, N,
+                                            (long long)g.nblk * 192, tv, P);
+  DD_LAUNCH_CHECK();
+}
+
+void orthonormalise_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
+                           const double2* tv, double2* P, hipStream_t s) {
+  const int m = a.asz * (d / 2);
+  DD_REQUIRE(N <= NMAX, "too many test vectors");
+  DD_REQUIRE(N <= m, "more test vectors than the aggregate dimension");
+  DD_REQUIRE(m <= 256 * EPT, "aggregate too large");
+  k_orth<CoarseMap><<<2 * a.nagg, 256, 0, s>>>(CoarseMap{ad.members, a.asz, d}, m, N, V * d, tv, P);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin, fine level: grid (aggregate, coarse column (sigma, k)), one
+// thread per fine site of the aggregate.  For the column u = P_k restricted
+// to chirality sigma the thread forms, in turn, the self part
+//   y = A(x) u(x) - 1/2 sum of the hops whose both ends lie in the aggregate
+// and the four forward face parts y = -1/2 (1-g_mu) U_mu(x) u(x+mu) (x+mu
+// outside), and projects each on the rows P_k'(x) (both chiralities).
+// ---------------------------------------------------------------------------
+struct GalFineGeom {
+  int nb[4];
+  int agg[4];
+};
+
+template <int MU, bool FWD>
+__device__ inline void gal_hop(const FineOpView<double>& op, const double2* __restrict__ Pk, int sigma,
+                               int blk, int loc, double2 acc[12]) {
+  constexpr int bit = 1 << MU;
+  int nb;
+  if constexpr (FWD) nb = (loc & bit) ? op.nbr[blk * 8 + 2 * MU] : blk;
+  else nb = (loc & bit) ? blk : op.nbr[blk * 8 + 2 * MU + 1];
+  double2 psi[12], u[9];
+  load_spinor<double>(Pk, nb, loc ^ bit, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c)
+    if ((c / 6) != sigma) psi[c] = czero<double>();
+  if constexpr (FWD) load_link<double>(op.U, blk, loc, MU, u);
+  else load_link<double>(op.U, nb, loc ^ bit, MU, u);
+  hop_apply<double, MU, FWD>(psi, u, acc);
+}
+
+template <int MU>
+__device__ inline void gal_hops_inside(const FineOpView<double>& op, const double2* Pk, int sigma,
+                                       int blk, int loc, const bool* fin, const bool* bin,
+                                       double2 acc[12]) {
+  if (fin[MU]) gal_hop<MU, true>(op, Pk, sigma, blk, loc, acc);
+  if (bin[MU]) gal_hop<MU, false>(op, Pk, sigma, blk, loc, acc);
+}
+
+__global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int* __restrict__ members,
+                                                       int nbpa, int N, FineOpView<double> op,
+                                                       const double2* __restrict__ P, long long fstride,
+                                                       double2* __restrict__ Dc) {
+  __shared__ double red[4 * NMAX * 4];
+  const int A = blockIdx.x, col = blockIdx.y;
+  const int sigma = col / N, k = col % N;
+  const int t = threadIdx.x;
+  const int blk = members[A * nbpa + (t >> 4)], loc = t & 15;
+  // fine coordinates -> which hops stay inside the aggregate
+  bool fin[4], bin[4];
+  {
+    int r = blk;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int bc = r % gg.nb[mu];
+      r /= gg.nb[mu];
+      const int x = 2 * bc + ((loc >> mu) & 1);
+      const int xm = x % gg.agg[mu];
+      fin[mu] = xm != gg.agg[mu] - 1;
+      bin[mu] = xm != 0;
+    }
+  }
+  const double2* Pk = P + k * fstride;
+  const int twoN = 2 * N;
+  for (int tau = 0; tau < 5; ++tau) {
+    double2 y[12], acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = czero<double>();
+    if (tau == 0) {
+      double2 u[12];
+      load_spinor<double>(Pk, blk, loc, u);
+#pragma unroll
+      for (int c = 0; c < 12; ++c)
+        if ((c / 6) != sigma) u[c] = czero<double>();
+      clover_apply<double>(op.A, blk, loc, u, y);
+      gal_hops_inside<0>(op, Pk, sigma, blk, loc, fin, bin, acc);
+      gal_hops_inside<1>(op, Pk, sigma, blk, loc, fin, bin, acc);
+      gal_hops_inside<2>(op, Pk, sigma, blk, loc, fin, bin, acc);
+      gal_hops_inside<3>(op, Pk, sigma, blk, loc, fin, bin, acc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = czero<double>();
+      const int mu = tau - 1;
+      if (!fin[mu]) {
+        if (mu == 0) gal_hop<0, true>(op, Pk, sigma, blk, loc, acc);
+        else if (mu == 1) gal_hop<1, true>(op, Pk, sigma, blk, loc, acc);
+        else if (mu == 2) gal_hop<2, true>(op, Pk, sigma, blk, loc, acc);
+        else gal_hop<3, true>(op, Pk, sigma, blk, loc, acc);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      y[c].x -= 0.5 * acc[c].x;
+      y[c].y -= 0.5 * acc[c].y;
+    }
+    for (int kp = 0; kp < N; ++kp) {
+      double2 w[12];
+      load_spinor<double>(P + kp * fstride, blk, loc, w);
+      double2 p0 = czero<double>(), p1 = czero<double>();
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cjfma(p0, w[c], y[c]);
+        cjfma(p1, w[6 + c], y[6 + c]);
+      }
+      stash4<double>(red, N, kp, p0.x, p0.y, p1.x, p1.y);
+    }
+    __syncthreads();
+    if (t < twoN)
+      Dc[(((long long)A * 5 + tau) * twoN + t) * twoN + col] = collect<double>(red, N, t / N, t % N);
+    __syncthreads();
+  }
+}
+
+void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
+                   const FineOpView<double>& op, const double2* P, double2* Dc, hipStream_t s) {
+  DD_REQUIRE(a.asz == 256, "fine Galerkin kernel expects 4^4-site aggregates");
+  DD_REQUIRE(N <= NMAX, "too many test vectors");
+  GalFineGeom gg;
+  for (int mu = 0; mu < 4; ++mu) { gg.nb[mu] = g.nb[mu]; gg.agg[mu] = a.agg[mu]; }
+  dim3 grid(a.nagg, 2 * N);
+  k_galerkin_fine<<<grid, 256, 0, s>>>(gg, ad.members, a.asz / 16, N, op, P, (long long)g.nblk * 192,
+                                       Dc);
+  DD_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin, coarse level: grid (aggregate, column), one thread per
+// (site of the aggregate, row i of level l).
+// ---------------------------------------------------------------------------
+struct GalCoarseGeom {
+  int dims[4];
+  int agg[4];
+};
+
+// row i of M v restricted to the column range [j0, j1) (forward-stored block)
+__device__ inline double2 row_fwd_rng(const double2* M, const double2* v, int i, int d, int j0, int j1) {
+  double2 acc = czero<double>();
+  for (int j = j0; j < j1; ++j) cfma(acc, M[(size_t)i * d + j], v[j]);
+  return acc;
+}
+// row i of G5 F^H G5 v restricted to columns [j0, j1)
+__device__ inline double2 row_bwd_rng(const double2* F, const double2* v, int i, int d, int j0, int j1) {
+  const int h = d / 2;
+  double2 acc = czero<double>();
+  for (int j = j0; j < j1; ++j) {
+    double2 t = cjmul(F[(size_t)j * d + i], v[j]);
+    const bool neg = (i < h) != (j < h);
+    acc = neg ? csub(acc, t) : cadd(acc, t);
+  }
+  return acc;
+}
+
+__global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N,
+                                  CoarseOpView<double> op, const double2* __restrict__ P,
+                                  long long fstride, double2* __restrict__ Dc) {
+  extern __shared__ unsigned char smem_raw[];
+  double* red = reinterpret_cast<double*>(smem_raw);
+  const int d = op.d, h = d / 2;
+  const int A = blockIdx.x, col = blockIdx.y;
+  const int sigma = col / N, k = col % N;
+  const int j0 = sigma * h, j1 = j0 + h;
+  const int t = threadIdx.x;
+  const bool valid = t < asz * d;
+  const int sl = valid ? t / d : 0, i = valid ? t % d : 0;
+  const int site = members[A * asz + sl];
+  bool fin[4], bin[4];
+  {
+    int r = site;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int x = r % gg.dims[mu];
+      r /= gg.dims[mu];
+      const int xm = x % gg.agg[mu];
+      fin[mu] = xm != gg.agg[mu] - 1;
+      bin[mu] = xm != 0;
+    }
+  }
+  const size_t bsz = (size_t)d * d;
+  const double2* Pk = P + k * fstride;
+  const double2* Ds = op.D + (size_t)site * 5 * bsz;
+  const int twoN = 2 * N;
+  for (int tau = 0; tau < 5; ++tau) {
+    double2 y = czero<double>();
+    if (valid) {
+      if (tau == 0) {
+        y = row_fwd_rng(Ds, Pk + (size_t)site * d, i, d, j0, j1);
+        for (int mu = 0; mu < 4; ++mu) {
+          if (fin[mu]) {
+            const int nf = op.nbr[site * 8 + 2 * mu];
+            y = cadd(y, row_fwd_rng(Ds + (1 + mu) * bsz, Pk + (size_t)nf * d, i, d, j0, j1));
+          }
+          if (bin[mu]) {
+            const int nb = op.nbr[site * 8 + 2 * mu + 1];
+            y = cadd(y, row_bwd_rng(op.D + ((size_t)nb * 5 + 1 + mu) * bsz, Pk + (size_t)nb * d, i, d,
+                                    j0, j1));
+          }
+        }
+      } else {
+        const int mu = tau - 1;
+        if (!fin[mu]) {
+          const int nf = op.nbr[site * 8 + 2 * mu];
+          y = row_fwd_rng(Ds + (1 + mu) * bsz, Pk + (size_t)nf * d, i, d, j0, j1);
+        }
+      }
+    }
+    const bool up = i < h;
+    for (int kp = 0; kp < N; ++kp) {
+      double2 p = czero<double>();
+      if (valid) cjfma(p, P[kp * fstride + (size_t)site * d + i], y);
+      stash4<double>(red, N, kp, up ? p.x : 0.0, up ? p.y : 0.0, up ? 0.0 : p.x, up ? 0.0 : p.y);
+    }
+    __syncthreads();
+    if (t < twoN)
+      Dc[(((long long)A * 5 + tau) * twoN + t) * twoN + col] = collect<double>(red, N, t / N, t % N);
+    __syncthreads();
+  }
+}
+
+void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad, int N,
+                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s) {
+  const int rows = a.asz * cg.d;
+  DD_REQUIRE(rows <= 1024, "coarse aggregate too large for one workgroup");
+  DD_REQUIRE(N <= NMAX, "too many test vectors");
+  GalCoarseGeom gg;
+  for (int mu = 0; mu < 4; ++mu) { gg.dims[mu] = cg.dims[mu]; gg.agg[mu] = a.agg[mu]; }
+  const int wg = 64 * ((rows + 63) / 64);
+  const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(double);
+  dim3 grid(a.nagg, 2 * N);
+  k_galerkin_coarse<<<grid, wg, sm, s>>>(gg, ad.members, a.asz, N, op, P, (long long)cg.V * cg.d, Dc);
+  DD_LAUNCH_CHECK();
+}
+
+#define DD_INST(T)                                                                                 \
+  template void restrict_fine<T>(const FineGeom&, const AggTables&, const AggDev&, int, const C<T>*, \
+                                 const C<T>*, C<T>*, hipStream_t);                                \
+  template void prolong_fine<T>(const FineGeom&, const AggDev&, int, const C<T>*, const C<T>*,     \
+                                C<T>*, hipStream_t);                                              \
+  template void restrict_coarse<T>(const AggTables&, const AggDev&, int, int, long long,          \
+                                   const C<T>*, const C<T>*, C<T>*, hipStream_t);                 \
+  template void prolong_coarse<T>(const AggDev&, int, int, long long, const C<T>*, const C<T>*,   \
+                                  C<T>*, hipStream_t);
+DD_INST(double)
+DD_INST(float)
+#undef DD_INST
+
+}  // namespace ddamg

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libddamg.so (C ABI in include/ddamg.h).
+
+Argument marshalling only: tensors are passed as device pointers
+(``tensor.data_ptr()``) together with torch's current HIP stream; every
+computation runs in the library's kernels.  The functions keep the names of
+the C entry points without the ``ddamg_`` prefix.  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddamg.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+CANONICAL, NATIVE = 0, 1
+KCYCLE, VCYCLE = 0, 1
+
+
+class DDAMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ddamg error {status}: {msg}")
+        self.status = status
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("m0", ctypes.c_double), ("csw", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int),
+        ("agg", (ctypes.c_int * 4) * 3),
+        ("ntv", ctypes.c_int * 3),
+        ("sap_block", ctypes.c_int * 4),
+        ("mu", ctypes.c_int), ("nu", ctypes.c_int),
+        ("mr_iters", ctypes.c_int),
+        ("n_inv", ctypes.c_int),
+        ("coarse_eps", ctypes.c_double),
+        ("coarse_restart", ctypes.c_int),
+        ("coarse_max_restarts", ctypes.c_int),
+        ("kc_len", ctypes.c_int),
+        ("kc_restarts", ctypes.c_int),
+        ("kc_tol", ctypes.c_double),
+        ("nkv", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_restarts", ctypes.c_int),
+        ("precond_prec", ctypes.c_int),
+        ("cycle", ctypes.c_int),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("outer_iters", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("kcycle_iters", ctypes.c_longlong),
+        ("coarsest_iters", ctypes.c_longlong),
+        ("true_relres", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "ddamg_params_default": (None, [ctypes.POINTER(Params), _I]),
+    "ddamg_last_error": (ctypes.c_char_p, []),
+    "ddamg_version": (ctypes.c_char_p, []),
+    "ddamg_create": (_I, [ctypes.POINTER(Lattice), _P, _P, ctypes.POINTER(_P)]),
+    "ddamg_destroy": (None, [_P]),
+    "ddamg_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _P]),
+    "ddamg_to_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
+    "ddamg_from_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
+    "ddamg_build_hierarchy": (_I, [_P, ctypes.POINTER(Params), _P, _P, _P, ctypes.POINTER(_P)]),
+    "ddamg_destroy_hierarchy": (None, [_P]),
+    "ddamg_level_info": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int * 4), ctypes.POINTER(_I)]),
+    "ddamg_apply_Dc": (_I, [_P, _I, _P, _P, _I, _I, _I, _P]),
+    "ddamg_restrict": (_I, [_P, _I, _P, _P, _I, _I, _I, _P]),
+    "ddamg_prolong": (_I, [_P, _I, _P, _P, _I, _I, _I, _P]),
+    "ddamg_sap_smooth": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P]),
+    "ddamg_precondition": (_I, [_P, _P, _P, _I, _I, _P]),
+    "ddamg_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveStats), _P]),
+    "ddamg_export_interpolation": (_I, [_P, _I, _P, _P]),
+    "ddamg_export_coarse_op": (_I, [_P, _I, _P, _P]),
+    "ddamg_import_test_vectors": (_I, [_P, _I, _P, _P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libddamg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (paper_1307_6101_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DDAMGError(rc, load_library().ddamg_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version() -> str:
+    return load_library().ddamg_version().decode()
+
+
+def params_default(levels: int) -> Params:
+    p = Params()
+    load_library().ddamg_params_default(ctypes.byref(p), levels)
+    return p
+
+
+class Context:
+    """Handle of one lattice operator D (ddamg_create / ddamg_destroy)."""
+
+    def __init__(self, dims, m0, csw, links):
+        lib = load_library()
+        lat = Lattice((ctypes.c_int * 4)(*dims), float(m0), float(csw))
+        h = ctypes.c_void_p()
+        _check(lib.ddamg_create(ctypes.byref(lat), _ptr(links), _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.dims = tuple(dims)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ddamg_destroy(self.handle)
+            self.handle = None
+
+
+class Hierarchy:
+    """Handle of a multilevel hierarchy (ddamg_build_hierarchy / destroy)."""
+
+    def __init__(self, ctx: Context, params: Params, tv, tv_extra=None):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.ddamg_build_hierarchy(ctx.handle, ctypes.byref(params), _ptr(tv), _ptr(tv_extra),
+                                         _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self.params = params
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ddamg_destroy_hierarchy(self.handle)
+            self.handle = None
+
+
+def create(dims, m0, csw, links) -> Context:
+    return Context(dims, m0, csw, links)
+
+
+def build_hierarchy(ctx, params, tv, tv_extra=None) -> Hierarchy:
+    return Hierarchy(ctx, params, tv, tv_extra)
+
+
+def apply_D(ctx, inp, out, nrhs=1, prec=F64, layout=CANONICAL):
+    _check(load_library().ddamg_apply_D(ctx.handle, _ptr(inp), _ptr(out), nrhs, prec, layout, _stream()))
+
+
+def to_native(ctx, hier, level, inp, out, nrhs=1, prec=F64):
+    h = hier.handle if hier is not None else None
+    _check(load_library().ddamg_to_native(ctx.handle, h, level, _ptr(inp), _ptr(out), nrhs, prec, _stream()))
+
+
+def from_native(ctx, hier, level, inp, out, nrhs=1, prec=F64):
+    h = hier.handle if hier is not None else None
+    _check(load_library().ddamg_from_native(ctx.handle, h, level, _ptr(inp), _ptr(out), nrhs, prec, _stream()))
+
+
+def level_info(hier, level):
+    dims = (ctypes.c_int * 4)()
+    dof = ctypes.c_int()
+    _check(load_library().ddamg_level_info(hier.handle, level, ctypes.byref(dims), ctypes.byref(dof)))
+    return tuple(dims), dof.value
+
+
+def apply_Dc(hier, level, inp, out, nrhs=1, prec=F64, layout=CANONICAL):
+    _check(load_library().ddamg_apply_Dc(hier.handle, level, _ptr(inp), _ptr(out), nrhs, prec, layout,
+                                         _stream()))
+
+
+def restrict(hier, level, fine, coarse, nrhs=1, prec=F64, layout=CANONICAL):
+    _check(load_library().ddamg_restrict(hier.handle, level, _ptr(fine), _ptr(coarse), nrhs, prec, layout,
+                                         _stream()))
+
+
+def prolong(hier, level, coarse, fine, nrhs=1, prec=F64, layout=CANONICAL):
+    _check(load_library().ddamg_prolong(hier.handle, level, _ptr(coarse), _ptr(fine), nrhs, prec, layout,
+                                        _stream()))
+
+
+def sap_smooth(hier, level, b, z, nsweeps, nrhs=1, prec=F64, layout=CANONICAL):
+    _check(load_library().ddamg_sap_smooth(hier.handle, level, _ptr(b), _ptr(z), nsweeps, nrhs, prec,
+                                           layout, _stream()))
+
+
+def precondition(hier, b, z, nrhs=1, layout=CANONICAL):
+    _check(load_library().ddamg_precondition(hier.handle, _ptr(b), _ptr(z), nrhs, layout, _stream()))
+
+
+def solve(hier, b, z, nrhs=1):
+    """Solve D z = b; returns (status, [stats dict per right-hand side]).
+    ENOCONV / ENONFINITE are returned, other failures raise."""
+    stats = (SolveStats * nrhs)()
+    rc = load_library().ddamg_solve(hier.handle, _ptr(b), _ptr(z), nrhs, stats, _stream())
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _check(rc)
+    return rc, [s.as_dict() for s in stats]
+
+
+def export_interpolation(hier, level, out):
+    _check(load_library().ddamg_export_interpolation(hier.handle, level, _ptr(out), _stream()))
+
+
+def export_coarse_op(hier, level, out):
+    _check(load_library().ddamg_export_coarse_op(hier.handle, level, _ptr(out), _stream()))
+
+
+def import_test_vectors(hier, level, tv):
+    _check(load_library().ddamg_import_test_vectors(hier.handle, level, _ptr(tv), _stream()))

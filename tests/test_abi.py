@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every symbol include/ddamg.h declares,
+its structs match the header's layout, and host-side argument checks reject
+bad input before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddamg.h")
+
+
+@pytest.fixture(scope="module")
+def dd():
+    from paper_1307_6101_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_1307_6101_amd import ddamg
+    ddamg.load_library()
+    return ddamg
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddamg_[a-zA-Z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(dd):
+    lib = dd.load_library()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each of them
+    assert set(names) == set(dd._SIGS), set(names) ^ set(dd._SIGS)
+
+
+def test_struct_layout_matches_header(tmp_path, dd):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "ddamg.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(ddamg_lattice), sizeof(ddamg_params), sizeof(ddamg_solve_stats));
+  printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
+         offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
+  printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(dd.Lattice)
+    assert vals[1] == ctypes.sizeof(dd.Params)
+    assert vals[2] == ctypes.sizeof(dd.SolveStats)
+    assert vals[3] == dd.Params.coarse_eps.offset
+    assert vals[4] == dd.Params.kc_tol.offset
+    assert vals[5] == dd.Params.tol.offset
+    assert vals[6] == dd.Params.cycle.offset
+    assert vals[7] == dd.SolveStats.true_relres.offset
+    assert vals[8] == dd.SolveStats.seconds.offset
+
+
+def test_params_default_is_table1(dd):
+    p = dd.params_default(3)
+    assert p.levels == 3
+    assert list(p.agg[0]) == [4, 4, 4, 4] and list(p.agg[1]) == [2, 2, 2, 2]
+    assert list(p.ntv) == [20, 20, 20]
+    assert list(p.sap_block) == [2, 2, 2, 2]
+    assert (p.mu, p.nu, p.mr_iters, p.n_inv) == (0, 5, 3, 6)
+    assert (p.kc_len, p.kc_restarts, p.nkv) == (5, 2, 10)
+    assert p.coarse_eps == 5e-2 and p.kc_tol == 1e-1 and p.tol == 1e-10
+    assert p.precond_prec == dd.F32 and p.cycle == dd.KCYCLE
+
+
+def test_host_validation_rejects_bad_lattice(dd):
+    lib = dd.load_library()
+    h = ctypes.c_void_p()
+    for dims in ((6, 8, 8, 8), (8, 8, 8, 0), (8, 8, 2, 8)):
+        lat = dd.Lattice((ctypes.c_int * 4)(*dims), -0.3, 1.0)
+        rc = lib.ddamg_create(ctypes.byref(lat), ctypes.c_void_p(16), None, ctypes.byref(h))
+        assert rc == dd.EINVAL
+        assert b"multiple of 4" in lib.ddamg_last_error()
+    lat = dd.Lattice((ctypes.c_int * 4)(8, 8, 8, 8), -0.3, 1.0)
+    assert lib.ddamg_create(ctypes.byref(lat), None, None, ctypes.byref(h)) == dd.EINVAL
+    assert lib.ddamg_create(None, ctypes.c_void_p(16), None, ctypes.byref(h)) == dd.EINVAL
+
+
+def test_null_handles_rejected(dd):
+    lib = dd.load_library()
+    assert lib.ddamg_apply_D(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, 0, 0, None) == dd.EINVAL
+    assert lib.ddamg_solve(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, None, None) == dd.EINVAL
+    assert lib.ddamg_apply_Dc(None, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, 0, 0, None) == dd.EINVAL
+    assert b"null" in lib.ddamg_last_error()

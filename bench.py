@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the DD-alpha-AMG hot path on one MI355X.
+
+A step is one complete solve of D z = b to relative residual 1e-10 (outer
+FP64 FGMRES, FP32 K-cycle preconditioner, three levels) on the 16^3x32
+Wilson-clover workload (eps 0.5, m0 -0.4, c_sw 1, one complex Gaussian
+right-hand side), with the hierarchy built beforehand (setup timed
+separately) and b resident in HBM.  `value` is solves per second.
+
+Also reported on the same inputs: the plain FP64 GPU solve (everything FP64,
+no batching) for the time-to-solution comparison, the setup times, the
+Wilson-clover stencil's achieved bandwidth (HIP events around launches on the
+library's stream) against the HBM roofline, and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "clover16x32_3lvl"
+# compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
+# 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
+# (24 reals) -> 192 reals
+DPSI_REALS_PER_SITE = 192
+# one SAP sweep (both colours) per site: b, z in, z out (72 reals), links and
+# clover (144 reals)
+SAP_REALS_PER_SITE = 216
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1307_6101_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_1307_6101_amd import ddamg as dd
+
+    cfg = W.CONFIGS[WORKLOAD]
+    dims = cfg["dims"]
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {WORKLOAD} dims={dims} V={V}")
+    t0 = time.time()
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+    tv = W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s")
+    Ud = torch.from_numpy(U).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    tvd = torch.from_numpy(tv).to(dev)
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], Ud)
+    del Ud
+
+    def params(prec):
+        p = dd.params_default(cfg["levels"])
+        for l, a in enumerate(cfg["agg"]):
+            for mu in range(4):
+                p.agg[l][mu] = a[mu]
+        for l, n in enumerate(cfg["ntv"]):
+            p.ntv[l] = n
+        p.nu = cfg["nu"]
+        p.precond_prec = prec
+        return p
+
+    def setup(prec):
+        torch.cuda.synchronize()
+        t = time.time()
+        H = dd.build_hierarchy(ctx, params(prec), tvd)
+        torch.cuda.synchronize()
+        return H, time.time() - t
+
+    H32, t_setup32 = setup(dd.F32)
+    log(f"[bench] mixed-precision setup {t_setup32:.2f}s")
+    z = torch.zeros_like(bd)
+
+    def one_solve(H):
+        z.zero_()
+        rc, st = dd.solve(H, bd, z)
+        if rc != dd.OK:
+            raise RuntimeError(f"solve failed rc={rc} {st}")
+        return st[0]
+
+    for i in range(args.warmup):
+        st = one_solve(H32)
+        log(f"[bench] warmup {i}: {st['outer_iters']} its, {st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    t = time.time()
+    stats = []
+    for i in range(args.steps):
+        st = one_solve(H32)
+        stats.append(st)
+        log(f"[bench] step {i}: {st['outer_iters']} its, relres {st['true_relres']:.2e}, "
+            f"{st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    elapsed = time.time() - t
+    ms = 1000.0 * elapsed / args.steps
+    z_mixed = z.clone()
+
+    # plain FP64 GPU method on the same inputs
+    plain = None
+    if not args.no_plain:
+        H64, t_setup64 = setup(dd.F64)
+        log(f"[bench] plain FP64 setup {t_setup64:.2f}s")
+        one_solve(H64)
+        torch.cuda.synchronize()
+        t = time.time()
+        pst = [one_solve(H64) for _ in range(max(1, min(args.steps, 3)))]
+        torch.cuda.synchronize()
+        t_plain = (time.time() - t) / len(pst)
+        plain = dict(time_to_solution_s=t_plain, setup_s=t_setup64,
+                     outer_iters=pst[-1]["outer_iters"], true_relres=pst[-1]["true_relres"])
+        log(f"[bench] plain FP64 solve {t_plain:.3f}s, {pst[-1]['outer_iters']} its")
+        diff = torch.linalg.vector_norm(z - z_mixed) / torch.linalg.vector_norm(z)
+        plain["rel_diff_vs_mixed_solution"] = float(diff)
+        del H64
+
+    # dominant fine kernels, timed with events on the stream the library uses
+    kern = {}
+    stream = torch.cuda.current_stream()
+    nat32 = torch.zeros(V * 12, dtype=torch.complex64, device=dev)
+    out32 = torch.zeros_like(nat32)
+    dd.to_native(ctx, None, 0, bd, nat32, prec=dd.F32)
+    nat64 = torch.zeros(V * 12, dtype=torch.complex128, device=dev)
+    out64 = torch.zeros_like(nat64)
+    dd.to_native(ctx, None, 0, bd, nat64, prec=dd.F64)
+
+    def time_launches(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1000.0 / reps
+
+    t_d32 = time_launches(lambda: dd.apply_D(ctx, nat32, out32, prec=dd.F32, layout=dd.NATIVE),
+                          args.kernel_reps)
+    t_d64 = time_launches(lambda: dd.apply_D(ctx, nat64, out64, prec=dd.F64, layout=dd.NATIVE),
+                          args.kernel_reps)
+    zs = torch.zeros_like(nat32)
+    t_sap32 = time_launches(lambda: dd.sap_smooth(H32, 0, nat32, zs, 1, prec=dd.F32,
+                                                  layout=dd.NATIVE), args.kernel_reps)
+    for name, tk, bytes_per_real in (("dslash_f32", t_d32, 4), ("dslash_f64", t_d64, 8)):
+        nbytes = DPSI_REALS_PER_SITE * bytes_per_real * V
+        kern[name] = dict(seconds=tk, algorithmic_bytes=nbytes, gbs=nbytes / tk / 1e9)
+    sbytes = SAP_REALS_PER_SITE * 4 * V
+    kern["sap_sweep_f32"] = dict(seconds=t_sap32, algorithmic_bytes=sbytes, gbs=sbytes / t_sap32 / 1e9,
+                                 launches=2)
+    for k, v in kern.items():
+        log(f"[bench] {k}: {v['seconds'] * 1e6:.1f} us, {v['gbs']:.0f} GB/s")
+
+    dom = kern["dslash_f32"]
+    roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_dslash<float> (Wilson-clover, FP32)",
+                "note": "16^3x32 working set ~175 MB fits the 256 MB Infinity Cache"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, U, b, stats[-1]["outer_iters"], V)
+
+    mean_its = float(np.mean([s["outer_iters"] for s in stats]))
+    line = {
+        "metric": "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU",
+        "value": round(1000.0 / ms, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner, f64 outer",
+        "data": "synthetic (seeded SU(3) links exp(i eps H), Gaussian rhs)",
+        "config": {"workload": "16^3x32 Wilson-clover, 3 levels (4^4, 2^4 aggregates, N=20), "
+                               "c_sw=1, eps=0.5, m0=-0.4, 1 rhs, tol 1e-10",
+                   "parallelism": "1 GPU"},
+        "time_to_solution_s": round(ms / 1000.0, 4),
+        "setup_s": round(t_setup32, 3),
+        "outer_iters": mean_its,
+        "true_relres": stats[-1]["true_relres"],
+        "kcycle_iters": stats[-1]["kcycle_iters"],
+        "coarsest_iters": stats[-1]["coarsest_iters"],
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
+        "kernels": {k: {"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)} for k, v in kern.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(cfg, U, b, outer_iters, V):
+    """The FP64 numpy oracle, unmodified, on a bounded sample of the same
+    workload: one outer iteration's fine-level work (nu = 5 SAP sweeps and one
+    Wilson-clover apply) on the full 16^3x32 lattice, scaled to a whole solve
+    by the GPU run's outer iteration count.  Coarse levels and setup are left
+    out, so the figure is an upper bound on the oracle's solves per second."""
+    import numpy as np
+
+    from oracle.dirac import WilsonClover
+    from oracle.sap import sap_sweep
+    t_build = time.time()
+    op = WilsonClover(U, cfg["m0"], cfg["csw"])
+    log(f"[bench] oracle operator built in {time.time() - t_build:.1f}s")
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t = time.time()
+    z = np.zeros_like(b)
+    for _ in range(cfg["nu"]):
+        z = sap_sweep(op, b, z, (2, 2, 2, 2), cfg["mr_iters"])
+    op.apply(z)
+    wall = time.time() - t
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    per_solve = wall * outer_iters
+    log(f"[bench] oracle sample {wall:.1f}s wall, {cpu_s:.1f}s cpu")
+    return {"value": round(1.0 / per_solve, 6), "unit": "solves/s",
+            "cores": max(1, int(round(cpu_s / wall))), "kind": "oracle",
+            "sample": f"fine-level work of one outer iteration (5 SAP sweeps + 1 Dpsi, FP64 numpy) on the "
+                      f"full 16^3x32 lattice took {wall:.2f}s; x{outer_iters} outer iterations; coarse "
+                      f"levels and setup excluded (upper bound)"}
+
+
+if __name__ == "__main__":
+    main()

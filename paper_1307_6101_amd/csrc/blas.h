@@ -31,8 +31,13 @@ template <typename T, typename TZ>
 void vlincomb(const Coefs& c, int k, const C<TZ>* Z, long long stride, C<T>* y, long long n,
               hipStream_t s);
 
-// Device part of the fused inner products <V_j, w> (j < k) and, if with_norm,
-// <w, w> as entry k.  Results (double2) land in dev_out[0..k(+1)].
+// y += sum_j c_j Z_j, then dst = scale * y (one pass)
+template <typename T>
+void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>* y, long long n,
+                    double scale, C<T>* dst, hipStream_t s);
+
+// Fused inner products <V_j, w> (j < k) and <w, w> (entry k), accumulated in
+// FP64 in a fixed order; fetch() copies them to the host.
 class Reducer {
  public:
   Reducer();
@@ -40,10 +45,17 @@ class Reducer {
   template <typename T>
   void dots(const C<T>* V, long long stride, int k, const C<T>* w, long long n, bool with_norm,
             hipStream_t s);
+  // w += sum_j c_j V_j, then the inner products of the updated w (one pass)
+  template <typename T>
+  void update_dots(const Coefs& c, const C<T>* V, long long stride, int k, C<T>* w, long long n,
+                   hipStream_t s);
   // copy the last results to the host (synchronises the stream)
   void fetch(int count, std::complex<double>* out, hipStream_t s);
 
  private:
+  template <typename T>
+  void launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd, const Coefs* c,
+              hipStream_t s);
   double* partial_ = nullptr;   // [GMAX][2*(KMAX+1)]
   double2* result_ = nullptr;   // [KMAX+1]
   double2* host_ = nullptr;     // pinned

@@ -2,7 +2,7 @@
 
 namespace ddamg {
 
-constexpr int GMAX = 512;      // max workgroups of the first reduction pass
+constexpr int GMAX = 256;      // max workgroups of the first reduction pass
 constexpr int RED_BS = 256;
 
 template <typename T>
@@ -84,7 +84,12 @@ void vlincomb(const Coefs& c, int k, const C<TZ>* Z, long long stride, C<T>* y, 
 }
 
 // ---------------------------------------------------------------------------
-// fused inner products
+// fused inner products: <V_j, w> for j < k and optionally <w, w>, FP64
+// accumulation.  With `upd`, the kernel first updates w += sum_j c_j V_j
+// element by element and takes the inner products of the updated w (the
+// second pass of classical Gram-Schmidt with re-orthogonalisation).
+// A per-workgroup first pass (skipped second pass when one workgroup covers
+// the vector) and a parallel second pass.
 // ---------------------------------------------------------------------------
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -92,57 +97,114 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(RED_BS) k_dots_pass1(const C<T>* __restrict__ V, long long stride,
-                                                       int k, const C<T>* __restrict__ w, long long n,
-                                                       int with_norm, double* __restrict__ partial) {
-  __shared__ double lds[RED_BS / 64][2 * (KMAX + 1)];
-  double acc[2 * KMAX];
+template <typename T, int BS, int KK>
+__device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C<T>* __restrict__ w,
+                                 long long n, bool upd, const Coefs& c, double* __restrict__ dst) {
+  constexpr int k = KK;
+  __shared__ double lds[BS / 64][2 * (KMAX + 1)];
+  double acc[2 * KK + 1];
   double nrm = 0;
 #pragma unroll
-  for (int j = 0; j < 2 * KMAX; ++j) acc[j] = 0;
+  for (int j = 0; j < 2 * KK + 1; ++j) acc[j] = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const double2 wi = ccast<double>(w[i]);
+    double2 wi = ccast<double>(w[i]);
+    if (upd) {
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) {
-        const double2 v = ccast<double>(V[j * stride + i]);
-        acc[2 * j] += v.x * wi.x + v.y * wi.y;
-        acc[2 * j + 1] += v.x * wi.y - v.y * wi.x;
-      }
+      for (int j = 0; j < KK; ++j) cfma(wi, c.c[j], ccast<double>(V[j * stride + i]));
+      const C<T> wt = ccast<T>(wi);
+      w[i] = wt;
+      wi = ccast<double>(wt);
+    }
+#pragma unroll
+    for (int j = 0; j < KK; ++j) {
+      const double2 v = ccast<double>(V[j * stride + i]);
+      acc[2 * j] += v.x * wi.x + v.y * wi.y;
+      acc[2 * j + 1] += v.x * wi.y - v.y * wi.x;
+    }
     nrm += wi.x * wi.x + wi.y * wi.y;
   }
-  const int nv = 2 * (k + (with_norm ? 1 : 0));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < 2 * KMAX; ++j)
-    if (j < 2 * k) {
-      const double s = wsum(acc[j]);
-      if (lane == 0) lds[wave][j] = s;
-    }
-  if (with_norm) {
-    const double s = wsum(nrm);
+  for (int j = 0; j < 2 * KK; ++j) {
+    const double sj = wsum(acc[j]);
+    if (lane == 0) lds[wave][j] = sj;
+  }
+  {
+    const double sn = wsum(nrm);
     if (lane == 0) {
-      lds[wave][2 * k] = s;
+      lds[wave][2 * k] = sn;
       lds[wave][2 * k + 1] = 0;
     }
   }
   __syncthreads();
+  const int nv = 2 * (k + 1);
   for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-    double s = 0;
-    for (int q = 0; q < RED_BS / 64; ++q) s += lds[q][j];
-    partial[(long long)blockIdx.x * 2 * (KMAX + 1) + j] = s;
+    double sj = 0;
+    for (int q = 0; q < BS / 64; ++q) sj += lds[q][j];
+    dst[j] = sj;
   }
 }
 
-__global__ void k_dots_pass2(const double* __restrict__ partial, int g, int nv, double2* __restrict__ out) {
-  // one thread per value, fixed summation order
-  const int j = threadIdx.x;
-  if (j >= nv) return;
-  double s = 0;
-  for (int q = 0; q < g; ++q) s += partial[(long long)q * 2 * (KMAX + 1) + j];
-  reinterpret_cast<double*>(out)[j] = s;
+template <typename T, int KK>
+__global__ void __launch_bounds__(RED_BS) k_dots_pass1(const C<T>* __restrict__ V, long long stride,
+                                                       C<T>* __restrict__ w, long long n, int upd,
+                                                       Coefs c, double* __restrict__ partial) {
+  dots_body<T, RED_BS, KK>(V, stride, w, n, upd != 0, c, partial + (long long)blockIdx.x * 2 * (KMAX + 1));
+}
+
+// launch k_dots_pass1<T, KK> for the runtime count k (0..KMAX)
+template <typename T, int KK>
+struct DotsLaunch {
+  static void go(int k, unsigned g, hipStream_t s, const C<T>* V, long long stride, C<T>* w,
+                 long long n, int upd, const Coefs& c, double* out) {
+    if (k == KK) {
+      k_dots_pass1<T, KK><<<g, RED_BS, 0, s>>>(V, stride, w, n, upd, c, out);
+      return;
+    }
+    DotsLaunch<T, KK + 1>::go(k, g, s, V, stride, w, n, upd, c, out);
+  }
+};
+template <typename T>
+struct DotsLaunch<T, KMAX + 1> {
+  static void go(int, unsigned, hipStream_t, const C<T>*, long long, C<T>*, long long, int,
+                 const Coefs&, double*) {}
+};
+
+// second pass: thread t owns first-pass row t (g <= 256 rows); each value is
+// reduced across the rows with wavefront sums
+__global__ void __launch_bounds__(256) k_dots_pass2(const double* __restrict__ partial, int g, int nv,
+                                                    double* __restrict__ out) {
+  __shared__ double lds[4][2 * (KMAX + 1)];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int j = 0; j < nv; ++j) {
+    const double v = t < g ? partial[(long long)t * 2 * (KMAX + 1) + j] : 0.0;
+    const double sv = wsum(v);
+    if (lane == 0) lds[wave][j] = sv;
+  }
+  __syncthreads();
+  if (t < nv) out[t] = lds[0][t] + lds[1][t] + lds[2][t] + lds[3][t];
+}
+
+template <typename T, typename TZ>
+__global__ void k_lincomb_scale(Coefs c, int k, const C<TZ>* __restrict__ Z, long long stride,
+                                C<T>* __restrict__ y, long long n, double scale, C<T>* __restrict__ dst) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double2 acc = ccast<double>(y[i]);
+    for (int j = 0; j < k; ++j) cfma(acc, c.c[j], ccast<double>(Z[j * stride + i]));
+    const C<T> v = ccast<T>(acc);
+    y[i] = v;
+    dst[i] = ccast<T>(cscale(ccast<double>(v), scale));
+  }
+}
+
+template <typename T>
+void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>* y, long long n,
+                    double scale, C<T>* dst, hipStream_t s) {
+  DD_REQUIRE(k >= 0 && k <= KMAX, "too many vectors in a linear combination");
+  k_lincomb_scale<T, T><<<grid_for(n), 256, 0, s>>>(c, k, Z, stride, y, n, scale, dst);
+  DD_LAUNCH_CHECK();
 }
 
 Reducer::Reducer() {
@@ -157,17 +219,36 @@ Reducer::~Reducer() {
 }
 
 template <typename T>
-void Reducer::dots(const C<T>* V, long long stride, int k, const C<T>* w, long long n, bool with_norm,
-                   hipStream_t s) {
-  DD_REQUIRE(k <= KMAX, "too many vectors in a fused dot product");
-  long long g = (n + RED_BS - 1) / RED_BS;
+void Reducer::launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd,
+                     const Coefs* c, hipStream_t s) {
+  DD_REQUIRE(k >= 0 && k <= KMAX, "too many vectors in a fused dot product");
+  Coefs cc;
+  if (c) cc = *c;
+  double* out = reinterpret_cast<double*>(result_);
+  // about four elements per thread in the first pass; one workgroup writes
+  // the result directly
+  long long g = (n + RED_BS * 4 - 1) / (RED_BS * 4);
   if (g > GMAX) g = GMAX;
   if (g < 1) g = 1;
-  k_dots_pass1<T><<<(unsigned)g, RED_BS, 0, s>>>(V, stride, k, w, n, with_norm ? 1 : 0, partial_);
+  DotsLaunch<T, 0>::go(k, (unsigned)g, s, V, stride, w, n, upd ? 1 : 0, cc, g == 1 ? out : partial_);
   DD_LAUNCH_CHECK();
-  const int nv = 2 * (k + (with_norm ? 1 : 0));
-  k_dots_pass2<<<1, 128, 0, s>>>(partial_, (int)g, nv, result_);
-  DD_LAUNCH_CHECK();
+  if (g > 1) {
+    k_dots_pass2<<<1, 256, 0, s>>>(partial_, (int)g, 2 * (k + 1), out);
+    DD_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+void Reducer::dots(const C<T>* V, long long stride, int k, const C<T>* w, long long n, bool with_norm,
+                   hipStream_t s) {
+  (void)with_norm;   // the norm is always formed (entry k)
+  launch<T>(V, stride, k, const_cast<C<T>*>(w), n, false, nullptr, s);
+}
+
+template <typename T>
+void Reducer::update_dots(const Coefs& c, const C<T>* V, long long stride, int k, C<T>* w, long long n,
+                          hipStream_t s) {
+  launch<T>(V, stride, k, w, n, true, &c, s);
 }
 
 void Reducer::fetch(int count, std::complex<double>* out, hipStream_t s) {
@@ -182,7 +263,11 @@ void Reducer::fetch(int count, std::complex<double>* out, hipStream_t s) {
   template void vscale<T>(double2, C<T>*, long long, hipStream_t);                           \
   template void vbmy<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
   template void Reducer::dots<T>(const C<T>*, long long, int, const C<T>*, long long, bool,  \
-                                 hipStream_t);
+                                 hipStream_t);                                               \
+  template void Reducer::update_dots<T>(const Coefs&, const C<T>*, long long, int, C<T>*,     \
+                                        long long, hipStream_t);                              \
+  template void vlincomb_scale<T>(const Coefs&, int, const C<T>*, long long, C<T>*, long long, \
+                                  double, C<T>*, hipStream_t);
 DD_INST(double)
 DD_INST(float)
 #undef DD_INST

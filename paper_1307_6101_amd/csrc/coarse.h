@@ -3,11 +3,16 @@
 // the coarsest solve (Sec. 3), and the interpolation P between levels.
 //
 // Layout: a level-l field is [V_l][d] complex (canonical coarse site order,
-// d = 2N_{l-1}, components 0..d/2-1 carry Gamma5 = +1).  The operator stores
-// per site the self block and the four forward blocks, [V_l][5][d][d]
-// row-major; the backward block follows from gamma5-symmetry,
-//   B_mu(x) = G5 F_mu(x - mu)^H G5,   B_mu(x)[i][j] = g_i g_j conj(F_mu(x-mu)[j][i]),
-// so 5 of the 9 blocks are read per site.
+// d = 2N_{l-1}, components 0..d/2-1 carry Gamma5 = +1).
+// The Galerkin product produces, in FP64, the self block and the four
+// forward blocks per site, [V_l][5][d][d] row-major; the backward blocks
+// follow from gamma5-symmetry,
+//   B_mu(x) = G5 F_mu(x - mu)^H G5,   B_mu(x)[i][j] = g_i g_j conj(F_mu(x-mu)[j][i]).
+// For applying the operator each precision keeps an expanded copy with all
+// nine blocks, [V_l][9][d][d], block k = self, +x,+y,+z,+t, -x,-y,-z,-t, each
+// stored column-major (element (i, j) at j*d + i): one wavefront handles one
+// site with lane i computing row i, so every matrix load is one contiguous
+// segment across the lanes.
 #pragma once
 
 #include <vector>
@@ -21,13 +26,12 @@ struct CoarseGeom {
   int V;
   int d;                       // complex components per site
   // host tables
-  std::vector<int> nbr;        // [V][8]: 2*mu + (0 fwd | 1 bwd)
+  std::vector<int> nbr9;       // [V][9]: self, +x..+t, -x..-t
   // SAP blocks
   int sap[4];
   int nblk, bs;                // blocks, sites per block
   std::vector<int> blk_sites;  // [nblk][bs], blocks colour-major (colour 0 first)
   std::vector<int> site_blk;   // [V] block id
-  std::vector<int> site_loc;   // [V] position inside its block
   // parity (odd-even)
   bool bipartite;
   std::vector<int> even, odd;
@@ -35,30 +39,37 @@ struct CoarseGeom {
 
 CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]);
 
-struct CoarseDev {             // device copies of the tables
-  int* nbr = nullptr;
-  int* blk_sites = nullptr;
-  int* site_blk = nullptr;
-  int* site_loc = nullptr;
-  int* even = nullptr;
-  int* odd = nullptr;
-};
 
 template <typename T>
 struct CoarseOpView {
-  const C<T>* D;       // [V][5][d][d]
-  const int* nbr;
+  const C<T>* K;       // [V][9][d][d], column-major blocks
+  const int* nbr9;     // [V][9]: site itself, then +mu, then -mu neighbours
   int V, d;
 };
+
+// expand the FP64 Galerkin output [V][5][d][d] (row-major) into the
+// nine-block column-major apply layout at precision T
+template <typename T>
+void expand_coarse(const double2* D5, const int* nbr9, int V, int d, C<T>* K, hipStream_t s);
 
 template <typename T>
 void coarse_apply(const CoarseOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s);
 
-// one SAP colour pass on a coarse level
+// Work buffers of a coarse SAP colour pass (each [V][d], part [V][4]);
+// ping-ponged by MR step.
 template <typename T>
-void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const int* site_blk,
-                       const int* site_loc, int nblk, int bs, int colour, int mr_iters,
-                       const C<T>* b, C<T>* z, hipStream_t s);
+struct SapScratch {
+  C<T>* rho[2] = {nullptr, nullptr};
+  C<T>* q[2] = {nullptr, nullptr};
+  T* part[2] = {nullptr, nullptr};
+};
+
+// one SAP colour pass z <- z + MR_blocks(b - D z) on the blocks of colour
+// `colour` (blk_sites lists the sites of every block, blocks colour-major)
+template <typename T>
+void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const int* site_blk, int nblk,
+                       int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
+                       hipStream_t s);
 
 // odd-even: out(x) = gamma in_c(x) + alpha S(x) in_s(x) + beta sum_hops(in_h)(x)
 // for x in `sites` (other sites of out untouched)
@@ -66,15 +77,19 @@ template <typename T>
 void coarse_site_apply(const CoarseOpView<T>& op, const int* sites, int nsites, T gamma,
                        const C<T>* in_c, T alpha, const C<T>* in_s, T beta, const C<T>* in_h,
                        C<T>* out, hipStream_t s);
-// out(x) = M(x) in(x) for x in `sites`, M = [nsites][d][d] (dense per-site matrices)
+// out(x) = M(x) in(x) for x in `sites`, M = [nsites][d][d] (dense per-site
+// matrices, column-major)
 template <typename T>
 void site_matvec(const C<T>* M, const int* sites, int nsites, int d, const C<T>* in, C<T>* out,
                  hipStream_t s);
-// inverses of the self blocks of `sites` (FP64, Gauss-Jordan with partial pivoting)
+// inverses of the self blocks (taken from the FP64 [V][5][d][d] Galerkin
+// output) of `sites`, FP64 Gauss-Jordan with partial pivoting; written
+// column-major, [nsites][d][d]
 void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv,
                         hipStream_t s);
 
-// canonical copy [V][9][d][d] (self, +x..+t, -x..-t) of an FP64 coarse operator
+// canonical copy [V][9][d][d] row-major (self, +x..+t, -x..-t) of the FP64
+// nine-block operator
 void export_coarse(const CoarseOpView<double>& op, double2* out, hipStream_t s);
 
 }  // namespace ddamg

@@ -2,13 +2,12 @@
 // reductions (shared by the coarse apply, SAP, transfer and Galerkin kernels).
 #pragma once
 
+#include <type_traits>
+
 #include "coarse.h"
 
 namespace ddamg {
 
-// ---------------------------------------------------------------------------
-// workgroup reductions
-// ---------------------------------------------------------------------------
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll
@@ -37,42 +36,45 @@ __device__ inline void wg_sum(T (&v)[NV], T* scratch) {
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// stencil rows
-// ---------------------------------------------------------------------------
-// row i of B_k(x) v(y), summed over j: forward-stored block M (row-major d x d)
-template <typename T>
-__device__ inline C<T> row_fwd(const C<T>* __restrict__ M, const C<T>* __restrict__ v, int i, int d) {
-  C<T> acc = czero<T>();
-  const C<T>* m = M + (size_t)i * d;
-  for (int j = 0; j < d; ++j) cfma(acc, m[j], v[j]);
-  return acc;
-}
-// row i of G5 F^H G5 v: g_i sum_j g_j conj(F[j][i]) v_j
-template <typename T>
-__device__ inline C<T> row_bwd(const C<T>* __restrict__ F, const C<T>* __restrict__ v, int i, int d) {
-  const int h = d >> 1;
-  C<T> a = czero<T>(), b = czero<T>();
-  for (int j = 0; j < h; ++j) cjfma(a, F[(size_t)j * d + i], v[j]);
-  for (int j = h; j < d; ++j) cjfma(b, F[(size_t)j * d + i], v[j]);
-  C<T> r = csub(a, b);
-  return i < h ? r : mk<T>(-r.x, -r.y);
+// Row i of a column-major d x d block times a vector held in LDS (every lane
+// reads the same v[j], a broadcast): acc += sum_j M[j*d + i] v[j].
+// NCH = ceil(d / 8) is a compile-time bound, so all d loads of the row are
+// issued before the first multiply: one memory round trip per block.
+// GMAX caps the chunks loaded at once (FP64 rows at most three chunks).
+template <typename T, int NCH, int GMAX = 8>
+__device__ inline void colmajor_row(const C<T>* __restrict__ M, const C<T>* v, int i, int d, C<T>& acc) {
+  constexpr int G0 = sizeof(T) == 4 ? NCH : (NCH < 3 ? NCH : 3);
+  constexpr int G = G0 < GMAX ? G0 : GMAX;
+  C<T> a[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
+#pragma unroll 1
+  for (int c0 = 0; c0 < NCH; c0 += G) {
+    C<T> m[8 * G];
+#pragma unroll
+    for (int u = 0; u < 8 * G; ++u) {
+      const int j = 8 * c0 + u;
+      m[u] = j < d ? M[(size_t)j * d + i] : czero<T>();
+    }
+#pragma unroll
+    for (int u = 0; u < 8 * G; ++u)
+      if (8 * c0 + u < d) cfma(a[u & 3], m[u], v[8 * c0 + u]);
+  }
+  acc = cadd(acc, cadd(cadd(a[0], a[1]), cadd(a[2], a[3])));
 }
 
-// full stencil row: (D v)(site)[i]
-template <typename T>
-__device__ inline C<T> stencil_row(const CoarseOpView<T>& op, const C<T>* __restrict__ v, int site, int i) {
-  const int d = op.d;
-  const size_t bsz = (size_t)d * d;
-  const C<T>* Ds = op.D + (size_t)site * 5 * bsz;
-  C<T> acc = row_fwd<T>(Ds, v + (size_t)site * d, i, d);
-  for (int mu = 0; mu < 4; ++mu) {
-    const int nf = op.nbr[site * 8 + 2 * mu];
-    acc = cadd(acc, row_fwd<T>(Ds + (1 + mu) * bsz, v + (size_t)nf * d, i, d));
-    const int nb = op.nbr[site * 8 + 2 * mu + 1];
-    acc = cadd(acc, row_bwd<T>(op.D + ((size_t)nb * 5 + 1 + mu) * bsz, v + (size_t)nb * d, i, d));
+// run f(std::integral_constant<int, NCH>) for NCH = ceil(d / 8), d <= 64
+template <typename F>
+inline void with_nch(int d, F&& f) {
+  switch ((d + 7) / 8) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: throw Error(-1, "coarse levels support at most 64 components per site");
   }
-  return acc;
 }
 
 }  // namespace ddamg

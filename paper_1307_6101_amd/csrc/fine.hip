@@ -292,21 +292,32 @@ void clover_build(const FineGeom& g, const double2* links, double m0, double csw
   DD_LAUNCH_CHECK();
 }
 
+// the eight neighbour blocks of `blk` (2*mu + 0: +mu, 2*mu + 1: -mu), two
+// 16-byte loads issued together so that no later load waits on an index
+struct Nbr8 {
+  int v[8];
+};
+__device__ inline Nbr8 load_nbr8(const int* __restrict__ nbr, int blk) {
+  const int4* p = reinterpret_cast<const int4*>(nbr + (size_t)blk * 8);
+  const int4 a = p[0], b = p[1];
+  return Nbr8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
+}
+
 template <typename T, int MU>
 __device__ inline void hops_mu(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk, int loc,
-                               C<T> acc[12]) {
+                               const Nbr8& nb8, C<T> acc[12]) {
   constexpr int bit = 1 << MU;
   C<T> psi[12], u[9];
   // forward: psi(x+mu), U_mu(x)
   {
-    int nb = (loc & bit) ? op.nbr[blk * 8 + 2 * MU] : blk;
+    const int nb = (loc & bit) ? nb8.v[2 * MU] : blk;
     load_spinor<T>(in, nb, loc ^ bit, psi);
     load_link<T>(op.U, blk, loc, MU, u);
     hop_apply<T, MU, true>(psi, u, acc);
   }
   // backward: psi(x-mu), U_mu(x-mu)^H
   {
-    int nb = (loc & bit) ? blk : op.nbr[blk * 8 + 2 * MU + 1];
+    const int nb = (loc & bit) ? blk : nb8.v[2 * MU + 1];
     load_spinor<T>(in, nb, loc ^ bit, psi);
     load_link<T>(op.U, nb, loc ^ bit, MU, u);
     hop_apply<T, MU, false>(psi, u, acc);
@@ -317,13 +328,14 @@ __device__ inline void hops_mu(const FineOpView<T>& op, const C<T>* __restrict__
 template <typename T>
 __device__ inline void dslash_site(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk,
                                    int loc, C<T> out[12]) {
+  const Nbr8 nb8 = load_nbr8(op.nbr, blk);
   C<T> acc[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-  hops_mu<T, 0>(op, in, blk, loc, acc);
-  hops_mu<T, 1>(op, in, blk, loc, acc);
-  hops_mu<T, 2>(op, in, blk, loc, acc);
-  hops_mu<T, 3>(op, in, blk, loc, acc);
+  hops_mu<T, 0>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, 1>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, 2>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, 3>(op, in, blk, loc, nb8, acc);
   C<T> psi[12];
   load_spinor<T>(in, blk, loc, psi);
   clover_apply<T>(op.A, blk, loc, psi, out);

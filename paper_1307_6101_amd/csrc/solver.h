@@ -79,9 +79,17 @@ struct LevelStore {
   long long V = 0, n = 0;
   // coarse operator (level >= 1)
   CoarseGeom cg;
-  DevArray<int> c_nbr, c_blk_sites, c_site_blk, c_site_loc, c_even, c_odd;
-  DevArray<double2> D64, Einv64;
-  DevArray<float2> D32, Einv32;
+  DevArray<int> c_nbr9, c_blk_sites, c_site_blk, c_even, c_odd;
+  DevArray<double2> D64;           // Galerkin output: self + forward blocks, row-major
+  DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
+  DevArray<float2> K32, Einv32;
+  // coarse SAP work buffers (rho, q ping-pong; per-site inner products)
+  DevArray<double2> sr64, sq64;
+  DevArray<float2> sr32, sq32;
+  DevArray<double> sp64;
+  DevArray<float> sp32;
+  SapScratch<double> ss64;
+  SapScratch<float> ss32;
   // interpolation to the next level
   int N = 0;
   AggTables at;

@@ -30,10 +30,10 @@ template <> FineOpView<float> Context::view<float>() const {
   return FineOpView<float>{U32.p, A32.p, nbr.p, g.nblk};
 }
 template <> CoarseOpView<double> LevelStore::cview<double>() const {
-  return CoarseOpView<double>{D64.p, c_nbr.p, (int)V, d};
+  return CoarseOpView<double>{K64.p, c_nbr9.p, (int)V, d};
 }
 template <> CoarseOpView<float> LevelStore::cview<float>() const {
-  return CoarseOpView<float>{D32.p, c_nbr.p, (int)V, d};
+  return CoarseOpView<float>{K32.p, c_nbr9.p, (int)V, d};
 }
 template <> Work<double>& Hierarchy::work<double>(int l) { return w64[l]; }
 template <> Work<float>& Hierarchy::work<float>(int l) { return w32[l]; }
@@ -82,15 +82,19 @@ template <typename T> void Hierarchy::apply(int l, const C<T>* in, C<T>* out) {
   else coarse_apply<T>(lv[l].cview<T>(), in, out, s);
 }
 
+template <typename T> SapScratch<T>& sap_scratch(LevelStore& L_);
+template <> SapScratch<double>& sap_scratch<double>(LevelStore& L_) { return L_.ss64; }
+template <> SapScratch<float>& sap_scratch<float>(LevelStore& L_) { return L_.ss32; }
+
 template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsweeps) {
   for (int it = 0; it < nsweeps; ++it)
     for (int col = 0; col < 2; ++col) {
       if (l == 0) {
         sap_colour<T>(ctx->view<T>(), ctx->cblk.p, col, p.mr_iters, b, z, s);
       } else {
-        const LevelStore& L_ = lv[l];
-        coarse_sap_colour<T>(L_.cview<T>(), L_.c_blk_sites.p, L_.c_site_blk.p, L_.c_site_loc.p,
-                             L_.cg.nblk, L_.cg.bs, col, p.mr_iters, b, z, s);
+        LevelStore& L_ = lv[l];
+        coarse_sap_colour<T>(L_.cview<T>(), L_.c_blk_sites.p, L_.c_site_blk.p, L_.cg.nblk, L_.cg.bs, col,
+                             p.mr_iters, b, z, sap_scratch<T>(L_), s);
       }
     }
 }
@@ -120,6 +124,34 @@ double Hierarchy::norm(const double2* v, long long n) {
 // with classical Gram-Schmidt and one re-orthogonalisation pass (two fused
 // inner-product launches per step); Givens rotations on the host.
 // ---------------------------------------------------------------------------
+// One Arnoldi orthogonalisation step against V_0..V_j (classical Gram-Schmidt,
+// second pass only when the first removed more than half of ||w||^2, the
+// criterion of Daniel, Gragg, Kaufman and Stewart).  Fills h[0..j] with the
+// Hessenberg column, returns ||w_perp||, and leaves in `c` the coefficients
+// that the caller applies as w += V c together with V_{j+1} = w / hn.
+template <typename T>
+static double gs_step(Reducer& red, const C<T>* V, long long n, int j, C<T>* w, std::vector<cd>& h,
+                      std::vector<cd>& h2, Coefs& c, hipStream_t s) {
+  red.dots<T>(V, n, j + 1, w, n, true, s);
+  red.fetch(j + 2, h.data(), s);
+  const double ww = h[j + 1].real();
+  double proj = 0;
+  for (int i = 0; i <= j; ++i) {
+    proj += std::norm(h[i]);
+    c.c[i] = d2(-h[i]);
+  }
+  if (ww - proj > 0.5 * ww) return std::sqrt(ww - proj);
+  red.update_dots<T>(c, V, n, j + 1, w, n, s);
+  red.fetch(j + 2, h2.data(), s);
+  double nn = h2[j + 1].real();
+  for (int i = 0; i <= j; ++i) {
+    c.c[i] = d2(-h2[i]);
+    nn -= std::norm(h2[i]);
+    h[i] += h2[i];
+  }
+  return std::sqrt(std::max(nn, 0.0));
+}
+
 template <typename T, typename Op, typename Pre>
 int Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m,
                       int max_cycles, double tol) {
@@ -152,21 +184,9 @@ int Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* 
       C<T>* Zj = Z + (size_t)j * n;
       if (use_pre) pre(Vj, Zj);
       op(Zj, w);
-      red->dots<T>(V, n, j + 1, w, n, false, s);
-      red->fetch(j + 1, h.data(), s);
       Coefs c;
-      for (int i = 0; i <= j; ++i) c.c[i] = d2(-h[i]);
-      vlincomb<T, T>(c, j + 1, V, n, w, n, s);
-      red->dots<T>(V, n, j + 1, w, n, true, s);
-      red->fetch(j + 2, h2.data(), s);
-      double nn = h2[j + 1].real();
-      for (int i = 0; i <= j; ++i) {
-        c.c[i] = d2(-h2[i]);
-        nn -= std::norm(h2[i]);
-        H[(size_t)i * m + j] = h[i] + h2[i];
-      }
-      vlincomb<T, T>(c, j + 1, V, n, w, n, s);
-      const double hn = std::sqrt(std::max(nn, 0.0));
+      const double hn = gs_step<T>(*red, V, n, j, w, h, h2, c, s);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
       H[(size_t)(j + 1) * m + j] = hn;
       // apply previous rotations, then a new one that zeroes H[j+1][j]
       for (int i = 0; i < j; ++i) {
@@ -193,11 +213,9 @@ int Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* 
       jend = j + 1;
       const double est = std::abs(g[j + 1]);
       if (!std::isfinite(est)) throw Error(DDAMG_ENONFINITE, "non-finite residual in GMRES");
-      if (est <= target || hn == 0.0) { conv = est <= target || hn == 0.0; break; }
-      if (j + 1 < m) {
-        vcopy<T, T>(w, V + (size_t)(j + 1) * n, n, s);
-        vscale<T>(make_double2(1.0 / hn, 0), V + (size_t)(j + 1) * n, n, s);
-      }
+      if (est <= target || hn == 0.0) { conv = true; break; }
+      // w += V c and V_{j+1} = w / hn in one pass
+      if (j + 1 < m) vlincomb_scale<T>(c, j + 1, V, n, w, n, 1.0 / hn, V + (size_t)(j + 1) * n, s);
     }
     // y = R^{-1} g, x += Z y
     std::vector<cd> y(jend);
@@ -218,8 +236,7 @@ int Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* 
     red->fetch(1, &rr, s);
     beta = std::sqrt(rr.real());
     if (!(beta > 0)) break;
-    vcopy<T, T>(w, V, n, s);
-    vscale<T>(make_double2(1.0 / beta, 0), V, n, s);
+    vlincomb_scale<T>(Coefs{}, 0, V, n, w, n, 1.0 / beta, V, s);
   }
   return iters;
 }
@@ -340,8 +357,7 @@ template <typename T> int Hierarchy::outer(const double2* b, double2* x, ddamg_s
   Work<T>& W0 = work<T>(0);
   while (status == DDAMG_ENOCONV && restarts < p.max_restarts) {
     if (!std::isfinite(beta)) { status = DDAMG_ENONFINITE; break; }
-    vcopy<double, double>(w, V, n, s);
-    vscale<double>(make_double2(1.0 / beta, 0), V, n, s);
+    vlincomb_scale<double>(Coefs{}, 0, V, n, w, n, 1.0 / beta, V, s);
     std::fill(Hm.begin(), Hm.end(), cd(0));
     std::fill(g.begin(), g.end(), cd(0));
     g[0] = beta;
@@ -358,21 +374,9 @@ template <typename T> int Hierarchy::outer(const double2* b, double2* x, ddamg_s
         vcopy<T, double>(Zj, ot.p, n, s);
         dslash<double>(D, ot.p, w, s);
       }
-      red->dots<double>(V, n, j + 1, w, n, false, s);
-      red->fetch(j + 1, h.data(), s);
       Coefs c;
-      for (int i = 0; i <= j; ++i) c.c[i] = d2(-h[i]);
-      vlincomb<double, double>(c, j + 1, V, n, w, n, s);
-      red->dots<double>(V, n, j + 1, w, n, true, s);
-      red->fetch(j + 2, h2.data(), s);
-      double nn = h2[j + 1].real();
-      for (int i = 0; i <= j; ++i) {
-        c.c[i] = d2(-h2[i]);
-        nn -= std::norm(h2[i]);
-        Hm[(size_t)i * m + j] = h[i] + h2[i];
-      }
-      vlincomb<double, double>(c, j + 1, V, n, w, n, s);
-      const double hn = std::sqrt(std::max(nn, 0.0));
+      const double hn = gs_step<double>(*red, V, n, j, w, h, h2, c, s);
+      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
       for (int i = 0; i < j; ++i) {
         cd a = Hm[(size_t)i * m + j], bq = Hm[(size_t)(i + 1) * m + j];
         Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
@@ -396,10 +400,7 @@ template <typename T> int Hierarchy::outer(const double2* b, double2* x, ddamg_s
       const double est = std::abs(g[j + 1]);
       if (!std::isfinite(est)) { status = DDAMG_ENONFINITE; break; }
       if (est <= target || hn == 0.0) break;
-      if (j + 1 < m) {
-        vcopy<double, double>(w, V + (size_t)(j + 1) * n, n, s);
-        vscale<double>(make_double2(1.0 / hn, 0), V + (size_t)(j + 1) * n, n, s);
-      }
+      if (j + 1 < m) vlincomb_scale<double>(c, j + 1, V, n, w, n, 1.0 / hn, V + (size_t)(j + 1) * n, s);
     }
     if (status == DDAMG_ENONFINITE) break;
     std::vector<cd> y(jend);
@@ -475,8 +476,8 @@ void Hierarchy::build_level(int l, bool from32) {
   // Galerkin in FP64
   if (l == 0) galerkin_fine(ctx->g, F.at, F.ad(), N, ctx->view<double>(), F.P64.p, Cc.D64.p, s);
   else galerkin_coarse(F.cg, F.at, F.ad(), N, F.cview<double>(), F.P64.p, Cc.D64.p, s);
-  const long long dsz = Cc.V * 5 * (long long)Cc.d * Cc.d;
-  vcopy<double, float>(Cc.D64.p, Cc.D32.p, dsz, s);
+  expand_coarse<double>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K64.p, s);
+  expand_coarse<float>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K32.p, s);
   if (l + 1 == L - 1 && Cc.cg.bipartite) {
     const int ne = (int)Cc.cg.even.size();
     self_block_inverse(Cc.D64.p, Cc.c_even.p, ne, Cc.d, Cc.Einv64.p, s);
@@ -617,14 +618,31 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       int sap[4] = {0, 0, 0, 0};
       if (l < L - 1) for (int mu = 0; mu < 4; ++mu) sap[mu] = p.sap_block[mu];
       S.cg = make_coarse_geom(dims, d, sap);
-      S.c_nbr.upload(S.cg.nbr, s);
+      S.c_nbr9.upload(S.cg.nbr9, s);
       S.c_blk_sites.upload(S.cg.blk_sites, s);
       S.c_site_blk.upload(S.cg.site_blk, s);
-      S.c_site_loc.upload(S.cg.site_loc, s);
       S.c_even.upload(S.cg.even, s);
       S.c_odd.upload(S.cg.odd, s);
       S.D64.alloc((size_t)S.V * 5 * d * d);
-      S.D32.alloc((size_t)S.V * 5 * d * d);
+      S.K64.alloc((size_t)S.V * 9 * d * d);
+      S.K32.alloc((size_t)S.V * 9 * d * d);
+      if (l < L - 1) {
+        const size_t nv = (size_t)S.V * d;
+        S.sr64.alloc(2 * nv);
+        S.sq64.alloc(2 * nv);
+        S.sr32.alloc(2 * nv);
+        S.sq32.alloc(2 * nv);
+        S.sp64.alloc(2 * (size_t)S.V * 4);
+        S.sp32.alloc(2 * (size_t)S.V * 4);
+        for (int k = 0; k < 2; ++k) {
+          S.ss64.rho[k] = S.sr64.p + k * nv;
+          S.ss64.q[k] = S.sq64.p + k * nv;
+          S.ss64.part[k] = S.sp64.p + k * (size_t)S.V * 4;
+          S.ss32.rho[k] = S.sr32.p + k * nv;
+          S.ss32.q[k] = S.sq32.p + k * nv;
+          S.ss32.part[k] = S.sp32.p + k * (size_t)S.V * 4;
+        }
+      }
       if (l == L - 1 && S.cg.bipartite) {
         S.Einv64.alloc(S.cg.even.size() * (size_t)d * d);
         S.Einv32.alloc(S.cg.even.size() * (size_t)d * d);

@@ -480,22 +480,10 @@ struct GalCoarseGeom {
   int agg[4];
 };
 
-// row i of M v restricted to the column range [j0, j1) (forward-stored block)
-__device__ inline double2 row_fwd_rng(const double2* M, const double2* v, int i, int d, int j0, int j1) {
-  double2 acc = czero<double>();
-  for (int j = j0; j < j1; ++j) cfma(acc, M[(size_t)i * d + j], v[j]);
-  return acc;
-}
-// row i of G5 F^H G5 v restricted to columns [j0, j1)
-__device__ inline double2 row_bwd_rng(const double2* F, const double2* v, int i, int d, int j0, int j1) {
-  const int h = d / 2;
-  double2 acc = czero<double>();
-  for (int j = j0; j < j1; ++j) {
-    double2 t = cjmul(F[(size_t)j * d + i], v[j]);
-    const bool neg = (i < h) != (j < h);
-    acc = neg ? csub(acc, t) : cadd(acc, t);
-  }
-  return acc;
+// row i of a column-major block times u restricted to the columns [j0, j1)
+__device__ inline void colmajor_row_rng(const double2* M, const double2* u, int i, int d, int j0, int j1,
+                                        double2& acc) {
+  for (int j = j0; j < j1; ++j) cfma(acc, M[(size_t)j * d + i], u[j]);
 }
 
 __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N,
@@ -524,30 +512,24 @@ __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ memb
   }
   const size_t bsz = (size_t)d * d;
   const double2* Pk = P + k * fstride;
-  const double2* Ds = op.D + (size_t)site * 5 * bsz;
+  const double2* Kx = op.K + (size_t)site * 9 * bsz;
+  const int* nb9 = op.nbr9 + (size_t)site * 9;
   const int twoN = 2 * N;
   for (int tau = 0; tau < 5; ++tau) {
     double2 y = czero<double>();
     if (valid) {
       if (tau == 0) {
-        y = row_fwd_rng(Ds, Pk + (size_t)site * d, i, d, j0, j1);
+        colmajor_row_rng(Kx, Pk + (size_t)site * d, i, d, j0, j1, y);
         for (int mu = 0; mu < 4; ++mu) {
-          if (fin[mu]) {
-            const int nf = op.nbr[site * 8 + 2 * mu];
-            y = cadd(y, row_fwd_rng(Ds + (1 + mu) * bsz, Pk + (size_t)nf * d, i, d, j0, j1));
-          }
-          if (bin[mu]) {
-            const int nb = op.nbr[site * 8 + 2 * mu + 1];
-            y = cadd(y, row_bwd_rng(op.D + ((size_t)nb * 5 + 1 + mu) * bsz, Pk + (size_t)nb * d, i, d,
-                                    j0, j1));
-          }
+          if (fin[mu])
+            colmajor_row_rng(Kx + (1 + mu) * bsz, Pk + (size_t)nb9[1 + mu] * d, i, d, j0, j1, y);
+          if (bin[mu])
+            colmajor_row_rng(Kx + (5 + mu) * bsz, Pk + (size_t)nb9[5 + mu] * d, i, d, j0, j1, y);
         }
       } else {
         const int mu = tau - 1;
-        if (!fin[mu]) {
-          const int nf = op.nbr[site * 8 + 2 * mu];
-          y = row_fwd_rng(Ds + (1 + mu) * bsz, Pk + (size_t)nf * d, i, d, j0, j1);
-        }
+        if (!fin[mu])
+          colmajor_row_rng(Kx + (1 + mu) * bsz, Pk + (size_t)nb9[1 + mu] * d, i, d, j0, j1, y);
       }
     }
     const bool up = i < h;

@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic per launch of the FP32 stencil on the bench lattice, from the
+# FETCH_SIZE / WRITE_SIZE counter runs summarised in
+# profiles/dslash_clover16x32_counters.md (null once the kernel changes)
+DSLASH_F32_TRAFFIC_BYTES = 139.43e6
 WORKLOAD = "clover16x32_3lvl"
 # compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
@@ -44,6 +48,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the Wilson-clover stencil loops and a reference copy of known size "
+                         "(for hardware-counter runs)")
+    ap.add_argument("--lattice", default=None,
+                    help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
 
 
@@ -67,6 +76,9 @@ def main():
     from paper_1307_6101_amd import ddamg as dd
 
     cfg = W.CONFIGS[WORKLOAD]
+    if args.kernels_only:
+        kernels_only(args, cfg, dd, W, np, torch)
+        return
     dims = cfg["dims"]
     V = int(np.prod(dims))
     dev = torch.device("cuda:0")
@@ -185,7 +197,7 @@ def main():
 
     dom = kern["dslash_f32"]
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": DSLASH_F32_TRAFFIC_BYTES,
                 "kernel": "k_dslash<float> (Wilson-clover, FP32)",
                 "note": "16^3x32 working set ~175 MB fits the 256 MB Infinity Cache"}
 
@@ -223,6 +235,49 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def kernels_only(args, cfg, dd, W, np, torch):
+    """Stencil launches in FP32 and FP64 plus a 1 GiB device copy (the
+    reference for scaling FETCH_SIZE / WRITE_SIZE counters)."""
+    dims = tuple(int(x) for x in args.lattice.split(",")) if args.lattice else cfg["dims"]
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+    log(f"[bench] kernels-only dims={dims} inputs in {time.time() - t0:.1f}s")
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], torch.from_numpy(U).to(dev))
+    del U
+    bd = torch.from_numpy(b).to(dev)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, prec, cdt, bpr in (("dslash_f32", dd.F32, torch.complex64, 4),
+                                 ("dslash_f64", dd.F64, torch.complex128, 8)):
+        x = torch.zeros(V * 12, dtype=cdt, device=dev)
+        y = torch.zeros_like(x)
+        dd.to_native(ctx, None, 0, bd, x, prec=prec)
+        dd.apply_D(ctx, x, y, prec=prec, layout=dd.NATIVE)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            dd.apply_D(ctx, x, y, prec=prec, layout=dd.NATIVE)
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1000.0 / args.kernel_reps
+        nbytes = DPSI_REALS_PER_SITE * bpr * V
+        out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1),
+                     "algorithmic_bytes": nbytes}
+        log(f"[bench] {name}: {t * 1e6:.1f} us, {nbytes / t / 1e9:.0f} GB/s")
+        del x, y
+    # reference copy of known size: 1 GiB read + 1 GiB written
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"lattice": dims, "kernels": out, "copy_bytes_each_way": a.numel() * 8}), flush=True)
 
 
 def cpu_baseline(cfg, U, b, outer_iters, V):

@@ -349,7 +349,7 @@ __device__ inline void dslash_site(const FineOpView<T>& op, const C<T>* __restri
 template <typename T>
 __global__ void __launch_bounds__(256) k_dslash(FineOpView<T> op, const C<T>* __restrict__ in,
                                                 C<T>* __restrict__ out) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = xcd_slab_index(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= op.nblk) return;
   C<T> o[12];
@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int*
                                                     C<T>* __restrict__ z) {
   __shared__ C<T> rs[12 * 256];
   const int t = threadIdx.x;
-  const int jb = blockIdx.x * 16 + (t >> 4);
+  const int jb = xcd_slab_index(blockIdx.x, gridDim.x) * 16 + (t >> 4);
   const int loc = t & 15;
   const bool valid = jb < ncb;
   const int blk = valid ? cblk[jb] : 0;

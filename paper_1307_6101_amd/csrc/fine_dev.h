@@ -61,6 +61,15 @@ __device__ inline void hop_apply(const C<T> psi[12], const C<T> u[9], C<T> acc[1
   }
 }
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup i runs on XCD
+// i mod 8), each with its own L2.  Map workgroup i to a logical index so that
+// every XCD processes one contiguous slab of blocks: lattice neighbours then
+// share an L2 instead of being fetched again by another XCD.
+__device__ inline int xcd_slab_index(int bid, int nwg) {
+  if (nwg % 8 != 0) return bid;
+  return (bid & 7) * (nwg >> 3) + (bid >> 3);
+}
+
 template <typename T>
 __device__ inline void load_spinor(const C<T>* __restrict__ f, int blk, int loc, C<T> v[12]) {
   const C<T>* p = f + (long long)blk * 192 + loc;

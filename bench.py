@@ -35,6 +35,7 @@ WORKLOAD = "clover16x32_3lvl"
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
 # (24 reals) -> 192 reals
 DPSI_REALS_PER_SITE = 192
+DPSI_SPINOR_REALS_PER_SITE = 48
 # one SAP sweep (both colours) per site: b, z in, z out (72 reals), links and
 # clover (144 reals)
 SAP_REALS_PER_SITE = 216
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-half", action="store_true",
+                    help="skip the FP16-operator-storage variant of the mixed solve")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
@@ -94,7 +97,7 @@ def main():
     ctx = dd.create(dims, cfg["m0"], cfg["csw"], Ud)
     del Ud
 
-    def params(prec):
+    def params(prec, half=False):
         p = dd.params_default(cfg["levels"])
         for l, a in enumerate(cfg["agg"]):
             for mu in range(4):
@@ -103,12 +106,13 @@ def main():
             p.ntv[l] = n
         p.nu = cfg["nu"]
         p.precond_prec = prec
+        p.half_storage = 1 if half else 0
         return p
 
-    def setup(prec):
+    def setup(prec, half=False):
         torch.cuda.synchronize()
         t = time.time()
-        H = dd.build_hierarchy(ctx, params(prec), tvd)
+        H = dd.build_hierarchy(ctx, params(prec, half), tvd)
         torch.cuda.synchronize()
         return H, time.time() - t
 
@@ -157,6 +161,23 @@ def main():
         plain["rel_diff_vs_mixed_solution"] = float(diff)
         del H64
 
+    # the mixed solve with the preconditioner's operator data stored in FP16
+    half = None
+    H16 = None
+    if not args.no_half:
+        H16, t_setup16 = setup(dd.F32, half=True)
+        log(f"[bench] FP16-storage setup {t_setup16:.2f}s")
+        one_solve(H16)
+        torch.cuda.synchronize()
+        t = time.time()
+        hst = [one_solve(H16) for _ in range(max(1, min(args.steps, 3)))]
+        torch.cuda.synchronize()
+        t_half = (time.time() - t) / len(hst)
+        half = dict(time_to_solution_s=round(t_half, 4), setup_s=round(t_setup16, 3),
+                    outer_iters=hst[-1]["outer_iters"], true_relres=hst[-1]["true_relres"],
+                    speedup_vs_fp32_storage=round((ms / 1000.0) / t_half, 3))
+        log(f"[bench] FP16-storage solve {t_half:.3f}s, {hst[-1]['outer_iters']} its")
+
     # dominant fine kernels, timed with events on the stream the library uses
     kern = {}
     stream = torch.cuda.current_stream()
@@ -189,6 +210,12 @@ def main():
     for name, tk, bytes_per_real in (("dslash_f32", t_d32, 4), ("dslash_f64", t_d64, 8)):
         nbytes = DPSI_REALS_PER_SITE * bytes_per_real * V
         kern[name] = dict(seconds=tk, algorithmic_bytes=nbytes, gbs=nbytes / tk / 1e9)
+    if H16 is not None:
+        t_d16 = time_launches(lambda: dd.apply_Dc(H16, 0, nat32, out32, prec=dd.F32, layout=dd.NATIVE),
+                              args.kernel_reps)
+        # FP32 spinor in and out, FP16 links and clover
+        nbytes = (DPSI_SPINOR_REALS_PER_SITE * 4 + (DPSI_REALS_PER_SITE - DPSI_SPINOR_REALS_PER_SITE) * 2) * V
+        kern["dslash_f16store"] = dict(seconds=t_d16, algorithmic_bytes=nbytes, gbs=nbytes / t_d16 / 1e9)
     sbytes = SAP_REALS_PER_SITE * 4 * V
     kern["sap_sweep_f32"] = dict(seconds=t_sap32, algorithmic_bytes=sbytes, gbs=sbytes / t_sap32 / 1e9,
                                  launches=2)
@@ -229,6 +256,7 @@ def main():
         "kcycle_iters": stats[-1]["kcycle_iters"],
         "coarsest_iters": stats[-1]["coarsest_iters"],
         "plain_fp64": plain,
+        "fp16_storage": half,
         "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
         "kernels": {k: {"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)} for k, v in kern.items()},
         "roofline": roofline,

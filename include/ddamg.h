@@ -96,6 +96,17 @@ typedef struct {
   int max_restarts;           /* outer restart cycles before DDAMG_ENOCONV */
   int precond_prec;           /* DDAMG_F32 (mixed) or DDAMG_F64 (plain) */
   int cycle;                  /* DDAMG_KCYCLE or DDAMG_VCYCLE */
+  int half_storage;           /* 0: the preconditioner's operator data (fine
+                                 links and clover, every P_l, every coarse D_l)
+                                 are stored at precond_prec.  1: stored as IEEE
+                                 binary16 and widened to FP32 on load, the
+                                 arithmetic staying FP32 (needs precond_prec =
+                                 DDAMG_F32); the hierarchy's FP32 level
+                                 operations (apply_Dc, restrict, prolong,
+                                 sap_smooth with prec = DDAMG_F32) then read
+                                 these FP16 copies too.  Orthonormalisation,
+                                 Galerkin products and the outer solver
+                                 always use the FP64 masters. */
 } ddamg_params;
 
 typedef struct {

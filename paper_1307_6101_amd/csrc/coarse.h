@@ -40,20 +40,20 @@ struct CoarseGeom {
 CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]);
 
 
-template <typename T>
+template <typename T, typename S = C<T>>
 struct CoarseOpView {
-  const C<T>* K;       // [V][9][d][d], column-major blocks
+  const S* K;          // [V][9][d][d], column-major blocks (stored as S)
   const int* nbr9;     // [V][9]: site itself, then +mu, then -mu neighbours
   int V, d;
 };
 
 // expand the FP64 Galerkin output [V][5][d][d] (row-major) into the
-// nine-block column-major apply layout at precision T
-template <typename T>
-void expand_coarse(const double2* D5, const int* nbr9, int V, int d, C<T>* K, hipStream_t s);
+// nine-block column-major apply layout, stored as S (double2, float2, __half2)
+template <typename S>
+void expand_coarse(const double2* D5, const int* nbr9, int V, int d, S* K, hipStream_t s);
 
-template <typename T>
-void coarse_apply(const CoarseOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s);
+template <typename T, typename S>
+void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s);
 
 // Work buffers of a coarse SAP colour pass (each [V][d], part [V][4]);
 // ping-ponged by MR step.
@@ -66,15 +66,15 @@ struct SapScratch {
 
 // one SAP colour pass z <- z + MR_blocks(b - D z) on the blocks of colour
 // `colour` (blk_sites lists the sites of every block, blocks colour-major)
-template <typename T>
-void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const int* site_blk, int nblk,
+template <typename T, typename S>
+void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
                        int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
                        hipStream_t s);
 
 // odd-even: out(x) = gamma in_c(x) + alpha S(x) in_s(x) + beta sum_hops(in_h)(x)
 // for x in `sites` (other sites of out untouched)
-template <typename T>
-void coarse_site_apply(const CoarseOpView<T>& op, const int* sites, int nsites, T gamma,
+template <typename T, typename S>
+void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsites, T gamma,
                        const C<T>* in_c, T alpha, const C<T>* in_s, T beta, const C<T>* in_h,
                        C<T>* out, hipStream_t s);
 // out(x) = M(x) in(x) for x in `sites`, M = [nsites][d][d] (dense per-site

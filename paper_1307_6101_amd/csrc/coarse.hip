@@ -74,13 +74,20 @@ CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]) {
 // ---------------------------------------------------------------------------
 // nine-block expansion (gamma5-symmetry gives the backward blocks)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename S> __device__ inline S store_as(double2 v);
+template <> __device__ inline double2 store_as<double2>(double2 v) { return v; }
+template <> __device__ inline float2 store_as<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ inline __half2 store_as<__half2>(double2 v) {
+  return __floats2half2_rn((float)v.x, (float)v.y);
+}
+
+template <typename S>
 __global__ void k_expand(const double2* __restrict__ D5, const int* __restrict__ nbr9, int d,
-                         C<T>* __restrict__ K) {
+                         S* __restrict__ K) {
   const int x = blockIdx.x, k = blockIdx.y;
   const int h = d / 2;
   const size_t bsz = (size_t)d * d;
-  C<T>* o = K + ((size_t)x * 9 + k) * bsz;
+  S* o = K + ((size_t)x * 9 + k) * bsz;
   for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
     const int j = e / d, i = e % d;        // column-major position of element (i, j)
     double2 v;
@@ -92,14 +99,14 @@ __global__ void k_expand(const double2* __restrict__ D5, const int* __restrict__
       v = cconj(D5[((size_t)nb * 5 + 1 + mu) * bsz + (size_t)j * d + i]);
       if ((i < h) != (j < h)) v = mk<double>(-v.x, -v.y);
     }
-    o[e] = ccast<T>(v);
+    o[e] = store_as<S>(v);
   }
 }
 
-template <typename T>
-void expand_coarse(const double2* D5, const int* nbr9, int V, int d, C<T>* K, hipStream_t s) {
+template <typename S>
+void expand_coarse(const double2* D5, const int* nbr9, int V, int d, S* K, hipStream_t s) {
   dim3 grid(V, 9);
-  k_expand<T><<<grid, 256, 0, s>>>(D5, nbr9, d, K);
+  k_expand<S><<<grid, 256, 0, s>>>(D5, nbr9, d, K);
   DD_LAUNCH_CHECK();
 }
 
@@ -112,30 +119,38 @@ void expand_coarse(const double2* D5, const int* nbr9, int V, int d, C<T>* K, hi
 // ---------------------------------------------------------------------------
 constexpr int SW = 8;   // wavefronts per site workgroup
 
-template <typename T, int NCH>
-__device__ inline C<T> site_cols(const C<T>* __restrict__ Kx, size_t bsz, const C<T> (*vin)[64],
-                                 unsigned mask, int j0, int lane, int d) {
+template <typename T, typename S, int NCH>
+__device__ __forceinline__ C<T> site_cols(const S* __restrict__ Kx, size_t bsz, const C<T> (*vin)[64],
+                                          unsigned mask, int j0, int lane, int d) {
   constexpr int KG = sizeof(T) == 4 ? 9 : 3;
+  // lanes past the last row read row 0 and return zero, so every
+  // load of a group is unconditional within the wavefront; the block mask
+  // and the column bound are wavefront-uniform
+  const int row = lane < d ? lane : 0;
   C<T> acc = czero<T>();
 #pragma unroll 1
   for (int k0 = 0; k0 < 9; k0 += KG) {
-    C<T> m[KG][NCH];
+    // raw stored values: all loads issue before the first conversion
+    S m[KG][NCH];
 #pragma unroll
-    for (int kk = 0; kk < KG; ++kk)
+    for (int kk = 0; kk < KG; ++kk) {
+      const bool blk = (mask >> (k0 + kk)) & 1u;
 #pragma unroll
       for (int u = 0; u < NCH; ++u) {
-        const int k = k0 + kk;
-        const bool use = k < 9 && ((mask >> k) & 1u) && lane < d && j0 + u < d;
-        m[kk][u] = use ? Kx[k * bsz + (size_t)(j0 + u) * d + lane] : czero<T>();
+        const int j = j0 + u < d ? j0 + u : 0;
+        m[kk][u] = blk ? Kx[(k0 + kk) * bsz + (size_t)j * d + row] : szero<S>();
       }
+    }
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
       for (int u = 0; u < NCH; ++u)
-        if (k0 + kk < 9 && ((mask >> (k0 + kk)) & 1u) && j0 + u < d)
-          cfma(acc, m[kk][u], vin[k0 + kk][j0 + u]);
+        // masked blocks are skipped, not multiplied by zero: their LDS
+        // inputs are not loaded and may hold anything
+        if (((mask >> (k0 + kk)) & 1u) && j0 + u < d) cfma(acc, ldc<T, S>(m[kk][u]), vin[k0 + kk][j0 + u]);
   }
-  return acc;
+  // lanes past the last row return zero (callers reduce over all 64 lanes)
+  return lane < d ? acc : czero<T>();
 }
 
 // sum of the eight wavefronts' partial rows; valid in wavefront 0, lane < d
@@ -151,8 +166,8 @@ __device__ inline C<T> site_rows_sum(C<T> part, C<T> (*prow)[64]) {
   return s;
 }
 
-template <typename T, int NCH>
-__global__ void __launch_bounds__(64 * SW) k_capply(CoarseOpView<T> op, const C<T>* __restrict__ in,
+template <typename T, typename S, int NCH>
+__global__ void __launch_bounds__(64 * SW) k_capply(CoarseOpView<T, S> op, const C<T>* __restrict__ in,
                                                     C<T>* __restrict__ out) {
   __shared__ C<T> vin[9][64];
   __shared__ C<T> prow[SW][64];
@@ -161,15 +176,15 @@ __global__ void __launch_bounds__(64 * SW) k_capply(CoarseOpView<T> op, const C<
     vin[e / d][e % d] = in[(size_t)op.nbr9[site * 9 + e / d] * d + e % d];
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> r = site_rows_sum<T>(site_cols<T, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
+  const C<T> r = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
                                                      w * NCH, lane, d), prow);
   if (w == 0 && lane < d) out[(size_t)site * d + lane] = r;
 }
 
-template <typename T>
-void coarse_apply(const CoarseOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s) {
+template <typename T, typename S>
+void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s) {
   with_nch(op.d, [&](auto nch) {
-    k_capply<T, decltype(nch)::value><<<op.V, 64 * SW, 0, s>>>(op, in, out);
+    k_capply<T, S, decltype(nch)::value><<<op.V, 64 * SW, 0, s>>>(op, in, out);
   });
   DD_LAUNCH_CHECK();
 }
@@ -185,8 +200,8 @@ void coarse_apply(const CoarseOpView<T>& op, const C<T>* in, C<T>* out, hipStrea
 //   k_sap_fin:  z += alpha_{last} rho_{last}
 // Buffers rho, q, part are ping-ponged by step parity.
 // ---------------------------------------------------------------------------
-template <typename T, int NCH>
-__global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T> op, const int* __restrict__ csites,
+template <typename T, typename S, int NCH>
+__global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, const int* __restrict__ csites,
                                                      const C<T>* __restrict__ b, const C<T>* __restrict__ z,
                                                      C<T>* __restrict__ rho0) {
   __shared__ C<T> vin[9][64];
@@ -196,7 +211,7 @@ __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T> op, const i
     vin[e / d][e % d] = z[(size_t)op.nbr9[site * 9 + e / d] * d + e % d];
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> dz = site_rows_sum<T>(site_cols<T, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
+  const C<T> dz = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
                                                       w * NCH, lane, d), prow);
   if (w == 0 && lane < d) rho0[(size_t)site * d + lane] = csub(b[(size_t)site * d + lane], dz);
 }
@@ -214,8 +229,8 @@ __device__ inline C<T> block_alpha(const T* __restrict__ part, const int* __rest
   return s2 > T(0) ? mk<T>(s0 / s2, s1 / s2) : czero<T>();
 }
 
-template <typename T, int NCH>
-__global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T> op, const int* __restrict__ csites,
+template <typename T, typename S, int NCH>
+__global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const int* __restrict__ csites,
                                                    const int* __restrict__ blk_sites,
                                                    const int* __restrict__ site_blk, int bs, int step,
                                                    const C<T>* __restrict__ rho_prev,
@@ -245,7 +260,7 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T> op, const int
   }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> q = site_rows_sum<T>(site_cols<T, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
+  const C<T> q = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
                                                      w * NCH, lane, d), prow);
   if (w == 0) {
     C<T> rho = czero<T>();
@@ -291,8 +306,8 @@ __global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __re
   }
 }
 
-template <typename T>
-void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const int* site_blk, int nblk,
+template <typename T, typename S>
+void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
                        int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
                        hipStream_t s) {
   if (mr_iters <= 0) return;
@@ -302,10 +317,10 @@ void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const in
   with_nch(op.d, [&](auto nch) {
     constexpr int NCH = decltype(nch)::value;
     // the residual is rho_0 and lands in the "previous" buffer of step 0
-    k_sap_res<T, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, b, z, ws.rho[1]);
+    k_sap_res<T, S, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, b, z, ws.rho[1]);
     for (int t = 0; t < mr_iters; ++t) {
       const int pp = (t + 1) & 1, cc = t & 1;   // previous / current buffers
-      k_sap_q<T, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, blk_sites, site_blk, bs, t, ws.rho[pp], ws.q[pp],
+      k_sap_q<T, S, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, blk_sites, site_blk, bs, t, ws.rho[pp], ws.q[pp],
                                                 ws.part[pp], ws.rho[cc], ws.q[cc], ws.part[cc], z);
     }
   });
@@ -318,8 +333,8 @@ void coarse_sap_colour(const CoarseOpView<T>& op, const int* blk_sites, const in
 // ---------------------------------------------------------------------------
 // odd-even building blocks (site workgroups, as above)
 // ---------------------------------------------------------------------------
-template <typename T, int NCH>
-__global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T> op, const int* __restrict__ sites,
+template <typename T, typename S, int NCH>
+__global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T, S> op, const int* __restrict__ sites,
                                                     T gamma, const C<T>* __restrict__ in_c, T alpha,
                                                     const C<T>* __restrict__ in_s, T beta,
                                                     const C<T>* __restrict__ in_h, C<T>* __restrict__ out) {
@@ -338,7 +353,7 @@ __global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T> op, const in
   }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> r = site_rows_sum<T>(site_cols<T, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
+  const C<T> r = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
                                                      w * NCH, lane, d), prow);
   if (w == 0 && lane < d) {
     C<T> acc = r;
@@ -347,12 +362,12 @@ __global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T> op, const in
   }
 }
 
-template <typename T>
-void coarse_site_apply(const CoarseOpView<T>& op, const int* sites, int nsites, T gamma,
+template <typename T, typename S>
+void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsites, T gamma,
                        const C<T>* in_c, T alpha, const C<T>* in_s, T beta, const C<T>* in_h,
                        C<T>* out, hipStream_t s) {
   with_nch(op.d, [&](auto nch) {
-    k_csites<T, decltype(nch)::value><<<nsites, 64 * SW, 0, s>>>(op, sites, gamma, in_c, alpha, in_s, beta,
+    k_csites<T, S, decltype(nch)::value><<<nsites, 64 * SW, 0, s>>>(op, sites, gamma, in_c, alpha, in_s, beta,
                                                                  in_h, out);
   });
   DD_LAUNCH_CHECK();
@@ -367,7 +382,7 @@ __global__ void __launch_bounds__(64 * SW) k_site_matvec(const C<T>* __restrict_
   const int k = blockIdx.x, site = sites[k], w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int e = threadIdx.x; e < d; e += blockDim.x) vin[0][e] = in[(size_t)site * d + e];
   __syncthreads();
-  const C<T> r = site_rows_sum<T>(site_cols<T, NCH>(M + (size_t)k * d * d, (size_t)d * d, vin, 1u,
+  const C<T> r = site_rows_sum<T>(site_cols<T, C<T>, NCH>(M + (size_t)k * d * d, (size_t)d * d, vin, 1u,
                                                      w * NCH, lane, d), prow);
   if (w == 0 && lane < d) out[(size_t)site * d + lane] = r;
 }
@@ -464,16 +479,21 @@ void export_coarse(const CoarseOpView<double>& op, double2* out, hipStream_t s) 
   DD_LAUNCH_CHECK();
 }
 
-#define DD_INST(T)                                                                              \
-  template void expand_coarse<T>(const double2*, const int*, int, int, C<T>*, hipStream_t);    \
-  template void coarse_apply<T>(const CoarseOpView<T>&, const C<T>*, C<T>*, hipStream_t);      \
-  template void coarse_sap_colour<T>(const CoarseOpView<T>&, const int*, const int*, int, int, int, \
-                                     int, const C<T>*, C<T>*, SapScratch<T>&, hipStream_t);     \
-  template void coarse_site_apply<T>(const CoarseOpView<T>&, const int*, int, T, const C<T>*, T, \
-                                     const C<T>*, T, const C<T>*, C<T>*, hipStream_t);          \
-  template void site_matvec<T>(const C<T>*, const int*, int, int, const C<T>*, C<T>*, hipStream_t);
-DD_INST(double)
-DD_INST(float)
+template void expand_coarse<double2>(const double2*, const int*, int, int, double2*, hipStream_t);
+template void expand_coarse<float2>(const double2*, const int*, int, int, float2*, hipStream_t);
+template void expand_coarse<__half2>(const double2*, const int*, int, int, __half2*, hipStream_t);
+
+#define DD_INST(T, S)                                                                            \
+  template void coarse_apply<T, S>(const CoarseOpView<T, S>&, const C<T>*, C<T>*, hipStream_t);  \
+  template void coarse_sap_colour<T, S>(const CoarseOpView<T, S>&, const int*, const int*, int, int, \
+                                        int, int, const C<T>*, C<T>*, SapScratch<T>&, hipStream_t); \
+  template void coarse_site_apply<T, S>(const CoarseOpView<T, S>&, const int*, int, T, const C<T>*, T, \
+                                        const C<T>*, T, const C<T>*, C<T>*, hipStream_t);
+DD_INST(double, double2)
+DD_INST(float, float2)
+DD_INST(float, __half2)
 #undef DD_INST
+template void site_matvec<double>(const double2*, const int*, int, int, const double2*, double2*, hipStream_t);
+template void site_matvec<float>(const float2*, const int*, int, int, const float2*, float2*, hipStream_t);
 
 }  // namespace ddamg

@@ -2,6 +2,7 @@
 // HIP vector types, error handling, launch helpers and wavefront reductions.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -75,6 +76,25 @@ template <typename V> __host__ __device__ inline V cmulmi(V a) { V c; c.x = a.y;
 template <typename To, typename From> __host__ __device__ inline C<To> ccast(From a) {
   return mk<To>(static_cast<To>(a.x), static_cast<To>(a.y));
 }
+
+// Operator storage: the arithmetic type T reads stored complex numbers of
+// type S (C<T> itself, or __half2 for FP16 storage with FP32 arithmetic).
+template <typename T, typename S> struct Load;
+template <> struct Load<double, double2> {
+  static __device__ inline double2 f(const double2& v) { return v; }
+};
+template <> struct Load<float, float2> {
+  static __device__ inline float2 f(const float2& v) { return v; }
+};
+template <> struct Load<float, __half2> {
+  static __device__ inline float2 f(const __half2& v) { return __half22float2(v); }
+};
+template <typename T, typename S> __device__ inline C<T> ldc(const S& v) { return Load<T, S>::f(v); }
+// zero of a storage type (__half2's default constructor leaves it unset)
+template <typename S> __device__ inline S szero();
+template <> __device__ inline double2 szero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ inline float2 szero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ inline __half2 szero<__half2>() { return __float2half2_rn(0.f); }
 
 // ---------------------------------------------------------------------------
 // Wavefront-level reductions (64 lanes) within groups of `width` lanes.

@@ -28,10 +28,10 @@ FineGeom make_fine_geom(const int dims[4]);
 // host tables: nbr_blk[blk*8 + 2*mu + (0 fwd | 1 bwd)], colour lists
 void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks /* [2][nblk/2] */);
 
-template <typename T>
+template <typename T, typename S = C<T>>
 struct FineOpView {
-  const C<T>* U;      // native links
-  const C<T>* A;      // native clover (mass folded in)
+  const S* U;         // native links
+  const S* A;         // native clover (mass folded in)
   const int* nbr;     // nbr_blk table
   int nblk;
 };
@@ -49,12 +49,15 @@ void links_to_native(const FineGeom& g, const double2* links, C<T>* out, hipStre
 void clover_build(const FineGeom& g, const double2* links, double m0, double csw, double2* out,
                   hipStream_t s);
 
-template <typename T>
-void dslash(const FineOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s);
+template <typename T, typename S>
+void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s);
 
 // one SAP colour pass: z += MR-block-solve(b - D z) on blocks of colour c
-template <typename T>
-void sap_colour(const FineOpView<T>& op, const int* colour_blocks, int colour, int mr_iters,
+template <typename T, typename S>
+void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,
                 const C<T>* b, C<T>* z, hipStream_t s);
+
+// FP64 -> FP16 copy of n complex numbers (operator storage)
+void to_half(const double2* in, __half2* out, long long n, hipStream_t s);
 
 }  // namespace ddamg

@@ -303,8 +303,8 @@ __device__ inline Nbr8 load_nbr8(const int* __restrict__ nbr, int blk) {
   return Nbr8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
 }
 
-template <typename T, int MU>
-__device__ inline void hops_mu(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk, int loc,
+template <typename T, typename S, int MU>
+__device__ inline void hops_mu(const FineOpView<T, S>& op, const C<T>* __restrict__ in, int blk, int loc,
                                const Nbr8& nb8, C<T> acc[12]) {
   constexpr int bit = 1 << MU;
   C<T> psi[12], u[9];
@@ -312,33 +312,33 @@ __device__ inline void hops_mu(const FineOpView<T>& op, const C<T>* __restrict__
   {
     const int nb = (loc & bit) ? nb8.v[2 * MU] : blk;
     load_spinor<T>(in, nb, loc ^ bit, psi);
-    load_link<T>(op.U, blk, loc, MU, u);
+    load_link<T, S>(op.U, blk, loc, MU, u);
     hop_apply<T, MU, true>(psi, u, acc);
   }
   // backward: psi(x-mu), U_mu(x-mu)^H
   {
     const int nb = (loc & bit) ? blk : nb8.v[2 * MU + 1];
     load_spinor<T>(in, nb, loc ^ bit, psi);
-    load_link<T>(op.U, nb, loc ^ bit, MU, u);
+    load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
     hop_apply<T, MU, false>(psi, u, acc);
   }
 }
 
 // out(x) = (D in)(x) for one site
-template <typename T>
-__device__ inline void dslash_site(const FineOpView<T>& op, const C<T>* __restrict__ in, int blk,
+template <typename T, typename S>
+__device__ inline void dslash_site(const FineOpView<T, S>& op, const C<T>* __restrict__ in, int blk,
                                    int loc, C<T> out[12]) {
   const Nbr8 nb8 = load_nbr8(op.nbr, blk);
   C<T> acc[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-  hops_mu<T, 0>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, 1>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, 2>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, 3>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, S, 0>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, S, 1>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, S, 2>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, S, 3>(op, in, blk, loc, nb8, acc);
   C<T> psi[12];
   load_spinor<T>(in, blk, loc, psi);
-  clover_apply<T>(op.A, blk, loc, psi, out);
+  clover_apply<T, S>(op.A, blk, loc, psi, out);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     out[c].x -= T(0.5) * acc[c].x;
@@ -346,22 +346,22 @@ __device__ inline void dslash_site(const FineOpView<T>& op, const C<T>* __restri
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_dslash(FineOpView<T> op, const C<T>* __restrict__ in,
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_dslash(FineOpView<T, S> op, const C<T>* __restrict__ in,
                                                 C<T>* __restrict__ out) {
   const int tid = xcd_slab_index(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= op.nblk) return;
   C<T> o[12];
-  dslash_site<T>(op, in, blk, loc, o);
+  dslash_site<T, S>(op, in, blk, loc, o);
   C<T>* p = out + (long long)blk * 192 + loc;
 #pragma unroll
   for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
 }
 
-template <typename T>
-void dslash(const FineOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s) {
-  k_dslash<T><<<nblocks((size_t)op.nblk * 16, 256), 256, 0, s>>>(op, in, out);
+template <typename T, typename S>
+void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s) {
+  k_dslash<T, S><<<nblocks((size_t)op.nblk * 16, 256), 256, 0, s>>>(op, in, out);
   DD_LAUNCH_CHECK();
 }
 
@@ -371,21 +371,21 @@ void dslash(const FineOpView<T>& op, const C<T>* in, C<T>* out, hipStream_t s) {
 // residual steps on the Dirichlet block operator D_i (self term + the four
 // in-block hops, partner spinors exchanged through LDS), z += x.
 // ---------------------------------------------------------------------------
-template <typename T, int MU>
-__device__ inline void inblock_hop(const FineOpView<T>& op, const C<T>* __restrict__ rs, int t, int blk,
+template <typename T, typename S, int MU>
+__device__ inline void inblock_hop(const FineOpView<T, S>& op, const C<T>* __restrict__ rs, int t, int blk,
                                    int loc, C<T> acc[12]) {
   constexpr int bit = 1 << MU;
   C<T> psi[12], u[9];
 #pragma unroll
   for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
   // the link joining loc and loc^bit belongs to the lower site of the pair
-  load_link<T>(op.U, blk, loc & ~bit, MU, u);
+  load_link<T, S>(op.U, blk, loc & ~bit, MU, u);
   if (loc & bit) hop_apply<T, MU, false>(psi, u, acc);
   else hop_apply<T, MU, true>(psi, u, acc);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int* __restrict__ cblk,
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
                                                     int ncb, int mr_iters, const C<T>* __restrict__ b,
                                                     C<T>* __restrict__ z) {
   __shared__ C<T> rs[12 * 256];
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int*
   C<T> rho[12], x[12];
   if (valid) {
     C<T> dz[12], bb[12];
-    dslash_site<T>(op, z, blk, loc, dz);
+    dslash_site<T, S>(op, z, blk, loc, dz);
     load_spinor<T>(b, blk, loc, bb);
 #pragma unroll
     for (int c = 0; c < 12; ++c) rho[c] = csub(bb[c], dz[c]);
@@ -416,11 +416,11 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int*
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
     if (valid) {
-      inblock_hop<T, 0>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, 1>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, 2>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, 3>(op, rs, t, blk, loc, acc);
-      clover_apply<T>(op.A, blk, loc, rho, q);
+      inblock_hop<T, S, 0>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, S, 1>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, S, 2>(op, rs, t, blk, loc, acc);
+      inblock_hop<T, S, 3>(op, rs, t, blk, loc, acc);
+      clover_apply<T, S>(op.A, blk, loc, rho, q);
     } else {
 #pragma unroll
       for (int c = 0; c < 12; ++c) q[c] = czero<T>();
@@ -453,11 +453,11 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T> op, const int*
   }
 }
 
-template <typename T>
-void sap_colour(const FineOpView<T>& op, const int* colour_blocks, int colour, int mr_iters,
+template <typename T, typename S>
+void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,
                 const C<T>* b, C<T>* z, hipStream_t s) {
   const int ncb = op.nblk / 2;
-  k_sap_colour<T><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters,
+  k_sap_colour<T, S><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters,
                                                    b, z);
   DD_LAUNCH_CHECK();
 }
@@ -467,11 +467,28 @@ void sap_colour(const FineOpView<T>& op, const int* colour_blocks, int colour, i
   template void fine_to_native<T>(const FineGeom&, const double2*, C<T>*, int, hipStream_t);   \
   template void fine_from_native<T>(const FineGeom&, const C<T>*, double2*, int, hipStream_t); \
   template void links_to_native<T>(const FineGeom&, const double2*, C<T>*, hipStream_t);       \
-  template void dslash<T>(const FineOpView<T>&, const C<T>*, C<T>*, hipStream_t);              \
-  template void sap_colour<T>(const FineOpView<T>&, const int*, int, int, const C<T>*, C<T>*,   \
-                              hipStream_t);
+  template void dslash<T, C<T>>(const FineOpView<T, C<T>>&, const C<T>*, C<T>*, hipStream_t); \
+  template void sap_colour<T, C<T>>(const FineOpView<T, C<T>>&, const int*, int, int, const C<T>*, \
+                                    C<T>*, hipStream_t);
 DD_INST(double)
 DD_INST(float)
 #undef DD_INST
+template void dslash<float, __half2>(const FineOpView<float, __half2>&, const float2*, float2*, hipStream_t);
+template void sap_colour<float, __half2>(const FineOpView<float, __half2>&, const int*, int, int, const float2*,
+                                         float2*, hipStream_t);
+
+__global__ void k_to_half(const double2* __restrict__ in, __half2* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = __floats2half2_rn((float)in[i].x, (float)in[i].y);
+}
+
+void to_half(const double2* in, __half2* out, long long n, hipStream_t s) {
+  long long g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  k_to_half<<<(unsigned)g, 256, 0, s>>>(in, out, n);
+  DD_LAUNCH_CHECK();
+}
 
 }  // namespace ddamg

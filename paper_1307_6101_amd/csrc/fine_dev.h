@@ -70,32 +70,32 @@ __device__ inline int xcd_slab_index(int bid, int nwg) {
   return (bid & 7) * (nwg >> 3) + (bid >> 3);
 }
 
-template <typename T>
-__device__ inline void load_spinor(const C<T>* __restrict__ f, int blk, int loc, C<T> v[12]) {
-  const C<T>* p = f + (long long)blk * 192 + loc;
+template <typename T, typename S = C<T>>
+__device__ inline void load_spinor(const S* __restrict__ f, int blk, int loc, C<T> v[12]) {
+  const S* p = f + (long long)blk * 192 + loc;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = p[c * 16];
+  for (int c = 0; c < 12; ++c) v[c] = ldc<T, S>(p[c * 16]);
 }
-template <typename T>
-__device__ inline void load_link(const C<T>* __restrict__ U, int blk, int loc, int mu, C<T> u[9]) {
-  const C<T>* p = U + (long long)blk * 576 + mu * 144 + loc;
+template <typename T, typename S = C<T>>
+__device__ inline void load_link(const S* __restrict__ U, int blk, int loc, int mu, C<T> u[9]) {
+  const S* p = U + (long long)blk * 576 + mu * 144 + loc;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) u[k] = p[k * 16];
+  for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(p[k * 16]);
 }
 
 // out = A(x) v (packed clover, both chiralities)
-template <typename T>
-__device__ inline void clover_apply(const C<T>* __restrict__ A, int blk, int loc, const C<T> v[12],
+template <typename T, typename S = C<T>>
+__device__ inline void clover_apply(const S* __restrict__ A, int blk, int loc, const C<T> v[12],
                                     C<T> out[12]) {
-  const C<T>* p = A + (long long)blk * 576 + loc;
+  const S* p = A + (long long)blk * 576 + loc;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const C<T>* q = p + h * 18 * 16;
+    const S* q = p + h * 18 * 16;
     const C<T>* w = v + 6 * h;
     C<T>* o = out + 6 * h;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      C<T> d = q[k * 16];
+      const C<T> d = ldc<T, S>(q[k * 16]);
       o[2 * k] = cscale(w[2 * k], d.x);
       o[2 * k + 1] = cscale(w[2 * k + 1], d.y);
     }
@@ -104,7 +104,7 @@ __device__ inline void clover_apply(const C<T>* __restrict__ A, int blk, int loc
     for (int a = 0; a < 6; ++a)
 #pragma unroll
       for (int b = a + 1; b < 6; ++b) {
-        C<T> m = q[e * 16];
+        const C<T> m = ldc<T, S>(q[e * 16]);
         ++e;
         cfma(o[a], m, w[b]);
         cjfma(o[b], m, w[a]);

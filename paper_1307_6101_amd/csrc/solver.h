@@ -59,10 +59,13 @@ struct Context {
   double m0 = 0, csw = 0;
   DevArray<double2> U64, A64;
   DevArray<float2> U32, A32;
+  DevArray<__half2> U16, A16;     // FP16 storage, made on first request
   DevArray<int> nbr, cblk;
   DevArray<double2> s64a, s64b;   // scratch for canonical-layout calls
   DevArray<float2> s32a, s32b;
   template <typename T> FineOpView<T> view() const;
+  FineOpView<float, __half2> view16() const { return {U16.p, A16.p, nbr.p, g.nblk}; }
+  void make_half(hipStream_t s);
 };
 
 template <typename T>
@@ -83,6 +86,7 @@ struct LevelStore {
   DevArray<double2> D64;           // Galerkin output: self + forward blocks, row-major
   DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
   DevArray<float2> K32, Einv32;
+  DevArray<__half2> K16;
   // coarse SAP work buffers (rho, q ping-pong; per-site inner products)
   DevArray<double2> sr64, sq64;
   DevArray<float2> sr32, sq32;
@@ -96,10 +100,12 @@ struct LevelStore {
   DevArray<int> a_members, a_member_agg;
   DevArray<double2> P64;
   DevArray<float2> P32;
+  DevArray<__half2> P16;
   DevArray<double2> tv64;  // test vectors (FP64 storage; setup in the preconditioner precision uses tv32)
   DevArray<float2> tv32;
   AggDev ad() const { return AggDev{a_members.p, a_member_agg.p}; }
   template <typename T> CoarseOpView<T> cview() const;
+  CoarseOpView<float, __half2> cview16() const { return {K16.p, c_nbr9.p, (int)V, d}; }
 };
 
 struct Hierarchy {
@@ -117,11 +123,17 @@ struct Hierarchy {
   std::unique_ptr<Reducer> red;
   hipStream_t s = nullptr;
   bool recording = false;
+  bool half = false;               // FP16 operator storage for the FP32 levels
   long long kc_iters = 0, cs_iters = 0;
   const double2* tv_extra = nullptr;
 
   template <typename T> Work<T>& work(int l);
   template <typename T> const C<T>* P(int l) const;
+  // call f with the operator view / interpolation the precision-T kernels
+  // read (the FP16 copies for T = float when `half` is set)
+  template <typename T, typename F> void fine_op(F&& f) const;
+  template <typename T, typename F> void coarse_op(int l, F&& f) const;
+  template <typename T, typename F> void interp(int l, F&& f) const;
   template <typename T> const C<T>* tv(int l) const;
   template <typename T> C<T>* tv(int l);
 

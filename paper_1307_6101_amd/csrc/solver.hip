@@ -42,6 +42,22 @@ template <> const C<float>* Hierarchy::P<float>(int l) const { return lv[l].P32.
 template <> C<double>* Hierarchy::tv<double>(int l) { return lv[l].tv64.p; }
 template <> C<float>* Hierarchy::tv<float>(int l) { return lv[l].tv32.p; }
 
+template <typename T, typename F> void Hierarchy::fine_op(F&& f) const {
+  if constexpr (std::is_same<T, float>::value)
+    if (half) return f(ctx->view16());
+  f(ctx->view<T>());
+}
+template <typename T, typename F> void Hierarchy::coarse_op(int l, F&& f) const {
+  if constexpr (std::is_same<T, float>::value)
+    if (half) return f(lv[l].cview16());
+  f(lv[l].cview<T>());
+}
+template <typename T, typename F> void Hierarchy::interp(int l, F&& f) const {
+  if constexpr (std::is_same<T, float>::value)
+    if (half) return f(static_cast<const __half2*>(lv[l].P16.p));
+  f(P<T>(l));
+}
+
 static inline double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
 
 // ---------------------------------------------------------------------------
@@ -74,12 +90,20 @@ Context* create_context(const ddamg_lattice* lat, const double2* links, hipStrea
   return c.release();
 }
 
+void Context::make_half(hipStream_t s) {
+  if (U16.p) return;
+  U16.alloc((size_t)g.V * 36);
+  A16.alloc((size_t)g.V * 36);
+  to_half(U64.p, U16.p, (long long)g.V * 36, s);
+  to_half(A64.p, A16.p, (long long)g.V * 36, s);
+}
+
 // ---------------------------------------------------------------------------
 // level operations
 // ---------------------------------------------------------------------------
 template <typename T> void Hierarchy::apply(int l, const C<T>* in, C<T>* out) {
-  if (l == 0) dslash<T>(ctx->view<T>(), in, out, s);
-  else coarse_apply<T>(lv[l].cview<T>(), in, out, s);
+  if (l == 0) fine_op<T>([&](const auto& op) { dslash(op, in, out, s); });
+  else coarse_op<T>(l, [&](const auto& op) { coarse_apply(op, in, out, s); });
 }
 
 template <typename T> SapScratch<T>& sap_scratch(LevelStore& L_);
@@ -90,25 +114,31 @@ template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsw
   for (int it = 0; it < nsweeps; ++it)
     for (int col = 0; col < 2; ++col) {
       if (l == 0) {
-        sap_colour<T>(ctx->view<T>(), ctx->cblk.p, col, p.mr_iters, b, z, s);
+        fine_op<T>([&](const auto& op) { sap_colour(op, ctx->cblk.p, col, p.mr_iters, b, z, s); });
       } else {
         LevelStore& L_ = lv[l];
-        coarse_sap_colour<T>(L_.cview<T>(), L_.c_blk_sites.p, L_.c_site_blk.p, L_.cg.nblk, L_.cg.bs, col,
-                             p.mr_iters, b, z, sap_scratch<T>(L_), s);
+        coarse_op<T>(l, [&](const auto& op) {
+          coarse_sap_colour(op, L_.c_blk_sites.p, L_.c_site_blk.p, L_.cg.nblk, L_.cg.bs, col, p.mr_iters, b,
+                            z, sap_scratch<T>(L_), s);
+        });
       }
     }
 }
 
 template <typename T> void Hierarchy::restrict_to(int l, const C<T>* fine, C<T>* coarse) {
   const LevelStore& L_ = lv[l];
-  if (l == 0) restrict_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P<T>(l), fine, coarse, s);
-  else restrict_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P<T>(l), fine, coarse, s);
+  interp<T>(l, [&](const auto* P_) {
+    if (l == 0) restrict_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, fine, coarse, s);
+    else restrict_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, fine, coarse, s);
+  });
 }
 
 template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T>* fine) {
   const LevelStore& L_ = lv[l];
-  if (l == 0) prolong_fine<T>(ctx->g, L_.ad(), L_.N, P<T>(l), coarse, fine, s);
-  else prolong_coarse<T>(L_.ad(), L_.d, L_.N, L_.V, P<T>(l), coarse, fine, s);
+  interp<T>(l, [&](const auto* P_) {
+    if (l == 0) prolong_fine<T>(ctx->g, L_.ad(), L_.N, P_, coarse, fine, s);
+    else prolong_coarse<T>(L_.ad(), L_.d, L_.N, L_.V, P_, coarse, fine, s);
+  });
 }
 
 double Hierarchy::norm(const double2* v, long long n) {
@@ -252,13 +282,14 @@ template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out) {
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
   Work<T>& W = work<T>(c);
-  const auto op = L_.cview<T>();
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
   // t3_e = D_eo v_o ; t4_e = D_ee^-1 t3_e ; out_o = D_oo v_o - D_oe t4_e
-  coarse_site_apply<T>(op, L_.c_even.p, ne, T(0), nullptr, T(0), nullptr, T(1), v, W.t3.p, s);
-  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, W.t3.p, W.t4.p, s);
-  vzero<T>(out, L_.n, s);
-  coarse_site_apply<T>(op, L_.c_odd.p, no, T(0), nullptr, T(1), v, T(-1), W.t4.p, out, s);
+  coarse_op<T>(c, [&](const auto& op) {
+    coarse_site_apply(op, L_.c_even.p, ne, T(0), nullptr, T(0), nullptr, T(1), v, W.t3.p, s);
+    site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, W.t3.p, W.t4.p, s);
+    vzero<T>(out, L_.n, s);
+    coarse_site_apply(op, L_.c_odd.p, no, T(0), nullptr, T(1), v, T(-1), W.t4.p, out, s);
+  });
 }
 
 template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z) {
@@ -272,19 +303,22 @@ template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z) {
         z, p.coarse_restart, p.coarse_max_restarts, p.coarse_eps);
     return;
   }
-  const auto op = L_.cview<T>();
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
   // u_e = D_ee^-1 b_e
   vzero<T>(W.t1.p, n, s);
   site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, b, W.t1.p, s);
   // rhs_o = b_o - D_oe u_e (zero on even sites)
   vzero<T>(W.t2.p, n, s);
-  coarse_site_apply<T>(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s);
+  coarse_op<T>(c, [&](const auto& op) {
+    coarse_site_apply(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s);
+  });
   cs_iters += fgmres<T>(
       c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o); }, [](const C<T>*, C<T>*) {}, false, W.t2.p, z,
       p.coarse_restart, p.coarse_max_restarts, p.coarse_eps);
   // z_e = D_ee^-1 (b_e - D_eo z_o)
-  coarse_site_apply<T>(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s);
+  coarse_op<T>(c, [&](const auto& op) {
+    coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s);
+  });
   site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, W.t1.p, z, s);
 }
 
@@ -472,16 +506,18 @@ void Hierarchy::build_level(int l, bool from32) {
   if (from32) vcopy<float, double>(F.tv32.p, F.tv64.p, (long long)N * n, s);
   if (l == 0) orthonormalise_fine(ctx->g, F.at, F.ad(), N, F.tv64.p, F.P64.p, s);
   else orthonormalise_coarse(F.at, F.ad(), F.d, N, F.V, F.tv64.p, F.P64.p, s);
-  vcopy<double, float>(F.P64.p, F.P32.p, (long long)N * n, s);
+  if (F.P32.p) vcopy<double, float>(F.P64.p, F.P32.p, (long long)N * n, s);
+  if (F.P16.p) to_half(F.P64.p, F.P16.p, (long long)N * n, s);
   // Galerkin in FP64
   if (l == 0) galerkin_fine(ctx->g, F.at, F.ad(), N, ctx->view<double>(), F.P64.p, Cc.D64.p, s);
   else galerkin_coarse(F.cg, F.at, F.ad(), N, F.cview<double>(), F.P64.p, Cc.D64.p, s);
-  expand_coarse<double>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K64.p, s);
-  expand_coarse<float>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K32.p, s);
+  expand_coarse<double2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K64.p, s);
+  if (Cc.K32.p) expand_coarse<float2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K32.p, s);
+  if (Cc.K16.p) expand_coarse<__half2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K16.p, s);
   if (l + 1 == L - 1 && Cc.cg.bipartite) {
     const int ne = (int)Cc.cg.even.size();
     self_block_inverse(Cc.D64.p, Cc.c_even.p, ne, Cc.d, Cc.Einv64.p, s);
-    vcopy<double, float>(Cc.Einv64.p, Cc.Einv32.p, (long long)ne * Cc.d * Cc.d, s);
+    if (Cc.Einv32.p) vcopy<double, float>(Cc.Einv64.p, Cc.Einv32.p, (long long)ne * Cc.d * Cc.d, s);
   }
   DD_CHECK_HIP(hipStreamSynchronize(s));
 }
@@ -551,6 +587,9 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.levels >= 2 && p.levels <= 4, "levels must be 2..4");
   DD_REQUIRE(p.precond_prec == DDAMG_F32 || p.precond_prec == DDAMG_F64, "bad precond_prec");
   DD_REQUIRE(p.cycle == DDAMG_KCYCLE || p.cycle == DDAMG_VCYCLE, "bad cycle");
+  DD_REQUIRE(p.half_storage == 0 || p.half_storage == 1, "half_storage must be 0 or 1");
+  DD_REQUIRE(p.half_storage == 0 || p.precond_prec == DDAMG_F32,
+             "FP16 operator storage needs the FP32 preconditioner");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
   DD_REQUIRE(p.nkv >= 1 && p.nkv <= KMAX - 1, "nkv out of range");
   DD_REQUIRE(p.kc_len >= 1 && p.kc_len <= KMAX - 1 && p.kc_restarts >= 1, "bad K-cycle length");
@@ -601,7 +640,9 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
   H->s = s;
   H->tv_extra = tv_extra;
   H->red.reset(new Reducer);
+  H->half = pp->half_storage == 1;
   const ddamg_params& p = H->p;
+  if (H->half) ctx->make_half(s);
   const int L = H->L;
   H->lv.resize(L);
   int dims[4];
@@ -625,7 +666,8 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.c_odd.upload(S.cg.odd, s);
       S.D64.alloc((size_t)S.V * 5 * d * d);
       S.K64.alloc((size_t)S.V * 9 * d * d);
-      S.K32.alloc((size_t)S.V * 9 * d * d);
+      if (!H->half) S.K32.alloc((size_t)S.V * 9 * d * d);
+      if (H->half) S.K16.alloc((size_t)S.V * 9 * d * d);
       if (l < L - 1) {
         const size_t nv = (size_t)S.V * d;
         S.sr64.alloc(2 * nv);
@@ -654,7 +696,8 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.a_members.upload(S.at.members, s);
       S.a_member_agg.upload(S.at.member_agg, s);
       S.P64.alloc((size_t)S.N * S.n);
-      S.P32.alloc((size_t)S.N * S.n);
+      if (!H->half) S.P32.alloc((size_t)S.N * S.n);
+      if (H->half) S.P16.alloc((size_t)S.N * S.n);
       S.tv64.alloc((size_t)S.N * S.n);
       if (p.precond_prec == DDAMG_F32) S.tv32.alloc((size_t)S.N * S.n);
       for (int mu = 0; mu < 4; ++mu) dims[mu] = S.at.cdims[mu];

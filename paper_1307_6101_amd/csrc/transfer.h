@@ -35,17 +35,18 @@ struct AggDev {
 };
 
 // restriction out = P^H in and prolongation out += P in
-template <typename T>
-void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const C<T>* P,
+// (P stored as S: C<T>, or __half2 with T = float)
+template <typename T, typename S>
+void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
                    const C<T>* in, C<T>* out, hipStream_t s);
-template <typename T>
-void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const C<T>* P, const C<T>* in,
+template <typename T, typename S>
+void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const S* P, const C<T>* in,
                   C<T>* out, hipStream_t s);
-template <typename T>
+template <typename T, typename S>
 void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                     const C<T>* P, const C<T>* in, C<T>* out, hipStream_t s);
-template <typename T>
-void prolong_coarse(const AggDev& ad, int d, int N, long long V, const C<T>* P, const C<T>* in,
+                     const S* P, const C<T>* in, C<T>* out, hipStream_t s);
+template <typename T, typename S>
+void prolong_coarse(const AggDev& ad, int d, int N, long long V, const S* P, const C<T>* in,
                     C<T>* out, hipStream_t s);
 
 // orthonormalise the N test-vector fields tv (FP64, layout of level l) per

@@ -99,9 +99,9 @@ __device__ inline C<T> collect(const T* red, int N, int sigma, int k) {
 // ---------------------------------------------------------------------------
 // restriction / prolongation, fine level
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename S>
 __global__ void k_restrict_fine(const int* __restrict__ members, int nbpa, int N, long long fstride,
-                                const C<T>* __restrict__ P, const C<T>* __restrict__ in,
+                                const S* __restrict__ P, const C<T>* __restrict__ in,
                                 C<T>* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);
@@ -111,7 +111,7 @@ __global__ void k_restrict_fine(const int* __restrict__ members, int nbpa, int N
   load_spinor<T>(in, blk, loc, v);
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
-    load_spinor<T>(P + k * fstride, blk, loc, w);
+    load_spinor<T, S>(P + k * fstride, blk, loc, w);
     C<T> s0 = czero<T>(), s1 = czero<T>();
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -124,18 +124,18 @@ __global__ void k_restrict_fine(const int* __restrict__ members, int nbpa, int N
   if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
 }
 
-template <typename T>
-void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const C<T>* P,
+template <typename T, typename S>
+void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
                    const C<T>* in, C<T>* out, hipStream_t s) {
   const size_t sm = (size_t)((a.asz + 63) / 64) * N * 4 * sizeof(T);
-  k_restrict_fine<T><<<a.nagg, a.asz, sm, s>>>(ad.members, a.asz / 16, N, (long long)g.nblk * 192,
+  k_restrict_fine<T, S><<<a.nagg, a.asz, sm, s>>>(ad.members, a.asz / 16, N, (long long)g.nblk * 192,
                                                P, in, out);
   DD_LAUNCH_CHECK();
 }
 
-template <typename T>
+template <typename T, typename S>
 __global__ void k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N, long long fstride,
-                               const C<T>* __restrict__ P, const C<T>* __restrict__ in,
+                               const S* __restrict__ P, const C<T>* __restrict__ in,
                                C<T>* __restrict__ out) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
@@ -146,7 +146,7 @@ __global__ void k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N,
   load_spinor<T>(out, blk, loc, acc);
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
-    load_spinor<T>(P + k * fstride, blk, loc, w);
+    load_spinor<T, S>(P + k * fstride, blk, loc, w);
     const C<T> p0 = phi[k], p1 = phi[N + k];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -159,10 +159,10 @@ __global__ void k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N,
   for (int c = 0; c < 12; ++c) o[c * 16] = acc[c];
 }
 
-template <typename T>
-void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const C<T>* P, const C<T>* in,
+template <typename T, typename S>
+void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const S* P, const C<T>* in,
                   C<T>* out, hipStream_t s) {
-  k_prolong_fine<T><<<nblocks((size_t)g.nblk * 16, 256), 256, 0, s>>>(
+  k_prolong_fine<T, S><<<nblocks((size_t)g.nblk * 16, 256), 256, 0, s>>>(
       ad.member_agg, g.nblk, N, (long long)g.nblk * 192, P, in, out);
   DD_LAUNCH_CHECK();
 }
@@ -170,9 +170,9 @@ void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const C<T>* P, con
 // ---------------------------------------------------------------------------
 // restriction / prolongation, coarse level (d components per site)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename S>
 __global__ void k_restrict_coarse(const int* __restrict__ members, int asz, int d, int N,
-                                  long long fstride, const C<T>* __restrict__ P,
+                                  long long fstride, const S* __restrict__ P,
                                   const C<T>* __restrict__ in, C<T>* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);
@@ -185,27 +185,27 @@ __global__ void k_restrict_coarse(const int* __restrict__ members, int asz, int 
   const bool up = i < d / 2;
   for (int k = 0; k < N; ++k) {
     C<T> p = czero<T>();
-    if (valid) cjfma(p, P[k * fstride + e], v);
+    if (valid) cjfma(p, ldc<T, S>(P[k * fstride + e]), v);
     stash4<T>(red, N, k, up ? p.x : T(0), up ? p.y : T(0), up ? T(0) : p.x, up ? T(0) : p.y);
   }
   __syncthreads();
   if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
 }
 
-template <typename T>
+template <typename T, typename S>
 void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                     const C<T>* P, const C<T>* in, C<T>* out, hipStream_t s) {
+                     const S* P, const C<T>* in, C<T>* out, hipStream_t s) {
   const int rows = a.asz * d;
   DD_REQUIRE(rows <= 1024, "coarse aggregate too large for one workgroup");
   const int wg = 64 * ((rows + 63) / 64);
   const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(T);
-  k_restrict_coarse<T><<<a.nagg, wg, sm, s>>>(ad.members, a.asz, d, N, V * d, P, in, out);
+  k_restrict_coarse<T, S><<<a.nagg, wg, sm, s>>>(ad.members, a.asz, d, N, V * d, P, in, out);
   DD_LAUNCH_CHECK();
 }
 
-template <typename T>
+template <typename T, typename S>
 __global__ void k_prolong_coarse(const int* __restrict__ site_agg, long long V, int d, int N,
-                                 long long fstride, const C<T>* __restrict__ P,
+                                 long long fstride, const S* __restrict__ P,
                                  const C<T>* __restrict__ in, C<T>* __restrict__ out) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= V * d) return;
@@ -213,14 +213,14 @@ __global__ void k_prolong_coarse(const int* __restrict__ site_agg, long long V, 
   const int sigma = i < d / 2 ? 0 : 1;
   const C<T>* phi = in + (long long)site_agg[site] * 2 * N + sigma * N;
   C<T> acc = out[e];
-  for (int k = 0; k < N; ++k) cfma(acc, P[k * fstride + e], phi[k]);
+  for (int k = 0; k < N; ++k) cfma(acc, ldc<T, S>(P[k * fstride + e]), phi[k]);
   out[e] = acc;
 }
 
-template <typename T>
-void prolong_coarse(const AggDev& ad, int d, int N, long long V, const C<T>* P, const C<T>* in,
+template <typename T, typename S>
+void prolong_coarse(const AggDev& ad, int d, int N, long long V, const S* P, const C<T>* in,
                     C<T>* out, hipStream_t s) {
-  k_prolong_coarse<T><<<nblocks((size_t)V * d, 256), 256, 0, s>>>(ad.member_agg, V, d, N, V * d, P,
+  k_prolong_coarse<T, S><<<nblocks((size_t)V * d, 256), 256, 0, s>>>(ad.member_agg, V, d, N, V * d, P,
                                                                   in, out);
   DD_LAUNCH_CHECK();
 }
@@ -559,17 +559,18 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   DD_LAUNCH_CHECK();
 }
 
-#define DD_INST(T)                                                                                 \
-  template void restrict_fine<T>(const FineGeom&, const AggTables&, const AggDev&, int, const C<T>*, \
-                                 const C<T>*, C<T>*, hipStream_t);                                \
-  template void prolong_fine<T>(const FineGeom&, const AggDev&, int, const C<T>*, const C<T>*,     \
-                                C<T>*, hipStream_t);                                              \
-  template void restrict_coarse<T>(const AggTables&, const AggDev&, int, int, long long,          \
-                                   const C<T>*, const C<T>*, C<T>*, hipStream_t);                 \
-  template void prolong_coarse<T>(const AggDev&, int, int, long long, const C<T>*, const C<T>*,   \
-                                  C<T>*, hipStream_t);
-DD_INST(double)
-DD_INST(float)
+#define DD_INST(T, S)                                                                              \
+  template void restrict_fine<T, S>(const FineGeom&, const AggTables&, const AggDev&, int, const S*, \
+                                    const C<T>*, C<T>*, hipStream_t);                            \
+  template void prolong_fine<T, S>(const FineGeom&, const AggDev&, int, const S*, const C<T>*,      \
+                                   C<T>*, hipStream_t);                                          \
+  template void restrict_coarse<T, S>(const AggTables&, const AggDev&, int, int, long long,        \
+                                      const S*, const C<T>*, C<T>*, hipStream_t);                \
+  template void prolong_coarse<T, S>(const AggDev&, int, int, long long, const S*, const C<T>*,    \
+                                     C<T>*, hipStream_t);
+DD_INST(double, double2)
+DD_INST(float, float2)
+DD_INST(float, __half2)
 #undef DD_INST
 
 }  // namespace ddamg

@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("max_restarts", ctypes.c_int),
         ("precond_prec", ctypes.c_int),
         ("cycle", ctypes.c_int),
+        ("half_storage", ctypes.c_int),
     ]
 
 

@@ -32,7 +32,7 @@ def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def to_params(dd, p, prec=None, cycle="K"):
+def to_params(dd, p, prec=None, cycle="K", half=False):
     P = dd.params_default(int(p["levels"]))
     for l, a in enumerate(p["agg"]):
         for mu in range(4):
@@ -52,6 +52,7 @@ def to_params(dd, p, prec=None, cycle="K"):
     P.max_restarts = p.get("max_restarts", 100)
     P.precond_prec = dd.F64 if prec is None else prec
     P.cycle = dd.KCYCLE if cycle == "K" else dd.VCYCLE
+    P.half_storage = 1 if half else 0
     return P
 
 

@@ -37,14 +37,14 @@ def _p(levels, agg, ntv, n_inv=1, nu=2, **kw):
 
 
 class Setup:
-    def __init__(self, dd, dims, p, eps=0.5, m0=-0.3, csw=1.0, seed=1234, prec=None):
+    def __init__(self, dd, dims, p, eps=0.5, m0=-0.3, csw=1.0, seed=1234, prec=None, half=False):
         say(f"hierarchy dims={dims} levels={p['levels']} ntv={p['ntv']}")
         self.dims, self.p = dims, p
         self.U = W.links(dims, eps, seed)
         self.op = WilsonClover(self.U, m0, csw)
         self.ctx = dd.create(dims, m0, csw, dev(self.U))
         self.tv = W.test_vectors(dims, 12, p["ntv"][0], seed + 1)
-        self.H = dd.build_hierarchy(self.ctx, to_params(dd, p, prec), dev(self.tv))
+        self.H = dd.build_hierarchy(self.ctx, to_params(dd, p, prec, half=half), dev(self.tv))
         torch.cuda.synchronize()
 
 

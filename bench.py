@@ -39,6 +39,7 @@ DPSI_SPINOR_REALS_PER_SITE = 48
 # one SAP sweep (both colours) per site: b, z in, z out (72 reals), links and
 # clover (144 reals)
 SAP_REALS_PER_SITE = 216
+SAP_SPINOR_REALS_PER_SITE = 72
 
 
 def parse():
@@ -216,6 +217,12 @@ def main():
         # FP32 spinor in and out, FP16 links and clover
         nbytes = (DPSI_SPINOR_REALS_PER_SITE * 4 + (DPSI_REALS_PER_SITE - DPSI_SPINOR_REALS_PER_SITE) * 2) * V
         kern["dslash_f16store"] = dict(seconds=t_d16, algorithmic_bytes=nbytes, gbs=nbytes / t_d16 / 1e9)
+        t_s16 = time_launches(lambda: dd.sap_smooth(H16, 0, nat32, zs, 1, prec=dd.F32, layout=dd.NATIVE),
+                              args.kernel_reps)
+        # b, z in, z out in FP32; links and clover in FP16
+        sb16 = (SAP_SPINOR_REALS_PER_SITE * 4 + (SAP_REALS_PER_SITE - SAP_SPINOR_REALS_PER_SITE) * 2) * V
+        kern["sap_sweep_f16store"] = dict(seconds=t_s16, algorithmic_bytes=sb16, gbs=sb16 / t_s16 / 1e9,
+                                          launches=2)
     sbytes = SAP_REALS_PER_SITE * 4 * V
     kern["sap_sweep_f32"] = dict(seconds=t_sap32, algorithmic_bytes=sbytes, gbs=sbytes / t_sap32 / 1e9,
                                  launches=2)

@@ -19,6 +19,8 @@
 #include "fine.h"
 #include "fine_dev.h"
 
+#include <type_traits>
+
 #include <vector>
 
 namespace ddamg {
@@ -369,20 +371,55 @@ void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s
 // SAP colour pass.  One thread per site, 16 lanes per 2^4 block, 16 blocks
 // per workgroup.  r = b - D z with the full operator, then mr_iters minimal
 // residual steps on the Dirichlet block operator D_i (self term + the four
-// in-block hops, partner spinors exchanged through LDS), z += x.
+// in-block hops, partner spinors exchanged through LDS), z += x.  The block
+// operator of a site (its four in-block links and its clover) is read once
+// into registers, in its stored precision, and reused by every MR step.
 // ---------------------------------------------------------------------------
 template <typename T, typename S, int MU>
-__device__ inline void inblock_hop(const FineOpView<T, S>& op, const C<T>* __restrict__ rs, int t, int blk,
-                                   int loc, C<T> acc[12]) {
+__device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, const C<T> (&u)[9],
+                                   C<T> acc[12]) {
   constexpr int bit = 1 << MU;
-  C<T> psi[12], u[9];
+  C<T> psi[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
-  // the link joining loc and loc^bit belongs to the lower site of the pair
-  load_link<T, S>(op.U, blk, loc & ~bit, MU, u);
   if (loc & bit) hop_apply<T, MU, false>(psi, u, acc);
   else hop_apply<T, MU, true>(psi, u, acc);
 }
+
+// The site's block operator: kept in registers (KEEP) or read again from
+// memory at every MR step (FP64, where registers do not suffice).
+template <typename T, typename S, bool KEEP> struct BlockOp;
+template <typename T, typename S> struct BlockOp<T, S, true> {
+  S ul[4][9], al[36];
+  __device__ void load(const FineOpView<T, S>& op, int blk, int loc, bool valid) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      // the link joining loc and loc ^ (1 << mu) belongs to the lower site
+      const S* p = op.U + (long long)blk * 576 + mu * 144 + (loc & ~(1 << mu));
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ul[mu][k] = valid ? p[k * 16] : szero<S>();
+    }
+    const S* pa = op.A + (long long)blk * 576 + loc;
+#pragma unroll
+    for (int e = 0; e < 36; ++e) al[e] = valid ? pa[e * 16] : szero<S>();
+  }
+  __device__ void link(const FineOpView<T, S>&, int, int, int mu, C<T> (&u)[9]) const {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(ul[mu][k]);
+  }
+  __device__ void clover(const FineOpView<T, S>&, int, int, const C<T> v[12], C<T> out[12]) const {
+    clover_mul<T>([&](int e) { return ldc<T, S>(al[e]); }, v, out);
+  }
+};
+template <typename T, typename S> struct BlockOp<T, S, false> {
+  __device__ void load(const FineOpView<T, S>&, int, int, bool) {}
+  __device__ void link(const FineOpView<T, S>& op, int blk, int loc, int mu, C<T> (&u)[9]) const {
+    load_link<T, S>(op.U, blk, loc & ~(1 << mu), mu, u);
+  }
+  __device__ void clover(const FineOpView<T, S>& op, int blk, int loc, const C<T> v[12], C<T> out[12]) const {
+    clover_apply<T, S>(op.A, blk, loc, v, out);
+  }
+};
 
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
@@ -395,6 +432,8 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
   const bool valid = jb < ncb;
   const int blk = valid ? cblk[jb] : 0;
   C<T> rho[12], x[12];
+  constexpr bool KEEP = !std::is_same<T, double>::value;
+  BlockOp<T, S, KEEP> bop;
   if (valid) {
     C<T> dz[12], bb[12];
     dslash_site<T, S>(op, z, blk, loc, dz);
@@ -405,6 +444,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
 #pragma unroll
     for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
   }
+  bop.load(op, blk, loc, valid);
 #pragma unroll
   for (int c = 0; c < 12; ++c) x[c] = czero<T>();
 
@@ -415,16 +455,18 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
     C<T> q[12], acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-    if (valid) {
-      inblock_hop<T, S, 0>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, S, 1>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, S, 2>(op, rs, t, blk, loc, acc);
-      inblock_hop<T, S, 3>(op, rs, t, blk, loc, acc);
-      clover_apply<T, S>(op.A, blk, loc, rho, q);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) q[c] = czero<T>();
+    {
+      C<T> u[9];
+      bop.link(op, blk, loc, 0, u);
+      inblock_hop<T, S, 0>(rs, t, loc, u, acc);
+      bop.link(op, blk, loc, 1, u);
+      inblock_hop<T, S, 1>(rs, t, loc, u, acc);
+      bop.link(op, blk, loc, 2, u);
+      inblock_hop<T, S, 2>(rs, t, loc, u, acc);
+      bop.link(op, blk, loc, 3, u);
+      inblock_hop<T, S, 3>(rs, t, loc, u, acc);
     }
+    bop.clover(op, blk, loc, rho, q);
     T qr_re = 0, qr_im = 0, qq = 0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {

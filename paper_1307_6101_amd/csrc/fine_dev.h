@@ -83,19 +83,18 @@ __device__ inline void load_link(const S* __restrict__ U, int blk, int loc, int 
   for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(p[k * 16]);
 }
 
-// out = A(x) v (packed clover, both chiralities)
-template <typename T, typename S = C<T>>
-__device__ inline void clover_apply(const S* __restrict__ A, int blk, int loc, const C<T> v[12],
-                                    C<T> out[12]) {
-  const S* p = A + (long long)blk * 576 + loc;
+// out = A(x) v for the packed clover of one site (both chiralities); get(e)
+// returns entry e = 0..35 as C<T>: per chirality 3 packed real diagonal
+// pairs, then the 15 upper off-diagonal entries row by row
+template <typename T, typename G>
+__device__ inline void clover_mul(G&& get, const C<T> v[12], C<T> out[12]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const S* q = p + h * 18 * 16;
     const C<T>* w = v + 6 * h;
     C<T>* o = out + 6 * h;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const C<T> d = ldc<T, S>(q[k * 16]);
+      const C<T> d = get(h * 18 + k);
       o[2 * k] = cscale(w[2 * k], d.x);
       o[2 * k + 1] = cscale(w[2 * k + 1], d.y);
     }
@@ -104,12 +103,19 @@ __device__ inline void clover_apply(const S* __restrict__ A, int blk, int loc, c
     for (int a = 0; a < 6; ++a)
 #pragma unroll
       for (int b = a + 1; b < 6; ++b) {
-        const C<T> m = ldc<T, S>(q[e * 16]);
+        const C<T> m = get(h * 18 + e);
         ++e;
         cfma(o[a], m, w[b]);
         cjfma(o[b], m, w[a]);
       }
   }
+}
+
+template <typename T, typename S = C<T>>
+__device__ inline void clover_apply(const S* __restrict__ A, int blk, int loc, const C<T> v[12],
+                                    C<T> out[12]) {
+  const S* p = A + (long long)blk * 576 + loc;
+  clover_mul<T>([&](int e) { return ldc<T, S>(p[e * 16]); }, v, out);
 }
 
 }  // namespace ddamg

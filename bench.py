@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3
+BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-colour sources)
 # HBM traffic per launch of the FP32 stencil on the bench lattice, from the
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in
 # profiles/dslash_clover16x32_counters.md (null once the kernel changes)
@@ -226,8 +228,40 @@ def main():
     sbytes = SAP_REALS_PER_SITE * 4 * V
     kern["sap_sweep_f32"] = dict(seconds=t_sap32, algorithmic_bytes=sbytes, gbs=sbytes / t_sap32 / 1e9,
                                  launches=2)
+    # batched right-hand sides: one launch per operation for NB fields
+    NB = BATCH_RHS
+    natb = torch.zeros((NB, V * 12), dtype=torch.complex64, device=dev)
+    for r in range(NB):
+        natb[r].copy_(nat32)
+    outb = torch.zeros_like(natb)
+    t_db = time_launches(lambda: dd.apply_D(ctx, natb, outb, nrhs=NB, prec=dd.F32, layout=dd.NATIVE),
+                         args.kernel_reps)
+    nbytes = (DPSI_SPINOR_REALS_PER_SITE * NB + DPSI_REALS_PER_SITE - DPSI_SPINOR_REALS_PER_SITE) * 4 * V
+    kern[f"dslash_f32_x{NB}"] = dict(seconds=t_db, algorithmic_bytes=nbytes, gbs=nbytes / t_db / 1e9)
+    zb = torch.zeros_like(natb)
+    t_sb = time_launches(lambda: dd.sap_smooth(H32, 0, natb, zb, 1, nrhs=NB, prec=dd.F32, layout=dd.NATIVE),
+                         max(2, args.kernel_reps // 5))
+    sbb = (SAP_SPINOR_REALS_PER_SITE * NB + SAP_REALS_PER_SITE - SAP_SPINOR_REALS_PER_SITE) * 4 * V
+    kern[f"sap_sweep_f32_x{NB}"] = dict(seconds=t_sb, algorithmic_bytes=sbb, gbs=sbb / t_sb / 1e9, launches=2)
+    # coarse operator of level 1 on the matrix cores
+    (cdims, cd) = dd.level_info(H32, 1)
+    cV = int(np.prod(cdims))
+    cin = torch.randn((NB, cV * cd), dtype=torch.complex64, device=dev)
+    cout = torch.zeros_like(cin)
+    t_cb = time_launches(lambda: dd.apply_Dc(H32, 1, cin, cout, nrhs=NB, prec=dd.F32, layout=dd.NATIVE),
+                         args.kernel_reps)
+    flops = 9 * cd * cd * 8 * NB * cV
+    kbytes = 9 * cd * cd * 8 * cV + 2 * NB * cd * 8 * cV       # nine stored blocks + vectors
+    kern[f"coarse_apply_mfma_f32_x{NB}"] = dict(seconds=t_cb, algorithmic_bytes=kbytes, gbs=kbytes / t_cb / 1e9,
+                                                tflops=flops / t_cb / 1e12,
+                                                mfma_frac=flops / t_cb / 1e12 / MFMA_F32_PEAK_TFLOPS)
+    t_c1 = time_launches(lambda: dd.apply_Dc(H32, 1, cin[0], cout[0], nrhs=1, prec=dd.F32, layout=dd.NATIVE),
+                         args.kernel_reps)
+    kern["coarse_apply_f32_x1"] = dict(seconds=t_c1, algorithmic_bytes=9 * cd * cd * 8 * cV + 2 * cd * 8 * cV,
+                                       gbs=(9 * cd * cd * 8 * cV + 2 * cd * 8 * cV) / t_c1 / 1e9)
     for k, v in kern.items():
-        log(f"[bench] {k}: {v['seconds'] * 1e6:.1f} us, {v['gbs']:.0f} GB/s")
+        extra = f", {v['tflops']:.1f} TFLOP/s ({100 * v['mfma_frac']:.1f}% of FP32 MFMA peak)" if "tflops" in v else ""
+        log(f"[bench] {k}: {v['seconds'] * 1e6:.1f} us, {v['gbs']:.0f} GB/s{extra}")
 
     dom = kern["dslash_f32"]
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -265,7 +299,9 @@ def main():
         "plain_fp64": plain,
         "fp16_storage": half,
         "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
-        "kernels": {k: {"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)} for k, v in kern.items()},
+        "kernels": {k: dict({"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)},
+                            **({"TFLOP/s": round(v["tflops"], 2), "mfma_frac": round(v["mfma_frac"], 4)}
+                               if "tflops" in v else {})) for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

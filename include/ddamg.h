@@ -107,6 +107,13 @@ typedef struct {
                                  these FP16 copies too.  Orthonormalisation,
                                  Galerkin products and the outer solver
                                  always use the FP64 masters. */
+  int batch;                  /* largest number of systems advanced together
+                                 (1..32, default 16): the right-hand sides of
+                                 one ddamg_solve call go through the solver in
+                                 batches of this size, and so do the test
+                                 vectors of a level in the setup.  Batched
+                                 systems share every launch but keep their own
+                                 Krylov scalars and stopping tests. */
 } ddamg_params;
 
 typedef struct {
@@ -191,7 +198,8 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
                      int prec, int layout, void* stream);
 
 /* One application of the level-0 cycle (the preconditioner) to b: z = C(b)
- * (Alg. 2, or Alg. 1 with params.cycle = DDAMG_VCYCLE). */
+ * (Alg. 2, or Alg. 1 with params.cycle = DDAMG_VCYCLE), for nrhs fields
+ * (batches of at most params.batch). */
 int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int layout,
                        void* stream);
 
@@ -199,8 +207,13 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
  * (restart nkv, double precision) preconditioned by the cycle, to
  * ||b - D z|| <= tol ||b|| (checked on the recomputed residual).  z holds the
  * initial guess on entry (zeros for none) and the solution on return.
- * stats (host, may be NULL) receives one record per right-hand side.
- * Returns DDAMG_ENOCONV / DDAMG_ENONFINITE if any right-hand side did. */
+ * The right-hand sides go through in batches of params.batch: every launch
+ * serves the whole batch while each system keeps its own Krylov scalars,
+ * stopping tests and restarts (at every level), so each result is the one
+ * a solve of that system alone gives, up to rounding.  stats (host, may be
+ * NULL) receives one record per right-hand side; `seconds` is the wall
+ * time of its batch.  Returns DDAMG_ENOCONV / DDAMG_ENONFINITE if any
+ * right-hand side did (a non-finite inner residual fails the whole batch). */
 int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
                 void* stream);
 

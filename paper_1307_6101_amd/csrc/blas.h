@@ -36,8 +36,25 @@ template <typename T>
 void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>* y, long long n,
                     double scale, C<T>* dst, hipStream_t s);
 
+// Batches: nb systems advance together; field r of a batched vector w sits
+// at w + r*n, basis vector j of system r at V + j*vstride + r*n.  Per-system
+// coefficients live on the device as [nb][KMAX] double2 (see
+// Reducer::upload).
+constexpr int NBMAX = 32;  // largest batch of the batched vector kernels
+
+// y_r += sum_j c[r][j] Z_{j,r} (j < k), then, if dst != nullptr,
+// dst_r = scale[r] * y_r (dst_r = 0 where scale[r] == 0)
+template <typename T, typename TZ>
+void blincomb(const double2* c, const double* scale, int k, const C<TZ>* Z, long long zstride, C<T>* y,
+              long long n, int nb, C<T>* dst, hipStream_t s);
+
+// dst_r = scale[r] * src_r (zero where scale[r] == 0); src may equal dst
+template <typename T>
+void bscale(const double* scale, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s);
+
 // Fused inner products <V_j, w> (j < k) and <w, w> (entry k), accumulated in
-// FP64 in a fixed order; fetch() copies them to the host.
+// FP64 in a fixed order; fetch() copies them to the host.  The batched forms
+// do this for every system r of a batch (results [nb][k+1]).
 class Reducer {
  public:
   Reducer();
@@ -52,13 +69,31 @@ class Reducer {
   // copy the last results to the host (synchronises the stream)
   void fetch(int count, std::complex<double>* out, hipStream_t s);
 
+  // batched: c == nullptr for plain inner products, else the update first
+  template <typename T>
+  void bdots(const double2* c, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
+             hipStream_t s);
+  // results of the last batched call, out[r * (k+1) + j] (synchronises)
+  void bfetch(int k1, int nb, std::complex<double>* out, hipStream_t s);
+  // stage nb x KMAX coefficients (row r: system r) and nb scales on the
+  // device; the returned pointers stay valid for the next 63 uploads
+  const double2* upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
+                        const double** scale_dev, hipStream_t s);
+
  private:
   template <typename T>
   void launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd, const Coefs* c,
               hipStream_t s);
-  double* partial_ = nullptr;   // [GMAX][2*(KMAX+1)]
-  double2* result_ = nullptr;   // [KMAX+1]
+  double* partial_ = nullptr;   // [NBMAX][GMAX][2*(KMAX+1)]
+  double2* result_ = nullptr;   // [NBMAX][KMAX+1]
   double2* host_ = nullptr;     // pinned
+  // coefficient ring: pinned staging and device slots, an event per slot
+  static constexpr int NSLOT = 64;
+  unsigned char* cstage_ = nullptr;
+  unsigned char* cdev_ = nullptr;
+  hipEvent_t cev_[NSLOT] = {};
+  bool cev_used_[NSLOT] = {};
+  int cslot_ = 0;
 };
 
 }  // namespace ddamg

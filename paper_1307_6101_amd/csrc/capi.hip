@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/ddamg.h.  Each checks its
 // arguments on the host, converts canonical <-> native layouts where asked,
 // and calls into the hierarchy / kernels on the caller's stream.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <string>
@@ -55,32 +56,33 @@ template <typename E> E* ensure(DevArray<E>& a, size_t n) {
   return a.p;
 }
 
-// canonical complex128 <-> native at T for a level-l field (one field)
+// canonical complex128 <-> native at T for nrhs level-l fields (n complex each)
 template <typename T>
-void to_nat(Context& c, int l, long long n, const double2* in, C<T>* out, hipStream_t s) {
-  if (l == 0) fine_to_native<T>(c.g, in, out, 1, s);
-  else vcopy<double, T>(in, out, n, s);
+void to_nat(Context& c, int l, long long n, int nrhs, const double2* in, C<T>* out, hipStream_t s) {
+  if (l == 0) fine_to_native<T>(c.g, in, out, nrhs, s);
+  else vcopy<double, T>(in, out, n * nrhs, s);
 }
 template <typename T>
-void from_nat(Context& c, int l, long long n, const C<T>* in, double2* out, hipStream_t s) {
-  if (l == 0) fine_from_native<T>(c.g, in, out, 1, s);
-  else vcopy<T, double>(in, out, n, s);
+void from_nat(Context& c, int l, long long n, int nrhs, const C<T>* in, double2* out, hipStream_t s) {
+  if (l == 0) fine_from_native<T>(c.g, in, out, nrhs, s);
+  else vcopy<T, double>(in, out, n * nrhs, s);
 }
 
+// Every entry point hands the whole batch of nrhs fields to one batched
+// call; with the canonical layout the batch is converted through scratch
+// fields first.
 template <typename T>
 void apply_D_impl(Context& c, const void* in, void* out, int nrhs, int layout, hipStream_t s) {
   const long long n = c.g.V * 12;
   const auto op = c.view<T>();
-  for (int r = 0; r < nrhs; ++r) {
-    if (layout == DDAMG_NATIVE) {
-      dslash<T>(op, static_cast<const C<T>*>(in) + r * n, static_cast<C<T>*>(out) + r * n, s);
-    } else {
-      C<T>* a = ensure(ctx_scratch<T>(c, 0), n);
-      C<T>* b = ensure(ctx_scratch<T>(c, 1), n);
-      to_nat<T>(c, 0, n, static_cast<const double2*>(in) + r * n, a, s);
-      dslash<T>(op, a, b, s);
-      from_nat<T>(c, 0, n, b, static_cast<double2*>(out) + r * n, s);
-    }
+  if (layout == DDAMG_NATIVE) {
+    dslash<T>(op, static_cast<const C<T>*>(in), static_cast<C<T>*>(out), s, nrhs);
+  } else {
+    C<T>* a = ensure(ctx_scratch<T>(c, 0), n * nrhs);
+    C<T>* b = ensure(ctx_scratch<T>(c, 1), n * nrhs);
+    to_nat<T>(c, 0, n, nrhs, static_cast<const double2*>(in), a, s);
+    dslash<T>(op, a, b, s, nrhs);
+    from_nat<T>(c, 0, n, nrhs, b, static_cast<double2*>(out), s);
   }
 }
 
@@ -89,89 +91,83 @@ Hierarchy& H_(ddamg_hier h) {
   return *h->h;
 }
 
-// Each *_impl loops over the right-hand sides; with the canonical layout it
-// converts through the hierarchy's scratch fields.
 template <typename T>
 void apply_Dc_impl(Hierarchy& H, int level, const void* in, void* out, int nrhs, int layout) {
   const long long n = H.lv[level].n;
-  for (int r = 0; r < nrhs; ++r) {
-    if (layout == DDAMG_NATIVE) {
-      H.apply<T>(level, static_cast<const C<T>*>(in) + r * n, static_cast<C<T>*>(out) + r * n);
-    } else {
-      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
-      C<T>* b = ensure(hier_scratch<T>(H, 1), n);
-      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(in) + r * n, a, H.s);
-      H.apply<T>(level, a, b);
-      from_nat<T>(*H.ctx, level, n, b, static_cast<double2*>(out) + r * n, H.s);
-    }
+  if (layout == DDAMG_NATIVE) {
+    H.apply<T>(level, static_cast<const C<T>*>(in), static_cast<C<T>*>(out), nrhs);
+  } else {
+    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nrhs);
+    C<T>* b = ensure(hier_scratch<T>(H, 1), n * nrhs);
+    to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(in), a, H.s);
+    H.apply<T>(level, a, b, nrhs);
+    from_nat<T>(*H.ctx, level, n, nrhs, b, static_cast<double2*>(out), H.s);
   }
 }
 
 template <typename T>
 void restrict_impl(Hierarchy& H, int level, const void* fine, void* coarse, int nrhs, int layout) {
   const long long nf = H.lv[level].n, nc = H.lv[level + 1].n;
-  for (int r = 0; r < nrhs; ++r) {
-    if (layout == DDAMG_NATIVE) {
-      H.restrict_to<T>(level, static_cast<const C<T>*>(fine) + r * nf, static_cast<C<T>*>(coarse) + r * nc);
-    } else {
-      C<T>* a = ensure(hier_scratch<T>(H, 0), nf);
-      C<T>* b = ensure(hier_scratch<T>(H, 1), nf);
-      to_nat<T>(*H.ctx, level, nf, static_cast<const double2*>(fine) + r * nf, a, H.s);
-      H.restrict_to<T>(level, a, b);
-      from_nat<T>(*H.ctx, level + 1, nc, b, static_cast<double2*>(coarse) + r * nc, H.s);
-    }
+  if (layout == DDAMG_NATIVE) {
+    H.restrict_to<T>(level, static_cast<const C<T>*>(fine), static_cast<C<T>*>(coarse), nrhs);
+  } else {
+    C<T>* a = ensure(hier_scratch<T>(H, 0), nf * nrhs);
+    C<T>* b = ensure(hier_scratch<T>(H, 1), nf * nrhs);
+    to_nat<T>(*H.ctx, level, nf, nrhs, static_cast<const double2*>(fine), a, H.s);
+    H.restrict_to<T>(level, a, b, nrhs);
+    from_nat<T>(*H.ctx, level + 1, nc, nrhs, b, static_cast<double2*>(coarse), H.s);
   }
 }
 
 template <typename T>
 void prolong_impl(Hierarchy& H, int level, const void* coarse, void* fine, int nrhs, int layout) {
   const long long nf = H.lv[level].n, nc = H.lv[level + 1].n;
-  for (int r = 0; r < nrhs; ++r) {
-    if (layout == DDAMG_NATIVE) {
-      H.prolong_add<T>(level, static_cast<const C<T>*>(coarse) + r * nc, static_cast<C<T>*>(fine) + r * nf);
-    } else {
-      C<T>* a = ensure(hier_scratch<T>(H, 0), nf);
-      C<T>* b = ensure(hier_scratch<T>(H, 1), nf);
-      to_nat<T>(*H.ctx, level, nf, static_cast<const double2*>(fine) + r * nf, a, H.s);
-      to_nat<T>(*H.ctx, level + 1, nc, static_cast<const double2*>(coarse) + r * nc, b, H.s);
-      H.prolong_add<T>(level, b, a);
-      from_nat<T>(*H.ctx, level, nf, a, static_cast<double2*>(fine) + r * nf, H.s);
-    }
+  if (layout == DDAMG_NATIVE) {
+    H.prolong_add<T>(level, static_cast<const C<T>*>(coarse), static_cast<C<T>*>(fine), nrhs);
+  } else {
+    C<T>* a = ensure(hier_scratch<T>(H, 0), nf * nrhs);
+    C<T>* b = ensure(hier_scratch<T>(H, 1), nf * nrhs);
+    to_nat<T>(*H.ctx, level, nf, nrhs, static_cast<const double2*>(fine), a, H.s);
+    to_nat<T>(*H.ctx, level + 1, nc, nrhs, static_cast<const double2*>(coarse), b, H.s);
+    H.prolong_add<T>(level, b, a, nrhs);
+    from_nat<T>(*H.ctx, level, nf, nrhs, a, static_cast<double2*>(fine), H.s);
   }
 }
 
 template <typename T>
 void sap_impl(Hierarchy& H, int level, const void* b, void* z, int nsweeps, int nrhs, int layout) {
   const long long n = H.lv[level].n;
-  for (int r = 0; r < nrhs; ++r) {
-    if (layout == DDAMG_NATIVE) {
-      H.sap<T>(level, static_cast<const C<T>*>(b) + r * n, static_cast<C<T>*>(z) + r * n, nsweeps);
-    } else {
-      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
-      C<T>* c = ensure(hier_scratch<T>(H, 1), n);
-      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(b) + r * n, a, H.s);
-      to_nat<T>(*H.ctx, level, n, static_cast<const double2*>(z) + r * n, c, H.s);
-      H.sap<T>(level, a, c, nsweeps);
-      from_nat<T>(*H.ctx, level, n, c, static_cast<double2*>(z) + r * n, H.s);
-    }
+  if (layout == DDAMG_NATIVE) {
+    H.sap<T>(level, static_cast<const C<T>*>(b), static_cast<C<T>*>(z), nsweeps, nrhs);
+  } else {
+    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nrhs);
+    C<T>* c = ensure(hier_scratch<T>(H, 1), n * nrhs);
+    to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(b), a, H.s);
+    to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(z), c, H.s);
+    H.sap<T>(level, a, c, nsweeps, nrhs);
+    from_nat<T>(*H.ctx, level, n, nrhs, c, static_cast<double2*>(z), H.s);
   }
 }
 
 template <typename T>
 void precondition_impl(Hierarchy& H, const void* b, void* z, int nrhs, int layout) {
   const long long n = H.lv[0].n;
-  for (int r = 0; r < nrhs; ++r) {
+  H.ensure_work<T>(std::min(nrhs, H.p.batch));
+  const int cap = H.work<T>(0).cap;
+  for (int r0 = 0; r0 < nrhs; r0 += cap) {
+    const int nb = std::min(cap, nrhs - r0);
+    std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
+    std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
+    // the cycle writes z before reading b's copy; b must stay intact
+    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nb);
     if (layout == DDAMG_NATIVE) {
-      // the cycle writes z before reading it; b must stay intact
-      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
-      vcopy<T, T>(static_cast<const C<T>*>(b) + r * n, a, n, H.s);
-      H.cycle<T>(0, a, static_cast<C<T>*>(z) + r * n);
+      vcopy<T, T>(static_cast<const C<T>*>(b) + r0 * n, a, n * nb, H.s);
+      H.cycle<T>(0, a, static_cast<C<T>*>(z) + r0 * n, nb);
     } else {
-      C<T>* a = ensure(hier_scratch<T>(H, 0), n);
-      C<T>* c = ensure(hier_scratch<T>(H, 1), n);
-      to_nat<T>(*H.ctx, 0, n, static_cast<const double2*>(b) + r * n, a, H.s);
-      H.cycle<T>(0, a, c);
-      from_nat<T>(*H.ctx, 0, n, c, static_cast<double2*>(z) + r * n, H.s);
+      C<T>* c = ensure(hier_scratch<T>(H, 1), n * nb);
+      to_nat<T>(*H.ctx, 0, n, nb, static_cast<const double2*>(b) + r0 * n, a, H.s);
+      H.cycle<T>(0, a, c, nb);
+      from_nat<T>(*H.ctx, 0, n, nb, c, static_cast<double2*>(z) + r0 * n, H.s);
     }
   }
 }
@@ -207,6 +203,8 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->max_restarts = 100;
   p->precond_prec = DDAMG_F32;
   p->cycle = DDAMG_KCYCLE;
+  p->half_storage = 0;
+  p->batch = 16;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {
@@ -374,24 +372,30 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     H.s = as_stream(stream);
     const long long n = H.lv[0].n;
-    for (int r = 0; r < nrhs; ++r) {
+    const int bmax = std::min(nrhs, H.p.batch);
+    if (H.p.precond_prec == DDAMG_F64) H.ensure_batch<double>(bmax);
+    else H.ensure_batch<float>(bmax);
+    std::vector<ddamg_solve_stats> st(bmax);
+    for (int r0 = 0; r0 < nrhs; r0 += bmax) {
+      const int nb = std::min(bmax, nrhs - r0);
       auto t0 = std::chrono::steady_clock::now();
-      ddamg_solve_stats st;
-      std::memset(&st, 0, sizeof(st));
-      H.kc_iters = 0;
-      H.cs_iters = 0;
-      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r * n, H.ob.p, 1, H.s);
-      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r * n, H.ox.p, 1, H.s);
-      int st_rc;
-      if (H.p.precond_prec == DDAMG_F64) st_rc = H.outer<double>(H.ob.p, H.ox.p, &st);
-      else st_rc = H.outer<float>(H.ob.p, H.ox.p, &st);
-      fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r * n, 1, H.s);
+      for (auto& e : st) std::memset(&e, 0, sizeof(e));
+      std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
+      std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r0 * n, H.ob.p, nb, H.s);
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r0 * n, H.ox.p, nb, H.s);
+      if (H.p.precond_prec == DDAMG_F64) H.outer<double>(H.ob.p, H.ox.p, st.data(), nb);
+      else H.outer<float>(H.ob.p, H.ox.p, st.data(), nb);
+      fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r0 * n, nb, H.s);
       DD_CHECK_HIP(hipStreamSynchronize(H.s));
-      st.kcycle_iters = H.kc_iters;
-      st.coarsest_iters = H.cs_iters;
-      st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      if (stats) stats[r] = st;
-      if (st_rc != DDAMG_OK && worst == DDAMG_OK) worst = st_rc;
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int r = 0; r < nb; ++r) {
+        st[r].kcycle_iters = H.kc_it[r];
+        st[r].coarsest_iters = H.cs_it[r];
+        st[r].seconds = secs;
+        if (stats) stats[r0 + r] = st[r];
+        if (st[r].status != DDAMG_OK && worst == DDAMG_OK) worst = st[r].status;
+      }
     }
   });
   if (rc != DDAMG_OK) return rc;

@@ -52,11 +52,12 @@ struct CoarseOpView {
 template <typename S>
 void expand_coarse(const double2* D5, const int* nbr9, int V, int d, S* K, hipStream_t s);
 
+// out = D in for nb fields of the level (field r at offset r * V * d)
 template <typename T, typename S>
-void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s);
+void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 
-// Work buffers of a coarse SAP colour pass (each [V][d], part [V][4]);
-// ping-ponged by MR step.
+// Work buffers of a coarse SAP colour pass (each [nb][V][d], part
+// [nb][V][4] for a batch of nb); ping-ponged by MR step.
 template <typename T>
 struct SapScratch {
   C<T>* rho[2] = {nullptr, nullptr};
@@ -69,19 +70,19 @@ struct SapScratch {
 template <typename T, typename S>
 void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
                        int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
-                       hipStream_t s);
+                       hipStream_t s, int nb = 1);
 
 // odd-even: out(x) = gamma in_c(x) + alpha S(x) in_s(x) + beta sum_hops(in_h)(x)
 // for x in `sites` (other sites of out untouched)
 template <typename T, typename S>
 void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsites, T gamma,
                        const C<T>* in_c, T alpha, const C<T>* in_s, T beta, const C<T>* in_h,
-                       C<T>* out, hipStream_t s);
+                       C<T>* out, hipStream_t s, int nb = 1);
 // out(x) = M(x) in(x) for x in `sites`, M = [nsites][d][d] (dense per-site
-// matrices, column-major)
+// matrices, column-major); nb fields n apart
 template <typename T>
-void site_matvec(const C<T>* M, const int* sites, int nsites, int d, const C<T>* in, C<T>* out,
-                 hipStream_t s);
+void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n, const C<T>* in, C<T>* out,
+                 hipStream_t s, int nb = 1);
 // inverses of the self blocks (taken from the FP64 [V][5][d][d] Galerkin
 // output) of `sites`, FP64 Gauss-Jordan with partial pivoting; written
 // column-major, [nsites][d][d]

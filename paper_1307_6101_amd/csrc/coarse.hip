@@ -115,19 +115,22 @@ void expand_coarse(const double2* D5, const int* nbr9, int V, int d, S* K, hipSt
 // owns columns w*NCH .. w*NCH+NCH-1 of the nine blocks, lane i the row i;
 // the nine input vectors of the site sit in LDS (broadcast reads) and the
 // eight partial rows are summed through LDS.  Every load of a block group is
-// in flight at once and the code stays compact.
+// in flight at once and the code stays compact.  A workgroup serves RB
+// right-hand sides of the batch (fields n apart): the block entries it
+// loads are applied to all of them.
 // ---------------------------------------------------------------------------
 constexpr int SW = 8;   // wavefronts per site workgroup
 
-template <typename T, typename S, int NCH>
-__device__ __forceinline__ C<T> site_cols(const S* __restrict__ Kx, size_t bsz, const C<T> (*vin)[64],
-                                          unsigned mask, int j0, int lane, int d) {
+template <typename T, typename S, int NCH, int RB>
+__device__ __forceinline__ void site_cols(const S* __restrict__ Kx, size_t bsz, const C<T> (*vin)[9][64],
+                                          unsigned mask, int j0, int lane, int d, C<T> (&acc)[RB]) {
   constexpr int KG = sizeof(T) == 4 ? 9 : 3;
-  // lanes past the last row read row 0 and return zero, so every
-  // load of a group is unconditional within the wavefront; the block mask
-  // and the column bound are wavefront-uniform
+  // lanes past the last row read row 0 and return zero, so every load of a
+  // group is unconditional within the wavefront; the block mask and the
+  // column bound are wavefront-uniform
   const int row = lane < d ? lane : 0;
-  C<T> acc = czero<T>();
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = czero<T>();
 #pragma unroll 1
   for (int k0 = 0; k0 < 9; k0 += KG) {
     // raw stored values: all loads issue before the first conversion
@@ -147,44 +150,178 @@ __device__ __forceinline__ C<T> site_cols(const S* __restrict__ Kx, size_t bsz, 
       for (int u = 0; u < NCH; ++u)
         // masked blocks are skipped, not multiplied by zero: their LDS
         // inputs are not loaded and may hold anything
-        if (((mask >> (k0 + kk)) & 1u) && j0 + u < d) cfma(acc, ldc<T, S>(m[kk][u]), vin[k0 + kk][j0 + u]);
+        if (((mask >> (k0 + kk)) & 1u) && j0 + u < d) {
+          const C<T> mv = ldc<T, S>(m[kk][u]);
+#pragma unroll
+          for (int r = 0; r < RB; ++r) cfma(acc[r], mv, vin[r][k0 + kk][j0 + u]);
+        }
   }
   // lanes past the last row return zero (callers reduce over all 64 lanes)
-  return lane < d ? acc : czero<T>();
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (lane >= d) acc[r] = czero<T>();
 }
 
 // sum of the eight wavefronts' partial rows; valid in wavefront 0, lane < d
-template <typename T>
-__device__ inline C<T> site_rows_sum(C<T> part, C<T> (*prow)[64]) {
+template <typename T, int RB>
+__device__ inline void site_rows_sum(C<T> (&part)[RB], C<T> (*prow)[RB][64]) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  prow[w][lane] = part;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) prow[w][r][lane] = part[r];
   __syncthreads();
-  C<T> s = czero<T>();
   if (w == 0)
 #pragma unroll
-    for (int v = 0; v < SW; ++v) s = cadd(s, prow[v][lane]);
-  return s;
+    for (int r = 0; r < RB; ++r) {
+      C<T> s = czero<T>();
+#pragma unroll
+      for (int v = 0; v < SW; ++v) s = cadd(s, prow[v][r][lane]);
+      part[r] = s;
+    }
 }
 
-template <typename T, typename S, int NCH>
+template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_capply(CoarseOpView<T, S> op, const C<T>* __restrict__ in,
-                                                    C<T>* __restrict__ out) {
-  __shared__ C<T> vin[9][64];
-  __shared__ C<T> prow[SW][64];
+                                                    C<T>* __restrict__ out, long long n) {
+  __shared__ C<T> vin[RB][9][64];
+  __shared__ C<T> prow[SW][RB][64];
   const int site = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
-  for (int e = threadIdx.x; e < 9 * d; e += blockDim.x)
-    vin[e / d][e % d] = in[(size_t)op.nbr9[site * 9 + e / d] * d + e % d];
+  in += (long long)blockIdx.y * RB * n;
+  out += (long long)blockIdx.y * RB * n;
+  for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
+    const int r = e / (9 * d), kj = e % (9 * d);
+    vin[r][kj / d][kj % d] = in[r * n + (size_t)op.nbr9[site * 9 + kj / d] * d + kj % d];
+  }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> r = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
-                                                     w * NCH, lane, d), prow);
-  if (w == 0 && lane < d) out[(size_t)site * d + lane] = r;
+  C<T> acc[RB];
+  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu, w * NCH, lane, d, acc);
+  site_rows_sum<T, RB>(acc, prow);
+  if (w == 0 && lane < d)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) out[r * n + (size_t)site * d + lane] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Batched apply on the matrix cores (FP32 arithmetic, 8..16 right-hand
+// sides per launch chunk).  Per site the product is a complex GEMM
+//   out (d x nb) = [K_0 .. K_8] (d x 9d)  *  [in(nbr_0); ..; in(nbr_8)] (9d x nb),
+// done as real 16x16x4 MFMA tiles: rows i of a 16-row tile, RHS r in the
+// 16 columns, four complex GEMM columns per step and four real products per
+// step (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Wavefront w handles row
+// tile w / 3 against block group w % 3 (blocks 3g .. 3g+2); the three
+// partial tiles are summed through LDS.  The B operand (the nine input
+// vectors of the site for every RHS, [9d][16] complex) is staged in LDS.
+// Operand layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result register v of lane l is D[4 (l / 16) + v][l % 16].
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MFMA_NB = 16;        // right-hand sides per launch chunk
+constexpr int MFMA_MAXD = 56;      // B tile [9d][16] complex within 64 KiB of LDS
+
+template <typename S, int NJ>
+__global__ void __launch_bounds__(64 * 12) k_capply_mfma(CoarseOpView<float, S> op, const float2* __restrict__ in,
+                                                         float2* __restrict__ out, long long n, int nb) {
+  extern __shared__ float2 lds_b[];   // [9d][16] B tile; reused for the partial tiles
+  const int site = blockIdx.x, d = op.d;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nmt = (d + 15) >> 4;
+  in += (long long)blockIdx.y * MFMA_NB * n;
+  out += (long long)blockIdx.y * MFMA_NB * n;
+  const int nr = min(MFMA_NB, nb - (int)blockIdx.y * MFMA_NB);
+  for (int e = threadIdx.x; e < 9 * d * MFMA_NB; e += blockDim.x) {
+    const int j = e / MFMA_NB, r = e % MFMA_NB, k = j / d, jj = j % d;
+    lds_b[e] = r < nr ? in[r * n + (size_t)op.nbr9[site * 9 + k] * d + jj] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+  const int mt = w / 3, g = w % 3;
+  if (mt < nmt) {
+    const int i = mt * 16 + (lane & 15);
+    const bool iv = i < d;
+    const int ic = iv ? i : 0;
+    const int kk = lane >> 4, rl = lane & 15;
+    const size_t bsz = (size_t)d * d;
+#pragma unroll 1
+    for (int k = 3 * g; k < 3 * g + 3; ++k) {
+      const S* Kb = op.K + ((size_t)site * 9 + k) * bsz + ic;
+      S a[NJ];
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) a[t] = Kb[(size_t)(4 * t + kk) * d];
+      const float2* bt = lds_b + (size_t)(k * d + kk) * MFMA_NB + rl;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        float2 av = ldc<float, S>(a[t]);
+        if (!iv) av = make_float2(0.f, 0.f);
+        const float2 bv = bt[(size_t)4 * t * MFMA_NB];
+        cr = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.y, bv.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.x, ci, 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();   // B tile no longer needed: reuse LDS for the partials
+  float2* part = lds_b;   // [3][nmt][16 rows][16 rhs]
+  if (mt < nmt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * (lane >> 4) + v;
+      part[((size_t)(g * nmt + mt) * 16 + row) * 16 + (lane & 15)] = make_float2(cr[v], ci[v]);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nmt * 16 * 16; e += blockDim.x) {
+    const int mtile = e / 256, row = (e / 16) % 16, r = e % 16;
+    const int i = mtile * 16 + row;
+    if (i < d && r < nr) {
+      float2 sum = part[((size_t)(0 * nmt + mtile) * 16 + row) * 16 + r];
+      sum = cadd(sum, part[((size_t)(1 * nmt + mtile) * 16 + row) * 16 + r]);
+      sum = cadd(sum, part[((size_t)(2 * nmt + mtile) * 16 + row) * 16 + r]);
+      out[r * n + (size_t)site * d + i] = sum;
+    }
+  }
+}
+
+template <int LO, int HI, typename F>
+inline void with_int(int v, F&& f) {
+  if constexpr (LO <= HI) {
+    if (v == LO) f(std::integral_constant<int, LO>{});
+    else with_int<LO + 1, HI>(v, f);
+  } else {
+    throw Error(-1, "unsupported size");
+  }
+}
+
+// whether the matrix-core path takes a batch of nb on d components
+inline bool use_mfma(int d, int nb) { return nb >= 8 && d % 4 == 0 && d <= MFMA_MAXD; }
+
+template <typename S>
+void coarse_apply_mfma(const CoarseOpView<float, S>& op, const float2* in, float2* out, hipStream_t s, int nb) {
+  const long long n = (long long)op.V * op.d;
+  const int nmt = (op.d + 15) / 16;
+  const size_t lds = std::max((size_t)9 * op.d * MFMA_NB, (size_t)3 * nmt * 256) * sizeof(float2);
+  const int nch = (nb + MFMA_NB - 1) / MFMA_NB;
+  with_int<1, MFMA_MAXD / 4>(op.d / 4, [&](auto nj) {
+    k_capply_mfma<S, decltype(nj)::value><<<dim3(op.V, nch), 64 * 3 * nmt, lds, s>>>(op, in, out, n, nb);
+  });
+  DD_LAUNCH_CHECK();
 }
 
 template <typename T, typename S>
-void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s) {
+void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_mfma(op.d, nb)) {
+      coarse_apply_mfma<S>(op, in, out, s, nb);
+      return;
+    }
+  }
+  const long long n = (long long)op.V * op.d;
   with_nch(op.d, [&](auto nch) {
-    k_capply<T, S, decltype(nch)::value><<<op.V, 64 * SW, 0, s>>>(op, in, out);
+    constexpr int NCH = decltype(nch)::value;
+    rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
+      constexpr int RB = decltype(rb)::value;
+      k_capply<T, S, NCH, RB><<<dim3(op.V, nc), 64 * SW, 0, s>>>(op, in + first * n, out + first * n, n);
+    });
   });
   DD_LAUNCH_CHECK();
 }
@@ -198,22 +335,35 @@ void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipSt
 //               sites, recomputed locally), z += alpha rho_{t-1};
 //               q_t = D_i rho_t, per-site <q_t, rho_t>, <q_t, q_t>
 //   k_sap_fin:  z += alpha_{last} rho_{last}
-// Buffers rho, q, part are ping-ponged by step parity.
+// Buffers rho, q, part are ping-ponged by step parity.  Vectors of the batch
+// are n apart, per-site partials V*4 apart.
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int NCH>
+template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, const int* __restrict__ csites,
                                                      const C<T>* __restrict__ b, const C<T>* __restrict__ z,
-                                                     C<T>* __restrict__ rho0) {
-  __shared__ C<T> vin[9][64];
-  __shared__ C<T> prow[SW][64];
+                                                     C<T>* __restrict__ rho0, long long n) {
+  __shared__ C<T> vin[RB][9][64];
+  __shared__ C<T> prow[SW][RB][64];
   const int site = csites[blockIdx.x], w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
-  for (int e = threadIdx.x; e < 9 * d; e += blockDim.x)
-    vin[e / d][e % d] = z[(size_t)op.nbr9[site * 9 + e / d] * d + e % d];
+  const long long off = (long long)blockIdx.y * RB * n;
+  b += off;
+  z += off;
+  rho0 += off;
+  for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
+    const int r = e / (9 * d), kj = e % (9 * d);
+    vin[r][kj / d][kj % d] = z[r * n + (size_t)op.nbr9[site * 9 + kj / d] * d + kj % d];
+  }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> dz = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu,
-                                                      w * NCH, lane, d), prow);
-  if (w == 0 && lane < d) rho0[(size_t)site * d + lane] = csub(b[(size_t)site * d + lane], dz);
+  C<T> acc[RB];
+  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu, w * NCH, lane, d, acc);
+  site_rows_sum<T, RB>(acc, prow);
+  if (w == 0 && lane < d)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const size_t o = r * n + (size_t)site * d + lane;
+      rho0[o] = csub(b[o], acc[r]);
+    }
 }
 
 // block alpha of step t from the per-site partials of the block's sites
@@ -229,7 +379,7 @@ __device__ inline C<T> block_alpha(const T* __restrict__ part, const int* __rest
   return s2 > T(0) ? mk<T>(s0 / s2, s1 / s2) : czero<T>();
 }
 
-template <typename T, typename S, int NCH>
+template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const int* __restrict__ csites,
                                                    const int* __restrict__ blk_sites,
                                                    const int* __restrict__ site_blk, int bs, int step,
@@ -237,53 +387,67 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
                                                    const C<T>* __restrict__ q_prev,
                                                    const T* __restrict__ part_prev, C<T>* __restrict__ rho_cur,
                                                    C<T>* __restrict__ q_cur, T* __restrict__ part_cur,
-                                                   C<T>* __restrict__ z) {
-  __shared__ C<T> vin[9][64];
-  __shared__ C<T> prow[SW][64];
-  __shared__ C<T> alpha_s;
+                                                   C<T>* __restrict__ z, long long n) {
+  __shared__ C<T> vin[RB][9][64];
+  __shared__ C<T> prow[SW][RB][64];
+  __shared__ C<T> alpha_s[RB];
   const int site = csites[blockIdx.x], w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
+  const long long off = (long long)blockIdx.y * RB * n, pn = (long long)op.V * 4;
+  const long long poff = (long long)blockIdx.y * RB * pn;
+  rho_prev += off;
+  q_prev += off;
+  rho_cur += off;
+  q_cur += off;
+  z += off;
+  part_prev += poff;
+  part_cur += poff;
   const int blk = site_blk[site];
   unsigned mask = 1u;   // self and the in-block neighbours
   for (int k = 1; k < 9; ++k)
     if (site_blk[op.nbr9[site * 9 + k]] == blk) mask |= 1u << k;
-  if (step > 0 && threadIdx.x == 0) alpha_s = block_alpha<T>(part_prev, blk_sites + (size_t)blk * bs, bs);
+  if (step > 0 && threadIdx.x < RB)
+    alpha_s[threadIdx.x] = block_alpha<T>(part_prev + threadIdx.x * pn, blk_sites + (size_t)blk * bs, bs);
   __syncthreads();
-  const C<T> alpha = step > 0 ? alpha_s : czero<T>();
-  for (int e = threadIdx.x; e < 9 * d; e += blockDim.x) {
-    const int k = e / d, j = e % d;
+  for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
+    const int r = e / (9 * d), kj = e % (9 * d), k = kj / d, j = kj % d;
     if ((mask >> k) & 1u) {
-      const size_t o = (size_t)op.nbr9[site * 9 + k] * d + j;
-      C<T> r = rho_prev[o];
-      if (step > 0) r = csub(r, cmul(alpha, q_prev[o]));
-      vin[k][j] = r;
+      const size_t o = r * n + (size_t)op.nbr9[site * 9 + k] * d + j;
+      C<T> v = rho_prev[o];
+      if (step > 0) v = csub(v, cmul(alpha_s[r], q_prev[o]));
+      vin[r][k][j] = v;
     }
   }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> q = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
-                                                     w * NCH, lane, d), prow);
+  C<T> q[RB];
+  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask, w * NCH, lane, d, q);
+  site_rows_sum<T, RB>(q, prow);
   if (w == 0) {
-    C<T> rho = czero<T>();
-    if (lane < d) {
-      const size_t o = (size_t)site * d + lane;
-      rho = vin[0][lane];
-      rho_cur[o] = rho;
-      q_cur[o] = q;
-      if (step > 0) {
-        C<T> zz = z[o];
-        cfma(zz, alpha, rho_prev[o]);
-        z[o] = zz;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      C<T> rho = czero<T>();
+      if (lane < d) {
+        const size_t o = r * n + (size_t)site * d + lane;
+        rho = vin[r][0][lane];
+        rho_cur[o] = rho;
+        q_cur[o] = q[r];
+        if (step > 0) {
+          C<T> zz = z[o];
+          cfma(zz, alpha_s[r], rho_prev[o]);
+          z[o] = zz;
+        }
       }
-    }
-    T a0 = q.x * rho.x + q.y * rho.y, a1 = q.x * rho.y - q.y * rho.x, a2 = q.x * q.x + q.y * q.y;
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    a2 = wave_sum(a2);
-    if (lane == 0) {
-      T* p = part_cur + (size_t)site * 4;
-      p[0] = a0;
-      p[1] = a1;
-      p[2] = a2;
+      const C<T> qq = lane < d ? q[r] : czero<T>();
+      T a0 = qq.x * rho.x + qq.y * rho.y, a1 = qq.x * rho.y - qq.y * rho.x, a2 = qq.x * qq.x + qq.y * qq.y;
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      if (lane == 0) {
+        T* p = part_cur + r * pn + (size_t)site * 4;
+        p[0] = a0;
+        p[1] = a1;
+        p[2] = a2;
+      }
     }
   }
 }
@@ -291,10 +455,13 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
 template <typename T>
 __global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __restrict__ blk_sites,
                           const int* __restrict__ site_blk, int bs, const C<T>* __restrict__ rho,
-                          const T* __restrict__ part, C<T>* __restrict__ z) {
+                          const T* __restrict__ part, C<T>* __restrict__ z, long long n, long long pn) {
   __shared__ C<T> alpha_s;
   const int site = csites[blockIdx.x];
   const int blk = site_blk[site];
+  rho += blockIdx.y * n;
+  z += blockIdx.y * n;
+  part += blockIdx.y * pn;
   if (threadIdx.x == 0) alpha_s = block_alpha<T>(part, blk_sites + (size_t)blk * bs, bs);
   __syncthreads();
   const int i = threadIdx.x;
@@ -309,89 +476,119 @@ __global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __re
 template <typename T, typename S>
 void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
                        int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
-                       hipStream_t s) {
+                       hipStream_t s, int nb) {
   if (mr_iters <= 0) return;
   DD_REQUIRE(op.d <= 64, "coarse levels support at most 64 components per site");
   const int nsites = (nblk / 2) * bs;
   const int* csites = blk_sites + (size_t)colour * (nblk / 2) * bs;   // blocks are colour-major
+  const long long n = (long long)op.V * op.d, pn = (long long)op.V * 4;
   with_nch(op.d, [&](auto nch) {
     constexpr int NCH = decltype(nch)::value;
-    // the residual is rho_0 and lands in the "previous" buffer of step 0
-    k_sap_res<T, S, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, b, z, ws.rho[1]);
-    for (int t = 0; t < mr_iters; ++t) {
-      const int pp = (t + 1) & 1, cc = t & 1;   // previous / current buffers
-      k_sap_q<T, S, NCH><<<nsites, 64 * SW, 0, s>>>(op, csites, blk_sites, site_blk, bs, t, ws.rho[pp], ws.q[pp],
-                                                ws.part[pp], ws.rho[cc], ws.q[cc], ws.part[cc], z);
-    }
+    rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
+      constexpr int RB = decltype(rb)::value;
+      const long long o = first * n, po = first * pn;
+      // the residual is rho_0 and lands in the "previous" buffer of step 0
+      k_sap_res<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(op, csites, b + o, z + o, ws.rho[1] + o, n);
+      for (int t = 0; t < mr_iters; ++t) {
+        const int pp = (t + 1) & 1, cc = t & 1;   // previous / current buffers
+        k_sap_q<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(
+            op, csites, blk_sites, site_blk, bs, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po,
+            ws.rho[cc] + o, ws.q[cc] + o, ws.part[cc] + po, z + o, n);
+      }
+    });
   });
   const int last = (mr_iters - 1) & 1;
-  k_sap_fin<T><<<nsites, 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, blk_sites, site_blk, bs,
-                                                         ws.rho[last], ws.part[last], z);
+  k_sap_fin<T><<<dim3(nsites, nb), 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, blk_sites, site_blk, bs,
+                                                                   ws.rho[last], ws.part[last], z, n, pn);
   DD_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
 // odd-even building blocks (site workgroups, as above)
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int NCH>
+template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T, S> op, const int* __restrict__ sites,
                                                     T gamma, const C<T>* __restrict__ in_c, T alpha,
                                                     const C<T>* __restrict__ in_s, T beta,
-                                                    const C<T>* __restrict__ in_h, C<T>* __restrict__ out) {
-  __shared__ C<T> vin[9][64];
-  __shared__ C<T> prow[SW][64];
+                                                    const C<T>* __restrict__ in_h, C<T>* __restrict__ out,
+                                                    long long n) {
+  __shared__ C<T> vin[RB][9][64];
+  __shared__ C<T> prow[SW][RB][64];
   const int site = sites[blockIdx.x], w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
+  const long long off = (long long)blockIdx.y * RB * n;
   unsigned mask = 0;
   if (alpha != T(0)) mask |= 1u;
   if (beta != T(0)) mask |= 0x1FEu;
-  for (int e = threadIdx.x; e < 9 * d; e += blockDim.x) {
-    const int k = e / d, j = e % d;
+  for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
+    const int r = e / (9 * d), kj = e % (9 * d), k = kj / d, j = kj % d;
     if ((mask >> k) & 1u) {
-      const C<T> v = (k == 0 ? in_s : in_h)[(size_t)op.nbr9[site * 9 + k] * d + j];
-      vin[k][j] = k == 0 ? cscale(v, alpha) : cscale(v, beta);
+      const C<T> v = (k == 0 ? in_s : in_h)[off + r * n + (size_t)op.nbr9[site * 9 + k] * d + j];
+      vin[r][k][j] = k == 0 ? cscale(v, alpha) : cscale(v, beta);
     }
   }
   __syncthreads();
   const size_t bsz = (size_t)d * d;
-  const C<T> r = site_rows_sum<T>(site_cols<T, S, NCH>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask,
-                                                     w * NCH, lane, d), prow);
-  if (w == 0 && lane < d) {
-    C<T> acc = r;
-    if (gamma != T(0)) acc = cadd(acc, cscale(in_c[(size_t)site * d + lane], gamma));
-    out[(size_t)site * d + lane] = acc;
-  }
+  C<T> acc[RB];
+  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask, w * NCH, lane, d, acc);
+  site_rows_sum<T, RB>(acc, prow);
+  if (w == 0 && lane < d)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const size_t o = off + r * n + (size_t)site * d + lane;
+      C<T> a = acc[r];
+      if (gamma != T(0)) a = cadd(a, cscale(in_c[o], gamma));
+      out[o] = a;
+    }
 }
 
 template <typename T, typename S>
 void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsites, T gamma,
                        const C<T>* in_c, T alpha, const C<T>* in_s, T beta, const C<T>* in_h,
-                       C<T>* out, hipStream_t s) {
+                       C<T>* out, hipStream_t s, int nb) {
+  const long long n = (long long)op.V * op.d;
   with_nch(op.d, [&](auto nch) {
-    k_csites<T, S, decltype(nch)::value><<<nsites, 64 * SW, 0, s>>>(op, sites, gamma, in_c, alpha, in_s, beta,
-                                                                 in_h, out);
+    constexpr int NCH = decltype(nch)::value;
+    rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
+      constexpr int RB = decltype(rb)::value;
+      const long long o = first * n;
+      k_csites<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(
+          op, sites, gamma, in_c ? in_c + o : nullptr, alpha, in_s ? in_s + o : nullptr, beta,
+          in_h ? in_h + o : nullptr, out + o, n);
+    });
   });
   DD_LAUNCH_CHECK();
 }
 
-template <typename T, int NCH>
+template <typename T, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_site_matvec(const C<T>* __restrict__ M,
                                                          const int* __restrict__ sites, int d,
-                                                         const C<T>* __restrict__ in, C<T>* __restrict__ out) {
-  __shared__ C<T> vin[9][64];
-  __shared__ C<T> prow[SW][64];
+                                                         const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                         long long n) {
+  __shared__ C<T> vin[RB][9][64];
+  __shared__ C<T> prow[SW][RB][64];
   const int k = blockIdx.x, site = sites[k], w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int e = threadIdx.x; e < d; e += blockDim.x) vin[0][e] = in[(size_t)site * d + e];
+  const long long off = (long long)blockIdx.y * RB * n;
+  for (int e = threadIdx.x; e < RB * d; e += blockDim.x)
+    vin[e / d][0][e % d] = in[off + (e / d) * n + (size_t)site * d + e % d];
   __syncthreads();
-  const C<T> r = site_rows_sum<T>(site_cols<T, C<T>, NCH>(M + (size_t)k * d * d, (size_t)d * d, vin, 1u,
-                                                     w * NCH, lane, d), prow);
-  if (w == 0 && lane < d) out[(size_t)site * d + lane] = r;
+  C<T> acc[RB];
+  site_cols<T, C<T>, NCH, RB>(M + (size_t)k * d * d, (size_t)d * d, vin, 1u, w * NCH, lane, d, acc);
+  site_rows_sum<T, RB>(acc, prow);
+  if (w == 0 && lane < d)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) out[off + r * n + (size_t)site * d + lane] = acc[r];
 }
 
 template <typename T>
-void site_matvec(const C<T>* M, const int* sites, int nsites, int d, const C<T>* in, C<T>* out,
-                 hipStream_t s) {
+void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n, const C<T>* in, C<T>* out,
+                 hipStream_t s, int nb) {
   with_nch(d, [&](auto nch) {
-    k_site_matvec<T, decltype(nch)::value><<<nsites, 64 * SW, 0, s>>>(M, sites, d, in, out);
+    constexpr int NCH = decltype(nch)::value;
+    rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
+      constexpr int RB = decltype(rb)::value;
+      k_site_matvec<T, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(M, sites, d, in + first * n,
+                                                                     out + first * n, n);
+    });
   });
   DD_LAUNCH_CHECK();
 }
@@ -483,17 +680,20 @@ template void expand_coarse<double2>(const double2*, const int*, int, int, doubl
 template void expand_coarse<float2>(const double2*, const int*, int, int, float2*, hipStream_t);
 template void expand_coarse<__half2>(const double2*, const int*, int, int, __half2*, hipStream_t);
 
-#define DD_INST(T, S)                                                                            \
-  template void coarse_apply<T, S>(const CoarseOpView<T, S>&, const C<T>*, C<T>*, hipStream_t);  \
-  template void coarse_sap_colour<T, S>(const CoarseOpView<T, S>&, const int*, const int*, int, int, \
-                                        int, int, const C<T>*, C<T>*, SapScratch<T>&, hipStream_t); \
+#define DD_INST(T, S)                                                                              \
+  template void coarse_apply<T, S>(const CoarseOpView<T, S>&, const C<T>*, C<T>*, hipStream_t, int); \
+  template void coarse_sap_colour<T, S>(const CoarseOpView<T, S>&, const int*, const int*, int, int,   \
+                                        int, int, const C<T>*, C<T>*, SapScratch<T>&, hipStream_t,   \
+                                        int);                                                        \
   template void coarse_site_apply<T, S>(const CoarseOpView<T, S>&, const int*, int, T, const C<T>*, T, \
-                                        const C<T>*, T, const C<T>*, C<T>*, hipStream_t);
+                                        const C<T>*, T, const C<T>*, C<T>*, hipStream_t, int);
 DD_INST(double, double2)
 DD_INST(float, float2)
 DD_INST(float, __half2)
 #undef DD_INST
-template void site_matvec<double>(const double2*, const int*, int, int, const double2*, double2*, hipStream_t);
-template void site_matvec<float>(const float2*, const int*, int, int, const float2*, float2*, hipStream_t);
+template void site_matvec<double>(const double2*, const int*, int, int, long long, const double2*, double2*,
+                                  hipStream_t, int);
+template void site_matvec<float>(const float2*, const int*, int, int, long long, const float2*, float2*,
+                                 hipStream_t, int);
 
 }  // namespace ddamg

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 namespace ddamg {
 
@@ -106,6 +107,25 @@ template <int WIDTH, typename T> __device__ inline T group_sum(T v) {
 }
 
 inline unsigned nblocks(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Batches of nb right-hand sides are cut into launches that give every
+// thread RB of them (4 in FP32, 2 in FP64, 1 for the rest): f(rb, first,
+// nchunks) launches nchunks chunks of rb fields starting at field `first`.
+template <typename T, typename F>
+inline void rhs_chunks(int nb, F&& f) {
+  int done = 0;
+  if constexpr (sizeof(T) == 4) {
+    if (nb >= 4) {
+      f(std::integral_constant<int, 4>{}, 0, nb / 4);
+      done = nb / 4 * 4;
+    }
+  }
+  if (done == 0 && nb >= 2) {
+    f(std::integral_constant<int, 2>{}, 0, nb / 2);
+    done = nb / 2 * 2;
+  }
+  if (nb > done) f(std::integral_constant<int, 1>{}, done, nb - done);
+}
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 

@@ -49,13 +49,15 @@ void links_to_native(const FineGeom& g, const double2* links, C<T>* out, hipStre
 void clover_build(const FineGeom& g, const double2* links, double m0, double csw, double2* out,
                   hipStream_t s);
 
+// out = D in for nb native fields (field r at offset r * nblk * 192)
 template <typename T, typename S>
-void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s);
+void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 
-// one SAP colour pass: z += MR-block-solve(b - D z) on blocks of colour c
+// one SAP colour pass: z += MR-block-solve(b - D z) on blocks of colour c,
+// for nb right-hand sides (fields as for dslash)
 template <typename T, typename S>
 void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,
-                const C<T>* b, C<T>* z, hipStream_t s);
+                const C<T>* b, C<T>* z, hipStream_t s, int nb = 1);
 
 // FP64 -> FP16 copy of n complex numbers (operator storage)
 void to_half(const double2* in, __half2* out, long long n, hipStream_t s);

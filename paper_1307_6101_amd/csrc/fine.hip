@@ -348,22 +348,78 @@ __device__ inline void dslash_site(const FineOpView<T, S>& op, const C<T>* __res
   }
 }
 
-template <typename T, typename S>
+// RB right-hand sides (fields in + r * fs) at once: every link is loaded
+// once and applied to the RB neighbour spinors, which are all loaded before
+// the first product so that their loads are in flight together
+template <typename T, typename S, int MU, int RB>
+__device__ inline void hops_mu_rb(const FineOpView<T, S>& op, const C<T>* __restrict__ in, long long fs,
+                                  int blk, int loc, const Nbr8& nb8, C<T> (&acc)[RB][12]) {
+  constexpr int bit = 1 << MU;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const bool fwd = dir == 0;
+    const int nb = fwd ? ((loc & bit) ? nb8.v[2 * MU] : blk) : ((loc & bit) ? blk : nb8.v[2 * MU + 1]);
+    C<T> psi[RB][12], u[9];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) load_spinor<T>(in + r * fs, nb, loc ^ bit, psi[r]);
+    if (fwd) load_link<T, S>(op.U, blk, loc, MU, u);
+    else load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (fwd) hop_apply<T, MU, true>(psi[r], u, acc[r]);
+      else hop_apply<T, MU, false>(psi[r], u, acc[r]);
+    }
+  }
+}
+
+template <typename T, typename S, int RB>
 __global__ void __launch_bounds__(256) k_dslash(FineOpView<T, S> op, const C<T>* __restrict__ in,
-                                                C<T>* __restrict__ out) {
+                                                C<T>* __restrict__ out, long long fs) {
   const int tid = xcd_slab_index(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= op.nblk) return;
-  C<T> o[12];
-  dslash_site<T, S>(op, in, blk, loc, o);
-  C<T>* p = out + (long long)blk * 192 + loc;
+  in += (long long)blockIdx.y * RB * fs;
+  out += (long long)blockIdx.y * RB * fs;
+  if constexpr (RB == 1) {
+    C<T> o[12];
+    dslash_site<T, S>(op, in, blk, loc, o);
+    C<T>* p = out + (long long)blk * 192 + loc;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
+    for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
+  } else {
+    const Nbr8 nb8 = load_nbr8(op.nbr, blk);
+    C<T> acc[RB][12];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[r][c] = czero<T>();
+    hops_mu_rb<T, S, 0, RB>(op, in, fs, blk, loc, nb8, acc);
+    hops_mu_rb<T, S, 1, RB>(op, in, fs, blk, loc, nb8, acc);
+    hops_mu_rb<T, S, 2, RB>(op, in, fs, blk, loc, nb8, acc);
+    hops_mu_rb<T, S, 3, RB>(op, in, fs, blk, loc, nb8, acc);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      C<T> psi[12], o[12];
+      load_spinor<T>(in + r * fs, blk, loc, psi);
+      clover_apply<T, S>(op.A, blk, loc, psi, o);
+      C<T>* p = out + r * fs + (long long)blk * 192 + loc;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        o[c].x -= T(0.5) * acc[r][c].x;
+        o[c].y -= T(0.5) * acc[r][c].y;
+        p[c * 16] = o[c];
+      }
+    }
+  }
 }
 
 template <typename T, typename S>
-void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s) {
-  k_dslash<T, S><<<nblocks((size_t)op.nblk * 16, 256), 256, 0, s>>>(op, in, out);
+void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  const long long fs = (long long)op.nblk * 192;
+  const unsigned gx = nblocks((size_t)op.nblk * 16, 256);
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
+    k_dslash<T, S, decltype(rb)::value><<<dim3(gx, nch), 256, 0, s>>>(op, in + first * fs, out + first * fs, fs);
+  });
   DD_LAUNCH_CHECK();
 }
 
@@ -421,86 +477,97 @@ template <typename T, typename S> struct BlockOp<T, S, false> {
   }
 };
 
-template <typename T, typename S>
+// NBC: the batch size when fixed at compile time (1), else 0 and nb is read
+template <typename T, typename S, int NBC>
 __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
                                                     int ncb, int mr_iters, const C<T>* __restrict__ b,
-                                                    C<T>* __restrict__ z) {
+                                                    C<T>* __restrict__ z, int nb, long long fs) {
+  if constexpr (NBC > 0) nb = NBC;
   __shared__ C<T> rs[12 * 256];
   const int t = threadIdx.x;
   const int jb = xcd_slab_index(blockIdx.x, gridDim.x) * 16 + (t >> 4);
   const int loc = t & 15;
   const bool valid = jb < ncb;
   const int blk = valid ? cblk[jb] : 0;
-  C<T> rho[12], x[12];
   constexpr bool KEEP = !std::is_same<T, double>::value;
   BlockOp<T, S, KEEP> bop;
-  if (valid) {
-    C<T> dz[12], bb[12];
-    dslash_site<T, S>(op, z, blk, loc, dz);
-    load_spinor<T>(b, blk, loc, bb);
+  // the right-hand sides one after the other, sharing the block operator
+  // (read after the first residual, which needs the registers)
+  for (int rhs = 0; rhs < nb; ++rhs, b += fs, z += fs) {
+    C<T> rho[12], x[12];
+    if (valid) {
+      C<T> dz[12], bb[12];
+      dslash_site<T, S>(op, z, blk, loc, dz);
+      load_spinor<T>(b, blk, loc, bb);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rho[c] = csub(bb[c], dz[c]);
-  } else {
+      for (int c = 0; c < 12; ++c) rho[c] = csub(bb[c], dz[c]);
+    } else {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
-  }
-  bop.load(op, blk, loc, valid);
+      for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
+    }
+    if (rhs == 0) bop.load(op, blk, loc, valid);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) x[c] = czero<T>();
+    for (int c = 0; c < 12; ++c) x[c] = czero<T>();
 
-  for (int it = 0; it < mr_iters; ++it) {
+    for (int it = 0; it < mr_iters; ++it) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rs[c * 256 + t] = rho[c];
-    __syncthreads();
-    C<T> q[12], acc[12];
+      for (int c = 0; c < 12; ++c) rs[c * 256 + t] = rho[c];
+      __syncthreads();
+      C<T> q[12], acc[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-    {
-      C<T> u[9];
-      bop.link(op, blk, loc, 0, u);
-      inblock_hop<T, S, 0>(rs, t, loc, u, acc);
-      bop.link(op, blk, loc, 1, u);
-      inblock_hop<T, S, 1>(rs, t, loc, u, acc);
-      bop.link(op, blk, loc, 2, u);
-      inblock_hop<T, S, 2>(rs, t, loc, u, acc);
-      bop.link(op, blk, loc, 3, u);
-      inblock_hop<T, S, 3>(rs, t, loc, u, acc);
+      for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
+      {
+        C<T> u[9];
+        bop.link(op, blk, loc, 0, u);
+        inblock_hop<T, S, 0>(rs, t, loc, u, acc);
+        bop.link(op, blk, loc, 1, u);
+        inblock_hop<T, S, 1>(rs, t, loc, u, acc);
+        bop.link(op, blk, loc, 2, u);
+        inblock_hop<T, S, 2>(rs, t, loc, u, acc);
+        bop.link(op, blk, loc, 3, u);
+        inblock_hop<T, S, 3>(rs, t, loc, u, acc);
+      }
+      bop.clover(op, blk, loc, rho, q);
+      T qr_re = 0, qr_im = 0, qq = 0;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        q[c].x -= T(0.5) * acc[c].x;
+        q[c].y -= T(0.5) * acc[c].y;
+        qr_re += q[c].x * rho[c].x + q[c].y * rho[c].y;
+        qr_im += q[c].x * rho[c].y - q[c].y * rho[c].x;
+        qq += q[c].x * q[c].x + q[c].y * q[c].y;
+      }
+      qr_re = group_sum<16>(qr_re);
+      qr_im = group_sum<16>(qr_im);
+      qq = group_sum<16>(qq);
+      C<T> alpha = qq > T(0) ? mk<T>(qr_re / qq, qr_im / qq) : czero<T>();
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        cfma(x[c], alpha, rho[c]);
+        C<T> aq = cmul(alpha, q[c]);
+        rho[c] = csub(rho[c], aq);
+      }
+      __syncthreads();
     }
-    bop.clover(op, blk, loc, rho, q);
-    T qr_re = 0, qr_im = 0, qq = 0;
+    if (valid) {
+      C<T>* p = z + (long long)blk * 192 + loc;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      q[c].x -= T(0.5) * acc[c].x;
-      q[c].y -= T(0.5) * acc[c].y;
-      qr_re += q[c].x * rho[c].x + q[c].y * rho[c].y;
-      qr_im += q[c].x * rho[c].y - q[c].y * rho[c].x;
-      qq += q[c].x * q[c].x + q[c].y * q[c].y;
+      for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
     }
-    qr_re = group_sum<16>(qr_re);
-    qr_im = group_sum<16>(qr_im);
-    qq = group_sum<16>(qq);
-    C<T> alpha = qq > T(0) ? mk<T>(qr_re / qq, qr_im / qq) : czero<T>();
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      cfma(x[c], alpha, rho[c]);
-      C<T> aq = cmul(alpha, q[c]);
-      rho[c] = csub(rho[c], aq);
-    }
-    __syncthreads();
-  }
-  if (valid) {
-    C<T>* p = z + (long long)blk * 192 + loc;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
   }
 }
 
 template <typename T, typename S>
 void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,
-                const C<T>* b, C<T>* z, hipStream_t s) {
+                const C<T>* b, C<T>* z, hipStream_t s, int nb) {
   const int ncb = op.nblk / 2;
-  k_sap_colour<T, S><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters,
-                                                   b, z);
+  const long long fs = (long long)op.nblk * 192;
+  if (nb == 1)
+    k_sap_colour<T, S, 1><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z,
+                                                        nb, fs);
+  else
+    k_sap_colour<T, S, 0><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z,
+                                                        nb, fs);
   DD_LAUNCH_CHECK();
 }
 
@@ -509,15 +576,16 @@ void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour
   template void fine_to_native<T>(const FineGeom&, const double2*, C<T>*, int, hipStream_t);   \
   template void fine_from_native<T>(const FineGeom&, const C<T>*, double2*, int, hipStream_t); \
   template void links_to_native<T>(const FineGeom&, const double2*, C<T>*, hipStream_t);       \
-  template void dslash<T, C<T>>(const FineOpView<T, C<T>>&, const C<T>*, C<T>*, hipStream_t); \
+  template void dslash<T, C<T>>(const FineOpView<T, C<T>>&, const C<T>*, C<T>*, hipStream_t, int); \
   template void sap_colour<T, C<T>>(const FineOpView<T, C<T>>&, const int*, int, int, const C<T>*, \
-                                    C<T>*, hipStream_t);
+                                    C<T>*, hipStream_t, int);
 DD_INST(double)
 DD_INST(float)
 #undef DD_INST
-template void dslash<float, __half2>(const FineOpView<float, __half2>&, const float2*, float2*, hipStream_t);
+template void dslash<float, __half2>(const FineOpView<float, __half2>&, const float2*, float2*, hipStream_t,
+                                    int);
 template void sap_colour<float, __half2>(const FineOpView<float, __half2>&, const int*, int, int, const float2*,
-                                         float2*, hipStream_t);
+                                         float2*, hipStream_t, int);
 
 __global__ void k_to_half(const double2* __restrict__ in, __half2* __restrict__ out, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;

@@ -68,11 +68,14 @@ struct Context {
   void make_half(hipStream_t s);
 };
 
+// Work fields of one level for a batch of up to `cap` systems (each buffer
+// [cap][n]; the Krylov bases [m+1][cap][n])
 template <typename T>
 struct Work {
   DevArray<C<T>> bin, z, r, rec, x, w, t1, t2, t3, t4;
   DevArray<C<T>> V, Z;     // Krylov bases of this level
   int m = 0;               // basis length
+  int cap = 0;             // batch capacity
 };
 
 struct LevelStore {
@@ -87,7 +90,8 @@ struct LevelStore {
   DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
   DevArray<float2> K32, Einv32;
   DevArray<__half2> K16;
-  // coarse SAP work buffers (rho, q ping-pong; per-site inner products)
+  // coarse SAP work buffers (rho, q ping-pong; per-site inner products),
+  // sized for the largest batch seen
   DevArray<double2> sr64, sq64;
   DevArray<float2> sr32, sq32;
   DevArray<double> sp64;
@@ -123,8 +127,12 @@ struct Hierarchy {
   std::unique_ptr<Reducer> red;
   hipStream_t s = nullptr;
   bool recording = false;
+  // setup record: visit[r] says whether system r is really being visited
+  // (live in every enclosing FGMRES), so its record may be overwritten
+  std::vector<char> visit;
   bool half = false;               // FP16 operator storage for the FP32 levels
-  long long kc_iters = 0, cs_iters = 0;
+  int ocap = 0;                    // batch capacity of the outer solver's buffers
+  std::vector<long long> kc_it, cs_it;   // per system of the batch: K-cycle / coarsest iterations
   const double2* tv_extra = nullptr;
 
   template <typename T> Work<T>& work(int l);
@@ -138,17 +146,32 @@ struct Hierarchy {
   template <typename T> C<T>* tv(int l);
 
   // level operations at precision T
-  template <typename T> void apply(int l, const C<T>* in, C<T>* out);
-  template <typename T> void sap(int l, const C<T>* b, C<T>* z, int nsweeps);
-  template <typename T> void restrict_to(int l, const C<T>* fine, C<T>* coarse);
-  template <typename T> void prolong_add(int l, const C<T>* coarse, C<T>* fine);
-  template <typename T> void cycle(int l, const C<T>* b, C<T>* z);
-  template <typename T> void coarsest_solve(const C<T>* b, C<T>* z);
-  template <typename T> void schur(const C<T>* v, C<T>* out);
+  // (nb fields of the level, contiguous, processed by batched launches)
+  template <typename T> void apply(int l, const C<T>* in, C<T>* out, int nb = 1);
+  template <typename T> void sap(int l, const C<T>* b, C<T>* z, int nsweeps, int nb = 1);
+  template <typename T> void restrict_to(int l, const C<T>* fine, C<T>* coarse, int nb = 1);
+  template <typename T> void prolong_add(int l, const C<T>* coarse, C<T>* fine, int nb = 1);
+  // Solvers on batches of nb systems advancing together (fields n apart);
+  // every system keeps its own Krylov scalars and stopping test, so the
+  // result for each equals that of a solve on its own.
+  template <typename T> void cycle(int l, const C<T>* b, C<T>* z, int nb = 1);
+  template <typename T> void coarsest_solve(const C<T>* b, C<T>* z, int nb);
+  template <typename T> void schur(const C<T>* v, C<T>* out, int nb);
+  // FGMRES(m) from x = 0; iters[r] += iterations of system r
   template <typename T, typename Op, typename Pre>
-  int fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m, int max_cycles,
-             double tol);
-  template <typename T> int outer(const double2* b, double2* x, ddamg_solve_stats* st);
+  void fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m, int max_cycles,
+              double tol, int nb, long long* iters);
+  // one Arnoldi step of every system: w_r orthogonalised against
+  // V_{0..j, r}; h[r * (KMAX + 1) + i] the Hessenberg column, hn[r] the
+  // norm left; cf[r * KMAX + i] the coefficients of w + V c
+  template <typename T>
+  void arnoldi(const C<T>* V, long long vstride, long long n, int nb, int j, C<T>* w,
+               const std::vector<char>& live, std::vector<std::complex<double>>& h, std::vector<double>& hn,
+               std::vector<std::complex<double>>& cf);
+  // outer FP64 FGMRES for nb right-hand sides (native FP64 fields)
+  template <typename T> void outer(const double2* b, double2* x, ddamg_solve_stats* st, int nb);
+  template <typename T> void ensure_batch(int nb);
+  template <typename T> void ensure_work(int nb);
 
   // setup
   template <typename T> void setup(const double2* tv_canonical);
@@ -157,7 +180,7 @@ struct Hierarchy {
   // construct P_l (FP64 orthonormalisation) and D_{l+1} (FP64 Galerkin);
   // from32: the FP32 test vectors are the current ones
   void build_level(int l, bool from32);
-  template <typename T> void alloc_work();
+  template <typename T> void alloc_work(int cap);
 
   double norm(const double2* v, long long n);
 };

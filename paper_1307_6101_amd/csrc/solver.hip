@@ -15,6 +15,7 @@
 //    odd-even reduced (Schur) system, solved by GMRES from zero.
 #include "solver.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -101,43 +102,64 @@ void Context::make_half(hipStream_t s) {
 // ---------------------------------------------------------------------------
 // level operations
 // ---------------------------------------------------------------------------
-template <typename T> void Hierarchy::apply(int l, const C<T>* in, C<T>* out) {
-  if (l == 0) fine_op<T>([&](const auto& op) { dslash(op, in, out, s); });
-  else coarse_op<T>(l, [&](const auto& op) { coarse_apply(op, in, out, s); });
+template <typename T> void Hierarchy::apply(int l, const C<T>* in, C<T>* out, int nb) {
+  if (l == 0) fine_op<T>([&](const auto& op) { dslash(op, in, out, s, nb); });
+  else coarse_op<T>(l, [&](const auto& op) { coarse_apply(op, in, out, s, nb); });
 }
 
-template <typename T> SapScratch<T>& sap_scratch(LevelStore& L_);
-template <> SapScratch<double>& sap_scratch<double>(LevelStore& L_) { return L_.ss64; }
-template <> SapScratch<float>& sap_scratch<float>(LevelStore& L_) { return L_.ss32; }
+// coarse SAP work buffers of level l for a batch of nb (grown on demand)
+template <typename T, typename E>
+static SapScratch<T>& sap_buffers(DevArray<C<T>>& rho, DevArray<C<T>>& q, DevArray<E>& part, SapScratch<T>& ss,
+                                  long long nv, long long V, int nb) {
+  if (rho.n < 2 * (size_t)nv * nb) {
+    rho.alloc(2 * (size_t)nv * nb);
+    q.alloc(2 * (size_t)nv * nb);
+    part.alloc(2 * (size_t)V * 4 * nb);
+    for (int k = 0; k < 2; ++k) {
+      ss.rho[k] = rho.p + (size_t)k * nv * nb;
+      ss.q[k] = q.p + (size_t)k * nv * nb;
+      ss.part[k] = part.p + (size_t)k * V * 4 * nb;
+    }
+  }
+  return ss;
+}
+template <typename T> SapScratch<T>& sap_scratch(LevelStore& L_, int nb);
+template <> SapScratch<double>& sap_scratch<double>(LevelStore& L_, int nb) {
+  return sap_buffers<double>(L_.sr64, L_.sq64, L_.sp64, L_.ss64, L_.n, L_.V, nb);
+}
+template <> SapScratch<float>& sap_scratch<float>(LevelStore& L_, int nb) {
+  return sap_buffers<float>(L_.sr32, L_.sq32, L_.sp32, L_.ss32, L_.n, L_.V, nb);
+}
 
-template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsweeps) {
+template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsweeps, int nb) {
   for (int it = 0; it < nsweeps; ++it)
     for (int col = 0; col < 2; ++col) {
       if (l == 0) {
-        fine_op<T>([&](const auto& op) { sap_colour(op, ctx->cblk.p, col, p.mr_iters, b, z, s); });
+        fine_op<T>([&](const auto& op) { sap_colour(op, ctx->cblk.p, col, p.mr_iters, b, z, s, nb); });
       } else {
         LevelStore& L_ = lv[l];
+        SapScratch<T>& ws = sap_scratch<T>(L_, nb);
         coarse_op<T>(l, [&](const auto& op) {
           coarse_sap_colour(op, L_.c_blk_sites.p, L_.c_site_blk.p, L_.cg.nblk, L_.cg.bs, col, p.mr_iters, b,
-                            z, sap_scratch<T>(L_), s);
+                            z, ws, s, nb);
         });
       }
     }
 }
 
-template <typename T> void Hierarchy::restrict_to(int l, const C<T>* fine, C<T>* coarse) {
+template <typename T> void Hierarchy::restrict_to(int l, const C<T>* fine, C<T>* coarse, int nb) {
   const LevelStore& L_ = lv[l];
   interp<T>(l, [&](const auto* P_) {
-    if (l == 0) restrict_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, fine, coarse, s);
-    else restrict_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, fine, coarse, s);
+    if (l == 0) restrict_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, fine, coarse, s, nb);
+    else restrict_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, fine, coarse, s, nb);
   });
 }
 
-template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T>* fine) {
+template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T>* fine, int nb) {
   const LevelStore& L_ = lv[l];
   interp<T>(l, [&](const auto* P_) {
-    if (l == 0) prolong_fine<T>(ctx->g, L_.ad(), L_.N, P_, coarse, fine, s);
-    else prolong_coarse<T>(L_.ad(), L_.d, L_.N, L_.V, P_, coarse, fine, s);
+    if (l == 0) prolong_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, coarse, fine, s, nb);
+    else prolong_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, coarse, fine, s, nb);
   });
 }
 
@@ -149,126 +171,218 @@ double Hierarchy::norm(const double2* v, long long n) {
 }
 
 // ---------------------------------------------------------------------------
-// Flexible GMRES(m) on level l from x = 0, at most max_cycles restart
-// cycles, stop when the Arnoldi residual estimate <= tol ||b||.  Arnoldi
-// with classical Gram-Schmidt and one re-orthogonalisation pass (two fused
-// inner-product launches per step); Givens rotations on the host.
+// Batched Krylov building blocks.  Every system r of a batch has its own
+// Hessenberg matrix, Givens rotations and stopping test on the host; the
+// vector work of all systems goes through one launch per operation.  A
+// system that has stopped is carried along with zero basis vectors (scale
+// 0), so it costs work but never changes again.
 // ---------------------------------------------------------------------------
-// One Arnoldi orthogonalisation step against V_0..V_j (classical Gram-Schmidt,
-// second pass only when the first removed more than half of ||w||^2, the
-// criterion of Daniel, Gragg, Kaufman and Stewart).  Fills h[0..j] with the
-// Hessenberg column, returns ||w_perp||, and leaves in `c` the coefficients
-// that the caller applies as w += V c together with V_{j+1} = w / hn.
+// norms ||v_r|| of a batch
 template <typename T>
-static double gs_step(Reducer& red, const C<T>* V, long long n, int j, C<T>* w, std::vector<cd>& h,
-                      std::vector<cd>& h2, Coefs& c, hipStream_t s) {
-  red.dots<T>(V, n, j + 1, w, n, true, s);
-  red.fetch(j + 2, h.data(), s);
-  const double ww = h[j + 1].real();
-  double proj = 0;
-  for (int i = 0; i <= j; ++i) {
-    proj += std::norm(h[i]);
-    c.c[i] = d2(-h[i]);
-  }
-  if (ww - proj > 0.5 * ww) return std::sqrt(ww - proj);
-  red.update_dots<T>(c, V, n, j + 1, w, n, s);
-  red.fetch(j + 2, h2.data(), s);
-  double nn = h2[j + 1].real();
-  for (int i = 0; i <= j; ++i) {
-    c.c[i] = d2(-h2[i]);
-    nn -= std::norm(h2[i]);
-    h[i] += h2[i];
-  }
-  return std::sqrt(std::max(nn, 0.0));
+static void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector<double>& out, hipStream_t s) {
+  red.bdots<T>(nullptr, v, 0, 0, const_cast<C<T>*>(v), n, nb, s);
+  std::vector<cd> r(nb);
+  red.bfetch(1, nb, r.data(), s);
+  out.resize(nb);
+  for (int k = 0; k < nb; ++k) out[k] = std::sqrt(std::max(r[k].real(), 0.0));
 }
 
+// dst_r = scale_r * src_r
+template <typename T>
+static void bscale_host(Reducer& red, const std::vector<double>& scale, const C<T>* src, C<T>* dst, long long n,
+                        int nb, hipStream_t s) {
+  const double* sd = nullptr;
+  red.upload(std::vector<cd>(), scale, nb, &sd, s);
+  bscale<T>(sd, src, dst, n, nb, s);
+}
+
+// Arnoldi step with classical Gram-Schmidt; a second pass for the systems
+// whose first pass removed more than half of ||w||^2 (the criterion of
+// Daniel, Gragg, Kaufman and Stewart).
+template <typename T>
+void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, int j, C<T>* w,
+                        const std::vector<char>& live, std::vector<cd>& h, std::vector<double>& hn,
+                        std::vector<cd>& cf) {
+  const int k1 = j + 2;
+  std::vector<cd> h1((size_t)nb * k1), h2((size_t)nb * k1), c1((size_t)nb * KMAX, cd(0));
+  red->bdots<T>(nullptr, V, vstride, j + 1, w, n, nb, s);
+  red->bfetch(k1, nb, h1.data(), s);
+  h.assign((size_t)nb * (KMAX + 1), cd(0));
+  hn.assign(nb, 0.0);
+  cf.assign((size_t)nb * KMAX, cd(0));
+  std::vector<char> again(nb, 0);
+  bool any = false;
+  for (int r = 0; r < nb; ++r) {
+    const cd* hr = &h1[(size_t)r * k1];
+    const double ww = hr[j + 1].real();
+    double proj = 0;
+    for (int i = 0; i <= j; ++i) proj += std::norm(hr[i]);
+    for (int i = 0; i <= j; ++i) {
+      h[(size_t)r * (KMAX + 1) + i] = hr[i];
+      cf[(size_t)r * KMAX + i] = -hr[i];
+    }
+    hn[r] = std::sqrt(std::max(ww - proj, 0.0));
+    if (live[r] && !(ww - proj > 0.5 * ww)) {
+      again[r] = 1;
+      any = true;
+      for (int i = 0; i <= j; ++i) c1[(size_t)r * KMAX + i] = -hr[i];
+    }
+  }
+  if (!any) return;
+  const double2* cdev = red->upload(c1, std::vector<double>(), nb, nullptr, s);
+  red->bdots<T>(cdev, V, vstride, j + 1, w, n, nb, s);
+  red->bfetch(k1, nb, h2.data(), s);
+  for (int r = 0; r < nb; ++r) {
+    if (!again[r]) continue;
+    const cd* hr = &h2[(size_t)r * k1];
+    double nn = hr[j + 1].real();
+    for (int i = 0; i <= j; ++i) {
+      nn -= std::norm(hr[i]);
+      h[(size_t)r * (KMAX + 1) + i] += hr[i];
+      cf[(size_t)r * KMAX + i] = -hr[i];
+    }
+    hn[r] = std::sqrt(std::max(nn, 0.0));
+  }
+}
+
+// Givens update of column j of system r's Hessenberg matrix H (row-major
+// (m+1) x m) and of its right-hand side g; returns |g[j+1]|
+static double givens_column(cd* H, cd* g, cd* cs, cd* sn, int m, int j, const cd* h, double hn) {
+  for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+  H[(size_t)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const cd a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+    H[(size_t)(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bq;
+  }
+  const cd a = H[(size_t)j * m + j];
+  const double rho = std::sqrt(std::norm(a) + hn * hn);
+  if (rho == 0.0) { cs[j] = 1; sn[j] = 0; }
+  else if (std::abs(a) == 0.0) { cs[j] = 0; sn[j] = 1; }
+  else {
+    cs[j] = std::abs(a) / rho;
+    sn[j] = (a / std::abs(a)) * hn / rho;
+  }
+  H[(size_t)j * m + j] = cs[j] * a + sn[j] * hn;
+  H[(size_t)(j + 1) * m + j] = 0;
+  g[j + 1] = -std::conj(sn[j]) * g[j];
+  g[j] = cs[j] * g[j];
+  return std::abs(g[j + 1]);
+}
+
+// y = R^{-1} g for the leading jend x jend triangle
+static void back_substitute(const cd* H, const cd* g, int m, int jend, cd* y) {
+  for (int i = jend - 1; i >= 0; --i) {
+    cd acc = g[i];
+    for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
+    y[i] = acc / H[(size_t)i * m + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Flexible GMRES(m) on level l for a batch, from x = 0, at most max_cycles
+// restart cycles per system, system r stops when its Arnoldi residual
+// estimate <= tol ||b_r||.
+// ---------------------------------------------------------------------------
 template <typename T, typename Op, typename Pre>
-int Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m,
-                      int max_cycles, double tol) {
+void Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>* x, int m, int max_cycles,
+                       double tol, int nb, long long* iters) {
   Work<T>& W = work<T>(l);
-  const long long n = lv[l].n;
-  DD_REQUIRE(m <= W.m, "Krylov basis too short");
+  const long long n = lv[l].n, vs = (long long)nb * n;
+  DD_REQUIRE(m <= W.m && nb <= W.cap, "Krylov basis too short for the batch");
   C<T>* V = W.V.p;
   C<T>* Z = use_pre ? W.Z.p : W.V.p;
   C<T>* w = W.w.p;
-  vzero<T>(x, n, s);
-  red->dots<T>(b, 0, 0, b, n, true, s);
-  cd bb;
-  red->fetch(1, &bb, s);
-  const double bnorm = std::sqrt(bb.real());
-  if (!(bnorm > 0)) return 0;
-  const double target = tol * bnorm;
-  vcopy<T, T>(b, V, n, s);
-  vscale<T>(make_double2(1.0 / bnorm, 0), V, n, s);
-  double beta = bnorm;
-  int iters = 0;
-  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h(KMAX + 1), h2(KMAX + 1);
+  vzero<T>(x, vs, s);
+  std::vector<double> beta, target(nb), scale(nb);
+  bnorms<T>(*red, b, n, nb, beta, s);
+  std::vector<char> active(nb);
+  bool any = false;
+  for (int r = 0; r < nb; ++r) {
+    active[r] = beta[r] > 0;
+    target[r] = tol * beta[r];
+    scale[r] = active[r] ? 1.0 / beta[r] : 0.0;
+    any = any || active[r];
+  }
+  if (!any) return;
+  bscale_host<T>(*red, scale, b, V, n, nb, s);
+  std::vector<cd> H((size_t)nb * (m + 1) * m), g((size_t)nb * (m + 1)), cs((size_t)nb * m), sn((size_t)nb * m);
+  std::vector<cd> h, cf, y(m), cy((size_t)nb * KMAX);
+  std::vector<double> hn;
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     std::fill(H.begin(), H.end(), cd(0));
     std::fill(g.begin(), g.end(), cd(0));
-    g[0] = beta;
-    int jend = 0;
-    bool conv = false;
+    for (int r = 0; r < nb; ++r) g[(size_t)r * (m + 1)] = active[r] ? beta[r] : 0.0;
+    std::vector<int> jend(nb, 0);
+    std::vector<char> live = active, conv(nb, 0);
     for (int j = 0; j < m; ++j) {
-      C<T>* Vj = V + (size_t)j * n;
-      C<T>* Zj = Z + (size_t)j * n;
-      if (use_pre) pre(Vj, Zj);
+      C<T>* Vj = V + (size_t)j * vs;
+      C<T>* Zj = Z + (size_t)j * vs;
+      if (use_pre) {
+        // a stopped system is carried with zero input: not a visit of the
+        // levels below for the setup's record
+        const std::vector<char> outer_visit = visit;
+        for (int r = 0; r < nb && r < (int)visit.size(); ++r) visit[r] = visit[r] && live[r];
+        pre(Vj, Zj);
+        visit = outer_visit;
+      }
       op(Zj, w);
-      Coefs c;
-      const double hn = gs_step<T>(*red, V, n, j, w, h, h2, c, s);
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
-      H[(size_t)(j + 1) * m + j] = hn;
-      // apply previous rotations, then a new one that zeroes H[j+1][j]
-      for (int i = 0; i < j; ++i) {
-        cd a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
-        H[(size_t)(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bq;
-      }
-      {
-        cd a = H[(size_t)j * m + j];
-        const double bq = hn;
-        const double rho = std::sqrt(std::norm(a) + bq * bq);
-        if (rho == 0.0) { cs[j] = 1; sn[j] = 0; }
-        else if (std::abs(a) == 0.0) { cs[j] = 0; sn[j] = 1; }
-        else {
-          cs[j] = std::abs(a) / rho;
-          sn[j] = (a / std::abs(a)) * bq / rho;
+      arnoldi<T>(V, vs, n, nb, j, w, live, h, hn, cf);
+      bool still = false;
+      for (int r = 0; r < nb; ++r) {
+        if (!live[r]) continue;
+        const double est = givens_column(&H[(size_t)r * (m + 1) * m], &g[(size_t)r * (m + 1)], &cs[(size_t)r * m],
+                                         &sn[(size_t)r * m], m, j, &h[(size_t)r * (KMAX + 1)], hn[r]);
+        if (iters) ++iters[r];
+        jend[r] = j + 1;
+        if (!std::isfinite(est)) throw Error(DDAMG_ENONFINITE, "non-finite residual in GMRES");
+        if (est <= target[r] || hn[r] == 0.0) {
+          live[r] = 0;
+          conv[r] = 1;
         }
-        H[(size_t)j * m + j] = cs[j] * a + sn[j] * bq;
-        H[(size_t)(j + 1) * m + j] = 0;
-        g[j + 1] = -std::conj(sn[j]) * g[j];
-        g[j] = cs[j] * g[j];
+        still = still || live[r];
       }
-      ++iters;
-      jend = j + 1;
-      const double est = std::abs(g[j + 1]);
-      if (!std::isfinite(est)) throw Error(DDAMG_ENONFINITE, "non-finite residual in GMRES");
-      if (est <= target || hn == 0.0) { conv = true; break; }
-      // w += V c and V_{j+1} = w / hn in one pass
-      if (j + 1 < m) vlincomb_scale<T>(c, j + 1, V, n, w, n, 1.0 / hn, V + (size_t)(j + 1) * n, s);
+      if (!still) break;
+      // w += V c and V_{j+1} = w / hn in one pass (zero for stopped systems)
+      if (j + 1 < m) {
+        for (int r = 0; r < nb; ++r) scale[r] = live[r] ? 1.0 / hn[r] : 0.0;
+        const double* sd = nullptr;
+        const double2* cdev = red->upload(cf, scale, nb, &sd, s);
+        blincomb<T, T>(cdev, sd, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+      }
     }
-    // y = R^{-1} g, x += Z y
-    std::vector<cd> y(jend);
-    for (int i = jend - 1; i >= 0; --i) {
-      cd acc = g[i];
-      for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
-      y[i] = acc / H[(size_t)i * m + i];
+    // x_r += Z_r y_r
+    int kmax = 0;
+    std::fill(cy.begin(), cy.end(), cd(0));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[r] || jend[r] == 0) continue;
+      back_substitute(&H[(size_t)r * (m + 1) * m], &g[(size_t)r * (m + 1)], m, jend[r], y.data());
+      for (int i = 0; i < jend[r]; ++i) cy[(size_t)r * KMAX + i] = y[i];
+      kmax = std::max(kmax, jend[r]);
     }
-    Coefs c;
-    for (int i = 0; i < jend; ++i) c.c[i] = d2(y[i]);
-    vlincomb<T, T>(c, jend, Z, n, x, n, s);
-    if (conv || cyc + 1 == max_cycles) break;
-    // restart from the true residual
+    if (kmax > 0) {
+      const double2* cdev = red->upload(cy, std::vector<double>(), nb, nullptr, s);
+      blincomb<T, T>(cdev, nullptr, kmax, Z, vs, x, n, nb, nullptr, s);
+    }
+    bool more = false;
+    for (int r = 0; r < nb; ++r) {
+      active[r] = active[r] && !conv[r];
+      more = more || active[r];
+    }
+    if (!more || cyc + 1 == max_cycles) break;
+    // restart the unfinished systems from their true residuals
     op(x, w);
-    vbmy<T>(b, w, n, s);
-    red->dots<T>(w, 0, 0, w, n, true, s);
-    cd rr;
-    red->fetch(1, &rr, s);
-    beta = std::sqrt(rr.real());
-    if (!(beta > 0)) break;
-    vlincomb_scale<T>(Coefs{}, 0, V, n, w, n, 1.0 / beta, V, s);
+    vbmy<T>(b, w, vs, s);
+    bnorms<T>(*red, w, n, nb, beta, s);
+    more = false;
+    for (int r = 0; r < nb; ++r) {
+      active[r] = active[r] && beta[r] > 0;
+      scale[r] = active[r] ? 1.0 / beta[r] : 0.0;
+      more = more || active[r];
+    }
+    if (!more) break;
+    bscale_host<T>(*red, scale, w, V, n, nb, s);
   }
-  return iters;
 }
 
 // ---------------------------------------------------------------------------
@@ -278,187 +392,219 @@ template <typename T> const C<T>* einv(const LevelStore& L_);
 template <> const C<double>* einv<double>(const LevelStore& L_) { return L_.Einv64.p; }
 template <> const C<float>* einv<float>(const LevelStore& L_) { return L_.Einv32.p; }
 
-template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out) {
+template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out, int nb) {
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
   Work<T>& W = work<T>(c);
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
   // t3_e = D_eo v_o ; t4_e = D_ee^-1 t3_e ; out_o = D_oo v_o - D_oe t4_e
   coarse_op<T>(c, [&](const auto& op) {
-    coarse_site_apply(op, L_.c_even.p, ne, T(0), nullptr, T(0), nullptr, T(1), v, W.t3.p, s);
-    site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, W.t3.p, W.t4.p, s);
-    vzero<T>(out, L_.n, s);
-    coarse_site_apply(op, L_.c_odd.p, no, T(0), nullptr, T(1), v, T(-1), W.t4.p, out, s);
+    coarse_site_apply(op, L_.c_even.p, ne, T(0), nullptr, T(0), nullptr, T(1), v, W.t3.p, s, nb);
+    site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, W.t3.p, W.t4.p, s, nb);
+    vzero<T>(out, L_.n * nb, s);
+    coarse_site_apply(op, L_.c_odd.p, no, T(0), nullptr, T(1), v, T(-1), W.t4.p, out, s, nb);
   });
 }
 
-template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z) {
+template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z, int nb) {
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
   Work<T>& W = work<T>(c);
   const long long n = L_.n;
   if (!L_.cg.bipartite) {
-    cs_iters += fgmres<T>(
-        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o); }, [](const C<T>*, C<T>*) {}, false, b,
-        z, p.coarse_restart, p.coarse_max_restarts, p.coarse_eps);
+    fgmres<T>(
+        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); }, [](const C<T>*, C<T>*) {}, false, b, z,
+        p.coarse_restart, p.coarse_max_restarts, p.coarse_eps, nb, cs_it.data());
     return;
   }
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
   // u_e = D_ee^-1 b_e
-  vzero<T>(W.t1.p, n, s);
-  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, b, W.t1.p, s);
+  vzero<T>(W.t1.p, n * nb, s);
+  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, b, W.t1.p, s, nb);
   // rhs_o = b_o - D_oe u_e (zero on even sites)
-  vzero<T>(W.t2.p, n, s);
+  vzero<T>(W.t2.p, n * nb, s);
   coarse_op<T>(c, [&](const auto& op) {
-    coarse_site_apply(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s);
+    coarse_site_apply(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s, nb);
   });
-  cs_iters += fgmres<T>(
-      c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o); }, [](const C<T>*, C<T>*) {}, false, W.t2.p, z,
-      p.coarse_restart, p.coarse_max_restarts, p.coarse_eps);
+  fgmres<T>(
+      c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o, nb); }, [](const C<T>*, C<T>*) {}, false, W.t2.p, z,
+      p.coarse_restart, p.coarse_max_restarts, p.coarse_eps, nb, cs_it.data());
   // z_e = D_ee^-1 (b_e - D_eo z_o)
   coarse_op<T>(c, [&](const auto& op) {
-    coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s);
+    coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s, nb);
   });
-  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, W.t1.p, z, s);
+  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, W.t1.p, z, s, nb);
 }
 
 // ---------------------------------------------------------------------------
 // the level-l cycle (Alg. 1; Alg. 2 replaces the recursive call by FGMRES)
 // ---------------------------------------------------------------------------
-template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z) {
+template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int nb) {
   Work<T>& W = work<T>(l);
   Work<T>& Wc = work<T>(l + 1);
+  DD_REQUIRE(nb <= W.cap && nb <= Wc.cap, "batch larger than the work buffers");
   const long long n = lv[l].n;
-  vzero<T>(z, n, s);
+  vzero<T>(z, n * nb, s);
   if (p.mu > 0) {
-    sap<T>(l, b, z, p.mu);
-    apply<T>(l, z, W.r.p);
-    vbmy<T>(b, W.r.p, n, s);
-    restrict_to<T>(l, W.r.p, Wc.bin.p);
+    sap<T>(l, b, z, p.mu, nb);
+    apply<T>(l, z, W.r.p, nb);
+    vbmy<T>(b, W.r.p, n * nb, s);
+    restrict_to<T>(l, W.r.p, Wc.bin.p, nb);
   } else {
-    restrict_to<T>(l, b, Wc.bin.p);
+    restrict_to<T>(l, b, Wc.bin.p, nb);
   }
   if (l + 1 == L - 1) {
-    coarsest_solve<T>(Wc.bin.p, Wc.z.p);
+    coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb);
   } else if (p.cycle == DDAMG_KCYCLE) {
     const int c = l + 1;
-    kc_iters += fgmres<T>(
-        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o); },
-        [&](const C<T>* a, C<T>* o) { cycle<T>(c, a, o); }, true, Wc.bin.p, Wc.z.p, p.kc_len,
-        p.kc_restarts, p.kc_tol);
+    fgmres<T>(
+        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); },
+        [&](const C<T>* a, C<T>* o) { cycle<T>(c, a, o, nb); }, true, Wc.bin.p, Wc.z.p, p.kc_len,
+        p.kc_restarts, p.kc_tol, nb, kc_it.data());
   } else {
-    cycle<T>(l + 1, Wc.bin.p, Wc.z.p);
+    cycle<T>(l + 1, Wc.bin.p, Wc.z.p, nb);
   }
-  if (recording) vcopy<T, T>(Wc.z.p, Wc.rec.p, lv[l + 1].n, s);
-  prolong_add<T>(l, Wc.z.p, z);
-  if (p.nu > 0) sap<T>(l, b, z, p.nu);
+  if (recording) {
+    const long long nc = lv[l + 1].n;
+    for (int r = 0; r < nb; ++r)
+      if (visit[r]) vcopy<T, T>(Wc.z.p + r * nc, Wc.rec.p + r * nc, nc, s);
+  }
+  prolong_add<T>(l, Wc.z.p, z, nb);
+  if (p.nu > 0) sap<T>(l, b, z, p.nu, nb);
 }
 
 // ---------------------------------------------------------------------------
-// outer FGMRES in FP64, right-preconditioned by the level-0 cycle at T
+// outer FGMRES in FP64 for a batch, right-preconditioned by the level-0
+// cycle at T; every system is certified by its true residual, recomputed in
+// FP64, and restarted until it meets tol (or max_restarts).
 // ---------------------------------------------------------------------------
-template <typename T> C<T>* outerZ(Hierarchy& H);
-template <> C<double>* outerZ<double>(Hierarchy& H) { return H.oZ64.p; }
-template <> C<float>* outerZ<float>(Hierarchy& H) { return H.oZ32.p; }
+template <typename T> DevArray<C<T>>& outerZ(Hierarchy& H);
+template <> DevArray<C<double>>& outerZ<double>(Hierarchy& H) { return H.oZ64; }
+template <> DevArray<C<float>>& outerZ<float>(Hierarchy& H) { return H.oZ32; }
 
-template <typename T> int Hierarchy::outer(const double2* b, double2* x, ddamg_solve_stats* st) {
-  const long long n = lv[0].n;
+template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_solve_stats* st, int nb) {
+  const long long n = lv[0].n, vs = (long long)nb * n;
   const int m = p.nkv;
+  ensure_batch<T>(nb);
   const FineOpView<double> D = ctx->view<double>();
   double2* V = oV.p;
-  C<T>* Z = outerZ<T>(*this);
+  C<T>* Z = outerZ<T>(*this).p;
   double2* w = ow.p;
-  const double bnorm = norm(b, n);
-  if (!std::isfinite(bnorm)) {
-    st->status = DDAMG_ENONFINITE;
-    return DDAMG_ENONFINITE;
+  std::vector<double> bnorm, beta, target(nb), scale(nb);
+  bnorms<double>(*red, b, n, nb, bnorm, s);
+  std::vector<int> status(nb, DDAMG_ENOCONV);
+  std::vector<char> active(nb, 0);
+  for (int r = 0; r < nb; ++r) {
+    st[r].outer_iters = 0;
+    st[r].restarts = 0;
+    st[r].true_relres = 0;
+    if (!std::isfinite(bnorm[r])) status[r] = DDAMG_ENONFINITE;
+    else if (bnorm[r] == 0.0) status[r] = DDAMG_OK;
+    target[r] = p.tol * bnorm[r];
   }
-  if (bnorm == 0.0) {
-    vzero<double>(x, n, s);
-    st->true_relres = 0;
-    st->status = DDAMG_OK;
-    return DDAMG_OK;
+  // systems with b_r = 0 have the solution 0
+  {
+    std::vector<double> keep(nb);
+    for (int r = 0; r < nb; ++r) keep[r] = (bnorm[r] == 0.0) ? 0.0 : 1.0;
+    bscale_host<double>(*red, keep, x, x, n, nb, s);
   }
-  const double target = p.tol * bnorm;
   // r = b - D x
-  dslash<double>(D, x, w, s);
-  vbmy<double>(b, w, n, s);
-  double beta = norm(w, n);
-  std::vector<cd> Hm((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h(KMAX + 1), h2(KMAX + 1);
-  int iters = 0, restarts = 0;
-  int status = DDAMG_ENOCONV;
-  if (beta <= target) status = DDAMG_OK;
-  Work<T>& W0 = work<T>(0);
-  while (status == DDAMG_ENOCONV && restarts < p.max_restarts) {
-    if (!std::isfinite(beta)) { status = DDAMG_ENONFINITE; break; }
-    vlincomb_scale<double>(Coefs{}, 0, V, n, w, n, 1.0 / beta, V, s);
-    std::fill(Hm.begin(), Hm.end(), cd(0));
-    std::fill(g.begin(), g.end(), cd(0));
-    g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
-      double2* Vj = V + (size_t)j * n;
-      C<T>* Zj = Z + (size_t)j * n;
-      if constexpr (std::is_same<T, double>::value) {
-        cycle<double>(0, Vj, Zj);
-        dslash<double>(D, Zj, w, s);
-      } else {
-        vcopy<double, T>(Vj, W0.bin.p, n, s);
-        cycle<T>(0, W0.bin.p, Zj);
-        vcopy<T, double>(Zj, ot.p, n, s);
-        dslash<double>(D, ot.p, w, s);
-      }
-      Coefs c;
-      const double hn = gs_step<double>(*red, V, n, j, w, h, h2, c, s);
-      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
-      for (int i = 0; i < j; ++i) {
-        cd a = Hm[(size_t)i * m + j], bq = Hm[(size_t)(i + 1) * m + j];
-        Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
-        Hm[(size_t)(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bq;
-      }
-      {
-        cd a = Hm[(size_t)j * m + j];
-        const double rho = std::sqrt(std::norm(a) + hn * hn);
-        if (rho == 0.0) { cs[j] = 1; sn[j] = 0; }
-        else if (std::abs(a) == 0.0) { cs[j] = 0; sn[j] = 1; }
-        else {
-          cs[j] = std::abs(a) / rho;
-          sn[j] = (a / std::abs(a)) * hn / rho;
-        }
-        Hm[(size_t)j * m + j] = cs[j] * a + sn[j] * hn;
-        g[j + 1] = -std::conj(sn[j]) * g[j];
-        g[j] = cs[j] * g[j];
-      }
-      ++iters;
-      jend = j + 1;
-      const double est = std::abs(g[j + 1]);
-      if (!std::isfinite(est)) { status = DDAMG_ENONFINITE; break; }
-      if (est <= target || hn == 0.0) break;
-      if (j + 1 < m) vlincomb_scale<double>(c, j + 1, V, n, w, n, 1.0 / hn, V + (size_t)(j + 1) * n, s);
-    }
-    if (status == DDAMG_ENONFINITE) break;
-    std::vector<cd> y(jend);
-    for (int i = jend - 1; i >= 0; --i) {
-      cd acc = g[i];
-      for (int k = i + 1; k < jend; ++k) acc -= Hm[(size_t)i * m + k] * y[k];
-      y[i] = acc / Hm[(size_t)i * m + i];
-    }
-    Coefs c;
-    for (int i = 0; i < jend; ++i) c.c[i] = d2(y[i]);
-    vlincomb<double, T>(c, jend, Z, n, x, n, s);
-    ++restarts;
-    // true residual in FP64
-    dslash<double>(D, x, w, s);
-    vbmy<double>(b, w, n, s);
-    beta = norm(w, n);
-    if (!std::isfinite(beta)) { status = DDAMG_ENONFINITE; break; }
-    if (beta <= target) status = DDAMG_OK;
+  dslash<double>(D, x, w, s, nb);
+  vbmy<double>(b, w, vs, s);
+  bnorms<double>(*red, w, n, nb, beta, s);
+  for (int r = 0; r < nb; ++r) {
+    if (status[r] != DDAMG_ENOCONV) continue;
+    if (!std::isfinite(beta[r])) status[r] = DDAMG_ENONFINITE;
+    else if (beta[r] <= target[r]) status[r] = DDAMG_OK;
+    active[r] = status[r] == DDAMG_ENOCONV;
   }
-  st->status = status;
-  st->outer_iters = iters;
-  st->restarts = restarts;
-  st->true_relres = beta / bnorm;
-  return status;
+  std::vector<cd> H((size_t)nb * (m + 1) * m), g((size_t)nb * (m + 1)), cs((size_t)nb * m), sn((size_t)nb * m);
+  std::vector<cd> h, cf, y(m), cy((size_t)nb * KMAX);
+  std::vector<double> hn;
+  Work<T>& W0 = work<T>(0);
+  for (int restart = 0; restart < p.max_restarts; ++restart) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) {
+      scale[r] = active[r] ? 1.0 / beta[r] : 0.0;
+      any = any || active[r];
+    }
+    if (!any) break;
+    bscale_host<double>(*red, scale, w, V, n, nb, s);
+    std::fill(H.begin(), H.end(), cd(0));
+    std::fill(g.begin(), g.end(), cd(0));
+    for (int r = 0; r < nb; ++r) g[(size_t)r * (m + 1)] = active[r] ? beta[r] : 0.0;
+    std::vector<int> jend(nb, 0);
+    std::vector<char> live = active;
+    for (int j = 0; j < m; ++j) {
+      double2* Vj = V + (size_t)j * vs;
+      C<T>* Zj = Z + (size_t)j * vs;
+      if constexpr (std::is_same<T, double>::value) {
+        cycle<double>(0, Vj, Zj, nb);
+        dslash<double>(D, Zj, w, s, nb);
+      } else {
+        vcopy<double, T>(Vj, W0.bin.p, vs, s);
+        cycle<T>(0, W0.bin.p, Zj, nb);
+        vcopy<T, double>(Zj, ot.p, vs, s);
+        dslash<double>(D, ot.p, w, s, nb);
+      }
+      arnoldi<double>(V, vs, n, nb, j, w, live, h, hn, cf);
+      bool still = false;
+      for (int r = 0; r < nb; ++r) {
+        if (!live[r]) continue;
+        const double est = givens_column(&H[(size_t)r * (m + 1) * m], &g[(size_t)r * (m + 1)], &cs[(size_t)r * m],
+                                         &sn[(size_t)r * m], m, j, &h[(size_t)r * (KMAX + 1)], hn[r]);
+        ++st[r].outer_iters;
+        jend[r] = j + 1;
+        if (!std::isfinite(est)) {
+          status[r] = DDAMG_ENONFINITE;
+          live[r] = 0;
+          active[r] = 0;
+          jend[r] = 0;
+        } else if (est <= target[r] || hn[r] == 0.0) {
+          live[r] = 0;
+        }
+        still = still || live[r];
+      }
+      if (!still) break;
+      if (j + 1 < m) {
+        for (int r = 0; r < nb; ++r) scale[r] = live[r] ? 1.0 / hn[r] : 0.0;
+        const double* sd = nullptr;
+        const double2* cdev = red->upload(cf, scale, nb, &sd, s);
+        blincomb<double, double>(cdev, sd, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+      }
+    }
+    int kmax = 0;
+    std::fill(cy.begin(), cy.end(), cd(0));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[r] || jend[r] == 0) continue;
+      back_substitute(&H[(size_t)r * (m + 1) * m], &g[(size_t)r * (m + 1)], m, jend[r], y.data());
+      for (int i = 0; i < jend[r]; ++i) cy[(size_t)r * KMAX + i] = y[i];
+      kmax = std::max(kmax, jend[r]);
+      ++st[r].restarts;
+    }
+    if (kmax > 0) {
+      const double2* cdev = red->upload(cy, std::vector<double>(), nb, nullptr, s);
+      blincomb<double, T>(cdev, nullptr, kmax, Z, vs, x, n, nb, nullptr, s);
+    }
+    // true residuals in FP64
+    dslash<double>(D, x, w, s, nb);
+    vbmy<double>(b, w, vs, s);
+    bnorms<double>(*red, w, n, nb, beta, s);
+    for (int r = 0; r < nb; ++r) {
+      if (!active[r]) continue;
+      if (!std::isfinite(beta[r])) {
+        status[r] = DDAMG_ENONFINITE;
+        active[r] = 0;
+      } else if (beta[r] <= target[r]) {
+        status[r] = DDAMG_OK;
+        active[r] = 0;
+      }
+    }
+  }
+  for (int r = 0; r < nb; ++r) {
+    st[r].status = status[r];
+    st[r].true_relres = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -468,17 +614,23 @@ template <typename T> std::vector<Work<T>>& work_vec(Hierarchy& H);
 template <> std::vector<Work<double>>& work_vec<double>(Hierarchy& H) { return H.w64; }
 template <> std::vector<Work<float>>& work_vec<float>(Hierarchy& H) { return H.w32; }
 
-template <typename T> void Hierarchy::alloc_work() {
+template <typename T> void Hierarchy::alloc_work(int cap) {
   std::vector<Work<T>>& W = work_vec<T>(*this);
   W.clear();
   W.resize(L);
   for (int l = 0; l < L; ++l) {
-    const long long n = lv[l].n;
+    const size_t n = (size_t)lv[l].n * cap;
     Work<T>& w = W[l];
+    w.cap = cap;
     w.bin.alloc(n);
+    w.rec.alloc(n);
+    if (l == 0) {
+      w.x.alloc(n);
+      if (p.mu > 0) w.r.alloc(n);
+      continue;
+    }
     w.z.alloc(n);
     w.r.alloc(n);
-    w.rec.alloc(n);
     w.x.alloc(n);
     w.w.alloc(n);
     if (l == L - 1) {
@@ -488,12 +640,38 @@ template <typename T> void Hierarchy::alloc_work() {
       w.t4.alloc(n);
       w.m = p.coarse_restart;
       w.V.alloc((size_t)(w.m + 1) * n);
-    } else if (l > 0) {
+    } else {
       w.m = p.kc_len;
       w.V.alloc((size_t)(w.m + 1) * n);
       w.Z.alloc((size_t)w.m * n);
     }
   }
+}
+
+// work buffers at precision T for a batch of nb
+template <typename T> void Hierarchy::ensure_work(int nb) {
+  DD_REQUIRE(nb >= 1 && nb <= NBMAX, "batch size out of range");
+  if (work_vec<T>(*this).empty() || work_vec<T>(*this)[0].cap < nb) alloc_work<T>(nb);
+  if ((int)kc_it.size() < nb) kc_it.resize(nb, 0);
+  if ((int)cs_it.size() < nb) cs_it.resize(nb, 0);
+}
+
+// work buffers and outer-solver buffers for a batch of nb
+template <typename T> void Hierarchy::ensure_batch(int nb) {
+  ensure_work<T>(nb);
+  if (ocap >= nb) return;
+  const size_t n0 = (size_t)lv[0].n * nb;
+  oV.alloc((size_t)(p.nkv + 1) * n0);
+  ow.alloc(n0);
+  ob.alloc(n0);
+  ox.alloc(n0);
+  if (std::is_same<T, float>::value) {
+    oZ32.alloc((size_t)p.nkv * n0);
+    ot.alloc(n0);
+  } else {
+    oZ64.alloc((size_t)p.nkv * n0);
+  }
+  ocap = nb;
 }
 
 void Hierarchy::build_level(int l, bool from32) {
@@ -522,6 +700,10 @@ void Hierarchy::build_level(int l, bool from32) {
   DD_CHECK_HIP(hipStreamSynchronize(s));
 }
 
+// The N test vectors of a level form a batch: Alg. 3 smooths each of them
+// on its own and Alg. 4 cycles each with the hierarchy fixed until all are
+// done, so the N updates are independent and run together (in chunks of
+// the work capacity).
 template <typename T> void Hierarchy::initial_setup(int l) {
   LevelStore& F = lv[l];
   const long long n = F.n;
@@ -529,8 +711,10 @@ template <typename T> void Hierarchy::initial_setup(int l) {
   Work<T>& W = work<T>(l);
   if (l > 0) {
     const int Np = lv[l - 1].N;
-    for (int j = 0; j < N && j < Np; ++j)
-      restrict_to<T>(l - 1, tv<T>(l - 1) + (size_t)j * lv[l - 1].n, tv<T>(l) + (size_t)j * n);
+    const int nr = std::min(N, Np);
+    for (int j0 = 0; j0 < nr; j0 += W.cap)
+      restrict_to<T>(l - 1, tv<T>(l - 1) + (size_t)j0 * lv[l - 1].n, tv<T>(l) + (size_t)j0 * n,
+                     std::min(W.cap, nr - j0));
     if (N > Np) {
       DD_REQUIRE(tv_extra != nullptr, "extra test vectors needed for a level with more test vectors");
       long long off = 0;
@@ -540,11 +724,12 @@ template <typename T> void Hierarchy::initial_setup(int l) {
     }
   }
   for (int eta = 1; eta <= 3; ++eta)
-    for (int j = 0; j < N; ++j) {
-      C<T>* v = tv<T>(l) + (size_t)j * n;
-      vzero<T>(W.x.p, n, s);
-      sap<T>(l, v, W.x.p, eta);
-      vcopy<T, T>(W.x.p, v, n, s);
+    for (int j0 = 0; j0 < N; j0 += W.cap) {
+      const int nb = std::min(W.cap, N - j0);
+      C<T>* v = tv<T>(l) + (size_t)j0 * n;
+      vzero<T>(W.x.p, n * nb, s);
+      sap<T>(l, v, W.x.p, eta, nb);
+      vcopy<T, T>(W.x.p, v, n * nb, s);
     }
   build_level(l, std::is_same<T, float>::value);
   if (l < L - 2) initial_setup<T>(l + 1);
@@ -553,22 +738,28 @@ template <typename T> void Hierarchy::initial_setup(int l) {
 template <typename T> void Hierarchy::iterative_setup(int l, int i) {
   if (l >= L - 1) return;
   const int N = lv[l].N;
-  for (int j = 0; j < N; ++j) {
+  const int cap = work<T>(l).cap;
+  for (int j0 = 0; j0 < N; j0 += cap) {
+    const int nb = std::min(cap, N - j0);
     recording = true;
-    cycle<T>(l, tv<T>(l) + (size_t)j * lv[l].n, work<T>(l).rec.p);
+    visit.assign(nb, 1);
+    cycle<T>(l, tv<T>(l) + (size_t)j0 * lv[l].n, work<T>(l).rec.p, nb);
     recording = false;
+    visit.clear();
     for (int k = l; k < L - 1; ++k) {
-      if (j >= lv[k].N) continue;
+      // test vectors j0 .. j0+cnt-1 of level k are replaced
+      const int cnt = std::min(nb, lv[k].N - j0);
+      if (cnt <= 0) continue;
       const long long nk = lv[k].n;
       C<T>* src = work<T>(k).rec.p;
-      red->dots<T>(src, 0, 0, src, nk, true, s);
-      cd rr;
-      red->fetch(1, &rr, s);
-      const double nrm = std::sqrt(rr.real());
-      DD_REQUIRE(nrm > 0 && std::isfinite(nrm), "setup produced a zero or non-finite test vector");
-      C<T>* dst = tv<T>(k) + (size_t)j * nk;
-      vcopy<T, T>(src, dst, nk, s);
-      vscale<T>(make_double2(1.0 / nrm, 0), dst, nk, s);
+      std::vector<double> nrm;
+      bnorms<T>(*red, src, nk, cnt, nrm, s);
+      std::vector<double> scale(cnt);
+      for (int r = 0; r < cnt; ++r) {
+        DD_REQUIRE(nrm[r] > 0 && std::isfinite(nrm[r]), "setup produced a zero or non-finite test vector");
+        scale[r] = 1.0 / nrm[r];
+      }
+      bscale_host<T>(*red, scale, src, tv<T>(k) + (size_t)j0 * nk, nk, cnt, s);
     }
   }
   for (int k = l; k < L - 1; ++k) build_level(k, std::is_same<T, float>::value);
@@ -597,6 +788,7 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
              "bad coarsest GMRES restart");
   DD_REQUIRE(p.tol > 0 && p.kc_tol > 0 && p.coarse_eps > 0, "tolerances must be positive");
   DD_REQUIRE(p.max_restarts >= 1, "max_restarts must be >= 1");
+  DD_REQUIRE(p.batch >= 1 && p.batch <= NBMAX, "batch must be 1..32");
   int dims[4] = {ctx.g.dims[0], ctx.g.dims[1], ctx.g.dims[2], ctx.g.dims[3]};
   for (int mu = 0; mu < 4; ++mu)
     DD_REQUIRE(p.sap_block[mu] >= 1, "bad SAP block");
@@ -668,23 +860,6 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.K64.alloc((size_t)S.V * 9 * d * d);
       if (!H->half) S.K32.alloc((size_t)S.V * 9 * d * d);
       if (H->half) S.K16.alloc((size_t)S.V * 9 * d * d);
-      if (l < L - 1) {
-        const size_t nv = (size_t)S.V * d;
-        S.sr64.alloc(2 * nv);
-        S.sq64.alloc(2 * nv);
-        S.sr32.alloc(2 * nv);
-        S.sq32.alloc(2 * nv);
-        S.sp64.alloc(2 * (size_t)S.V * 4);
-        S.sp32.alloc(2 * (size_t)S.V * 4);
-        for (int k = 0; k < 2; ++k) {
-          S.ss64.rho[k] = S.sr64.p + k * nv;
-          S.ss64.q[k] = S.sq64.p + k * nv;
-          S.ss64.part[k] = S.sp64.p + k * (size_t)S.V * 4;
-          S.ss32.rho[k] = S.sr32.p + k * nv;
-          S.ss32.q[k] = S.sq32.p + k * nv;
-          S.ss32.part[k] = S.sp32.p + k * (size_t)S.V * 4;
-        }
-      }
       if (l == L - 1 && S.cg.bipartite) {
         S.Einv64.alloc(S.cg.even.size() * (size_t)d * d);
         S.Einv32.alloc(S.cg.even.size() * (size_t)d * d);
@@ -704,19 +879,15 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       d = 2 * S.N;
     }
   }
-  const long long n0 = H->lv[0].n;
-  H->oV.alloc((size_t)(p.nkv + 1) * n0);
-  H->ow.alloc(n0);
-  H->ob.alloc(n0);
-  H->ox.alloc(n0);
+  // setup batches: the test vectors of a level, at most `batch` at once
+  int cap = 1;
+  for (int l = 0; l < L - 1; ++l) cap = std::max(cap, p.ntv[l]);
+  cap = std::min(cap, p.batch);
   if (p.precond_prec == DDAMG_F32) {
-    H->alloc_work<float>();
-    H->oZ32.alloc((size_t)p.nkv * n0);
-    H->ot.alloc(n0);
+    H->ensure_work<float>(cap);
     H->setup<float>(tvc);
   } else {
-    H->alloc_work<double>();
-    H->oZ64.alloc((size_t)p.nkv * n0);
+    H->ensure_work<double>(cap);
     H->setup<double>(tvc);
   }
   H->tv_extra = nullptr;
@@ -724,21 +895,25 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
 }
 
 // explicit instantiations used by the C ABI
-template void Hierarchy::apply<double>(int, const C<double>*, C<double>*);
-template void Hierarchy::apply<float>(int, const C<float>*, C<float>*);
-template void Hierarchy::sap<double>(int, const C<double>*, C<double>*, int);
-template void Hierarchy::sap<float>(int, const C<float>*, C<float>*, int);
-template void Hierarchy::restrict_to<double>(int, const C<double>*, C<double>*);
-template void Hierarchy::restrict_to<float>(int, const C<float>*, C<float>*);
-template void Hierarchy::prolong_add<double>(int, const C<double>*, C<double>*);
-template void Hierarchy::prolong_add<float>(int, const C<float>*, C<float>*);
-template void Hierarchy::cycle<double>(int, const C<double>*, C<double>*);
-template void Hierarchy::cycle<float>(int, const C<float>*, C<float>*);
-template int Hierarchy::outer<double>(const double2*, double2*, ddamg_solve_stats*);
-template int Hierarchy::outer<float>(const double2*, double2*, ddamg_solve_stats*);
+template void Hierarchy::apply<double>(int, const C<double>*, C<double>*, int);
+template void Hierarchy::apply<float>(int, const C<float>*, C<float>*, int);
+template void Hierarchy::sap<double>(int, const C<double>*, C<double>*, int, int);
+template void Hierarchy::sap<float>(int, const C<float>*, C<float>*, int, int);
+template void Hierarchy::restrict_to<double>(int, const C<double>*, C<double>*, int);
+template void Hierarchy::restrict_to<float>(int, const C<float>*, C<float>*, int);
+template void Hierarchy::prolong_add<double>(int, const C<double>*, C<double>*, int);
+template void Hierarchy::prolong_add<float>(int, const C<float>*, C<float>*, int);
+template void Hierarchy::cycle<double>(int, const C<double>*, C<double>*, int);
+template void Hierarchy::cycle<float>(int, const C<float>*, C<float>*, int);
+template void Hierarchy::outer<double>(const double2*, double2*, ddamg_solve_stats*, int);
+template void Hierarchy::outer<float>(const double2*, double2*, ddamg_solve_stats*, int);
+template void Hierarchy::ensure_batch<double>(int);
+template void Hierarchy::ensure_batch<float>(int);
+template void Hierarchy::ensure_work<double>(int);
+template void Hierarchy::ensure_work<float>(int);
 template void Hierarchy::setup<double>(const double2*);
 template void Hierarchy::setup<float>(const double2*);
-template void Hierarchy::alloc_work<double>();
-template void Hierarchy::alloc_work<float>();
+template void Hierarchy::alloc_work<double>(int);
+template void Hierarchy::alloc_work<float>(int);
 
 }  // namespace ddamg

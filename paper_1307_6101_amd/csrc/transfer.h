@@ -34,20 +34,21 @@ struct AggDev {
   int* member_agg = nullptr;
 };
 
-// restriction out = P^H in and prolongation out += P in
+// restriction out = P^H in and prolongation out += P in for nb right-hand
+// sides (fields of the batch contiguous, each of the length of its level)
 // (P stored as S: C<T>, or __half2 with T = float)
 template <typename T, typename S>
 void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
-                   const C<T>* in, C<T>* out, hipStream_t s);
+                   const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 template <typename T, typename S>
-void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const S* P, const C<T>* in,
-                  C<T>* out, hipStream_t s);
+void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
+                  const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 template <typename T, typename S>
 void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                     const S* P, const C<T>* in, C<T>* out, hipStream_t s);
+                     const S* P, const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 template <typename T, typename S>
-void prolong_coarse(const AggDev& ad, int d, int N, long long V, const S* P, const C<T>* in,
-                    C<T>* out, hipStream_t s);
+void prolong_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V, const S* P,
+                    const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 
 // orthonormalise the N test-vector fields tv (FP64, layout of level l) per
 // (aggregate, chirality) in index order (Gram-Schmidt with one

@@ -97,131 +97,189 @@ __device__ inline C<T> collect(const T* red, int N, int sigma, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// restriction / prolongation, fine level
+// restriction / prolongation, fine level.  RB right-hand sides per thread:
+// each column of P is loaded once and applied to all of them.  Fine fields
+// of the batch are fstride apart, coarse fields cstride apart.
 // ---------------------------------------------------------------------------
-template <typename T, typename S>
-__global__ void k_restrict_fine(const int* __restrict__ members, int nbpa, int N, long long fstride,
+template <typename T, typename S, int RB>
+__global__ void __launch_bounds__(256) k_restrict_fine(const int* __restrict__ members, int nbpa, int N, long long fstride,
                                 const S* __restrict__ P, const C<T>* __restrict__ in,
-                                C<T>* __restrict__ out) {
+                                C<T>* __restrict__ out, long long cstride) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);
   const int A = blockIdx.x, t = threadIdx.x;
   const int blk = members[A * nbpa + (t >> 4)], loc = t & 15;
-  C<T> v[12];
-  load_spinor<T>(in, blk, loc, v);
+  in += (long long)blockIdx.y * RB * fstride;
+  out += (long long)blockIdx.y * RB * cstride;
+  C<T> v[RB][12];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) load_spinor<T>(in + r * fstride, blk, loc, v[r]);
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
     load_spinor<T, S>(P + k * fstride, blk, loc, w);
-    C<T> s0 = czero<T>(), s1 = czero<T>();
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      cjfma(s0, w[c], v[c]);
-      cjfma(s1, w[6 + c], v[6 + c]);
+    for (int r = 0; r < RB; ++r) {
+      C<T> s0 = czero<T>(), s1 = czero<T>();
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cjfma(s0, w[c], v[r][c]);
+        cjfma(s1, w[6 + c], v[r][6 + c]);
+      }
+      stash4<T>(red, RB * N, r * N + k, s0.x, s0.y, s1.x, s1.y);
     }
-    stash4<T>(red, N, k, s0.x, s0.y, s1.x, s1.y);
   }
   __syncthreads();
-  if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
+  for (int e = t; e < RB * 2 * N; e += blockDim.x) {
+    const int r = e / (2 * N), q = e % (2 * N);
+    out[r * cstride + (long long)A * 2 * N + q] = collect<T>(red, RB * N, q / N, r * N + q % N);
+  }
 }
 
 template <typename T, typename S>
 void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
-                   const C<T>* in, C<T>* out, hipStream_t s) {
-  const size_t sm = (size_t)((a.asz + 63) / 64) * N * 4 * sizeof(T);
-  k_restrict_fine<T, S><<<a.nagg, a.asz, sm, s>>>(ad.members, a.asz / 16, N, (long long)g.nblk * 192,
-                                               P, in, out);
+                   const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    const size_t sm = (size_t)((a.asz + 63) / 64) * RB * N * 4 * sizeof(T);
+    k_restrict_fine<T, S, RB><<<dim3(a.nagg, nch), a.asz, sm, s>>>(ad.members, a.asz / 16, N, fs, P,
+                                                                   in + first * fs, out + first * cs, cs);
+  });
   DD_LAUNCH_CHECK();
 }
 
-template <typename T, typename S>
-__global__ void k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N, long long fstride,
+template <typename T, typename S, int RB>
+__global__ void __launch_bounds__(256) k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N, long long fstride,
                                const S* __restrict__ P, const C<T>* __restrict__ in,
-                               C<T>* __restrict__ out) {
+                               C<T>* __restrict__ out, long long cstride) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= nblk) return;
+  in += (long long)blockIdx.y * RB * cstride;
+  out += (long long)blockIdx.y * RB * fstride;
   const int A = blk_agg[blk];
-  const C<T>* phi = in + (long long)A * 2 * N;
-  C<T> acc[12];
-  load_spinor<T>(out, blk, loc, acc);
+  C<T> acc[RB][12];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) load_spinor<T>(out + r * fstride, blk, loc, acc[r]);
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
     load_spinor<T, S>(P + k * fstride, blk, loc, w);
-    const C<T> p0 = phi[k], p1 = phi[N + k];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      cfma(acc[c], w[c], p0);
-      cfma(acc[6 + c], w[6 + c], p1);
+    for (int r = 0; r < RB; ++r) {
+      const C<T>* phi = in + r * cstride + (long long)A * 2 * N;
+      const C<T> p0 = phi[k], p1 = phi[N + k];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cfma(acc[r][c], w[c], p0);
+        cfma(acc[r][6 + c], w[6 + c], p1);
+      }
     }
   }
-  C<T>* o = out + (long long)blk * 192 + loc;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) o[c * 16] = acc[c];
+  for (int r = 0; r < RB; ++r) {
+    C<T>* o = out + r * fstride + (long long)blk * 192 + loc;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c * 16] = acc[r][c];
+  }
 }
 
 template <typename T, typename S>
-void prolong_fine(const FineGeom& g, const AggDev& ad, int N, const S* P, const C<T>* in,
-                  C<T>* out, hipStream_t s) {
-  k_prolong_fine<T, S><<<nblocks((size_t)g.nblk * 16, 256), 256, 0, s>>>(
-      ad.member_agg, g.nblk, N, (long long)g.nblk * 192, P, in, out);
+void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
+                  const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    k_prolong_fine<T, S, RB><<<dim3(nblocks((size_t)g.nblk * 16, 256), nch), 256, 0, s>>>(
+        ad.member_agg, g.nblk, N, fs, P, in + first * cs, out + first * fs, cs);
+  });
   DD_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
 // restriction / prolongation, coarse level (d components per site)
 // ---------------------------------------------------------------------------
-template <typename T, typename S>
+template <typename T, typename S, int RB>
 __global__ void k_restrict_coarse(const int* __restrict__ members, int asz, int d, int N,
                                   long long fstride, const S* __restrict__ P,
-                                  const C<T>* __restrict__ in, C<T>* __restrict__ out) {
+                                  const C<T>* __restrict__ in, C<T>* __restrict__ out, long long cstride) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);
   const int A = blockIdx.x, t = threadIdx.x;
+  in += (long long)blockIdx.y * RB * fstride;
+  out += (long long)blockIdx.y * RB * cstride;
   const bool valid = t < asz * d;
   const int sl = valid ? t / d : 0, i = valid ? t % d : 0;
   const int site = members[A * asz + sl];
   const long long e = (long long)site * d + i;
-  const C<T> v = valid ? in[e] : czero<T>();
+  C<T> v[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) v[r] = valid ? in[r * fstride + e] : czero<T>();
   const bool up = i < d / 2;
   for (int k = 0; k < N; ++k) {
-    C<T> p = czero<T>();
-    if (valid) cjfma(p, ldc<T, S>(P[k * fstride + e]), v);
-    stash4<T>(red, N, k, up ? p.x : T(0), up ? p.y : T(0), up ? T(0) : p.x, up ? T(0) : p.y);
+    const C<T> pk = valid ? ldc<T, S>(P[k * fstride + e]) : czero<T>();
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      C<T> p = czero<T>();
+      cjfma(p, pk, v[r]);
+      stash4<T>(red, RB * N, r * N + k, up ? p.x : T(0), up ? p.y : T(0), up ? T(0) : p.x,
+                up ? T(0) : p.y);
+    }
   }
   __syncthreads();
-  if (t < 2 * N) out[(long long)A * 2 * N + t] = collect<T>(red, N, t / N, t % N);
+  for (int q2 = t; q2 < RB * 2 * N; q2 += blockDim.x) {
+    const int r = q2 / (2 * N), q = q2 % (2 * N);
+    out[r * cstride + (long long)A * 2 * N + q] = collect<T>(red, RB * N, q / N, r * N + q % N);
+  }
 }
 
 template <typename T, typename S>
 void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                     const S* P, const C<T>* in, C<T>* out, hipStream_t s) {
+                     const S* P, const C<T>* in, C<T>* out, hipStream_t s, int nb) {
   const int rows = a.asz * d;
   DD_REQUIRE(rows <= 1024, "coarse aggregate too large for one workgroup");
   const int wg = 64 * ((rows + 63) / 64);
-  const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(T);
-  k_restrict_coarse<T, S><<<a.nagg, wg, sm, s>>>(ad.members, a.asz, d, N, V * d, P, in, out);
+  const long long fs = V * d, cs = (long long)a.nagg * 2 * N;
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    const size_t sm = (size_t)(wg / 64) * RB * N * 4 * sizeof(T);
+    k_restrict_coarse<T, S, RB><<<dim3(a.nagg, nch), wg, sm, s>>>(ad.members, a.asz, d, N, fs, P,
+                                                                  in + first * fs, out + first * cs, cs);
+  });
   DD_LAUNCH_CHECK();
 }
 
-template <typename T, typename S>
+template <typename T, typename S, int RB>
 __global__ void k_prolong_coarse(const int* __restrict__ site_agg, long long V, int d, int N,
                                  long long fstride, const S* __restrict__ P,
-                                 const C<T>* __restrict__ in, C<T>* __restrict__ out) {
+                                 const C<T>* __restrict__ in, C<T>* __restrict__ out, long long cstride) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= V * d) return;
+  in += (long long)blockIdx.y * RB * cstride;
+  out += (long long)blockIdx.y * RB * fstride;
   const int site = (int)(e / d), i = (int)(e % d);
   const int sigma = i < d / 2 ? 0 : 1;
-  const C<T>* phi = in + (long long)site_agg[site] * 2 * N + sigma * N;
-  C<T> acc = out[e];
-  for (int k = 0; k < N; ++k) cfma(acc, ldc<T, S>(P[k * fstride + e]), phi[k]);
-  out[e] = acc;
+  const long long po = (long long)site_agg[site] * 2 * N + sigma * N;
+  C<T> acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = out[r * fstride + e];
+  for (int k = 0; k < N; ++k) {
+    const C<T> pk = ldc<T, S>(P[k * fstride + e]);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) cfma(acc[r], pk, in[r * cstride + po + k]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) out[r * fstride + e] = acc[r];
 }
 
 template <typename T, typename S>
-void prolong_coarse(const AggDev& ad, int d, int N, long long V, const S* P, const C<T>* in,
-                    C<T>* out, hipStream_t s) {
-  k_prolong_coarse<T, S><<<nblocks((size_t)V * d, 256), 256, 0, s>>>(ad.member_agg, V, d, N, V * d, P,
-                                                                  in, out);
+void prolong_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V, const S* P,
+                    const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  const long long fs = V * d, cs = (long long)a.nagg * 2 * N;
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    k_prolong_coarse<T, S, RB><<<dim3(nblocks((size_t)V * d, 256), nch), 256, 0, s>>>(
+        ad.member_agg, V, d, N, fs, P, in + first * cs, out + first * fs, cs);
+  });
   DD_LAUNCH_CHECK();
 }
 
@@ -559,15 +617,15 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   DD_LAUNCH_CHECK();
 }
 
-#define DD_INST(T, S)                                                                              \
-  template void restrict_fine<T, S>(const FineGeom&, const AggTables&, const AggDev&, int, const S*, \
-                                    const C<T>*, C<T>*, hipStream_t);                            \
-  template void prolong_fine<T, S>(const FineGeom&, const AggDev&, int, const S*, const C<T>*,      \
-                                   C<T>*, hipStream_t);                                          \
-  template void restrict_coarse<T, S>(const AggTables&, const AggDev&, int, int, long long,        \
-                                      const S*, const C<T>*, C<T>*, hipStream_t);                \
-  template void prolong_coarse<T, S>(const AggDev&, int, int, long long, const S*, const C<T>*,    \
-                                     C<T>*, hipStream_t);
+#define DD_INST(T, S)                                                                               \
+  template void restrict_fine<T, S>(const FineGeom&, const AggTables&, const AggDev&, int, const S*,  \
+                                    const C<T>*, C<T>*, hipStream_t, int);                        \
+  template void prolong_fine<T, S>(const FineGeom&, const AggTables&, const AggDev&, int, const S*,   \
+                                   const C<T>*, C<T>*, hipStream_t, int);                         \
+  template void restrict_coarse<T, S>(const AggTables&, const AggDev&, int, int, long long,         \
+                                      const S*, const C<T>*, C<T>*, hipStream_t, int);            \
+  template void prolong_coarse<T, S>(const AggTables&, const AggDev&, int, int, long long, const S*, \
+                                     const C<T>*, C<T>*, hipStream_t, int);
 DD_INST(double, double2)
 DD_INST(float, float2)
 DD_INST(float, __half2)

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("precond_prec", ctypes.c_int),
         ("cycle", ctypes.c_int),
         ("half_storage", ctypes.c_int),
+        ("batch", ctypes.c_int),
     ]
 
 

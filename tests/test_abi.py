@@ -49,7 +49,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
          offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
   printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
-  printf("%zu\n", offsetof(ddamg_params, half_storage));
+  printf("%zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch));
   return 0;
 }
 ''')
@@ -68,6 +68,7 @@ int main(void) {
     assert vals[7] == dd.SolveStats.true_relres.offset
     assert vals[8] == dd.SolveStats.seconds.offset
     assert vals[9] == dd.Params.half_storage.offset
+    assert vals[10] == dd.Params.batch.offset
 
 
 def test_params_default_is_table1(dd):
@@ -80,7 +81,7 @@ def test_params_default_is_table1(dd):
     assert (p.kc_len, p.kc_restarts, p.nkv) == (5, 2, 10)
     assert p.coarse_eps == 5e-2 and p.kc_tol == 1e-1 and p.tol == 1e-10
     assert p.precond_prec == dd.F32 and p.cycle == dd.KCYCLE
-    assert p.half_storage == 0
+    assert p.half_storage == 0 and p.batch == 16
 
 
 def test_host_validation_rejects_bad_lattice(dd):

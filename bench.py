@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched point-source solve")
     ap.add_argument("--no-half", action="store_true",
                     help="skip the FP16-operator-storage variant of the mixed solve")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -162,6 +163,43 @@ def main():
         log(f"[bench] plain FP64 solve {t_plain:.3f}s, {pst[-1]['outer_iters']} its")
         diff = torch.linalg.vector_norm(z - z_mixed) / torch.linalg.vector_norm(z)
         plain["rel_diff_vs_mixed_solution"] = float(diff)
+
+    # the 12 spin-colour point sources on the same lattice: one batch through
+    # the mixed-precision solver, against the plain FP64 method solving them
+    # one at a time
+    batched = None
+    if not args.no_batch:
+        bps = torch.from_numpy(W.point_sources(dims)).to(dev)
+        zps = torch.zeros_like(bps)
+
+        def batch_solve(H, nb):
+            zps.zero_()
+            torch.cuda.synchronize()
+            t = time.time()
+            rc, st = dd.solve(H, bps, zps, nrhs=nb)
+            torch.cuda.synchronize()
+            if rc != dd.OK:
+                raise RuntimeError(f"batched solve failed rc={rc}")
+            return time.time() - t, st
+
+        batch_solve(H32, BATCH_RHS)
+        t_b, st_b = batch_solve(H32, BATCH_RHS)
+        log(f"[bench] 12 point sources, one mixed batch: {t_b:.3f}s "
+            f"({1000 * t_b / BATCH_RHS:.2f} ms per rhs), its {[x['outer_iters'] for x in st_b]}")
+        batched = dict(rhs=BATCH_RHS, sources="12 spin-colour point sources at x = 0",
+                       mixed_batch_s=round(t_b, 4), mixed_per_rhs_s=round(t_b / BATCH_RHS, 5),
+                       outer_iters=[x["outer_iters"] for x in st_b],
+                       max_true_relres=max(x["true_relres"] for x in st_b))
+        if not args.no_plain:
+            p1 = params(dd.F64)
+            p1.batch = 1
+            H64b = dd.build_hierarchy(ctx, p1, tvd)
+            t_p, st_p = batch_solve(H64b, BATCH_RHS)
+            log(f"[bench] 12 point sources, plain FP64 one at a time: {t_p:.3f}s")
+            batched.update(plain_fp64_one_at_a_time_s=round(t_p, 4),
+                           speedup_vs_plain_fp64=round(t_p / t_b, 3))
+            del H64b
+    if not args.no_plain:
         del H64
 
     # the mixed solve with the preconditioner's operator data stored in FP16
@@ -298,6 +336,7 @@ def main():
         "coarsest_iters": stats[-1]["coarsest_iters"],
         "plain_fp64": plain,
         "fp16_storage": half,
+        "batched_point_sources": batched,
         "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
         "kernels": {k: dict({"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)},
                             **({"TFLOP/s": round(v["tflops"], 2), "mfma_frac": round(v["mfma_frac"], 4)}

@@ -37,20 +37,32 @@ void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>
                     double scale, C<T>* dst, hipStream_t s);
 
 // Batches: nb systems advance together; field r of a batched vector w sits
-// at w + r*n, basis vector j of system r at V + j*vstride + r*n.  Per-system
-// coefficients live on the device as [nb][KMAX] double2 (see
-// Reducer::upload).
+// at w + r*n, basis vector j of system r at V + j*vstride + r*n.
 constexpr int NBMAX = 32;  // largest batch of the batched vector kernels
+constexpr int NBINL = 4;   // batches up to this size pass their coefficients by value
+
+// Per-system coefficients c[r][j] (r < nb, j < KMAX) and scales sc[r] of a
+// batched call: in the kernel arguments for small batches, else in a
+// device slot filled by Reducer::upload.
+struct BArg {
+  const double2* c = nullptr;
+  const double* sc = nullptr;
+  int inl = 0;
+  double2 ic[NBINL * KMAX];
+  double isc[NBINL];
+  __device__ double2 coef(int r, int j) const { return inl ? ic[r * KMAX + j] : c[(size_t)r * KMAX + j]; }
+  __device__ double scale(int r) const { return inl ? isc[r] : sc[r]; }
+};
 
 // y_r += sum_j c[r][j] Z_{j,r} (j < k), then, if dst != nullptr,
-// dst_r = scale[r] * y_r (dst_r = 0 where scale[r] == 0)
+// dst_r = sc[r] * y_r (dst_r = 0 where sc[r] == 0)
 template <typename T, typename TZ>
-void blincomb(const double2* c, const double* scale, int k, const C<TZ>* Z, long long zstride, C<T>* y,
-              long long n, int nb, C<T>* dst, hipStream_t s);
+void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, long long n, int nb, C<T>* dst,
+              hipStream_t s);
 
-// dst_r = scale[r] * src_r (zero where scale[r] == 0); src may equal dst
+// dst_r = sc[r] * src_r (zero where sc[r] == 0); src may equal dst
 template <typename T>
-void bscale(const double* scale, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s);
+void bscale(const BArg& a, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s);
 
 // Fused inner products <V_j, w> (j < k) and <w, w> (entry k), accumulated in
 // FP64 in a fixed order; fetch() copies them to the host.  The batched forms
@@ -69,24 +81,24 @@ class Reducer {
   // copy the last results to the host (synchronises the stream)
   void fetch(int count, std::complex<double>* out, hipStream_t s);
 
-  // batched: c == nullptr for plain inner products, else the update first
+  // batched: a == nullptr for plain inner products, else the update
+  // w_r += sum_j c[r][j] V_{j,r} first
   template <typename T>
-  void bdots(const double2* c, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
+  void bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
              hipStream_t s);
   // results of the last batched call, out[r * (k+1) + j] (synchronises)
   void bfetch(int k1, int nb, std::complex<double>* out, hipStream_t s);
-  // stage nb x KMAX coefficients (row r: system r) and nb scales on the
-  // device; the returned pointers stay valid for the next 63 uploads
-  const double2* upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
-                        const double** scale_dev, hipStream_t s);
-
+  // the coefficients (row r: system r, KMAX per row; missing entries 0) and
+  // scales of a batched call; device slots stay valid for the next 63 calls
+  BArg upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
+              hipStream_t s);
  private:
   template <typename T>
   void launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd, const Coefs* c,
               hipStream_t s);
   double* partial_ = nullptr;   // [NBMAX][GMAX][2*(KMAX+1)]
-  double2* result_ = nullptr;   // [NBMAX][KMAX+1]
-  double2* host_ = nullptr;     // pinned
+  double2* result_ = nullptr;   // [NBMAX][KMAX+1], device alias of host_
+  double2* host_ = nullptr;     // coherent pinned host memory
   // coefficient ring: pinned staging and device slots, an event per slot
   static constexpr int NSLOT = 64;
   unsigned char* cstage_ = nullptr;

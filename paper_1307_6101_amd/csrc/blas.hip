@@ -211,19 +211,17 @@ void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>
 // batched kernels (blockIdx.y = system of the batch)
 // ---------------------------------------------------------------------------
 template <typename T, typename TZ>
-__global__ void k_blincomb(const double2* __restrict__ c, const double* __restrict__ scale, int k,
-                           const C<TZ>* __restrict__ Z, long long zstride, C<T>* __restrict__ y, long long n,
-                           C<T>* __restrict__ dst) {
+__global__ void k_blincomb(const BArg a, int k, const C<TZ>* __restrict__ Z, long long zstride,
+                           C<T>* __restrict__ y, long long n, C<T>* __restrict__ dst) {
   const int r = blockIdx.y;
-  const double2* cr = c + (size_t)r * KMAX;
   Z += (long long)r * n;
   y += (long long)r * n;
-  const double sc = dst ? scale[r] : 0.0;
+  const double sc = dst ? a.scale(r) : 0.0;
   if (dst) dst += (long long)r * n;
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   for (; i < n; i += (long long)gridDim.x * blockDim.x) {
     double2 acc = ccast<double>(y[i]);
-    for (int j = 0; j < k; ++j) cfma(acc, cr[j], ccast<double>(Z[j * zstride + i]));
+    for (int j = 0; j < k; ++j) cfma(acc, a.coef(r, j), ccast<double>(Z[j * zstride + i]));
     const C<T> v = ccast<T>(acc);
     y[i] = v;
     if (dst) dst[i] = sc == 0.0 ? czero<T>() : ccast<T>(cscale(ccast<double>(v), sc));
@@ -231,20 +229,19 @@ __global__ void k_blincomb(const double2* __restrict__ c, const double* __restri
 }
 
 template <typename T, typename TZ>
-void blincomb(const double2* c, const double* scale, int k, const C<TZ>* Z, long long zstride, C<T>* y,
-              long long n, int nb, C<T>* dst, hipStream_t s) {
+void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, long long n, int nb, C<T>* dst,
+              hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
   long long g = (n + 255) / 256;
   if (g > 1024) g = 1024;
-  k_blincomb<T, TZ><<<dim3((unsigned)g, nb), 256, 0, s>>>(c, scale, k, Z, zstride, y, n, dst);
+  k_blincomb<T, TZ><<<dim3((unsigned)g, nb), 256, 0, s>>>(a, k, Z, zstride, y, n, dst);
   DD_LAUNCH_CHECK();
 }
 
 template <typename T>
-__global__ void k_bscale(const double* __restrict__ scale, const C<T>* __restrict__ src, C<T>* __restrict__ dst,
-                         long long n) {
+__global__ void k_bscale(const BArg a, const C<T>* __restrict__ src, C<T>* __restrict__ dst, long long n) {
   const int r = blockIdx.y;
-  const double sc = scale[r];
+  const double sc = a.scale(r);
   src += (long long)r * n;
   dst += (long long)r * n;
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -253,42 +250,42 @@ __global__ void k_bscale(const double* __restrict__ scale, const C<T>* __restric
 }
 
 template <typename T>
-void bscale(const double* scale, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s) {
+void bscale(const BArg& a, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s) {
   DD_REQUIRE(nb >= 1 && nb <= NBMAX, "batch too large");
   long long g = (n + 255) / 256;
   if (g > 1024) g = 1024;
-  k_bscale<T><<<dim3((unsigned)g, nb), 256, 0, s>>>(scale, src, dst, n);
+  k_bscale<T><<<dim3((unsigned)g, nb), 256, 0, s>>>(a, src, dst, n);
   DD_LAUNCH_CHECK();
 }
 
 template <typename T, int KK>
-__global__ void __launch_bounds__(RED_BS) k_bdots_pass1(const double2* __restrict__ c, const C<T>* __restrict__ V,
+__global__ void __launch_bounds__(RED_BS) k_bdots_pass1(const BArg a, int upd, const C<T>* __restrict__ V,
                                                         long long vstride, C<T>* __restrict__ w, long long n,
                                                         double* __restrict__ partial, int g) {
   const int r = blockIdx.y;
   Coefs cc;
-  if (c) {
+  if (upd) {
 #pragma unroll
-    for (int j = 0; j < KK; ++j) cc.c[j] = c[(size_t)r * KMAX + j];
+    for (int j = 0; j < KK; ++j) cc.c[j] = a.coef(r, j);
   }
-  dots_body<T, RED_BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, c != nullptr, cc,
+  dots_body<T, RED_BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, upd != 0, cc,
                            partial + ((long long)r * g + blockIdx.x) * 2 * (KMAX + 1));
 }
 
 template <typename T, int KK>
 struct BDotsLaunch {
-  static void go(int k, unsigned g, int nb, hipStream_t s, const double2* c, const C<T>* V, long long vstride,
-                 C<T>* w, long long n, double* out) {
+  static void go(int k, unsigned g, int nb, hipStream_t s, const BArg& a, int upd, const C<T>* V,
+                 long long vstride, C<T>* w, long long n, double* out) {
     if (k == KK) {
-      k_bdots_pass1<T, KK><<<dim3(g, nb), RED_BS, 0, s>>>(c, V, vstride, w, n, out, (int)g);
+      k_bdots_pass1<T, KK><<<dim3(g, nb), RED_BS, 0, s>>>(a, upd, V, vstride, w, n, out, (int)g);
       return;
     }
-    BDotsLaunch<T, KK + 1>::go(k, g, nb, s, c, V, vstride, w, n, out);
+    BDotsLaunch<T, KK + 1>::go(k, g, nb, s, a, upd, V, vstride, w, n, out);
   }
 };
 template <typename T>
 struct BDotsLaunch<T, KMAX + 1> {
-  static void go(int, unsigned, int, hipStream_t, const double2*, const C<T>*, long long, C<T>*, long long,
+  static void go(int, unsigned, int, hipStream_t, const BArg&, int, const C<T>*, long long, C<T>*, long long,
                  double*) {}
 };
 
@@ -308,14 +305,16 @@ __global__ void __launch_bounds__(256) k_bdots_pass2(const double* __restrict__ 
 }
 
 template <typename T>
-void Reducer::bdots(const double2* c, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
+void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
                     hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched inner products");
   long long g = (n + RED_BS * 4 - 1) / (RED_BS * 4);
   if (g > GMAX) g = GMAX;
   if (g < 1) g = 1;
   double* out = reinterpret_cast<double*>(result_);
-  BDotsLaunch<T, 0>::go(k, (unsigned)g, nb, s, c, V, vstride, w, n, g == 1 ? out : partial_);
+  static const BArg none{};
+  BDotsLaunch<T, 0>::go(k, (unsigned)g, nb, s, a ? *a : none, a ? 1 : 0, V, vstride, w, n,
+                        g == 1 ? out : partial_);
   DD_LAUNCH_CHECK();
   if (g > 1) {
     k_bdots_pass2<<<nb, 256, 0, s>>>(partial_, (int)g, 2 * (k + 1), out);
@@ -324,44 +323,59 @@ void Reducer::bdots(const double2* c, const C<T>* V, long long vstride, int k, C
 }
 
 void Reducer::bfetch(int k1, int nb, std::complex<double>* out, hipStream_t s) {
-  DD_CHECK_HIP(hipMemcpyAsync(host_, result_, sizeof(double2) * (KMAX + 1) * nb, hipMemcpyDeviceToHost, s));
   DD_CHECK_HIP(hipStreamSynchronize(s));
   for (int r = 0; r < nb; ++r)
     for (int j = 0; j < k1; ++j)
       out[r * k1 + j] = std::complex<double>(host_[r * (KMAX + 1) + j].x, host_[r * (KMAX + 1) + j].y);
 }
 
-const double2* Reducer::upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale,
-                               int nb, const double** scale_dev, hipStream_t s) {
+BArg Reducer::upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
+                     hipStream_t s) {
   DD_REQUIRE(nb >= 1 && nb <= NBMAX, "batch too large");
-  const size_t cbytes = sizeof(double2) * KMAX * NBMAX, sbytes = sizeof(double) * NBMAX;
-  const size_t slot = cbytes + sbytes;
+  BArg a;
+  auto cval = [&](int r, int j) {
+    const size_t e = (size_t)r * KMAX + j;
+    return e < c.size() ? make_double2(c[e].real(), c[e].imag()) : make_double2(0, 0);
+  };
+  auto sval = [&](int r) { return (size_t)r < scale.size() ? scale[r] : 0.0; };
+  if (nb <= NBINL) {
+    a.inl = 1;
+    for (int r = 0; r < NBINL; ++r) {
+      for (int j = 0; j < KMAX; ++j) a.ic[r * KMAX + j] = r < nb ? cval(r, j) : make_double2(0, 0);
+      a.isc[r] = r < nb ? sval(r) : 0.0;
+    }
+    return a;
+  }
+  // slot layout: scales [NBMAX] then coefficients [nb][KMAX]; only the used
+  // part is copied
+  const size_t sbytes = sizeof(double) * NBMAX, slot = sbytes + sizeof(double2) * KMAX * NBMAX;
   const int k = cslot_;
   cslot_ = (cslot_ + 1) % NSLOT;
   // the staging slot is free once the copy that last used it has run
   if (cev_used_[k]) DD_CHECK_HIP(hipEventSynchronize(cev_[k]));
   unsigned char* hst = cstage_ + (size_t)k * slot;
   unsigned char* dvc = cdev_ + (size_t)k * slot;
-  double2* hc = reinterpret_cast<double2*>(hst);
-  double* hs = reinterpret_cast<double*>(hst + cbytes);
+  double* hs = reinterpret_cast<double*>(hst);
+  double2* hc = reinterpret_cast<double2*>(hst + sbytes);
   for (int r = 0; r < nb; ++r) {
-    for (int j = 0; j < KMAX; ++j) {
-      const size_t e = (size_t)r * KMAX + j;
-      hc[e] = e < c.size() ? make_double2(c[e].real(), c[e].imag()) : make_double2(0, 0);
-    }
-    hs[r] = (size_t)r < scale.size() ? scale[r] : 0.0;
+    hs[r] = sval(r);
+    for (int j = 0; j < KMAX; ++j) hc[(size_t)r * KMAX + j] = cval(r, j);
   }
-  DD_CHECK_HIP(hipMemcpyAsync(dvc, hst, slot, hipMemcpyHostToDevice, s));
+  DD_CHECK_HIP(hipMemcpyAsync(dvc, hst, sbytes + sizeof(double2) * KMAX * nb, hipMemcpyHostToDevice, s));
   DD_CHECK_HIP(hipEventRecord(cev_[k], s));
   cev_used_[k] = true;
-  if (scale_dev) *scale_dev = reinterpret_cast<const double*>(dvc + cbytes);
-  return reinterpret_cast<const double2*>(dvc);
+  a.sc = reinterpret_cast<const double*>(dvc);
+  a.c = reinterpret_cast<const double2*>(dvc + sbytes);
+  return a;
 }
 
 Reducer::Reducer() {
   DD_CHECK_HIP(hipMalloc(&partial_, sizeof(double) * NBMAX * GMAX * 2 * (KMAX + 1)));
-  DD_CHECK_HIP(hipMalloc(&result_, sizeof(double2) * NBMAX * (KMAX + 1)));
-  DD_CHECK_HIP(hipHostMalloc(&host_, sizeof(double2) * NBMAX * (KMAX + 1), hipHostMallocDefault));
+  // the final sums are written by the kernels straight into coherent pinned
+  // host memory: after the stream synchronisation the host reads them with
+  // no copy in between
+  DD_CHECK_HIP(hipHostMalloc(&host_, sizeof(double2) * NBMAX * (KMAX + 1), hipHostMallocCoherent));
+  DD_CHECK_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&result_), host_, 0));
   const size_t slot = sizeof(double2) * KMAX * NBMAX + sizeof(double) * NBMAX;
   DD_CHECK_HIP(hipHostMalloc(&cstage_, slot * NSLOT, hipHostMallocDefault));
   DD_CHECK_HIP(hipMalloc(&cdev_, slot * NSLOT));
@@ -371,7 +385,6 @@ Reducer::~Reducer() {
   for (int k = 0; k < NSLOT; ++k)
     if (cev_[k]) (void)hipEventDestroy(cev_[k]);
   (void)hipFree(partial_);
-  (void)hipFree(result_);
   (void)hipHostFree(host_);
   (void)hipHostFree(cstage_);
   (void)hipFree(cdev_);
@@ -411,7 +424,6 @@ void Reducer::update_dots(const Coefs& c, const C<T>* V, long long stride, int k
 }
 
 void Reducer::fetch(int count, std::complex<double>* out, hipStream_t s) {
-  DD_CHECK_HIP(hipMemcpyAsync(host_, result_, sizeof(double2) * count, hipMemcpyDeviceToHost, s));
   DD_CHECK_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < count; ++j) out[j] = std::complex<double>(host_[j].x, host_[j].y);
 }
@@ -427,11 +439,11 @@ void Reducer::fetch(int count, std::complex<double>* out, hipStream_t s) {
                                         long long, hipStream_t);                              \
   template void vlincomb_scale<T>(const Coefs&, int, const C<T>*, long long, C<T>*, long long, \
                                   double, C<T>*, hipStream_t);                                 \
-  template void Reducer::bdots<T>(const double2*, const C<T>*, long long, int, C<T>*, long long, int, \
+  template void Reducer::bdots<T>(const BArg*, const C<T>*, long long, int, C<T>*, long long, int, \
                                   hipStream_t);                                                \
-  template void blincomb<T, T>(const double2*, const double*, int, const C<T>*, long long, C<T>*, \
-                               long long, int, C<T>*, hipStream_t);                        \
-  template void bscale<T>(const double*, const C<T>*, C<T>*, long long, int, hipStream_t);
+  template void blincomb<T, T>(const BArg&, int, const C<T>*, long long, C<T>*, long long, int, C<T>*, \
+                               hipStream_t);                                               \
+  template void bscale<T>(const BArg&, const C<T>*, C<T>*, long long, int, hipStream_t);
 DD_INST(double)
 DD_INST(float)
 #undef DD_INST
@@ -445,7 +457,7 @@ template void vlincomb<double, float>(const Coefs&, int, const C<float>*, long l
                                       long long, hipStream_t);
 template void vlincomb<float, float>(const Coefs&, int, const C<float>*, long long, C<float>*,
                                      long long, hipStream_t);
-template void blincomb<double, float>(const double2*, const double*, int, const C<float>*, long long,
-                                      C<double>*, long long, int, C<double>*, hipStream_t);
+template void blincomb<double, float>(const BArg&, int, const C<float>*, long long, C<double>*, long long, int,
+                                      C<double>*, hipStream_t);
 
 }  // namespace ddamg

@@ -366,16 +366,22 @@ __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, cons
     }
 }
 
-// block alpha of step t from the per-site partials of the block's sites
+// block alpha of step t from the per-site partials of the block's sites,
+// summed by one wavefront (lane v takes sites v, v+64, ..) in a fixed order;
+// every lane of the wavefront gets the result
 template <typename T>
-__device__ inline C<T> block_alpha(const T* __restrict__ part, const int* __restrict__ bsites, int bs) {
+__device__ inline C<T> block_alpha_wave(const T* __restrict__ part, const int* __restrict__ bsites, int bs,
+                                        int lane) {
   T s0 = 0, s1 = 0, s2 = 0;
-  for (int v = 0; v < bs; ++v) {
+  for (int v = lane; v < bs; v += 64) {
     const T* p = part + (size_t)bsites[v] * 4;
     s0 += p[0];
     s1 += p[1];
     s2 += p[2];
   }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
   return s2 > T(0) ? mk<T>(s0 / s2, s1 / s2) : czero<T>();
 }
 
@@ -405,8 +411,10 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
   unsigned mask = 1u;   // self and the in-block neighbours
   for (int k = 1; k < 9; ++k)
     if (site_blk[op.nbr9[site * 9 + k]] == blk) mask |= 1u << k;
-  if (step > 0 && threadIdx.x < RB)
-    alpha_s[threadIdx.x] = block_alpha<T>(part_prev + threadIdx.x * pn, blk_sites + (size_t)blk * bs, bs);
+  if (step > 0 && w < RB) {
+    const C<T> a = block_alpha_wave<T>(part_prev + w * pn, blk_sites + (size_t)blk * bs, bs, lane);
+    if (lane == 0) alpha_s[w] = a;
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
     const int r = e / (9 * d), kj = e % (9 * d), k = kj / d, j = kj % d;
@@ -462,7 +470,10 @@ __global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __re
   rho += blockIdx.y * n;
   z += blockIdx.y * n;
   part += blockIdx.y * pn;
-  if (threadIdx.x == 0) alpha_s = block_alpha<T>(part, blk_sites + (size_t)blk * bs, bs);
+  if (threadIdx.x < 64) {
+    const C<T> a = block_alpha_wave<T>(part, blk_sites + (size_t)blk * bs, bs, threadIdx.x);
+    if (threadIdx.x == 0) alpha_s = a;
+  }
   __syncthreads();
   const int i = threadIdx.x;
   if (i < d) {

@@ -191,9 +191,8 @@ static void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector
 template <typename T>
 static void bscale_host(Reducer& red, const std::vector<double>& scale, const C<T>* src, C<T>* dst, long long n,
                         int nb, hipStream_t s) {
-  const double* sd = nullptr;
-  red.upload(std::vector<cd>(), scale, nb, &sd, s);
-  bscale<T>(sd, src, dst, n, nb, s);
+  const BArg a = red.upload(std::vector<cd>(), scale, nb, s);
+  bscale<T>(a, src, dst, n, nb, s);
 }
 
 // Arnoldi step with classical Gram-Schmidt; a second pass for the systems
@@ -229,8 +228,8 @@ void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, i
     }
   }
   if (!any) return;
-  const double2* cdev = red->upload(c1, std::vector<double>(), nb, nullptr, s);
-  red->bdots<T>(cdev, V, vstride, j + 1, w, n, nb, s);
+  const BArg a = red->upload(c1, std::vector<double>(), nb, s);
+  red->bdots<T>(&a, V, vstride, j + 1, w, n, nb, s);
   red->bfetch(k1, nb, h2.data(), s);
   for (int r = 0; r < nb; ++r) {
     if (!again[r]) continue;
@@ -346,9 +345,8 @@ void Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>*
       // w += V c and V_{j+1} = w / hn in one pass (zero for stopped systems)
       if (j + 1 < m) {
         for (int r = 0; r < nb; ++r) scale[r] = live[r] ? 1.0 / hn[r] : 0.0;
-        const double* sd = nullptr;
-        const double2* cdev = red->upload(cf, scale, nb, &sd, s);
-        blincomb<T, T>(cdev, sd, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+        const BArg a = red->upload(cf, scale, nb, s);
+        blincomb<T, T>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
       }
     }
     // x_r += Z_r y_r
@@ -361,8 +359,8 @@ void Hierarchy::fgmres(int l, Op op, Pre pre, bool use_pre, const C<T>* b, C<T>*
       kmax = std::max(kmax, jend[r]);
     }
     if (kmax > 0) {
-      const double2* cdev = red->upload(cy, std::vector<double>(), nb, nullptr, s);
-      blincomb<T, T>(cdev, nullptr, kmax, Z, vs, x, n, nb, nullptr, s);
+      const BArg a = red->upload(cy, std::vector<double>(), nb, s);
+      blincomb<T, T>(a, kmax, Z, vs, x, n, nb, nullptr, s);
     }
     bool more = false;
     for (int r = 0; r < nb; ++r) {
@@ -568,9 +566,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       if (!still) break;
       if (j + 1 < m) {
         for (int r = 0; r < nb; ++r) scale[r] = live[r] ? 1.0 / hn[r] : 0.0;
-        const double* sd = nullptr;
-        const double2* cdev = red->upload(cf, scale, nb, &sd, s);
-        blincomb<double, double>(cdev, sd, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+        const BArg a = red->upload(cf, scale, nb, s);
+        blincomb<double, double>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
       }
     }
     int kmax = 0;
@@ -583,8 +580,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       ++st[r].restarts;
     }
     if (kmax > 0) {
-      const double2* cdev = red->upload(cy, std::vector<double>(), nb, nullptr, s);
-      blincomb<double, T>(cdev, nullptr, kmax, Z, vs, x, n, nb, nullptr, s);
+      const BArg a = red->upload(cy, std::vector<double>(), nb, s);
+      blincomb<double, T>(a, kmax, Z, vs, x, n, nb, nullptr, s);
     }
     // true residuals in FP64
     dslash<double>(D, x, w, s, nb);

@@ -348,84 +348,37 @@ __device__ inline void dslash_site(const FineOpView<T, S>& op, const C<T>* __res
   }
 }
 
-// RB right-hand sides (fields in + r * fs) at once: every link is loaded
-// once and applied to the RB neighbour spinors, which are all loaded before
-// the first product so that their loads are in flight together
-template <typename T, typename S, int MU, int RB>
-__device__ inline void hops_mu_rb(const FineOpView<T, S>& op, const C<T>* __restrict__ in, long long fs,
-                                  int blk, int loc, const Nbr8& nb8, C<T> (&acc)[RB][12]) {
-  constexpr int bit = 1 << MU;
-#pragma unroll
-  for (int dir = 0; dir < 2; ++dir) {
-    const bool fwd = dir == 0;
-    const int nb = fwd ? ((loc & bit) ? nb8.v[2 * MU] : blk) : ((loc & bit) ? blk : nb8.v[2 * MU + 1]);
-    C<T> psi[RB][12], u[9];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) load_spinor<T>(in + r * fs, nb, loc ^ bit, psi[r]);
-    if (fwd) load_link<T, S>(op.U, blk, loc, MU, u);
-    else load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      if (fwd) hop_apply<T, MU, true>(psi[r], u, acc[r]);
-      else hop_apply<T, MU, false>(psi[r], u, acc[r]);
-    }
-  }
-}
-
-template <typename T, typename S, int RB>
+// One site per thread.  A batch of nb fields runs over a one-dimensional
+// grid of gx * nb workgroups with the XCD-aware batch mapping.
+template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_dslash(FineOpView<T, S> op, const C<T>* __restrict__ in,
-                                                C<T>* __restrict__ out, long long fs) {
-  const int tid = xcd_slab_index(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                                C<T>* __restrict__ out, long long fs, int gx, int nb) {
+  int x, r;
+  xcd_slab_rhs(blockIdx.x, gx, nb, x, r);
+  const int tid = x * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= op.nblk) return;
-  in += (long long)blockIdx.y * RB * fs;
-  out += (long long)blockIdx.y * RB * fs;
-  if constexpr (RB == 1) {
-    C<T> o[12];
-    dslash_site<T, S>(op, in, blk, loc, o);
-    C<T>* p = out + (long long)blk * 192 + loc;
+  in += (long long)r * fs;
+  out += (long long)r * fs;
+  C<T> o[12];
+  dslash_site<T, S>(op, in, blk, loc, o);
+  C<T>* p = out + (long long)blk * 192 + loc;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
-  } else {
-    const Nbr8 nb8 = load_nbr8(op.nbr, blk);
-    C<T> acc[RB][12];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[r][c] = czero<T>();
-    hops_mu_rb<T, S, 0, RB>(op, in, fs, blk, loc, nb8, acc);
-    hops_mu_rb<T, S, 1, RB>(op, in, fs, blk, loc, nb8, acc);
-    hops_mu_rb<T, S, 2, RB>(op, in, fs, blk, loc, nb8, acc);
-    hops_mu_rb<T, S, 3, RB>(op, in, fs, blk, loc, nb8, acc);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      C<T> psi[12], o[12];
-      load_spinor<T>(in + r * fs, blk, loc, psi);
-      clover_apply<T, S>(op.A, blk, loc, psi, o);
-      C<T>* p = out + r * fs + (long long)blk * 192 + loc;
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        o[c].x -= T(0.5) * acc[r][c].x;
-        o[c].y -= T(0.5) * acc[r][c].y;
-        p[c * 16] = o[c];
-      }
-    }
-  }
+  for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
 }
 
 template <typename T, typename S>
 void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb) {
   const long long fs = (long long)op.nblk * 192;
   const unsigned gx = nblocks((size_t)op.nblk * 16, 256);
-  rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
-    k_dslash<T, S, decltype(rb)::value><<<dim3(gx, nch), 256, 0, s>>>(op, in + first * fs, out + first * fs, fs);
-  });
+  k_dslash<T, S><<<gx * nb, 256, 0, s>>>(op, in, out, fs, (int)gx, nb);
   DD_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
 // SAP colour pass.  One thread per site, 16 lanes per 2^4 block, 16 blocks
-// per workgroup.  r = b - D z with the full operator, then mr_iters minimal
+// per workgroup; a batch of fields runs one field per workgroup with the
+// XCD-aware batch mapping.  r = b - D z with the full operator, then mr_iters minimal
 // residual steps on the Dirichlet block operator D_i (self term + the four
 // in-block hops, partner spinors exchanged through LDS), z += x.  The block
 // operator of a site (its four in-block links and its clover) is read once
@@ -477,23 +430,24 @@ template <typename T, typename S> struct BlockOp<T, S, false> {
   }
 };
 
-// NBC: the batch size when fixed at compile time (1), else 0 and nb is read
-template <typename T, typename S, int NBC>
+// one workgroup per (chunk of 16 blocks, field of the batch), gx chunks
+template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
                                                     int ncb, int mr_iters, const C<T>* __restrict__ b,
-                                                    C<T>* __restrict__ z, int nb, long long fs) {
-  if constexpr (NBC > 0) nb = NBC;
+                                                    C<T>* __restrict__ z, int nb, long long fs, int gx) {
   __shared__ C<T> rs[12 * 256];
   const int t = threadIdx.x;
-  const int jb = xcd_slab_index(blockIdx.x, gridDim.x) * 16 + (t >> 4);
+  int xw, rw;
+  xcd_slab_rhs(blockIdx.x, gx, nb, xw, rw);
+  b += (long long)rw * fs;
+  z += (long long)rw * fs;
+  const int jb = xw * 16 + (t >> 4);
   const int loc = t & 15;
   const bool valid = jb < ncb;
   const int blk = valid ? cblk[jb] : 0;
   constexpr bool KEEP = !std::is_same<T, double>::value;
   BlockOp<T, S, KEEP> bop;
-  // the right-hand sides one after the other, sharing the block operator
-  // (read after the first residual, which needs the registers)
-  for (int rhs = 0; rhs < nb; ++rhs, b += fs, z += fs) {
+  {
     C<T> rho[12], x[12];
     if (valid) {
       C<T> dz[12], bb[12];
@@ -505,7 +459,8 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
 #pragma unroll
       for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
     }
-    if (rhs == 0) bop.load(op, blk, loc, valid);
+    // the block operator is read after the residual, which needs the registers
+    bop.load(op, blk, loc, valid);
 #pragma unroll
     for (int c = 0; c < 12; ++c) x[c] = czero<T>();
 
@@ -562,12 +517,9 @@ void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour
                 const C<T>* b, C<T>* z, hipStream_t s, int nb) {
   const int ncb = op.nblk / 2;
   const long long fs = (long long)op.nblk * 192;
-  if (nb == 1)
-    k_sap_colour<T, S, 1><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z,
-                                                        nb, fs);
-  else
-    k_sap_colour<T, S, 0><<<nblocks(ncb, 16), 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z,
-                                                        nb, fs);
+  const unsigned gx = nblocks(ncb, 16);
+  k_sap_colour<T, S><<<gx * nb, 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z, nb, fs,
+                                             (int)gx);
   DD_LAUNCH_CHECK();
 }
 

@@ -69,6 +69,21 @@ __device__ inline int xcd_slab_index(int bid, int nwg) {
   if (nwg % 8 != 0) return bid;
   return (bid & 7) * (nwg >> 3) + (bid >> 3);
 }
+// The same for a batch of nb fields over a one-dimensional grid of gx * nb
+// workgroups: each XCD takes one slab of blocks and runs the nb fields of a
+// block chunk back to back, so the operator data of the chunk is fetched
+// into that XCD's L2 once for all of them.  Sets the workgroup's block-chunk
+// index x and field r.
+__device__ inline void xcd_slab_rhs(int bid, int gx, int nb, int& x, int& r) {
+  if (gx % 8 != 0) {
+    x = bid % gx;
+    r = bid / gx;
+    return;
+  }
+  const int k = bid >> 3;
+  x = (bid & 7) * (gx >> 3) + k / nb;
+  r = k % nb;
+}
 
 template <typename T, typename S = C<T>>
 __device__ inline void load_spinor(const S* __restrict__ f, int blk, int loc, C<T> v[12]) {

@@ -31,7 +31,7 @@ BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-
 # HBM traffic per launch of the FP32 stencil on the bench lattice, from the
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in
 # profiles/dslash_clover16x32_counters.md (null once the kernel changes)
-DSLASH_F32_TRAFFIC_BYTES = 139.43e6
+DSLASH_F32_TRAFFIC_BYTES = 139.41e6
 WORKLOAD = "clover16x32_3lvl"
 # compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out

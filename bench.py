@@ -33,6 +33,8 @@ BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-
 # profiles/dslash_clover16x32_counters.md (null once the kernel changes)
 DSLASH_F32_TRAFFIC_BYTES = 139.41e6
 WORKLOAD = "clover16x32_3lvl"
+METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
+BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"
 # compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
 # (24 reals) -> 192 reals
@@ -58,6 +60,9 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD],
+                    help="the bench workload (default) or the 32^3x64 lattice with the 12 point sources "
+                         "solved in one batch")
     ap.add_argument("--lattice", default=None,
                     help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
@@ -85,6 +90,9 @@ def main():
     cfg = W.CONFIGS[WORKLOAD]
     if args.kernels_only:
         kernels_only(args, cfg, dd, W, np, torch)
+        return
+    if args.workload == BATCH_WORKLOAD:
+        batch_workload(args, W.CONFIGS[BATCH_WORKLOAD], dd, W, np, torch)
         return
     dims = cfg["dims"]
     V = int(np.prod(dims))
@@ -313,7 +321,7 @@ def main():
 
     mean_its = float(np.mean([s["outer_iters"] for s in stats]))
     line = {
-        "metric": "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU",
+        "metric": METRIC,
         "value": round(1000.0 / ms, 4),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -343,6 +351,105 @@ def main():
                                if "tflops" in v else {})) for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def batch_workload(args, cfg, dd, W, np, torch):
+    """The 32^3x64 three-level clover lattice with the 12 spin-colour point
+    sources: a step is one solve of all 12 in one batch with the FP32
+    preconditioner on FP16-stored operator data (matrix-core coarse operator
+    over the 12 fields); the plain FP64 method solves sources one at a time
+    for comparison."""
+    dims = cfg["dims"]
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {BATCH_WORKLOAD} dims={dims} V={V}")
+    t0 = time.time()
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    tv = W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s")
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], torch.from_numpy(U).to(dev))
+    del U
+    tvd = torch.from_numpy(tv).to(dev)
+    del tv
+    b = torch.from_numpy(W.point_sources(dims)).to(dev)
+    z = torch.zeros_like(b)
+
+    def params(prec, half, batch):
+        p = dd.params_default(cfg["levels"])
+        for l, a in enumerate(cfg["agg"]):
+            for mu in range(4):
+                p.agg[l][mu] = a[mu]
+        for l, n in enumerate(cfg["ntv"]):
+            p.ntv[l] = n
+        p.nu = cfg["nu"]
+        p.precond_prec = prec
+        p.half_storage = 1 if half else 0
+        p.batch = batch
+        return p
+
+    torch.cuda.synchronize()
+    t = time.time()
+    H = dd.build_hierarchy(ctx, params(dd.F32, True, BATCH_RHS), tvd)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t
+    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
+
+    def solve(Hh, nb, k0=0):
+        z.zero_()
+        torch.cuda.synchronize()
+        t = time.time()
+        rc, st = dd.solve(Hh, b[k0:k0 + nb], z[k0:k0 + nb], nrhs=nb)
+        torch.cuda.synchronize()
+        if rc != dd.OK:
+            raise RuntimeError(f"solve failed rc={rc}")
+        return time.time() - t, st
+
+    for i in range(args.warmup):
+        tw, st = solve(H, BATCH_RHS)
+        log(f"[bench] warmup {i}: {tw:.3f}s")
+    times, stats = [], None
+    for i in range(args.steps):
+        tt, stats = solve(H, BATCH_RHS)
+        times.append(tt)
+        log(f"[bench] step {i}: 12 sources in {tt:.3f}s, its {[x['outer_iters'] for x in stats]}")
+    ms = 1000.0 * float(np.mean(times))
+    plain = None
+    if not args.no_plain:
+        del H
+        torch.cuda.synchronize()
+        t = time.time()
+        H64 = dd.build_hierarchy(ctx, params(dd.F64, False, 1), tvd)
+        torch.cuda.synchronize()
+        t_setup64 = time.time() - t
+        n_plain = 2
+        tp, stp = solve(H64, n_plain)
+        plain = dict(setup_s=round(t_setup64, 3), sources_timed=n_plain,
+                     per_source_s=round(tp / n_plain, 4), outer_iters=[x["outer_iters"] for x in stp])
+        log(f"[bench] plain FP64: setup {t_setup64:.2f}s, {tp / n_plain:.3f}s per source")
+    line = {
+        "metric": METRIC,
+        "value": round(BATCH_RHS / (ms / 1000.0), 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner on f16-stored operators, f64 outer",
+        "data": "synthetic (seeded SU(3) links exp(i eps H), 12 spin-colour point sources)",
+        "config": {"workload": "32^3x64 Wilson-clover, 3 levels (4^4, 2^4 aggregates, N=20), c_sw=1, "
+                               "eps=0.5, m0=-0.42, 12 point sources in one batch, tol 1e-10",
+                   "parallelism": "1 GPU"},
+        "setup_s": round(t_setup, 3),
+        "outer_iters": [x["outer_iters"] for x in stats],
+        "max_true_relres": max(x["true_relres"] for x in stats),
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64_per_source": (round(plain["per_source_s"] / (ms / 1000.0 / BATCH_RHS), 3)
+                                             if plain else None),
     }
     print(json.dumps(line), flush=True)
 

@@ -81,7 +81,7 @@ typedef struct {
   int levels;                 /* L >= 2 */
   int agg[3][4];              /* aggregate (lattice-block) shape, level l -> l+1 */
   int ntv[3];                 /* test vectors N on level l (l < L-1) */
-  int sap_block[4];           /* SAP block shape on every level (2^4) */
+  int sap_block[4];           /* SAP block shape (2^4; the fine level always 2^4) */
   int mu, nu;                 /* pre- / post-smoothing steps (0 / 5) */
   int mr_iters;               /* MR iterations per SAP block solve (3) */
   int n_inv;                  /* iterative setup iterations (6) */
@@ -114,6 +114,12 @@ typedef struct {
                                  vectors of a level in the setup.  Batched
                                  systems share every launch but keep their own
                                  Krylov scalars and stopping tests. */
+  int sap_block_l[3][4];      /* SAP block shape on coarse level l = 1..3 (row
+                                 l-1); a row with a zero entry takes
+                                 sap_block.  Lets a level whose extents give
+                                 an odd count of 2^4 blocks use e.g. 3^4
+                                 blocks (Sec. 2: the blocks of one colour
+                                 must not touch). */
 } ddamg_params;
 
 typedef struct {

@@ -38,10 +38,13 @@ class Hierarchy:
         self.tv = [None] * (self.L - 1)
         self.coarsest = None
         self.cycle_type = cycle
-        self.block = tuple(self.p.get("sap_block", (2, 2, 2, 2)))
+        # SAP block shape per smoothed level (levels 0..L-2); a level whose
+        # 2^4 blocks would come in odd counts takes e.g. 3^4 blocks
+        base = tuple(self.p.get("sap_block", (2, 2, 2, 2)))
+        self.blocks = [tuple(b) for b in self.p.get("sap_blocks", [base] * (self.L - 1))]
         dims = fine_op.dims
         for l in range(self.L - 1):
-            validate_blocks(dims, self.block)
+            validate_blocks(dims, self.blocks[l])
             agg = self.p["agg"][l]
             dims = tuple(d // a for d, a in zip(dims, agg))
         self.counters = {"coarsest_iters": 0, "kcycle_iters": 0}
@@ -49,7 +52,7 @@ class Hierarchy:
     # -- smoothing ---------------------------------------------------------
     def smooth(self, l, b, z, n):
         for _ in range(n):
-            z = sap_sweep(self.ops[l], b, z, self.block, self.p["mr_iters"])
+            z = sap_sweep(self.ops[l], b, z, self.blocks[l], self.p["mr_iters"])
         return z
 
     # -- Alg. 1 / Alg. 2 -----------------------------------------------------

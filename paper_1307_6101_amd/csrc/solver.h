@@ -189,5 +189,6 @@ Context* create_context(const ddamg_lattice* lat, const double2* links, hipStrea
 Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* p, const double2* tv,
                             const double2* tv_extra, hipStream_t s);
 void validate_params(const Context& ctx, const ddamg_params& p);
+void sap_block_of(const ddamg_params& p, int l, int out[4]);
 
 }  // namespace ddamg

@@ -771,6 +771,13 @@ template <typename T> void Hierarchy::setup(const double2* tvc) {
 }
 
 // ---------------------------------------------------------------------------
+// SAP block shape of level l: the per-level row where it is set, else sap_block
+void sap_block_of(const ddamg_params& p, int l, int out[4]) {
+  bool own = l >= 1 && l <= 3;
+  for (int mu = 0; own && mu < 4; ++mu) own = p.sap_block_l[l - 1][mu] > 0;
+  for (int mu = 0; mu < 4; ++mu) out[mu] = own ? p.sap_block_l[l - 1][mu] : p.sap_block[mu];
+}
+
 void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.levels >= 2 && p.levels <= 4, "levels must be 2..4");
   DD_REQUIRE(p.precond_prec == DDAMG_F32 || p.precond_prec == DDAMG_F64, "bad precond_prec");
@@ -789,12 +796,16 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   int dims[4] = {ctx.g.dims[0], ctx.g.dims[1], ctx.g.dims[2], ctx.g.dims[3]};
   for (int mu = 0; mu < 4; ++mu)
     DD_REQUIRE(p.sap_block[mu] >= 1, "bad SAP block");
+  for (int l = 0; l < 3; ++l)
+    for (int mu = 0; mu < 4; ++mu) DD_REQUIRE(p.sap_block_l[l][mu] >= 0, "bad per-level SAP block");
   int d = 12;
   for (int l = 0; l < p.levels - 1; ++l) {
     // SAP validity on level l
+    int blk[4];
+    sap_block_of(p, l, blk);
     for (int mu = 0; mu < 4; ++mu) {
-      if (l == 0) DD_REQUIRE(p.sap_block[mu] == 2, "the fine SAP blocks are 2^4");
-      DD_REQUIRE(dims[mu] % p.sap_block[mu] == 0 && (dims[mu] / p.sap_block[mu]) % 2 == 0,
+      if (l == 0) DD_REQUIRE(blk[mu] == 2, "the fine SAP blocks are 2^4");
+      DD_REQUIRE(dims[mu] % blk[mu] == 0 && (dims[mu] / blk[mu]) % 2 == 0,
                  "SAP blocks must tile level " + std::to_string(l) + " with an even count per direction");
       DD_REQUIRE(p.agg[l][mu] >= 1 && dims[mu] % p.agg[l][mu] == 0,
                  "aggregates must tile level " + std::to_string(l));
@@ -806,10 +817,6 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
                  "fine aggregates must hold 256 sites made of 2^4 blocks (e.g. 4^4)");
     else
       DD_REQUIRE(asz * d <= 1024, "coarse aggregate too large");
-    if (l > 0) {
-      int bs = p.sap_block[0] * p.sap_block[1] * p.sap_block[2] * p.sap_block[3];
-      DD_REQUIRE(bs * d <= 1024, "coarse SAP block too large");
-    }
     DD_REQUIRE(p.ntv[l] >= 1 && p.ntv[l] <= 32, "ntv must be 1..32");
     DD_REQUIRE(p.ntv[l] <= asz * d / 2, "more test vectors than an aggregate's dimension");
     for (int mu = 0; mu < 4; ++mu) dims[mu] /= p.agg[l][mu];
@@ -846,7 +853,7 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
     S.n = S.V * d;
     if (l > 0) {
       int sap[4] = {0, 0, 0, 0};
-      if (l < L - 1) for (int mu = 0; mu < 4; ++mu) sap[mu] = p.sap_block[mu];
+      if (l < L - 1) sap_block_of(p, l, sap);
       S.cg = make_coarse_geom(dims, d, sap);
       S.c_nbr9.upload(S.cg.nbr9, s);
       S.c_blk_sites.upload(S.cg.blk_sites, s);

@@ -54,6 +54,7 @@ class Params(ctypes.Structure):
         ("cycle", ctypes.c_int),
         ("half_storage", ctypes.c_int),
         ("batch", ctypes.c_int),
+        ("sap_block_l", (ctypes.c_int * 4) * 3),
     ]
 
 

@@ -41,6 +41,9 @@ def to_params(dd, p, prec=None, cycle="K", half=False):
         P.ntv[l] = n
     for mu in range(4):
         P.sap_block[mu] = p.get("sap_block", (2, 2, 2, 2))[mu]
+    for l, blk in enumerate(p.get("sap_blocks", [])[1:]):
+        for mu in range(4):
+            P.sap_block_l[l][mu] = blk[mu]
     P.mu, P.nu = p["mu"], p["nu"]
     P.mr_iters = p["mr_iters"]
     P.n_inv = p["n_inv"]

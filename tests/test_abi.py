@@ -49,7 +49,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
          offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
   printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
-  printf("%zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch));
+  printf("%zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
+         offsetof(ddamg_params, sap_block_l));
   return 0;
 }
 ''')
@@ -69,6 +70,7 @@ int main(void) {
     assert vals[8] == dd.SolveStats.seconds.offset
     assert vals[9] == dd.Params.half_storage.offset
     assert vals[10] == dd.Params.batch.offset
+    assert vals[11] == dd.Params.sap_block_l.offset
 
 
 def test_params_default_is_table1(dd):

@@ -35,6 +35,7 @@ DSLASH_F32_TRAFFIC_BYTES = 139.41e6
 WORKLOAD = "clover16x32_3lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
 BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"
+FOUR_LEVEL_WORKLOAD = "clover48x96_4lvl"
 # compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
 # (24 reals) -> 192 reals
@@ -60,9 +61,9 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD],
-                    help="the bench workload (default) or the 32^3x64 lattice with the 12 point sources "
-                         "solved in one batch")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD],
+                    help="the bench workload (default), the 32^3x64 lattice with the 12 point sources "
+                         "solved in one batch, or the 48^3x96 four-level lattice")
     ap.add_argument("--lattice", default=None,
                     help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
@@ -91,8 +92,8 @@ def main():
     if args.kernels_only:
         kernels_only(args, cfg, dd, W, np, torch)
         return
-    if args.workload == BATCH_WORKLOAD:
-        batch_workload(args, W.CONFIGS[BATCH_WORKLOAD], dd, W, np, torch)
+    if args.workload != WORKLOAD:
+        big_workload(args, args.workload, W.CONFIGS[args.workload], dd, W, np, torch)
         return
     dims = cfg["dims"]
     V = int(np.prod(dims))
@@ -355,26 +356,43 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batch_workload(args, cfg, dd, W, np, torch):
-    """The 32^3x64 three-level clover lattice with the 12 spin-colour point
-    sources: a step is one solve of all 12 in one batch with the FP32
-    preconditioner on FP16-stored operator data (matrix-core coarse operator
-    over the 12 fields); the plain FP64 method solves sources one at a time
-    for comparison."""
+def big_workload(args, name, cfg, dd, W, np, torch):
+    """The larger lattices, run on request: a step is one solve with the
+    FP32 preconditioner on FP16-stored operator data.  On the 32^3x64
+    lattice the 12 spin-colour point sources go through in one batch (the
+    coarse operator on the matrix cores); on the 48^3x96 lattice (four
+    levels) one Gaussian right-hand side.  The plain FP64 method solves
+    sources one at a time for comparison (its own hierarchy, built after the
+    first one is freed)."""
     dims = cfg["dims"]
     V = int(np.prod(dims))
     dev = torch.device("cuda:0")
-    log(f"[bench] workload {BATCH_WORKLOAD} dims={dims} V={V}")
+    nsrc = BATCH_RHS if name == BATCH_WORKLOAD else 1
+    log(f"[bench] workload {name} dims={dims} V={V}")
     t0 = time.time()
     U = W.links(dims, cfg["eps"], cfg["seed_links"])
-    tv = W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
-    log(f"[bench] inputs generated in {time.time() - t0:.1f}s")
+    log(f"[bench] links in {time.time() - t0:.1f}s")
     ctx = dd.create(dims, cfg["m0"], cfg["csw"], torch.from_numpy(U).to(dev))
     del U
+    tv = W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
     tvd = torch.from_numpy(tv).to(dev)
     del tv
-    b = torch.from_numpy(W.point_sources(dims)).to(dev)
+    log(f"[bench] test vectors in {time.time() - t0:.1f}s")
+    extra = None
+    if cfg["levels"] == 4 and cfg["ntv"][2] > cfg["ntv"][1]:
+        # fresh random test vectors for the level with more of them (level 2)
+        d2 = 2 * cfg["ntv"][1]
+        cd2 = tuple(x // (a1 * a2) for x, a1, a2 in zip(dims, cfg["agg"][0], cfg["agg"][1]))
+        extra = torch.from_numpy(W.test_vectors(cd2, d2, cfg["ntv"][2] - cfg["ntv"][1],
+                                                cfg["seed_tv"] + 7)).to(dev)
+    if nsrc > 1:
+        b = torch.from_numpy(W.point_sources(dims)).to(dev)
+        src = "12 spin-colour point sources in one batch"
+    else:
+        b = torch.from_numpy(W.gaussian_spinor(dims, cfg["seed_rhs"])).unsqueeze(0).to(dev)
+        src = "one complex Gaussian rhs"
     z = torch.zeros_like(b)
+    log(f"[bench] inputs in {time.time() - t0:.1f}s")
 
     def params(prec, half, batch):
         p = dd.params_default(cfg["levels"])
@@ -383,54 +401,58 @@ def batch_workload(args, cfg, dd, W, np, torch):
                 p.agg[l][mu] = a[mu]
         for l, n in enumerate(cfg["ntv"]):
             p.ntv[l] = n
+        for l, blk in enumerate(cfg.get("sap_blocks", [])[1:]):
+            for mu in range(4):
+                p.sap_block_l[l][mu] = blk[mu]
         p.nu = cfg["nu"]
         p.precond_prec = prec
         p.half_storage = 1 if half else 0
         p.batch = batch
         return p
 
-    torch.cuda.synchronize()
-    t = time.time()
-    H = dd.build_hierarchy(ctx, params(dd.F32, True, BATCH_RHS), tvd)
-    torch.cuda.synchronize()
-    t_setup = time.time() - t
-    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
+    def build(prec, half, batch):
+        torch.cuda.synchronize()
+        t = time.time()
+        H = dd.build_hierarchy(ctx, params(prec, half, batch), tvd, extra)
+        torch.cuda.synchronize()
+        return H, time.time() - t
 
-    def solve(Hh, nb, k0=0):
+    def solve(Hh, nb):
         z.zero_()
         torch.cuda.synchronize()
         t = time.time()
-        rc, st = dd.solve(Hh, b[k0:k0 + nb], z[k0:k0 + nb], nrhs=nb)
+        rc, st = dd.solve(Hh, b[:nb], z[:nb], nrhs=nb)
         torch.cuda.synchronize()
         if rc != dd.OK:
             raise RuntimeError(f"solve failed rc={rc}")
         return time.time() - t, st
 
+    H, t_setup = build(dd.F32, True, min(BATCH_RHS, 8 if cfg["levels"] == 4 else BATCH_RHS))
+    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
     for i in range(args.warmup):
-        tw, st = solve(H, BATCH_RHS)
+        tw, st = solve(H, nsrc)
         log(f"[bench] warmup {i}: {tw:.3f}s")
     times, stats = [], None
     for i in range(args.steps):
-        tt, stats = solve(H, BATCH_RHS)
+        tt, stats = solve(H, nsrc)
         times.append(tt)
-        log(f"[bench] step {i}: 12 sources in {tt:.3f}s, its {[x['outer_iters'] for x in stats]}")
+        log(f"[bench] step {i}: {nsrc} rhs in {tt:.3f}s, its {[x['outer_iters'] for x in stats]}")
     ms = 1000.0 * float(np.mean(times))
     plain = None
     if not args.no_plain:
         del H
         torch.cuda.synchronize()
-        t = time.time()
-        H64 = dd.build_hierarchy(ctx, params(dd.F64, False, 1), tvd)
-        torch.cuda.synchronize()
-        t_setup64 = time.time() - t
-        n_plain = 2
+        torch.cuda.empty_cache()
+        H64, t_setup64 = build(dd.F64, False, 1)
+        n_plain = min(2, nsrc)
         tp, stp = solve(H64, n_plain)
         plain = dict(setup_s=round(t_setup64, 3), sources_timed=n_plain,
                      per_source_s=round(tp / n_plain, 4), outer_iters=[x["outer_iters"] for x in stp])
         log(f"[bench] plain FP64: setup {t_setup64:.2f}s, {tp / n_plain:.3f}s per source")
+    aggs = ", ".join("x".join(str(a) for a in ag) for ag in cfg["agg"])
     line = {
         "metric": METRIC,
-        "value": round(BATCH_RHS / (ms / 1000.0), 4),
+        "value": round(nsrc / (ms / 1000.0), 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -440,15 +462,16 @@ def batch_workload(args, cfg, dd, W, np, torch):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 preconditioner on f16-stored operators, f64 outer",
-        "data": "synthetic (seeded SU(3) links exp(i eps H), 12 spin-colour point sources)",
-        "config": {"workload": "32^3x64 Wilson-clover, 3 levels (4^4, 2^4 aggregates, N=20), c_sw=1, "
-                               "eps=0.5, m0=-0.42, 12 point sources in one batch, tol 1e-10",
+        "data": "synthetic (seeded SU(3) links exp(i eps H), " + src + ")",
+        "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-clover, {cfg['levels']} levels "
+                               f"(aggregates {aggs}, N={cfg['ntv']}), c_sw={cfg['csw']}, eps={cfg['eps']}, "
+                               f"m0={cfg['m0']}, {src}, tol 1e-10",
                    "parallelism": "1 GPU"},
         "setup_s": round(t_setup, 3),
         "outer_iters": [x["outer_iters"] for x in stats],
         "max_true_relres": max(x["true_relres"] for x in stats),
         "plain_fp64": plain,
-        "speedup_vs_plain_fp64_per_source": (round(plain["per_source_s"] / (ms / 1000.0 / BATCH_RHS), 3)
+        "speedup_vs_plain_fp64_per_source": (round(plain["per_source_s"] / (ms / 1000.0 / nsrc), 3)
                                              if plain else None),
     }
     print(json.dumps(line), flush=True)

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace ddamg {
@@ -763,10 +765,29 @@ template <typename T> void Hierarchy::iterative_setup(int l, int i) {
   for (int q = 1; q <= i; ++q) iterative_setup<T>(l + 1, q);
 }
 
+// With DDAMG_VERBOSE set in the environment the setup reports each phase on
+// stderr as it completes (long setups on large lattices).
+static bool verbose() {
+  static const bool v = std::getenv("DDAMG_VERBOSE") != nullptr;
+  return v;
+}
+
 template <typename T> void Hierarchy::setup(const double2* tvc) {
+  const auto t0 = std::chrono::steady_clock::now();
+  auto report = [&](const char* what, int i) {
+    if (!verbose()) return;
+    DD_CHECK_HIP(hipStreamSynchronize(s));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[ddamg] setup: %s %d done at %.2f s\n", what, i, sec);
+    std::fflush(stderr);
+  };
   fine_to_native<T>(ctx->g, tvc, tv<T>(0), lv[0].N, s);
   initial_setup<T>(0);
-  for (int i = 1; i <= p.n_inv; ++i) iterative_setup<T>(0, i);
+  report("initial phase, levels", L);
+  for (int i = 1; i <= p.n_inv; ++i) {
+    iterative_setup<T>(0, i);
+    report("iterative phase, iteration", i);
+  }
   DD_CHECK_HIP(hipStreamSynchronize(s));
 }
 

@@ -138,9 +138,12 @@ CONFIGS = {
     "clover32x64_3lvl_12rhs": _cfg(2, dims=(32, 32, 32, 64), eps=0.5, m0=-0.42, csw=1.0,
                                    levels=3, agg=[(4, 4, 4, 4), (2, 2, 2, 2)], ntv=[20, 20]),
     # four-level, 48^3x96
+    # (level 2 is 6^3x12: 2^4 SAP blocks would come in odd counts, 3^4 blocks
+    # give 2^3x4 of them)
     "clover48x96_4lvl": _cfg(4, dims=(48, 48, 48, 96), eps=0.55, m0=-0.43, csw=1.0,
                              levels=4, agg=[(4, 4, 4, 4), (2, 2, 2, 2), (2, 2, 2, 2)],
-                             ntv=[20, 20, 28]),
+                             ntv=[20, 20, 28],
+                             sap_blocks=[(2, 2, 2, 2), (2, 2, 2, 2), (3, 3, 3, 3)]),
 }
 
 # the uneven batch of eight lattices: (dims, eps, m0)

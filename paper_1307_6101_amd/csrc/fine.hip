@@ -380,9 +380,9 @@ void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s
 // per workgroup; a batch of fields runs one field per workgroup with the
 // XCD-aware batch mapping.  r = b - D z with the full operator, then mr_iters minimal
 // residual steps on the Dirichlet block operator D_i (self term + the four
-// in-block hops, partner spinors exchanged through LDS), z += x.  The block
-// operator of a site (its four in-block links and its clover) is read once
-// into registers, in its stored precision, and reused by every MR step.
+// in-block hops, partner spinors exchanged through LDS), z += x.  The four
+// in-block links of a site are read once into registers, in their stored
+// precision, and reused by every MR step.
 // ---------------------------------------------------------------------------
 template <typename T, typename S, int MU>
 __device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, const C<T> (&u)[9],
@@ -395,35 +395,30 @@ __device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, 
   else hop_apply<T, MU, true>(psi, u, acc);
 }
 
-// The site's block operator: kept in registers (KEEP) or read again from
-// memory at every MR step (FP64, where registers do not suffice).
-template <typename T, typename S, bool KEEP> struct BlockOp;
-template <typename T, typename S> struct BlockOp<T, S, true> {
-  S ul[4][9], al[36];
+// The site's in-block links: kept in registers across the MR steps (FP32
+// and FP16 storage) or read again at every step (FP64, where registers do
+// not suffice).  The clover is read at every step: keeping it too (144 more
+// registers in FP32) leaves one wavefront per SIMD and was measured slower.
+template <typename T, typename S, bool KEEP> struct BlockOp {
+  S ul[KEEP ? 4 : 1][9];
   __device__ void load(const FineOpView<T, S>& op, int blk, int loc, bool valid) {
+    if constexpr (KEEP) {
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      // the link joining loc and loc ^ (1 << mu) belongs to the lower site
-      const S* p = op.U + (long long)blk * 576 + mu * 144 + (loc & ~(1 << mu));
+      for (int mu = 0; mu < 4; ++mu) {
+        // the link joining loc and loc ^ (1 << mu) belongs to the lower site
+        const S* p = op.U + (long long)blk * 576 + mu * 144 + (loc & ~(1 << mu));
 #pragma unroll
-      for (int k = 0; k < 9; ++k) ul[mu][k] = valid ? p[k * 16] : szero<S>();
+        for (int k = 0; k < 9; ++k) ul[mu][k] = valid ? p[k * 16] : szero<S>();
+      }
     }
-    const S* pa = op.A + (long long)blk * 576 + loc;
-#pragma unroll
-    for (int e = 0; e < 36; ++e) al[e] = valid ? pa[e * 16] : szero<S>();
   }
-  __device__ void link(const FineOpView<T, S>&, int, int, int mu, C<T> (&u)[9]) const {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(ul[mu][k]);
-  }
-  __device__ void clover(const FineOpView<T, S>&, int, int, const C<T> v[12], C<T> out[12]) const {
-    clover_mul<T>([&](int e) { return ldc<T, S>(al[e]); }, v, out);
-  }
-};
-template <typename T, typename S> struct BlockOp<T, S, false> {
-  __device__ void load(const FineOpView<T, S>&, int, int, bool) {}
   __device__ void link(const FineOpView<T, S>& op, int blk, int loc, int mu, C<T> (&u)[9]) const {
-    load_link<T, S>(op.U, blk, loc & ~(1 << mu), mu, u);
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(ul[mu][k]);
+    } else {
+      load_link<T, S>(op.U, blk, loc & ~(1 << mu), mu, u);
+    }
   }
   __device__ void clover(const FineOpView<T, S>& op, int blk, int loc, const C<T> v[12], C<T> out[12]) const {
     clover_apply<T, S>(op.A, blk, loc, v, out);

@@ -32,6 +32,8 @@ struct CoarseGeom {
   int nblk, bs;                // blocks, sites per block
   std::vector<int> blk_sites;  // [nblk][bs], blocks colour-major (colour 0 first)
   std::vector<int> site_blk;   // [V] block id
+  std::vector<int> site_pos;   // [V] block id * bs + index in the block
+  std::vector<unsigned> inmask;  // [V] bit k: nbr9[k] lies in the site's block
   // parity (odd-even)
   bool bipartite;
   std::vector<int> even, odd;
@@ -65,12 +67,19 @@ struct SapScratch {
   T* part[2] = {nullptr, nullptr};
 };
 
+// device SAP tables of a level (see CoarseGeom)
+struct SapTables {
+  const int* blk_sites;        // [nblk][bs], blocks colour-major
+  const int* site_pos;         // [V]
+  const unsigned* inmask;      // [V]
+  int nblk, bs;
+};
+
 // one SAP colour pass z <- z + MR_blocks(b - D z) on the blocks of colour
-// `colour` (blk_sites lists the sites of every block, blocks colour-major)
+// `colour`, for nb fields
 template <typename T, typename S>
-void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
-                       int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
-                       hipStream_t s, int nb = 1);
+void coarse_sap_colour(const CoarseOpView<T, S>& op, const SapTables& tb, int colour, int mr_iters, const C<T>* b,
+                       C<T>* z, SapScratch<T>& ws, hipStream_t s, int nb = 1);
 
 // odd-even: out(x) = gamma in_c(x) + alpha S(x) in_s(x) + beta sum_hops(in_h)(x)
 // for x in `sites` (other sites of out untouched)

@@ -51,6 +51,8 @@ CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]) {
     }
     g.blk_sites.resize((size_t)g.nblk * g.bs);
     g.site_blk.resize(g.V);
+    g.site_pos.resize(g.V);
+    g.inmask.resize(g.V);
     int nbk = 0;
     for (int col = 0; col < 2; ++col)
       for (int b : order[col]) {
@@ -64,9 +66,16 @@ CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]) {
           int site = idx(sc);
           g.blk_sites[(size_t)nbk * g.bs + l] = site;
           g.site_blk[site] = nbk;
+          g.site_pos[site] = nbk * g.bs + l;
         }
         ++nbk;
       }
+    for (int s = 0; s < g.V; ++s) {
+      unsigned m = 1u;
+      for (int k = 1; k < 9; ++k)
+        if (g.site_blk[g.nbr9[s * 9 + k]] == g.site_blk[s]) m |= 1u << k;
+      g.inmask[s] = m;
+    }
   }
   return g;
 }
@@ -121,20 +130,19 @@ void expand_coarse(const double2* D5, const int* nbr9, int V, int d, S* K, hipSt
 // ---------------------------------------------------------------------------
 constexpr int SW = 8;   // wavefronts per site workgroup
 
+// The block columns of one wavefront: prefetch() issues the loads of the
+// first block group (all nine blocks in FP32) into registers, so a kernel can
+// start them before it waits for its LDS inputs; apply() multiplies them
+// (and any further groups) into RB accumulators.
 template <typename T, typename S, int NCH, int RB>
-__device__ __forceinline__ void site_cols(const S* __restrict__ Kx, size_t bsz, const C<T> (*vin)[9][64],
-                                          unsigned mask, int j0, int lane, int d, C<T> (&acc)[RB]) {
-  constexpr int KG = sizeof(T) == 4 ? 9 : 3;
-  // lanes past the last row read row 0 and return zero, so every load of a
-  // group is unconditional within the wavefront; the block mask and the
-  // column bound are wavefront-uniform
-  const int row = lane < d ? lane : 0;
-#pragma unroll
-  for (int r = 0; r < RB; ++r) acc[r] = czero<T>();
-#pragma unroll 1
-  for (int k0 = 0; k0 < 9; k0 += KG) {
-    // raw stored values: all loads issue before the first conversion
-    S m[KG][NCH];
+struct SiteCols {
+  static constexpr int KG = sizeof(T) == 4 ? 9 : 3;
+  S m[KG][NCH];
+  const S* Kx;
+  size_t bsz;
+  unsigned mask;
+  int j0, lane, d, row;
+  __device__ __forceinline__ void load_group(int k0) {
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk) {
       const bool blk = (mask >> (k0 + kk)) & 1u;
@@ -144,22 +152,52 @@ __device__ __forceinline__ void site_cols(const S* __restrict__ Kx, size_t bsz, 
         m[kk][u] = blk ? Kx[(k0 + kk) * bsz + (size_t)j * d + row] : szero<S>();
       }
     }
-#pragma unroll
-    for (int kk = 0; kk < KG; ++kk)
-#pragma unroll
-      for (int u = 0; u < NCH; ++u)
-        // masked blocks are skipped, not multiplied by zero: their LDS
-        // inputs are not loaded and may hold anything
-        if (((mask >> (k0 + kk)) & 1u) && j0 + u < d) {
-          const C<T> mv = ldc<T, S>(m[kk][u]);
-#pragma unroll
-          for (int r = 0; r < RB; ++r) cfma(acc[r], mv, vin[r][k0 + kk][j0 + u]);
-        }
   }
-  // lanes past the last row return zero (callers reduce over all 64 lanes)
+  // lanes past the last row read row 0 and return zero, so every load of a
+  // group is unconditional within the wavefront; the block mask and the
+  // column bound are wavefront-uniform
+  __device__ __forceinline__ void prefetch(const S* __restrict__ K_, size_t bsz_, unsigned mask_, int j0_, int lane_,
+                                           int d_) {
+    Kx = K_;
+    bsz = bsz_;
+    mask = mask_;
+    j0 = j0_;
+    lane = lane_;
+    d = d_;
+    row = lane < d ? lane : 0;
+    load_group(0);
+  }
+  __device__ __forceinline__ void apply(const C<T> (*vin)[9][64], C<T> (&acc)[RB]) {
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
-    if (lane >= d) acc[r] = czero<T>();
+    for (int r = 0; r < RB; ++r) acc[r] = czero<T>();
+#pragma unroll 1
+    for (int k0 = 0; k0 < 9; k0 += KG) {
+      if (k0 > 0) load_group(k0);
+#pragma unroll
+      for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int u = 0; u < NCH; ++u)
+          // masked blocks are skipped, not multiplied by zero: their LDS
+          // inputs are not loaded and may hold anything
+          if (((mask >> (k0 + kk)) & 1u) && j0 + u < d) {
+            const C<T> mv = ldc<T, S>(m[kk][u]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) cfma(acc[r], mv, vin[r][k0 + kk][j0 + u]);
+          }
+    }
+    // lanes past the last row return zero (callers reduce over all 64 lanes)
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (lane >= d) acc[r] = czero<T>();
+  }
+};
+
+template <typename T, typename S, int NCH, int RB>
+__device__ __forceinline__ void site_cols(const S* __restrict__ Kx, size_t bsz, const C<T> (*vin)[9][64],
+                                          unsigned mask, int j0, int lane, int d, C<T> (&acc)[RB]) {
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(Kx, bsz, mask, j0, lane, d);
+  sc.apply(vin, acc);
 }
 
 // sum of the eight wavefronts' partial rows; valid in wavefront 0, lane < d
@@ -187,14 +225,16 @@ __global__ void __launch_bounds__(64 * SW) k_capply(CoarseOpView<T, S> op, const
   const int site = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
   in += (long long)blockIdx.y * RB * n;
   out += (long long)blockIdx.y * RB * n;
+  const size_t bsz = (size_t)d * d;
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, 0x1FFu, w * NCH, lane, d);
   for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
     const int r = e / (9 * d), kj = e % (9 * d);
     vin[r][kj / d][kj % d] = in[r * n + (size_t)op.nbr9[site * 9 + kj / d] * d + kj % d];
   }
   __syncthreads();
-  const size_t bsz = (size_t)d * d;
   C<T> acc[RB];
-  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu, w * NCH, lane, d, acc);
+  sc.apply(vin, acc);
   site_rows_sum<T, RB>(acc, prow);
   if (w == 0 && lane < d)
 #pragma unroll
@@ -336,7 +376,11 @@ void coarse_apply(const CoarseOpView<T, S>& op, const C<T>* in, C<T>* out, hipSt
 //               q_t = D_i rho_t, per-site <q_t, rho_t>, <q_t, q_t>
 //   k_sap_fin:  z += alpha_{last} rho_{last}
 // Buffers rho, q, part are ping-ponged by step parity.  Vectors of the batch
-// are n apart, per-site partials V*4 apart.
+// are n apart, per-site partials V*4 apart.  The per-site partials are
+// stored block-major (position pos(x) = block * bs + index in block) so that
+// a block's step size is one contiguous read, and each site's in-block
+// neighbour mask is a table: no kernel chases an index to find another.
+// The operator blocks are loaded before the kernel waits for its inputs.
 // ---------------------------------------------------------------------------
 template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, const int* __restrict__ csites,
@@ -349,14 +393,16 @@ __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, cons
   b += off;
   z += off;
   rho0 += off;
+  const size_t bsz = (size_t)d * d;
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, 0x1FFu, w * NCH, lane, d);
   for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
     const int r = e / (9 * d), kj = e % (9 * d);
     vin[r][kj / d][kj % d] = z[r * n + (size_t)op.nbr9[site * 9 + kj / d] * d + kj % d];
   }
   __syncthreads();
-  const size_t bsz = (size_t)d * d;
   C<T> acc[RB];
-  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, 0x1FFu, w * NCH, lane, d, acc);
+  sc.apply(vin, acc);
   site_rows_sum<T, RB>(acc, prow);
   if (w == 0 && lane < d)
 #pragma unroll
@@ -366,15 +412,14 @@ __global__ void __launch_bounds__(64 * SW) k_sap_res(CoarseOpView<T, S> op, cons
     }
 }
 
-// block alpha of step t from the per-site partials of the block's sites,
+// block step size from the block-major per-site partials of one block,
 // summed by one wavefront (lane v takes sites v, v+64, ..) in a fixed order;
 // every lane of the wavefront gets the result
 template <typename T>
-__device__ inline C<T> block_alpha_wave(const T* __restrict__ part, const int* __restrict__ bsites, int bs,
-                                        int lane) {
+__device__ inline C<T> block_alpha_wave(const T* __restrict__ part, int blk, int bs, int lane) {
   T s0 = 0, s1 = 0, s2 = 0;
   for (int v = lane; v < bs; v += 64) {
-    const T* p = part + (size_t)bsites[v] * 4;
+    const T* p = part + ((size_t)blk * bs + v) * 4;
     s0 += p[0];
     s1 += p[1];
     s2 += p[2];
@@ -387,13 +432,10 @@ __device__ inline C<T> block_alpha_wave(const T* __restrict__ part, const int* _
 
 template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const int* __restrict__ csites,
-                                                   const int* __restrict__ blk_sites,
-                                                   const int* __restrict__ site_blk, int bs, int step,
-                                                   const C<T>* __restrict__ rho_prev,
-                                                   const C<T>* __restrict__ q_prev,
-                                                   const T* __restrict__ part_prev, C<T>* __restrict__ rho_cur,
-                                                   C<T>* __restrict__ q_cur, T* __restrict__ part_cur,
-                                                   C<T>* __restrict__ z, long long n) {
+                                                   SapTables tb, int step, const C<T>* __restrict__ rho_prev,
+                                                   const C<T>* __restrict__ q_prev, const T* __restrict__ part_prev,
+                                                   C<T>* __restrict__ rho_cur, C<T>* __restrict__ q_cur,
+                                                   T* __restrict__ part_cur, C<T>* __restrict__ z, long long n) {
   __shared__ C<T> vin[RB][9][64];
   __shared__ C<T> prow[SW][RB][64];
   __shared__ C<T> alpha_s[RB];
@@ -407,12 +449,13 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
   z += off;
   part_prev += poff;
   part_cur += poff;
-  const int blk = site_blk[site];
-  unsigned mask = 1u;   // self and the in-block neighbours
-  for (int k = 1; k < 9; ++k)
-    if (site_blk[op.nbr9[site * 9 + k]] == blk) mask |= 1u << k;
+  const int pos = tb.site_pos[site], blk = pos / tb.bs;
+  const unsigned mask = tb.inmask[site];   // self and the in-block neighbours
+  const size_t bsz = (size_t)d * d;
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, mask, w * NCH, lane, d);
   if (step > 0 && w < RB) {
-    const C<T> a = block_alpha_wave<T>(part_prev + w * pn, blk_sites + (size_t)blk * bs, bs, lane);
+    const C<T> a = block_alpha_wave<T>(part_prev + w * pn, blk, tb.bs, lane);
     if (lane == 0) alpha_s[w] = a;
   }
   __syncthreads();
@@ -426,9 +469,8 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
     }
   }
   __syncthreads();
-  const size_t bsz = (size_t)d * d;
   C<T> q[RB];
-  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask, w * NCH, lane, d, q);
+  sc.apply(vin, q);
   site_rows_sum<T, RB>(q, prow);
   if (w == 0) {
 #pragma unroll
@@ -451,7 +493,7 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
       a1 = wave_sum(a1);
       a2 = wave_sum(a2);
       if (lane == 0) {
-        T* p = part_cur + r * pn + (size_t)site * 4;
+        T* p = part_cur + r * pn + (size_t)pos * 4;
         p[0] = a0;
         p[1] = a1;
         p[2] = a2;
@@ -461,17 +503,16 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
 }
 
 template <typename T>
-__global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __restrict__ blk_sites,
-                          const int* __restrict__ site_blk, int bs, const C<T>* __restrict__ rho,
+__global__ void k_sap_fin(int d, const int* __restrict__ csites, SapTables tb, const C<T>* __restrict__ rho,
                           const T* __restrict__ part, C<T>* __restrict__ z, long long n, long long pn) {
   __shared__ C<T> alpha_s;
   const int site = csites[blockIdx.x];
-  const int blk = site_blk[site];
+  const int blk = tb.site_pos[site] / tb.bs;
   rho += blockIdx.y * n;
   z += blockIdx.y * n;
   part += blockIdx.y * pn;
   if (threadIdx.x < 64) {
-    const C<T> a = block_alpha_wave<T>(part, blk_sites + (size_t)blk * bs, bs, threadIdx.x);
+    const C<T> a = block_alpha_wave<T>(part, blk, tb.bs, threadIdx.x);
     if (threadIdx.x == 0) alpha_s = a;
   }
   __syncthreads();
@@ -485,13 +526,12 @@ __global__ void k_sap_fin(int d, const int* __restrict__ csites, const int* __re
 }
 
 template <typename T, typename S>
-void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const int* site_blk, int nblk,
-                       int bs, int colour, int mr_iters, const C<T>* b, C<T>* z, SapScratch<T>& ws,
-                       hipStream_t s, int nb) {
+void coarse_sap_colour(const CoarseOpView<T, S>& op, const SapTables& tb, int colour, int mr_iters, const C<T>* b,
+                       C<T>* z, SapScratch<T>& ws, hipStream_t s, int nb) {
   if (mr_iters <= 0) return;
   DD_REQUIRE(op.d <= 64, "coarse levels support at most 64 components per site");
-  const int nsites = (nblk / 2) * bs;
-  const int* csites = blk_sites + (size_t)colour * (nblk / 2) * bs;   // blocks are colour-major
+  const int nsites = (tb.nblk / 2) * tb.bs;
+  const int* csites = tb.blk_sites + (size_t)colour * (tb.nblk / 2) * tb.bs;   // blocks are colour-major
   const long long n = (long long)op.V * op.d, pn = (long long)op.V * 4;
   with_nch(op.d, [&](auto nch) {
     constexpr int NCH = decltype(nch)::value;
@@ -503,14 +543,14 @@ void coarse_sap_colour(const CoarseOpView<T, S>& op, const int* blk_sites, const
       for (int t = 0; t < mr_iters; ++t) {
         const int pp = (t + 1) & 1, cc = t & 1;   // previous / current buffers
         k_sap_q<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(
-            op, csites, blk_sites, site_blk, bs, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po,
-            ws.rho[cc] + o, ws.q[cc] + o, ws.part[cc] + po, z + o, n);
+            op, csites, tb, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po, ws.rho[cc] + o, ws.q[cc] + o,
+            ws.part[cc] + po, z + o, n);
       }
     });
   });
   const int last = (mr_iters - 1) & 1;
-  k_sap_fin<T><<<dim3(nsites, nb), 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, blk_sites, site_blk, bs,
-                                                                   ws.rho[last], ws.part[last], z, n, pn);
+  k_sap_fin<T><<<dim3(nsites, nb), 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, tb, ws.rho[last],
+                                                                   ws.part[last], z, n, pn);
   DD_LAUNCH_CHECK();
 }
 
@@ -530,6 +570,9 @@ __global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T, S> op, const
   unsigned mask = 0;
   if (alpha != T(0)) mask |= 1u;
   if (beta != T(0)) mask |= 0x1FEu;
+  const size_t bsz = (size_t)d * d;
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, mask, w * NCH, lane, d);
   for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
     const int r = e / (9 * d), kj = e % (9 * d), k = kj / d, j = kj % d;
     if ((mask >> k) & 1u) {
@@ -538,9 +581,8 @@ __global__ void __launch_bounds__(64 * SW) k_csites(CoarseOpView<T, S> op, const
     }
   }
   __syncthreads();
-  const size_t bsz = (size_t)d * d;
   C<T> acc[RB];
-  site_cols<T, S, NCH, RB>(op.K + (size_t)site * 9 * bsz, bsz, vin, mask, w * NCH, lane, d, acc);
+  sc.apply(vin, acc);
   site_rows_sum<T, RB>(acc, prow);
   if (w == 0 && lane < d)
 #pragma unroll
@@ -693,9 +735,8 @@ template void expand_coarse<__half2>(const double2*, const int*, int, int, __hal
 
 #define DD_INST(T, S)                                                                              \
   template void coarse_apply<T, S>(const CoarseOpView<T, S>&, const C<T>*, C<T>*, hipStream_t, int); \
-  template void coarse_sap_colour<T, S>(const CoarseOpView<T, S>&, const int*, const int*, int, int,   \
-                                        int, int, const C<T>*, C<T>*, SapScratch<T>&, hipStream_t,   \
-                                        int);                                                        \
+  template void coarse_sap_colour<T, S>(const CoarseOpView<T, S>&, const SapTables&, int, int, const C<T>*, \
+                                        C<T>*, SapScratch<T>&, hipStream_t, int);                    \
   template void coarse_site_apply<T, S>(const CoarseOpView<T, S>&, const int*, int, T, const C<T>*, T, \
                                         const C<T>*, T, const C<T>*, C<T>*, hipStream_t, int);
 DD_INST(double, double2)

@@ -85,7 +85,9 @@ struct LevelStore {
   long long V = 0, n = 0;
   // coarse operator (level >= 1)
   CoarseGeom cg;
-  DevArray<int> c_nbr9, c_blk_sites, c_site_blk, c_even, c_odd;
+  DevArray<int> c_nbr9, c_blk_sites, c_site_blk, c_site_pos, c_even, c_odd;
+  DevArray<unsigned> c_inmask;
+  SapTables sap_tables() const { return SapTables{c_blk_sites.p, c_site_pos.p, c_inmask.p, cg.nblk, cg.bs}; }
   DevArray<double2> D64;           // Galerkin output: self + forward blocks, row-major
   DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
   DevArray<float2> K32, Einv32;

@@ -142,8 +142,7 @@ template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsw
         LevelStore& L_ = lv[l];
         SapScratch<T>& ws = sap_scratch<T>(L_, nb);
         coarse_op<T>(l, [&](const auto& op) {
-          coarse_sap_colour(op, L_.c_blk_sites.p, L_.c_site_blk.p, L_.cg.nblk, L_.cg.bs, col, p.mr_iters, b,
-                            z, ws, s, nb);
+          coarse_sap_colour(op, L_.sap_tables(), col, p.mr_iters, b, z, ws, s, nb);
         });
       }
     }
@@ -879,6 +878,8 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.c_nbr9.upload(S.cg.nbr9, s);
       S.c_blk_sites.upload(S.cg.blk_sites, s);
       S.c_site_blk.upload(S.cg.site_blk, s);
+      S.c_site_pos.upload(S.cg.site_pos, s);
+      S.c_inmask.upload(S.cg.inmask, s);
       S.c_even.upload(S.cg.even, s);
       S.c_odd.upload(S.cg.odd, s);
       S.D64.alloc((size_t)S.V * 5 * d * d);

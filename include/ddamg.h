@@ -28,8 +28,11 @@
  *                -x,-y,-z,-t: (D_l v)(x) = sum_k B_k(x) v(x + d_k)
  * Native layouts (DDAMG_NATIVE) are the library's internal ones, at the
  *   precision of the call (F64: complex128, F32: complex64):
- *   fine field   [nrhs][V/16][12][16]: 2^4 blocks of sites, aggregate-major;
- *                site (x,y,z,t) -> block, local index lx+2ly+4lz+8lt
+ *   fine field   [nrhs][V/16][12][16]: 2^4 blocks of sites; site (x,y,z,t)
+ *                has local index (x&1)+2(y&1)+4(z&1)+8(t&1) in block
+ *                (x/2,y/2,z/2,t/2); blocks are numbered tile-major: a tile is
+ *                the 2x2x2x2 blocks of one 4^4 brick (block bits in the same
+ *                order inside the tile), tiles lexicographic (x fastest)
  *   level-l field (l >= 1) [nrhs][V_l][2N] (canonical order)
  *   Use ddamg_to_native / ddamg_from_native to convert.
  * Levels are numbered from 0 (the fine lattice; the paper's level 1).

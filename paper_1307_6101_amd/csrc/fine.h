@@ -1,10 +1,16 @@
 // Fine-lattice (level 0) data layout and launchers.
 //
 // Native fine layout: the lattice is cut into 2^4 blocks of 16 sites (the SAP
-// blocks), numbered lexicographically over the block grid dims/2; inside a
-// block, site (lx,ly,lz,lt) has local index lx + 2ly + 4lz + 8lt.  A field is
-// stored [block][component][16 sites], so one 16-lane group of a wavefront
-// reads one block, and each component load is one contiguous segment.
+// blocks); inside a block, site (lx,ly,lz,lt) has local index
+// lx + 2ly + 4lz + 8lt.  Blocks are numbered tile by tile: sixteen
+// consecutive block numbers form a 2x2x2x2 tile of blocks (a 4^4 brick of
+// sites, the aggregate shape of the first level), tiles lexicographic over
+// the tile grid dims/4, blocks inside a tile in the same bit order as sites
+// inside a block.  A field is stored [block][component][16 sites], so one
+// 16-lane group of a wavefront reads one block, each component load is one
+// contiguous segment, and a 256-thread workgroup covers one compact 4^4
+// brick, whose neighbours are half as often outside it as those of a row of
+// blocks.
 //   spinor  [nblk][12][16]      component = spin*3 + colour
 //   links   [nblk][4][9][16]    U_mu(x) row-major, x the site of the block
 //   clover  [nblk][36][16]      per chirality 18 entries: 3 packed real
@@ -25,6 +31,22 @@ struct FineGeom {
 };
 
 FineGeom make_fine_geom(const int dims[4]);
+
+// block number of the block with coordinates b (block grid nb) and back
+__host__ __device__ inline int block_encode(const int nb[4], const int b[4]) {
+  const int it = (b[0] & 1) | ((b[1] & 1) << 1) | ((b[2] & 1) << 2) | ((b[3] & 1) << 3);
+  const int tile = (b[0] >> 1) + (nb[0] >> 1) * ((b[1] >> 1) + (nb[1] >> 1) * ((b[2] >> 1) + (nb[2] >> 1) * (b[3] >> 1)));
+  return tile * 16 + it;
+}
+__host__ __device__ inline void block_decode(const int nb[4], int blk, int b[4]) {
+  const int it = blk & 15;
+  int tile = blk >> 4;
+  for (int mu = 0; mu < 4; ++mu) {
+    const int nt = nb[mu] >> 1;
+    b[mu] = 2 * (tile % nt) + ((it >> mu) & 1);
+    tile /= nt;
+  }
+}
 // host tables: nbr_blk[blk*8 + 2*mu + (0 fwd | 1 bwd)], colour lists
 void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks /* [2][nblk/2] */);
 

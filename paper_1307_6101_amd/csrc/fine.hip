@@ -30,6 +30,7 @@ FineGeom make_fine_geom(const int dims[4]) {
   g.V = 1;
   g.nblk = 1;
   for (int mu = 0; mu < 4; ++mu) {
+    DD_REQUIRE(dims[mu] % 4 == 0, "every lattice extent must be a multiple of 4");
     g.dims[mu] = dims[mu];
     g.nb[mu] = dims[mu] / 2;
     g.V *= dims[mu];
@@ -42,14 +43,13 @@ void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks) {
   int n[2] = {0, 0};
   const int half = g.nblk / 2;
   for (int b = 0; b < g.nblk; ++b) {
-    int c[4], r = b;
-    for (int mu = 0; mu < 4; ++mu) { c[mu] = r % g.nb[mu]; r /= g.nb[mu]; }
+    int c[4];
+    block_decode(g.nb, b, c);
     for (int mu = 0; mu < 4; ++mu) {
       for (int dir = 0; dir < 2; ++dir) {
         int cc[4] = {c[0], c[1], c[2], c[3]};
         cc[mu] = (cc[mu] + (dir == 0 ? 1 : g.nb[mu] - 1)) % g.nb[mu];
-        nbr_blk[b * 8 + 2 * mu + dir] =
-            cc[0] + g.nb[0] * (cc[1] + g.nb[1] * (cc[2] + g.nb[2] * cc[3]));
+        nbr_blk[b * 8 + 2 * mu + dir] = block_encode(g.nb, cc);
       }
     }
     int col = (c[0] + c[1] + c[2] + c[3]) & 1;
@@ -61,11 +61,12 @@ void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks) {
 // index helpers
 // ---------------------------------------------------------------------------
 struct DevGeom {
-  int X, Y, Z, T, nb0, nb1, nb2;
+  int X, Y, Z, T;
+  int nb[4];
   long long V;
 };
 static DevGeom devgeom(const FineGeom& g) {
-  return DevGeom{g.dims[0], g.dims[1], g.dims[2], g.dims[3], g.nb[0], g.nb[1], g.nb[2], g.V};
+  return DevGeom{g.dims[0], g.dims[1], g.dims[2], g.dims[3], {g.nb[0], g.nb[1], g.nb[2], g.nb[3]}, g.V};
 }
 
 __device__ inline void canonical_to_native(const DevGeom& g, long long i, int& blk, int& loc) {
@@ -75,7 +76,8 @@ __device__ inline void canonical_to_native(const DevGeom& g, long long i, int& b
   r /= g.Y;
   int z = (int)(r % g.Z);
   int t = (int)(r / g.Z);
-  blk = (x >> 1) + g.nb0 * ((y >> 1) + g.nb1 * ((z >> 1) + g.nb2 * (t >> 1)));
+  const int b[4] = {x >> 1, y >> 1, z >> 1, t >> 1};
+  blk = block_encode(g.nb, b);
   loc = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((t & 1) << 3);
 }
 

@@ -32,7 +32,7 @@ AggTables make_fine_agg(const FineGeom& g, const int agg[4]) {
       for (int mu = 0; mu < 4; ++mu) { l[mu] = rr % bpa[mu]; rr /= bpa[mu]; }
       int b[4];
       for (int mu = 0; mu < 4; ++mu) b[mu] = c[mu] * bpa[mu] + l[mu];
-      int blk = b[0] + g.nb[0] * (b[1] + g.nb[1] * (b[2] + g.nb[2] * b[3]));
+      int blk = block_encode(g.nb, b);
       a.members[(size_t)A * nbpa + j] = blk;
       a.member_agg[blk] = A;
     }
@@ -456,10 +456,10 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int
   // fine coordinates -> which hops stay inside the aggregate
   bool fin[4], bin[4];
   {
-    int r = blk;
+    int bcs[4];
+    block_decode(gg.nb, blk, bcs);
     for (int mu = 0; mu < 4; ++mu) {
-      const int bc = r % gg.nb[mu];
-      r /= gg.nb[mu];
+      const int bc = bcs[mu];
       const int x = 2 * bc + ((loc >> mu) & 1);
       const int xm = x % gg.agg[mu];
       fin[mu] = xm != gg.agg[mu] - 1;

@@ -4,6 +4,8 @@ namespace ddamg {
 
 constexpr int GMAX = 256;      // max workgroups of the first reduction pass
 constexpr int RED_BS = 256;
+constexpr int RED_BS_ONE = 512;               // single-workgroup reduction
+constexpr long long RED_ONE_MAX = 32768;      // longest vector reduced by one workgroup
 
 template <typename T>
 __global__ void k_zero(C<T>* x, long long n) {
@@ -258,34 +260,37 @@ void bscale(const BArg& a, const C<T>* src, C<T>* dst, long long n, int nb, hipS
   DD_LAUNCH_CHECK();
 }
 
-template <typename T, int KK>
-__global__ void __launch_bounds__(RED_BS) k_bdots_pass1(const BArg a, int upd, const C<T>* __restrict__ V,
-                                                        long long vstride, C<T>* __restrict__ w, long long n,
-                                                        double* __restrict__ partial, int g) {
+template <typename T, int KK, int BS>
+__global__ void __launch_bounds__(BS) k_bdots_pass1(const BArg a, int upd, const C<T>* __restrict__ V,
+                                                    long long vstride, C<T>* __restrict__ w, long long n,
+                                                    double* __restrict__ partial, int g) {
   const int r = blockIdx.y;
   Coefs cc;
   if (upd) {
 #pragma unroll
     for (int j = 0; j < KK; ++j) cc.c[j] = a.coef(r, j);
   }
-  dots_body<T, RED_BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, upd != 0, cc,
-                           partial + ((long long)r * g + blockIdx.x) * 2 * (KMAX + 1));
+  dots_body<T, BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, upd != 0, cc,
+                       partial + ((long long)r * g + blockIdx.x) * 2 * (KMAX + 1));
 }
 
 template <typename T, int KK>
 struct BDotsLaunch {
-  static void go(int k, unsigned g, int nb, hipStream_t s, const BArg& a, int upd, const C<T>* V,
+  static void go(int k, unsigned g, int bs, int nb, hipStream_t s, const BArg& a, int upd, const C<T>* V,
                  long long vstride, C<T>* w, long long n, double* out) {
     if (k == KK) {
-      k_bdots_pass1<T, KK><<<dim3(g, nb), RED_BS, 0, s>>>(a, upd, V, vstride, w, n, out, (int)g);
+      if (bs == RED_BS_ONE)
+        k_bdots_pass1<T, KK, RED_BS_ONE><<<dim3(g, nb), RED_BS_ONE, 0, s>>>(a, upd, V, vstride, w, n, out, (int)g);
+      else
+        k_bdots_pass1<T, KK, RED_BS><<<dim3(g, nb), RED_BS, 0, s>>>(a, upd, V, vstride, w, n, out, (int)g);
       return;
     }
-    BDotsLaunch<T, KK + 1>::go(k, g, nb, s, a, upd, V, vstride, w, n, out);
+    BDotsLaunch<T, KK + 1>::go(k, g, bs, nb, s, a, upd, V, vstride, w, n, out);
   }
 };
 template <typename T>
 struct BDotsLaunch<T, KMAX + 1> {
-  static void go(int, unsigned, int, hipStream_t, const BArg&, int, const C<T>*, long long, C<T>*, long long,
+  static void go(int, unsigned, int, int, hipStream_t, const BArg&, int, const C<T>*, long long, C<T>*, long long,
                  double*) {}
 };
 
@@ -308,13 +313,16 @@ template <typename T>
 void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
                     hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched inner products");
-  long long g = (n + RED_BS * 4 - 1) / (RED_BS * 4);
+  // short vectors (the coarse levels): one workgroup of RED_BS_ONE threads
+  // per system writes the result directly, no second pass
+  const bool one = n <= RED_ONE_MAX;
+  long long g = one ? 1 : (n + RED_BS * 4 - 1) / (RED_BS * 4);
   if (g > GMAX) g = GMAX;
   if (g < 1) g = 1;
   double* out = reinterpret_cast<double*>(result_);
   static const BArg none{};
-  BDotsLaunch<T, 0>::go(k, (unsigned)g, nb, s, a ? *a : none, a ? 1 : 0, V, vstride, w, n,
-                        g == 1 ? out : partial_);
+  BDotsLaunch<T, 0>::go(k, (unsigned)g, one ? RED_BS_ONE : RED_BS, nb, s, a ? *a : none, a ? 1 : 0, V, vstride,
+                        w, n, g == 1 ? out : partial_);
   DD_LAUNCH_CHECK();
   if (g > 1) {
     k_bdots_pass2<<<nb, 256, 0, s>>>(partial_, (int)g, 2 * (k + 1), out);

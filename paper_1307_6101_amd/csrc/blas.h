@@ -20,21 +20,8 @@ struct Coefs {
 
 template <typename T> void vzero(C<T>* x, long long n, hipStream_t s);
 template <typename TA, typename TB> void vcopy(const C<TA>* x, C<TB>* y, long long n, hipStream_t s);
-// y += a x
-template <typename T> void vaxpy(double2 a, const C<T>* x, C<T>* y, long long n, hipStream_t s);
-// y = a y
-template <typename T> void vscale(double2 a, C<T>* y, long long n, hipStream_t s);
 // y = b - y
 template <typename T> void vbmy(const C<T>* b, C<T>* y, long long n, hipStream_t s);
-// y += sum_j c_j Z_j, Z_j = Z + j*stride (k <= KMAX)
-template <typename T, typename TZ>
-void vlincomb(const Coefs& c, int k, const C<TZ>* Z, long long stride, C<T>* y, long long n,
-              hipStream_t s);
-
-// y += sum_j c_j Z_j, then dst = scale * y (one pass)
-template <typename T>
-void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>* y, long long n,
-                    double scale, C<T>* dst, hipStream_t s);
 
 // Batches: nb systems advance together; field r of a batched vector w sits
 // at w + r*n, basis vector j of system r at V + j*vstride + r*n.
@@ -65,22 +52,11 @@ template <typename T>
 void bscale(const BArg& a, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s);
 
 // Fused inner products <V_j, w> (j < k) and <w, w> (entry k), accumulated in
-// FP64 in a fixed order; fetch() copies them to the host.  The batched forms
-// do this for every system r of a batch (results [nb][k+1]).
+// FP64 in a fixed order, for every system r of a batch (results [nb][k+1]).
 class Reducer {
  public:
   Reducer();
   ~Reducer();
-  template <typename T>
-  void dots(const C<T>* V, long long stride, int k, const C<T>* w, long long n, bool with_norm,
-            hipStream_t s);
-  // w += sum_j c_j V_j, then the inner products of the updated w (one pass)
-  template <typename T>
-  void update_dots(const Coefs& c, const C<T>* V, long long stride, int k, C<T>* w, long long n,
-                   hipStream_t s);
-  // copy the last results to the host (synchronises the stream)
-  void fetch(int count, std::complex<double>* out, hipStream_t s);
-
   // batched: a == nullptr for plain inner products, else the update
   // w_r += sum_j c[r][j] V_{j,r} first
   template <typename T>
@@ -93,9 +69,6 @@ class Reducer {
   BArg upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
               hipStream_t s);
  private:
-  template <typename T>
-  void launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd, const Coefs* c,
-              hipStream_t s);
   double* partial_ = nullptr;   // [NBMAX][GMAX][2*(KMAX+1)]
   double2* result_ = nullptr;   // [NBMAX][KMAX+1], device alias of host_
   double2* host_ = nullptr;     // coherent pinned host memory

@@ -18,37 +18,10 @@ __global__ void k_copy(const C<TA>* __restrict__ x, C<TB>* __restrict__ y, long 
   for (; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = ccast<TB>(x[i]);
 }
 template <typename T>
-__global__ void k_axpy(double2 a, const C<T>* __restrict__ x, C<T>* __restrict__ y, long long n) {
-  const C<T> aa = ccast<T>(a);
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
-    C<T> v = y[i];
-    cfma(v, aa, x[i]);
-    y[i] = v;
-  }
-}
-template <typename T>
-__global__ void k_scale(double2 a, C<T>* __restrict__ y, long long n) {
-  const C<T> aa = ccast<T>(a);
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = cmul(aa, y[i]);
-}
-template <typename T>
 __global__ void k_bmy(const C<T>* __restrict__ b, C<T>* __restrict__ y, long long n) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   for (; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = csub(b[i], y[i]);
 }
-template <typename T, typename TZ>
-__global__ void k_lincomb(Coefs c, int k, const C<TZ>* __restrict__ Z, long long stride,
-                          C<T>* __restrict__ y, long long n) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double2 acc = ccast<double>(y[i]);
-    for (int j = 0; j < k; ++j) cfma(acc, c.c[j], ccast<double>(Z[j * stride + i]));
-    y[i] = ccast<T>(acc);
-  }
-}
-
 static unsigned grid_for(long long n) {
   long long g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -64,27 +37,10 @@ template <typename TA, typename TB> void vcopy(const C<TA>* x, C<TB>* y, long lo
   k_copy<TA, TB><<<grid_for(n), 256, 0, s>>>(x, y, n);
   DD_LAUNCH_CHECK();
 }
-template <typename T> void vaxpy(double2 a, const C<T>* x, C<T>* y, long long n, hipStream_t s) {
-  k_axpy<T><<<grid_for(n), 256, 0, s>>>(a, x, y, n);
-  DD_LAUNCH_CHECK();
-}
-template <typename T> void vscale(double2 a, C<T>* y, long long n, hipStream_t s) {
-  k_scale<T><<<grid_for(n), 256, 0, s>>>(a, y, n);
-  DD_LAUNCH_CHECK();
-}
 template <typename T> void vbmy(const C<T>* b, C<T>* y, long long n, hipStream_t s) {
   k_bmy<T><<<grid_for(n), 256, 0, s>>>(b, y, n);
   DD_LAUNCH_CHECK();
 }
-template <typename T, typename TZ>
-void vlincomb(const Coefs& c, int k, const C<TZ>* Z, long long stride, C<T>* y, long long n,
-              hipStream_t s) {
-  if (k <= 0) return;
-  DD_REQUIRE(k <= KMAX, "too many vectors in a linear combination");
-  k_lincomb<T, TZ><<<grid_for(n), 256, 0, s>>>(c, k, Z, stride, y, n);
-  DD_LAUNCH_CHECK();
-}
-
 // ---------------------------------------------------------------------------
 // fused inner products: <V_j, w> for j < k and optionally <w, w>, FP64
 // accumulation.  With `upd`, the kernel first updates w += sum_j c_j V_j
@@ -146,67 +102,6 @@ __device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C
     for (int q = 0; q < BS / 64; ++q) sj += lds[q][j];
     dst[j] = sj;
   }
-}
-
-template <typename T, int KK>
-__global__ void __launch_bounds__(RED_BS) k_dots_pass1(const C<T>* __restrict__ V, long long stride,
-                                                       C<T>* __restrict__ w, long long n, int upd,
-                                                       Coefs c, double* __restrict__ partial) {
-  dots_body<T, RED_BS, KK>(V, stride, w, n, upd != 0, c, partial + (long long)blockIdx.x * 2 * (KMAX + 1));
-}
-
-// launch k_dots_pass1<T, KK> for the runtime count k (0..KMAX)
-template <typename T, int KK>
-struct DotsLaunch {
-  static void go(int k, unsigned g, hipStream_t s, const C<T>* V, long long stride, C<T>* w,
-                 long long n, int upd, const Coefs& c, double* out) {
-    if (k == KK) {
-      k_dots_pass1<T, KK><<<g, RED_BS, 0, s>>>(V, stride, w, n, upd, c, out);
-      return;
-    }
-    DotsLaunch<T, KK + 1>::go(k, g, s, V, stride, w, n, upd, c, out);
-  }
-};
-template <typename T>
-struct DotsLaunch<T, KMAX + 1> {
-  static void go(int, unsigned, hipStream_t, const C<T>*, long long, C<T>*, long long, int,
-                 const Coefs&, double*) {}
-};
-
-// second pass: thread t owns first-pass row t (g <= 256 rows); each value is
-// reduced across the rows with wavefront sums
-__global__ void __launch_bounds__(256) k_dots_pass2(const double* __restrict__ partial, int g, int nv,
-                                                    double* __restrict__ out) {
-  __shared__ double lds[4][2 * (KMAX + 1)];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int j = 0; j < nv; ++j) {
-    const double v = t < g ? partial[(long long)t * 2 * (KMAX + 1) + j] : 0.0;
-    const double sv = wsum(v);
-    if (lane == 0) lds[wave][j] = sv;
-  }
-  __syncthreads();
-  if (t < nv) out[t] = lds[0][t] + lds[1][t] + lds[2][t] + lds[3][t];
-}
-
-template <typename T, typename TZ>
-__global__ void k_lincomb_scale(Coefs c, int k, const C<TZ>* __restrict__ Z, long long stride,
-                                C<T>* __restrict__ y, long long n, double scale, C<T>* __restrict__ dst) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double2 acc = ccast<double>(y[i]);
-    for (int j = 0; j < k; ++j) cfma(acc, c.c[j], ccast<double>(Z[j * stride + i]));
-    const C<T> v = ccast<T>(acc);
-    y[i] = v;
-    dst[i] = ccast<T>(cscale(ccast<double>(v), scale));
-  }
-}
-
-template <typename T>
-void vlincomb_scale(const Coefs& c, int k, const C<T>* Z, long long stride, C<T>* y, long long n,
-                    double scale, C<T>* dst, hipStream_t s) {
-  DD_REQUIRE(k >= 0 && k <= KMAX, "too many vectors in a linear combination");
-  k_lincomb_scale<T, T><<<grid_for(n), 256, 0, s>>>(c, k, Z, stride, y, n, scale, dst);
-  DD_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -398,55 +293,9 @@ Reducer::~Reducer() {
   (void)hipFree(cdev_);
 }
 
-template <typename T>
-void Reducer::launch(const C<T>* V, long long stride, int k, C<T>* w, long long n, bool upd,
-                     const Coefs* c, hipStream_t s) {
-  DD_REQUIRE(k >= 0 && k <= KMAX, "too many vectors in a fused dot product");
-  Coefs cc;
-  if (c) cc = *c;
-  double* out = reinterpret_cast<double*>(result_);
-  // about four elements per thread in the first pass; one workgroup writes
-  // the result directly
-  long long g = (n + RED_BS * 4 - 1) / (RED_BS * 4);
-  if (g > GMAX) g = GMAX;
-  if (g < 1) g = 1;
-  DotsLaunch<T, 0>::go(k, (unsigned)g, s, V, stride, w, n, upd ? 1 : 0, cc, g == 1 ? out : partial_);
-  DD_LAUNCH_CHECK();
-  if (g > 1) {
-    k_dots_pass2<<<1, 256, 0, s>>>(partial_, (int)g, 2 * (k + 1), out);
-    DD_LAUNCH_CHECK();
-  }
-}
-
-template <typename T>
-void Reducer::dots(const C<T>* V, long long stride, int k, const C<T>* w, long long n, bool with_norm,
-                   hipStream_t s) {
-  (void)with_norm;   // the norm is always formed (entry k)
-  launch<T>(V, stride, k, const_cast<C<T>*>(w), n, false, nullptr, s);
-}
-
-template <typename T>
-void Reducer::update_dots(const Coefs& c, const C<T>* V, long long stride, int k, C<T>* w, long long n,
-                          hipStream_t s) {
-  launch<T>(V, stride, k, w, n, true, &c, s);
-}
-
-void Reducer::fetch(int count, std::complex<double>* out, hipStream_t s) {
-  DD_CHECK_HIP(hipStreamSynchronize(s));
-  for (int j = 0; j < count; ++j) out[j] = std::complex<double>(host_[j].x, host_[j].y);
-}
-
 #define DD_INST(T)                                                                            \
   template void vzero<T>(C<T>*, long long, hipStream_t);                                     \
-  template void vaxpy<T>(double2, const C<T>*, C<T>*, long long, hipStream_t);               \
-  template void vscale<T>(double2, C<T>*, long long, hipStream_t);                           \
   template void vbmy<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
-  template void Reducer::dots<T>(const C<T>*, long long, int, const C<T>*, long long, bool,  \
-                                 hipStream_t);                                               \
-  template void Reducer::update_dots<T>(const Coefs&, const C<T>*, long long, int, C<T>*,     \
-                                        long long, hipStream_t);                              \
-  template void vlincomb_scale<T>(const Coefs&, int, const C<T>*, long long, C<T>*, long long, \
-                                  double, C<T>*, hipStream_t);                                 \
   template void Reducer::bdots<T>(const BArg*, const C<T>*, long long, int, C<T>*, long long, int, \
                                   hipStream_t);                                                \
   template void blincomb<T, T>(const BArg&, int, const C<T>*, long long, C<T>*, long long, int, C<T>*, \
@@ -459,12 +308,6 @@ template void vcopy<double, double>(const C<double>*, C<double>*, long long, hip
 template void vcopy<double, float>(const C<double>*, C<float>*, long long, hipStream_t);
 template void vcopy<float, double>(const C<float>*, C<double>*, long long, hipStream_t);
 template void vcopy<float, float>(const C<float>*, C<float>*, long long, hipStream_t);
-template void vlincomb<double, double>(const Coefs&, int, const C<double>*, long long, C<double>*,
-                                       long long, hipStream_t);
-template void vlincomb<double, float>(const Coefs&, int, const C<float>*, long long, C<double>*,
-                                      long long, hipStream_t);
-template void vlincomb<float, float>(const Coefs&, int, const C<float>*, long long, C<float>*,
-                                     long long, hipStream_t);
 template void blincomb<double, float>(const BArg&, int, const C<float>*, long long, C<double>*, long long, int,
                                       C<double>*, hipStream_t);
 

@@ -184,7 +184,6 @@ struct Hierarchy {
   void build_level(int l, bool from32);
   template <typename T> void alloc_work(int cap);
 
-  double norm(const double2* v, long long n);
 };
 
 Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s);

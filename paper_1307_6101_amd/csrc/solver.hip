@@ -164,12 +164,6 @@ template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T
   });
 }
 
-double Hierarchy::norm(const double2* v, long long n) {
-  red->dots<double>(v, 0, 0, v, n, true, s);
-  cd r;
-  red->fetch(1, &r, s);
-  return std::sqrt(r.real());
-}
 
 // ---------------------------------------------------------------------------
 // Batched Krylov building blocks.  Every system r of a batch has its own

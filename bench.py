@@ -227,6 +227,21 @@ def main():
                     outer_iters=hst[-1]["outer_iters"], true_relres=hst[-1]["true_relres"],
                     speedup_vs_fp32_storage=round((ms / 1000.0) / t_half, 3))
         log(f"[bench] FP16-storage solve {t_half:.3f}s, {hst[-1]['outer_iters']} its")
+        # and with the outer directions in FP16 with per-site scales
+        pd = params(dd.F32, True)
+        pd.half_directions = 1
+        Hd = dd.build_hierarchy(ctx, pd, tvd)
+        one_solve(Hd)
+        torch.cuda.synchronize()
+        t = time.time()
+        dst = [one_solve(Hd) for _ in range(max(1, min(args.steps, 3)))]
+        torch.cuda.synchronize()
+        t_dir = (time.time() - t) / len(dst)
+        half["with_fp16_directions"] = dict(time_to_solution_s=round(t_dir, 4),
+                                            outer_iters=dst[-1]["outer_iters"],
+                                            true_relres=dst[-1]["true_relres"])
+        log(f"[bench] FP16 storage + FP16 directions solve {t_dir:.3f}s, {dst[-1]['outer_iters']} its")
+        del Hd
 
     # dominant fine kernels, timed with events on the stream the library uses
     kern = {}

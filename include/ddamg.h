@@ -123,6 +123,16 @@ typedef struct {
                                  an odd count of 2^4 blocks use e.g. 3^4
                                  blocks (Sec. 2: the blocks of one colour
                                  must not touch). */
+  int half_directions;        /* 1: the outer FGMRES keeps its preconditioned
+                                 directions Z_j in FP16 with one FP32 scale
+                                 per site (the largest |re|, |im| of the
+                                 site's 12 components) instead of FP32, and
+                                 applies D to exactly the stored values (the
+                                 flexible Arnoldi relation stays exact); about
+                                 half the memory of Z, for the largest
+                                 lattices, at the price of more outer
+                                 iterations.  Needs precond_prec = DDAMG_F32.
+                                 0 (default): FP32 directions. */
 } ddamg_params;
 
 typedef struct {

@@ -47,6 +47,11 @@ template <typename T, typename TZ>
 void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, long long n, int nb, C<T>* dst,
               hipStream_t s);
 
+// y_r += sum_j c[r][j] Z_{j,r} for fine fields stored in FP16 with one FP32
+// scale per site (half [k][nb][nblk*192], scale [k][nb][nblk*16])
+void blincomb_sites(const BArg& a, int k, const __half2* Z, const float* scale, double2* y, int nblk, int nb,
+                    hipStream_t s);
+
 // dst_r = sc[r] * src_r (zero where sc[r] == 0); src may equal dst
 template <typename T>
 void bscale(const BArg& a, const C<T>* src, C<T>* dst, long long n, int nb, hipStream_t s);

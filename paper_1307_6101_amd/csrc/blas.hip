@@ -135,6 +135,37 @@ void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, 
   DD_LAUNCH_CHECK();
 }
 
+__global__ void k_blincomb_sites(const BArg a, int k, const __half2* __restrict__ Z, const float* __restrict__ scale,
+                                 double2* __restrict__ y, int nblk, int nb) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15, r = blockIdx.y;
+  if (blk >= nblk) return;
+  const long long fs = (long long)nblk * 192, ss = (long long)nblk * 16;
+  const long long off = (long long)r * fs + (long long)blk * 192 + loc;
+  double2 acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = y[off + c * 16];
+  for (int j = 0; j < k; ++j) {
+    const double2 cj = a.coef(r, j);
+    const double m = scale[((long long)j * nb + r) * ss + (long long)blk * 16 + loc];
+    const __half2* zp = Z + (long long)j * nb * fs + off;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 h = __half22float2(zp[c * 16]);
+      cfma(acc[c], cj, make_double2((double)h.x * m, (double)h.y * m));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) y[off + c * 16] = acc[c];
+}
+
+void blincomb_sites(const BArg& a, int k, const __half2* Z, const float* scale, double2* y, int nblk, int nb,
+                    hipStream_t s) {
+  DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
+  k_blincomb_sites<<<dim3(nblocks((size_t)nblk * 16, 256), nb), 256, 0, s>>>(a, k, Z, scale, y, nblk, nb);
+  DD_LAUNCH_CHECK();
+}
+
 template <typename T>
 __global__ void k_bscale(const BArg a, const C<T>* __restrict__ src, C<T>* __restrict__ dst, long long n) {
   const int r = blockIdx.y;

@@ -205,6 +205,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->cycle = DDAMG_KCYCLE;
   p->half_storage = 0;
   p->batch = 16;
+  p->half_directions = 0;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {

@@ -84,4 +84,13 @@ void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour
 // FP64 -> FP16 copy of n complex numbers (operator storage)
 void to_half(const double2* in, __half2* out, long long n, hipStream_t s);
 
+// FP16 fine fields with one FP32 scale per site (the largest |re|, |im| of
+// the site's 12 components; entries stored divided by it), for nb fields:
+// half [nb][nblk*192], scale [nb][V] (site blk*16 + loc).  encode_sites also
+// writes the decoded FP64 field `dec` (the values the stored field stands
+// for).
+void encode_sites(const FineGeom& g, const float2* in, __half2* half, float* scale, double2* dec, int nb,
+                  hipStream_t s);
+
+
 }  // namespace ddamg

@@ -550,4 +550,36 @@ void to_half(const double2* in, __half2* out, long long n, hipStream_t s) {
   DD_LAUNCH_CHECK();
 }
 
+// one thread per site and field: largest |re|, |im| of the 12 components,
+// the components divided by it rounded to FP16, and their decoded FP64 value
+__global__ void k_encode_sites(const float2* __restrict__ in, __half2* __restrict__ half, float* __restrict__ scale,
+                               double2* __restrict__ dec, int nblk) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15;
+  if (blk >= nblk) return;
+  const long long fs = (long long)nblk * 192, off = (long long)blockIdx.y * fs + (long long)blk * 192 + loc;
+  float2 v[12];
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    v[c] = in[off + c * 16];
+    m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+  }
+  const float inv = m > 0.f ? 1.f / m : 0.f;
+  scale[(long long)blockIdx.y * nblk * 16 + (long long)blk * 16 + loc] = m;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const __half2 h = __floats2half2_rn(v[c].x * inv, v[c].y * inv);
+    half[off + c * 16] = h;
+    const float2 r = __half22float2(h);
+    dec[off + c * 16] = make_double2((double)r.x * m, (double)r.y * m);
+  }
+}
+
+void encode_sites(const FineGeom& g, const float2* in, __half2* half, float* scale, double2* dec, int nb,
+                  hipStream_t s) {
+  k_encode_sites<<<dim3(nblocks((size_t)g.nblk * 16, 256), nb), 256, 0, s>>>(in, half, scale, dec, g.nblk);
+  DD_LAUNCH_CHECK();
+}
+
 }  // namespace ddamg

@@ -124,6 +124,8 @@ struct Hierarchy {
   // outer FGMRES (FP64 basis, preconditioned directions at the preconditioner precision)
   DevArray<double2> oV, oZ64, ob, ox, ow, ot;
   DevArray<float2> oZ32;
+  DevArray<__half2> oZ16;          // FP16 directions with per-site scales (FP16 storage)
+  DevArray<float> oZs;
   DevArray<double2> sc64a, sc64b;   // scratch for canonical-layout calls
   DevArray<float2> sc32a, sc32b;
   std::unique_ptr<Reducer> red;

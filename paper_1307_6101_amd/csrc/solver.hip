@@ -482,6 +482,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
   const FineOpView<double> D = ctx->view<double>();
   double2* V = oV.p;
   C<T>* Z = outerZ<T>(*this).p;
+  // FP16 directions with per-site scales (FP16 storage, FP32 cycle)
+  const bool zh = std::is_same<T, float>::value && p.half_directions == 1;
   double2* w = ow.p;
   std::vector<double> bnorm, beta, target(nb), scale(nb);
   bnorms<double>(*red, b, n, nb, bnorm, s);
@@ -534,6 +536,13 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       if constexpr (std::is_same<T, double>::value) {
         cycle<double>(0, Vj, Zj, nb);
         dslash<double>(D, Zj, w, s, nb);
+      } else if (zh) {
+        vcopy<double, T>(Vj, W0.bin.p, vs, s);
+        cycle<T>(0, W0.bin.p, W0.x.p, nb);
+        // the stored direction is the FP16 one: D is applied to its decoded value
+        encode_sites(ctx->g, reinterpret_cast<const float2*>(W0.x.p), oZ16.p + (size_t)j * vs,
+                     oZs.p + (size_t)j * nb * ctx->g.V, ot.p, nb, s);
+        dslash<double>(D, ot.p, w, s, nb);
       } else {
         vcopy<double, T>(Vj, W0.bin.p, vs, s);
         cycle<T>(0, W0.bin.p, Zj, nb);
@@ -576,7 +585,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     }
     if (kmax > 0) {
       const BArg a = red->upload(cy, std::vector<double>(), nb, s);
-      blincomb<double, T>(a, kmax, Z, vs, x, n, nb, nullptr, s);
+      if (zh) blincomb_sites(a, kmax, oZ16.p, oZs.p, x, ctx->g.nblk, nb, s);
+      else blincomb<double, T>(a, kmax, Z, vs, x, n, nb, nullptr, s);
     }
     // true residuals in FP64
     dslash<double>(D, x, w, s, nb);
@@ -658,7 +668,13 @@ template <typename T> void Hierarchy::ensure_batch(int nb) {
   ob.alloc(n0);
   ox.alloc(n0);
   if (std::is_same<T, float>::value) {
-    oZ32.alloc((size_t)p.nkv * n0);
+    // FP16 preconditioned directions with one FP32 scale per site
+    if (p.half_directions == 1) {
+      oZ16.alloc((size_t)p.nkv * n0);
+      oZs.alloc((size_t)p.nkv * nb * ctx->g.V);
+    } else {
+      oZ32.alloc((size_t)p.nkv * n0);
+    }
     ot.alloc(n0);
   } else {
     oZ64.alloc((size_t)p.nkv * n0);
@@ -799,6 +815,9 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.half_storage == 0 || p.half_storage == 1, "half_storage must be 0 or 1");
   DD_REQUIRE(p.half_storage == 0 || p.precond_prec == DDAMG_F32,
              "FP16 operator storage needs the FP32 preconditioner");
+  DD_REQUIRE(p.half_directions == 0 || p.half_directions == 1, "half_directions must be 0 or 1");
+  DD_REQUIRE(p.half_directions == 0 || p.precond_prec == DDAMG_F32,
+             "FP16 directions need the FP32 preconditioner");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
   DD_REQUIRE(p.nkv >= 1 && p.nkv <= KMAX - 1, "nkv out of range");
   DD_REQUIRE(p.kc_len >= 1 && p.kc_len <= KMAX - 1 && p.kc_restarts >= 1, "bad K-cycle length");

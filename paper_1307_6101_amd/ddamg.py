@@ -55,6 +55,7 @@ class Params(ctypes.Structure):
         ("half_storage", ctypes.c_int),
         ("batch", ctypes.c_int),
         ("sap_block_l", (ctypes.c_int * 4) * 3),
+        ("half_directions", ctypes.c_int),
     ]
 
 

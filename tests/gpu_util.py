@@ -32,7 +32,7 @@ def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def to_params(dd, p, prec=None, cycle="K", half=False):
+def to_params(dd, p, prec=None, cycle="K", half=False, half_dirs=False):
     P = dd.params_default(int(p["levels"]))
     for l, a in enumerate(p["agg"]):
         for mu in range(4):
@@ -56,6 +56,7 @@ def to_params(dd, p, prec=None, cycle="K", half=False):
     P.precond_prec = dd.F64 if prec is None else prec
     P.cycle = dd.KCYCLE if cycle == "K" else dd.VCYCLE
     P.half_storage = 1 if half else 0
+    P.half_directions = 1 if half_dirs else 0
     return P
 
 

@@ -49,8 +49,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
          offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
   printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
-  printf("%zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
-         offsetof(ddamg_params, sap_block_l));
+  printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
+         offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions));
   return 0;
 }
 ''')
@@ -71,6 +71,7 @@ int main(void) {
     assert vals[9] == dd.Params.half_storage.offset
     assert vals[10] == dd.Params.batch.offset
     assert vals[11] == dd.Params.sap_block_l.offset
+    assert vals[12] == dd.Params.half_directions.offset
 
 
 def test_params_default_is_table1(dd):
@@ -83,7 +84,7 @@ def test_params_default_is_table1(dd):
     assert (p.kc_len, p.kc_restarts, p.nkv) == (5, 2, 10)
     assert p.coarse_eps == 5e-2 and p.kc_tol == 1e-1 and p.tol == 1e-10
     assert p.precond_prec == dd.F32 and p.cycle == dd.KCYCLE
-    assert p.half_storage == 0 and p.batch == 16
+    assert p.half_storage == 0 and p.batch == 16 and p.half_directions == 0
 
 
 def test_host_validation_rejects_bad_lattice(dd):

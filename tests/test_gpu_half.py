@@ -135,3 +135,22 @@ def test_half_solve_known_solution(dd, which, request):
     assert rc == dd.OK
     assert res <= 1e-10 and st[0]["true_relres"] <= 1e-10
     assert err < 1e-8
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_fp16_directions_solve(dd, three_h, half):
+    """outer directions stored in FP16 with a per-site scale: the solve still
+    reaches the certified tolerance (D is applied to the stored values)"""
+    P = to_params(dd, three_h.p, dd.F32, half=half, half_dirs=True)
+    H = dd.build_hierarchy(three_h.ctx, P, dev(three_h.tv))
+    zstar = W.gaussian_spinor(three_h.dims, 62, nrhs=3)
+    b = np.stack([three_h.op.apply(x) for x in zstar])
+    z = empty(b.shape)
+    rc, st = dd.solve(H, dev(b), z, nrhs=3)
+    zz = host(z)
+    say(f"  FP16 directions (half storage {half}): its {[s['outer_iters'] for s in st]}")
+    assert rc == dd.OK
+    for r in range(3):
+        assert norm(b[r] - three_h.op.apply(zz[r])) / norm(b[r]) <= 1e-10
+        assert relerr(zz[r], zstar[r]) < 1e-8
+

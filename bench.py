@@ -36,6 +36,10 @@ WORKLOAD = "clover16x32_3lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
 BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"
 FOUR_LEVEL_WORKLOAD = "clover48x96_4lvl"
+UNEVEN_WORKLOAD = "uneven8_3lvl"
+# coarsest GMRES of the graph-captured V-cycle: restart length, cycles (a
+# fixed launch sequence, steps after convergence doing nothing)
+GRAPH_COARSE = (8, 1)
 # compulsory bytes of one Wilson-clover apply per site: spinor in (24 reals),
 # 4 links (72 reals: each link serves two sites), clover (72 reals), spinor out
 # (24 reals) -> 192 reals
@@ -61,9 +65,10 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD],
                     help="the bench workload (default), the 32^3x64 lattice with the 12 point sources "
-                         "solved in one batch, or the 48^3x96 four-level lattice")
+                         "solved in one batch, the 48^3x96 four-level lattice, or the uneven batch of eight "
+                         "lattices (four 16^4, two 24^3x48, two 32^3x64) solved concurrently")
     ap.add_argument("--lattice", default=None,
                     help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
@@ -91,6 +96,9 @@ def main():
     cfg = W.CONFIGS[WORKLOAD]
     if args.kernels_only:
         kernels_only(args, cfg, dd, W, np, torch)
+        return
+    if args.workload == UNEVEN_WORKLOAD:
+        uneven_workload(args, dd, W, np, torch)
         return
     if args.workload != WORKLOAD:
         big_workload(args, args.workload, W.CONFIGS[args.workload], dd, W, np, torch)
@@ -564,6 +572,164 @@ def cpu_baseline(cfg, U, b, outer_iters, V):
             "sample": f"fine-level work of one outer iteration (5 SAP sweeps + 1 Dpsi, FP64 numpy) on the "
                       f"full 16^3x32 lattice took {wall:.2f}s; x{outer_iters} outer iterations; coarse "
                       f"levels and setup excluded (upper bound)"}
+
+
+def uneven_workload(args, dd, W, np, torch):
+    """The uneven batch: eight independent lattices (four 16^4, two 24^3x48,
+    two 32^3x64; own links, eps 0.45-0.6, m0 -0.45..-0.3), each with its own
+    three-level hierarchy (FP32 preconditioner, FP64 outer FGMRES, one
+    complex Gaussian right-hand side).  A step solves all eight with
+    ddamg_solve_many (concurrently, one stream per hierarchy) using the
+    K-cycle.  Also timed: the same eight one after another; the V-cycle,
+    host-driven and graph-captured (coarsest GMRES with device-side scalars
+    and a fixed launch sequence); the plain FP64 method one after another."""
+    dev = torch.device("cuda:0")
+    n = len(W.UNEVEN_BATCH)
+    cfgs = [W.uneven_batch_config(j) for j in range(n)]
+    sites = sum(int(np.prod(c["dims"])) for c in cfgs)
+    log(f"[bench] workload {UNEVEN_WORKLOAD}: {n} lattices, {sites} fine sites")
+
+    def params(cfg, prec, cycle, graph=False):
+        p = dd.params_default(cfg["levels"])
+        for l, a in enumerate(cfg["agg"]):
+            for mu in range(4):
+                p.agg[l][mu] = a[mu]
+        for l, k in enumerate(cfg["ntv"]):
+            p.ntv[l] = k
+        for l, blk in enumerate(cfg["sap_blocks"][1:]):
+            for mu in range(4):
+                p.sap_block_l[l][mu] = blk[mu]
+        p.nu = cfg["nu"]
+        p.cycle = dd.VCYCLE if cycle == "V" else dd.KCYCLE
+        p.precond_prec = prec
+        p.batch = 1
+        if graph:
+            p.graph = 1
+            p.coarse_restart, p.coarse_max_restarts = GRAPH_COARSE
+        return p
+
+    ctxs, tvs, bs, zs = [], [], [], []
+    for j, cfg in enumerate(cfgs):
+        t = time.time()
+        dims = cfg["dims"]
+        U = W.links(dims, cfg["eps"], cfg["seed_links"])
+        ctxs.append(dd.create(dims, cfg["m0"], cfg["csw"], torch.from_numpy(U).to(dev)))
+        del U
+        tvs.append(torch.from_numpy(W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])).to(dev))
+        bs.append(torch.from_numpy(W.gaussian_spinor(dims, cfg["seed_rhs"])).unsqueeze(0).to(dev))
+        zs.append(torch.zeros_like(bs[-1]))
+        log(f"[bench] lattice {j} {dims} eps={cfg['eps']} m0={cfg['m0']}: inputs {time.time() - t:.1f}s")
+
+    def build_set(prec, cycle, graph=False):
+        hs, su = [], []
+        for j, cfg in enumerate(cfgs):
+            torch.cuda.synchronize()
+            t = time.time()
+            hs.append(dd.build_hierarchy(ctxs[j], params(cfg, prec, cycle, graph), tvs[j]))
+            torch.cuda.synchronize()
+            su.append(round(time.time() - t, 3))
+        return hs, su
+
+    def zero_all():
+        for z in zs:
+            z.zero_()
+        torch.cuda.synchronize()
+
+    def together(hs):
+        zero_all()
+        t = time.time()
+        rc, st = dd.solve_many(hs, bs, zs)
+        torch.cuda.synchronize()
+        return time.time() - t, rc, st
+
+    def one_by_one(hs):
+        zero_all()
+        per, stats = [], []
+        for H, b, z in zip(hs, bs, zs):
+            t = time.time()
+            rc, st = dd.solve(H, b, z)
+            torch.cuda.synchronize()
+            per.append(time.time() - t)
+            stats += st
+        return per, stats
+
+    def summary(st):
+        return dict(status=[x["status"] for x in st], outer_iters=[x["outer_iters"] for x in st],
+                    coarsest_iters=[x["coarsest_iters"] for x in st],
+                    max_true_relres=max(x["true_relres"] for x in st))
+
+    def run_set(name, prec, cycle, graph, reps):
+        hs, su = build_set(prec, cycle, graph)
+        log(f"[bench] {name}: setup {su}")
+        times, st = [], None
+        for i in range(reps):
+            tt, rc, st = together(hs)
+            times.append(tt)
+            log(f"[bench] {name}, together #{i}: {tt:.3f}s rc={rc} its {[x['outer_iters'] for x in st]} "
+                f"coarsest {[x['coarsest_iters'] for x in st]}")
+        per, st1 = one_by_one(hs)
+        log(f"[bench] {name}, one after another: {sum(per):.3f}s {[round(x, 4) for x in per]} "
+            f"its {[x['outer_iters'] for x in st1]}")
+        out = dict(setup_s=su, together_s=round(float(np.mean(times[-max(1, reps - 1):])), 4),
+                   one_after_another_s=round(sum(per), 4), per_system_alone_s=[round(x, 4) for x in per],
+                   **summary(st))
+        del hs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out, times
+
+    reps = args.warmup + args.steps
+    kres, ktimes = run_set("mixed K-cycle", dd.F32, "K", False, reps)
+    vres, _ = run_set("mixed V-cycle", dd.F32, "V", False, 2)
+    gres, _ = run_set("mixed V-cycle, graph-captured", dd.F32, "V", True, 3)
+    gres["coarsest_budget"] = {"restart": GRAPH_COARSE[0], "cycles": GRAPH_COARSE[1]}
+    plain = None
+    if not args.no_plain:
+        per, its, su, stat = [], [], [], []
+        for j, cfg in enumerate(cfgs):
+            torch.cuda.synchronize()
+            t = time.time()
+            H64 = dd.build_hierarchy(ctxs[j], params(cfg, dd.F64, "K"), tvs[j])
+            torch.cuda.synchronize()
+            su.append(round(time.time() - t, 3))
+            zs[j].zero_()
+            torch.cuda.synchronize()
+            t = time.time()
+            rc, st = dd.solve(H64, bs[j], zs[j])
+            torch.cuda.synchronize()
+            per.append(time.time() - t)
+            its.append(st[0]["outer_iters"])
+            stat.append(st[0]["status"])
+            del H64
+            log(f"[bench] plain FP64 lattice {j}: setup {su[-1]:.2f}s, solve {per[-1]:.3f}s rc={rc}, its {its[-1]}")
+        plain = dict(total_s=round(sum(per), 4), per_system_s=[round(x, 4) for x in per], outer_iters=its,
+                     status=stat, setup_s=su)
+    ms = 1000.0 * float(np.mean(ktimes[args.warmup:] or ktimes))
+    line = {
+        "metric": METRIC,
+        "value": round(n / (ms / 1000.0), 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner, f64 outer",
+        "data": "synthetic (seeded SU(3) links exp(i eps H) per lattice, one Gaussian rhs each)",
+        "config": {"workload": "uneven batch of 8 independent Wilson-clover lattices (4 x 16^4, 2 x 24^3x48, "
+                               "2 x 32^3x64; eps 0.45-0.6, m0 -0.45..-0.3, massive side of criticality, c_sw=1), "
+                               "3 levels each, K-cycle, tol 1e-10, solved concurrently",
+                   "parallelism": "1 GPU"},
+        "fine_sites": sites,
+        "kcycle": kres,
+        "vcycle": vres,
+        "vcycle_graph_captured": gres,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": round(plain["total_s"] / (ms / 1000.0), 3) if plain else None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

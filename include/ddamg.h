@@ -133,6 +133,21 @@ typedef struct {
                                  lattices, at the price of more outer
                                  iterations.  Needs precond_prec = DDAMG_F32.
                                  0 (default): FP32 directions. */
+  int graph;                  /* 1: ddamg_solve applies the preconditioner by
+                                 replaying a HIP graph captured once per batch
+                                 size (no host round trip inside a cycle).
+                                 The coarsest GMRES then keeps its Krylov
+                                 scalars (Hessenberg matrix, Givens rotations,
+                                 stopping test) on the device and issues a
+                                 fixed sequence of launches: coarse_restart
+                                 steps in each of coarse_max_restarts cycles,
+                                 the steps after a system has reached
+                                 coarse_eps changing nothing, so results equal
+                                 those of the host-driven solve up to
+                                 rounding while costing the full launch
+                                 count.  Needs the V-cycle when levels >= 3
+                                 (the K-cycle's stopping tests are data
+                                 dependent).  0 (default): host-driven. */
 } ddamg_params;
 
 typedef struct {
@@ -235,6 +250,27 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
  * right-hand side did (a non-finite inner residual fails the whole batch). */
 int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
                 void* stream);
+
+/* Independent systems on different lattices (an uneven batch: the sizes,
+ * links, masses and hierarchy parameters of the n hierarchies may all
+ * differ), solved concurrently.  System i is ddamg_solve(hiers[i], b[i],
+ * z[i], nrhs[i], ...) with the same arguments, layout, ownership and result:
+ * b[i], z[i] are device pointers to nrhs[i] canonical complex128 fields of
+ * hiers[i]'s fine lattice, z[i] holding the initial guess.  Each hierarchy
+ * runs on a stream of its own (created on first use, default priority,
+ * destroyed with the hierarchy) driven by its own host thread, so the
+ * kernels of the systems overlap on the device; all of them start after
+ * the work already enqueued on `stream`.  stats (host, may be NULL) holds
+ * sum(nrhs) records, those of system i after those of systems 0..i-1.
+ * Synchronous: returns when every system is done.  1 <= n <=
+ * DDAMG_MAX_SYSTEMS; every hierarchy at most once (DDAMG_EINVAL otherwise);
+ * hierarchies may share a context.  Returns the first failure of the
+ * library (message names the system), else DDAMG_ENOCONV /
+ * DDAMG_ENONFINITE if any system did, else DDAMG_OK.  The hierarchies must
+ * not be used by other calls while this one runs. */
+#define DDAMG_MAX_SYSTEMS 64
+int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void* const* z, const int* nrhs,
+                     ddamg_solve_stats* stats, void* stream);
 
 /* Export the orthonormalised interpolation basis of level `level` as
  * ntv[level] canonical complex128 fields of that level ([N][V_l][d_l]), and

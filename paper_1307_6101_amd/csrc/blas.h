@@ -64,9 +64,11 @@ class Reducer {
   ~Reducer();
   // batched: a == nullptr for plain inner products, else the update
   // w_r += sum_j c[r][j] V_{j,r} first
+  // (results to `out` in device memory, same layout, when it is given;
+  // no host access then, so the call can be captured into a graph)
   template <typename T>
   void bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
-             hipStream_t s);
+             hipStream_t s, double2* out = nullptr);
   // results of the last batched call, out[r * (k+1) + j] (synchronises)
   void bfetch(int k1, int nb, std::complex<double>* out, hipStream_t s);
   // the coefficients (row r: system r, KMAX per row; missing entries 0) and

@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) k_bdots_pass2(const double* __restrict__ 
 
 template <typename T>
 void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
-                    hipStream_t s) {
+                    hipStream_t s, double2* dev_out) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched inner products");
   // short vectors (the coarse levels): one workgroup of RED_BS_ONE threads
   // per system writes the result directly, no second pass
@@ -245,7 +245,7 @@ void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>
   long long g = one ? 1 : (n + RED_BS * 4 - 1) / (RED_BS * 4);
   if (g > GMAX) g = GMAX;
   if (g < 1) g = 1;
-  double* out = reinterpret_cast<double*>(result_);
+  double* out = reinterpret_cast<double*>(dev_out ? dev_out : result_);
   static const BArg none{};
   BDotsLaunch<T, 0>::go(k, (unsigned)g, one ? RED_BS_ONE : RED_BS, nb, s, a ? *a : none, a ? 1 : 0, V, vstride,
                         w, n, g == 1 ? out : partial_);
@@ -328,7 +328,7 @@ Reducer::~Reducer() {
   template void vzero<T>(C<T>*, long long, hipStream_t);                                     \
   template void vbmy<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
   template void Reducer::bdots<T>(const BArg*, const C<T>*, long long, int, C<T>*, long long, int, \
-                                  hipStream_t);                                                \
+                                  hipStream_t, double2*);                                      \
   template void blincomb<T, T>(const BArg&, int, const C<T>*, long long, C<T>*, long long, int, C<T>*, \
                                hipStream_t);                                               \
   template void bscale<T>(const BArg&, const C<T>*, C<T>*, long long, int, hipStream_t);

@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "solver.h"
 
@@ -206,6 +208,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->half_storage = 0;
   p->batch = 16;
   p->half_directions = 0;
+  p->graph = 0;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {
@@ -365,44 +368,139 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
   });
 }
 
+namespace {
+
+// Solves the nrhs systems of one hierarchy on stream s, params.batch at a
+// time; fills stats (per system) and returns the worst per-system outcome
+// (DDAMG_OK, DDAMG_ENOCONV or DDAMG_ENONFINITE).  Failures of the library
+// itself throw.
+int solve_batches(Hierarchy& H, const void* b, void* z, int nrhs, ddamg_solve_stats* stats, hipStream_t s) {
+  int worst = DDAMG_OK;
+  if (H.p.graph && (!H.own_s || s != H.own_s)) {
+    // graphs are captured on the hierarchy's own stream (the caller's may be
+    // the null stream, which cannot be captured), ordered after the caller's
+    if (!H.own_s) DD_CHECK_HIP(hipStreamCreateWithFlags(&H.own_s, hipStreamNonBlocking));
+    hipEvent_t ready = nullptr;
+    DD_CHECK_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    const hipError_t e1 = hipEventRecord(ready, s);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(H.own_s, ready, 0) : e1;
+    (void)hipEventDestroy(ready);
+    DD_CHECK_HIP(e2);
+    s = H.own_s;
+  }
+  H.s = s;
+  const long long n = H.lv[0].n;
+  const int bmax = std::min(nrhs, H.p.batch);
+  if (H.p.precond_prec == DDAMG_F64) H.ensure_batch<double>(bmax);
+  else H.ensure_batch<float>(bmax);
+  std::vector<ddamg_solve_stats> st(bmax);
+  for (int r0 = 0; r0 < nrhs; r0 += bmax) {
+    const int nb = std::min(bmax, nrhs - r0);
+    auto t0 = std::chrono::steady_clock::now();
+    for (auto& e : st) std::memset(&e, 0, sizeof(e));
+    std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
+    std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
+    fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r0 * n, H.ob.p, nb, H.s);
+    fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r0 * n, H.ox.p, nb, H.s);
+    if (H.p.precond_prec == DDAMG_F64) H.outer<double>(H.ob.p, H.ox.p, st.data(), nb);
+    else H.outer<float>(H.ob.p, H.ox.p, st.data(), nb);
+    fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r0 * n, nb, H.s);
+    DD_CHECK_HIP(hipStreamSynchronize(H.s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nb; ++r) {
+      st[r].kcycle_iters = H.kc_it[r];
+      st[r].coarsest_iters = H.cs_it[r];
+      st[r].seconds = secs;
+      if (stats) stats[r0 + r] = st[r];
+      if (st[r].status != DDAMG_OK && worst == DDAMG_OK) worst = st[r].status;
+    }
+  }
+  return worst;
+}
+
+int report_worst(int worst) {
+  if (worst == DDAMG_ENOCONV) g_err = "outer FGMRES reached max_restarts before tol";
+  if (worst == DDAMG_ENONFINITE) g_err = "non-finite value in b or in a residual";
+  return worst;
+}
+
+}  // namespace
+
 int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
                 void* stream) {
   int worst = DDAMG_OK;
   int rc = guarded([&] {
     Hierarchy& H = H_(hier);
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
-    H.s = as_stream(stream);
-    const long long n = H.lv[0].n;
-    const int bmax = std::min(nrhs, H.p.batch);
-    if (H.p.precond_prec == DDAMG_F64) H.ensure_batch<double>(bmax);
-    else H.ensure_batch<float>(bmax);
-    std::vector<ddamg_solve_stats> st(bmax);
-    for (int r0 = 0; r0 < nrhs; r0 += bmax) {
-      const int nb = std::min(bmax, nrhs - r0);
-      auto t0 = std::chrono::steady_clock::now();
-      for (auto& e : st) std::memset(&e, 0, sizeof(e));
-      std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
-      std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
-      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r0 * n, H.ob.p, nb, H.s);
-      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r0 * n, H.ox.p, nb, H.s);
-      if (H.p.precond_prec == DDAMG_F64) H.outer<double>(H.ob.p, H.ox.p, st.data(), nb);
-      else H.outer<float>(H.ob.p, H.ox.p, st.data(), nb);
-      fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r0 * n, nb, H.s);
-      DD_CHECK_HIP(hipStreamSynchronize(H.s));
-      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      for (int r = 0; r < nb; ++r) {
-        st[r].kcycle_iters = H.kc_it[r];
-        st[r].coarsest_iters = H.cs_it[r];
-        st[r].seconds = secs;
-        if (stats) stats[r0 + r] = st[r];
-        if (st[r].status != DDAMG_OK && worst == DDAMG_OK) worst = st[r].status;
-      }
-    }
+    worst = solve_batches(H, b, z, nrhs, stats, as_stream(stream));
   });
   if (rc != DDAMG_OK) return rc;
-  if (worst == DDAMG_ENOCONV) g_err = "outer FGMRES reached max_restarts before tol";
-  if (worst == DDAMG_ENONFINITE) g_err = "non-finite value in b or in a residual";
-  return worst;
+  return report_worst(worst);
+}
+
+int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void* const* z, const int* nrhs,
+                     ddamg_solve_stats* stats, void* stream) {
+  std::vector<int> worst(n > 0 ? n : 0, DDAMG_OK), rcs(n > 0 ? n : 0, DDAMG_OK);
+  std::vector<std::string> msgs(n > 0 ? n : 0);
+  int rc = guarded([&] {
+    DD_REQUIRE(n >= 1 && n <= DDAMG_MAX_SYSTEMS, "n must be in 1..DDAMG_MAX_SYSTEMS");
+    DD_REQUIRE(hiers && b && z && nrhs, "null argument array");
+    std::vector<long long> off(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      DD_REQUIRE(hiers[i] != nullptr, "null hierarchy");
+      DD_REQUIRE(b[i] && z[i] && b[i] != z[i] && nrhs[i] >= 1, "bad argument for system " + std::to_string(i));
+      for (int k = 0; k < i; ++k)
+        DD_REQUIRE(hiers[k] != hiers[i], "a hierarchy appears twice (its solves would share buffers)");
+      off[i + 1] = off[i] + nrhs[i];
+    }
+    int dev = 0;
+    DD_CHECK_HIP(hipGetDevice(&dev));
+    // the inputs are ordered after the work already on the caller's stream
+    struct Ev {
+      hipEvent_t e = nullptr;
+      ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ready;
+    DD_CHECK_HIP(hipEventCreateWithFlags(&ready.e, hipEventDisableTiming));
+    DD_CHECK_HIP(hipEventRecord(ready.e, as_stream(stream)));
+    for (int i = 0; i < n; ++i) {
+      Hierarchy& H = H_(hiers[i]);
+      if (!H.own_s) DD_CHECK_HIP(hipStreamCreateWithFlags(&H.own_s, hipStreamNonBlocking));
+      DD_CHECK_HIP(hipStreamWaitEvent(H.own_s, ready.e, 0));
+    }
+    // one host thread per system: each drives its hierarchy's solver on the
+    // hierarchy's own stream, so the kernels of different systems overlap
+    // and one system's host round trips hide behind the others' work
+    struct Joiner {
+      std::vector<std::thread> t;
+      ~Joiner() { for (auto& x : t) if (x.joinable()) x.join(); }
+    } th;
+    th.t.reserve(n);
+    for (int i = 0; i < n; ++i)
+      th.t.emplace_back([&, i] {
+        try {
+          Hierarchy& H = H_(hiers[i]);
+          DD_CHECK_HIP(hipSetDevice(dev));
+          worst[i] = solve_batches(H, b[i], z[i], nrhs[i], stats ? stats + off[i] : nullptr, H.own_s);
+        } catch (const Error& e) {
+          rcs[i] = e.status;
+          msgs[i] = e.what();
+        } catch (const std::exception& e) {
+          rcs[i] = DDAMG_EHIP;
+          msgs[i] = e.what();
+        } catch (...) {
+          rcs[i] = DDAMG_EHIP;
+          msgs[i] = "unknown failure";
+        }
+      });
+    for (auto& t : th.t) t.join();
+    for (int i = 0; i < n; ++i)
+      if (rcs[i] != DDAMG_OK) throw Error(rcs[i], "system " + std::to_string(i) + ": " + msgs[i]);
+  });
+  if (rc != DDAMG_OK) return rc;
+  int w = DDAMG_OK;
+  for (int i = 0; i < n; ++i)
+    if (worst[i] != DDAMG_OK && w == DDAMG_OK) w = worst[i];
+  return report_worst(w);
 }
 
 int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream) {

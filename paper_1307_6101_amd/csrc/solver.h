@@ -13,6 +13,7 @@
 #include "../../include/ddamg.h"
 #include "blas.h"
 #include "coarse.h"
+#include "dgmres.h"
 #include "fine.h"
 #include "transfer.h"
 
@@ -130,6 +131,7 @@ struct Hierarchy {
   DevArray<float2> sc32a, sc32b;
   std::unique_ptr<Reducer> red;
   hipStream_t s = nullptr;
+  hipStream_t own_s = nullptr;     // the hierarchy's own stream (concurrent solves), made on first use
   bool recording = false;
   // setup record: visit[r] says whether system r is really being visited
   // (live in every enclosing FGMRES), so its record may be overwritten
@@ -138,6 +140,24 @@ struct Hierarchy {
   int ocap = 0;                    // batch capacity of the outer solver's buffers
   std::vector<long long> kc_it, cs_it;   // per system of the batch: K-cycle / coarsest iterations
   const double2* tv_extra = nullptr;
+  // device-side GMRES scalars (graph mode) and the captured preconditioner
+  // graphs, one per (precision, batch size); `gen` counts reallocations of
+  // the buffers a graph has baked in
+  DevArray<GmSys> gm_sys;
+  DevArray<double2> gm_res, gm_coef;
+  DevArray<double> gm_scale;
+  DevArray<long long> gm_iters;
+  bool dev_scalars = false;
+  long long gen = 0;
+  struct PreGraph {
+    hipGraphExec_t exec = nullptr;
+    int nb = 0;
+    bool f32 = false;
+    long long gen = -1;
+  };
+  std::vector<PreGraph> graphs;
+  DevGmres gm();
+  void drop_graphs();
 
   template <typename T> Work<T>& work(int l);
   template <typename T> const C<T>* P(int l) const;
@@ -160,6 +180,13 @@ struct Hierarchy {
   // result for each equals that of a solve on its own.
   template <typename T> void cycle(int l, const C<T>* b, C<T>* z, int nb = 1);
   template <typename T> void coarsest_solve(const C<T>* b, C<T>* z, int nb);
+  // the same with the GMRES scalars on the device (fixed launch sequence)
+  template <typename T> void coarsest_solve_dev(const C<T>* b, C<T>* z, int nb);
+  template <typename T, typename Op>
+  void gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb);
+  // level-0 cycle of the batch, work<T>(0).bin -> work<T>(0).x, by replaying
+  // the captured graph (captured on first use after an eager run)
+  template <typename T> void apply_pre_graph(int nb);
   template <typename T> void schur(const C<T>* v, C<T>* out, int nb);
   // FGMRES(m) from x = 0; iters[r] += iterations of system r
   template <typename T, typename Op, typename Pre>
@@ -186,6 +213,13 @@ struct Hierarchy {
   void build_level(int l, bool from32);
   template <typename T> void alloc_work(int cap);
 
+  Hierarchy() = default;
+  Hierarchy(const Hierarchy&) = delete;
+  Hierarchy& operator=(const Hierarchy&) = delete;
+  ~Hierarchy() {
+    drop_graphs();
+    if (own_s) (void)hipStreamDestroy(own_s);
+  }
 };
 
 Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s);

@@ -133,6 +133,10 @@ template <> SapScratch<float>& sap_scratch<float>(LevelStore& L_, int nb) {
   return sap_buffers<float>(L_.sr32, L_.sq32, L_.sp32, L_.ss32, L_.n, L_.V, nb);
 }
 
+template <typename T> const void* sap_scratch_base(const LevelStore& L_);
+template <> const void* sap_scratch_base<double>(const LevelStore& L_) { return L_.sr64.p; }
+template <> const void* sap_scratch_base<float>(const LevelStore& L_) { return L_.sr32.p; }
+
 template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsweeps, int nb) {
   for (int it = 0; it < nsweeps; ++it)
     for (int col = 0; col < 2; ++col) {
@@ -140,7 +144,9 @@ template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsw
         fine_op<T>([&](const auto& op) { sap_colour(op, ctx->cblk.p, col, p.mr_iters, b, z, s, nb); });
       } else {
         LevelStore& L_ = lv[l];
+        const void* before = sap_scratch_base<T>(L_);
         SapScratch<T>& ws = sap_scratch<T>(L_, nb);
+        if (sap_scratch_base<T>(L_) != before) ++gen;
         coarse_op<T>(l, [&](const auto& op) {
           coarse_sap_colour(op, L_.sap_tables(), col, p.mr_iters, b, z, ws, s, nb);
         });
@@ -430,6 +436,145 @@ template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z, int
 }
 
 // ---------------------------------------------------------------------------
+// GMRES(m) from x = 0 with the scalars on the device: the host-driven
+// fgmres above (unpreconditioned) as a fixed sequence of launches
+// ---------------------------------------------------------------------------
+DevGmres Hierarchy::gm() {
+  if (!gm_sys.p) {
+    gm_sys.alloc(NBMAX);
+    gm_res.alloc((size_t)NBMAX * (KMAX + 1));
+    gm_coef.alloc((size_t)NBMAX * KMAX);
+    gm_scale.alloc(NBMAX);
+    gm_iters.alloc(NBMAX);
+    ++gen;
+  }
+  DevGmres d;
+  d.sys = gm_sys.p;
+  d.res = gm_res.p;
+  d.coef = gm_coef.p;
+  d.scale = gm_scale.p;
+  d.iters = gm_iters.p;
+  return d;
+}
+
+template <typename T, typename Op>
+void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb) {
+  Work<T>& W = work<T>(l);
+  const long long n = lv[l].n, vs = (long long)nb * n;
+  DD_REQUIRE(m <= W.m && nb <= W.cap, "Krylov basis too short for the batch");
+  const DevGmres d = gm();
+  const BArg a = d.arg();
+  C<T>* V = W.V.p;
+  C<T>* w = W.w.p;
+  vzero<T>(x, vs, s);
+  for (int c = 0; c < cycles; ++c) {
+    // r = b (first cycle) or b - A x: its norm starts the cycle
+    const C<T>* r0 = b;
+    if (c > 0) {
+      op(x, w);
+      vbmy<T>(b, w, vs, s);
+      r0 = w;
+    }
+    red->bdots<T>(nullptr, r0, 0, 0, const_cast<C<T>*>(r0), n, nb, s, d.res);
+    gm_begin(d, m, nb, tol, c == 0, s);
+    bscale<T>(a, r0, V, n, nb, s);
+    for (int j = 0; j < m; ++j) {
+      op(V + (size_t)j * vs, w);
+      red->bdots<T>(nullptr, V, vs, j + 1, w, n, nb, s, d.res);
+      gm_cgs1(d, j, nb, s);
+      red->bdots<T>(&a, V, vs, j + 1, w, n, nb, s, d.res);
+      gm_step(d, j, m, nb, s);
+      if (j + 1 < m) blincomb<T, T>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+    }
+    gm_solve(d, m, nb, s);
+    blincomb<T, T>(a, m, V, vs, x, n, nb, nullptr, s);
+  }
+}
+
+template <typename T> void Hierarchy::coarsest_solve_dev(const C<T>* b, C<T>* z, int nb) {
+  const int c = L - 1;
+  const LevelStore& L_ = lv[c];
+  Work<T>& W = work<T>(c);
+  const long long n = L_.n;
+  if (!L_.cg.bipartite) {
+    gmres_dev<T>(
+        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); }, b, z, p.coarse_restart,
+        p.coarse_max_restarts, p.coarse_eps, nb);
+    return;
+  }
+  const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
+  vzero<T>(W.t1.p, n * nb, s);
+  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, b, W.t1.p, s, nb);
+  vzero<T>(W.t2.p, n * nb, s);
+  coarse_op<T>(c, [&](const auto& op) {
+    coarse_site_apply(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s, nb);
+  });
+  gmres_dev<T>(
+      c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o, nb); }, W.t2.p, z, p.coarse_restart,
+      p.coarse_max_restarts, p.coarse_eps, nb);
+  coarse_op<T>(c, [&](const auto& op) {
+    coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s, nb);
+  });
+  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, W.t1.p, z, s, nb);
+}
+
+void Hierarchy::drop_graphs() {
+  for (auto& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
+// The level-0 cycle captured into a HIP graph.  The first call for a batch
+// size (or after buffers were reallocated) runs the cycle eagerly, which
+// also grows any scratch it needs, and then captures the same launches;
+// later calls replay the graph.  The capture is thread-local, so other
+// threads may keep using the device meanwhile.
+template <typename T> void Hierarchy::apply_pre_graph(int nb) {
+  Work<T>& W0 = work<T>(0);
+  const bool f32 = std::is_same<T, float>::value;
+  PreGraph* G = nullptr;
+  for (auto& g : graphs)
+    if (g.nb == nb && g.f32 == f32) G = &g;
+  if (G && G->gen == gen && G->exec) {
+    DD_CHECK_HIP(hipGraphLaunch(G->exec, s));
+    return;
+  }
+  if (G && G->gen != gen) {
+    // buffers changed: every graph is stale
+    drop_graphs();
+    G = nullptr;
+  }
+  dev_scalars = true;
+  try {
+    cycle<T>(0, W0.bin.p, W0.x.p, nb);
+    hipGraph_t graph = nullptr;
+    DD_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      cycle<T>(0, W0.bin.p, W0.x.p, nb);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(s, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      (void)hipGetLastError();
+      throw;
+    }
+    DD_CHECK_HIP(hipStreamEndCapture(s, &graph));
+    PreGraph ng;
+    ng.nb = nb;
+    ng.f32 = f32;
+    ng.gen = gen;
+    const hipError_t e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    DD_CHECK_HIP(e);
+    graphs.push_back(ng);
+  } catch (...) {
+    dev_scalars = false;
+    throw;
+  }
+  dev_scalars = false;
+}
+
+// ---------------------------------------------------------------------------
 // the level-l cycle (Alg. 1; Alg. 2 replaces the recursive call by FGMRES)
 // ---------------------------------------------------------------------------
 template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int nb) {
@@ -447,7 +592,8 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
     restrict_to<T>(l, b, Wc.bin.p, nb);
   }
   if (l + 1 == L - 1) {
-    coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb);
+    if (dev_scalars) coarsest_solve_dev<T>(Wc.bin.p, Wc.z.p, nb);
+    else coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb);
   } else if (p.cycle == DDAMG_KCYCLE) {
     const int c = l + 1;
     fgmres<T>(
@@ -484,6 +630,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
   C<T>* Z = outerZ<T>(*this).p;
   // FP16 directions with per-site scales (FP16 storage, FP32 cycle)
   const bool zh = std::is_same<T, float>::value && p.half_directions == 1;
+  if (p.graph) gm_reset(gm(), nb, s);
   double2* w = ow.p;
   std::vector<double> bnorm, beta, target(nb), scale(nb);
   bnorms<double>(*red, b, n, nb, bnorm, s);
@@ -533,7 +680,22 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     for (int j = 0; j < m; ++j) {
       double2* Vj = V + (size_t)j * vs;
       C<T>* Zj = Z + (size_t)j * vs;
-      if constexpr (std::is_same<T, double>::value) {
+      if (p.graph) {
+        vcopy<double, T>(Vj, W0.bin.p, vs, s);
+        apply_pre_graph<T>(nb);
+        if (zh) {
+          encode_sites(ctx->g, reinterpret_cast<const float2*>(W0.x.p), oZ16.p + (size_t)j * vs,
+                       oZs.p + (size_t)j * nb * ctx->g.V, ot.p, nb, s);
+          dslash<double>(D, ot.p, w, s, nb);
+        } else if constexpr (std::is_same<T, double>::value) {
+          vcopy<double, double>(W0.x.p, Zj, vs, s);
+          dslash<double>(D, Zj, w, s, nb);
+        } else {
+          vcopy<T, T>(W0.x.p, Zj, vs, s);
+          vcopy<T, double>(W0.x.p, ot.p, vs, s);
+          dslash<double>(D, ot.p, w, s, nb);
+        }
+      } else if constexpr (std::is_same<T, double>::value) {
         cycle<double>(0, Vj, Zj, nb);
         dslash<double>(D, Zj, w, s, nb);
       } else if (zh) {
@@ -607,6 +769,12 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     st[r].status = status[r];
     st[r].true_relres = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
   }
+  if (p.graph) {
+    std::vector<long long> it(nb);
+    DD_CHECK_HIP(hipMemcpyAsync(it.data(), gm_iters.p, sizeof(long long) * nb, hipMemcpyDeviceToHost, s));
+    DD_CHECK_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nb; ++r) cs_it[r] += it[r];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -617,6 +785,7 @@ template <> std::vector<Work<double>>& work_vec<double>(Hierarchy& H) { return H
 template <> std::vector<Work<float>>& work_vec<float>(Hierarchy& H) { return H.w32; }
 
 template <typename T> void Hierarchy::alloc_work(int cap) {
+  ++gen;
   std::vector<Work<T>>& W = work_vec<T>(*this);
   W.clear();
   W.resize(L);
@@ -683,6 +852,7 @@ template <typename T> void Hierarchy::ensure_batch(int nb) {
 }
 
 void Hierarchy::build_level(int l, bool from32) {
+  ++gen;
   LevelStore& F = lv[l];
   LevelStore& Cc = lv[l + 1];
   const long long n = F.n;
@@ -818,6 +988,9 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.half_directions == 0 || p.half_directions == 1, "half_directions must be 0 or 1");
   DD_REQUIRE(p.half_directions == 0 || p.precond_prec == DDAMG_F32,
              "FP16 directions need the FP32 preconditioner");
+  DD_REQUIRE(p.graph == 0 || p.graph == 1, "graph must be 0 or 1");
+  DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle == DDAMG_VCYCLE,
+             "a graph-captured preconditioner needs the V-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
   DD_REQUIRE(p.nkv >= 1 && p.nkv <= KMAX - 1, "nkv out of range");
   DD_REQUIRE(p.kc_len >= 1 && p.kc_len <= KMAX - 1 && p.kc_restarts >= 1, "bad K-cycle length");

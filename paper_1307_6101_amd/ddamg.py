@@ -56,6 +56,7 @@ class Params(ctypes.Structure):
         ("batch", ctypes.c_int),
         ("sap_block_l", (ctypes.c_int * 4) * 3),
         ("half_directions", ctypes.c_int),
+        ("graph", ctypes.c_int),
     ]
 
 
@@ -94,6 +95,8 @@ _SIGS = {
     "ddamg_sap_smooth": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P]),
     "ddamg_precondition": (_I, [_P, _P, _P, _I, _I, _P]),
     "ddamg_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveStats), _P]),
+    "ddamg_solve_many": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                              ctypes.POINTER(_I), ctypes.POINTER(SolveStats), _P]),
     "ddamg_export_interpolation": (_I, [_P, _I, _P, _P]),
     "ddamg_export_coarse_op": (_I, [_P, _I, _P, _P]),
     "ddamg_import_test_vectors": (_I, [_P, _I, _P, _P]),
@@ -244,6 +247,26 @@ def solve(hier, b, z, nrhs=1):
     if rc not in (OK, ENOCONV, ENONFINITE):
         _check(rc)
     return rc, [s.as_dict() for s in stats]
+
+
+def solve_many(hiers, bs, zs, nrhs=None):
+    """Solve the independent systems hiers[i]: D z_i = b_i concurrently (the
+    hierarchies may belong to lattices of different sizes); returns (status,
+    [stats dicts of system 0's right-hand sides, then system 1's, ...]).
+    ENOCONV / ENONFINITE are returned, other failures raise."""
+    n = len(hiers)
+    if len(bs) != n or len(zs) != n:
+        raise ValueError("one b and one z per hierarchy")
+    nrhs = [1] * n if nrhs is None else list(nrhs)
+    hv = (_P * n)(*[h.handle for h in hiers])
+    bv = (_P * n)(*[_ptr(b) for b in bs])
+    zv = (_P * n)(*[_ptr(z) for z in zs])
+    nv = (_I * n)(*nrhs)
+    stats = (SolveStats * max(1, sum(nrhs)))()
+    rc = load_library().ddamg_solve_many(n, hv, bv, zv, nv, stats, _stream())
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _check(rc)
+    return rc, [s.as_dict() for s in stats[:sum(nrhs)]]
 
 
 def export_interpolation(hier, level, out):

@@ -49,8 +49,9 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
          offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
   printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
-  printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
-         offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
+         offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions),
+         offsetof(ddamg_params, graph));
   return 0;
 }
 ''')
@@ -72,6 +73,7 @@ int main(void) {
     assert vals[10] == dd.Params.batch.offset
     assert vals[11] == dd.Params.sap_block_l.offset
     assert vals[12] == dd.Params.half_directions.offset
+    assert vals[13] == dd.Params.graph.offset
 
 
 def test_params_default_is_table1(dd):
@@ -106,3 +108,26 @@ def test_null_handles_rejected(dd):
     assert lib.ddamg_solve(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, None, None) == dd.EINVAL
     assert lib.ddamg_apply_Dc(None, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), 1, 0, 0, None) == dd.EINVAL
     assert b"null" in lib.ddamg_last_error()
+
+
+def test_solve_many_validation(dd):
+    """Checked on the host before any device call."""
+    lib = dd.load_library()
+    P = ctypes.c_void_p
+    one = (P * 1)(P(16))
+    bz = (P * 1)(P(32))
+    zz = (P * 1)(P(48))
+    n1 = (ctypes.c_int * 1)(1)
+    assert lib.ddamg_solve_many(0, one, bz, zz, n1, None, None) == dd.EINVAL
+    assert lib.ddamg_solve_many(65, one, bz, zz, n1, None, None) == dd.EINVAL
+    assert lib.ddamg_solve_many(1, None, bz, zz, n1, None, None) == dd.EINVAL
+    assert lib.ddamg_solve_many(1, (P * 1)(None), bz, zz, n1, None, None) == dd.EINVAL
+    assert b"null" in lib.ddamg_last_error()
+    two = (P * 2)(P(16), P(16))
+    b2 = (P * 2)(P(32), P(64))
+    z2 = (P * 2)(P(48), P(80))
+    n2 = (ctypes.c_int * 2)(1, 1)
+    assert lib.ddamg_solve_many(2, two, b2, z2, n2, None, None) == dd.EINVAL
+    assert b"twice" in lib.ddamg_last_error()
+    assert lib.ddamg_solve_many(1, one, bz, bz, n1, None, None) == dd.EINVAL
+    assert lib.ddamg_solve_many(1, one, bz, zz, (ctypes.c_int * 1)(0), None, None) == dd.EINVAL

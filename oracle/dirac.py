@@ -131,6 +131,10 @@ class WilsonClover:
             out += self.hop(v, mu, -1)
         return out
 
+    def apply_dagger(self, v: np.ndarray) -> np.ndarray:
+        """D^H v = Gamma5 D Gamma5 v (the gamma5-symmetry after eq. (1))."""
+        return self.apply(v @ GAMMA5_12) @ GAMMA5_12
+
     def self_matrix(self) -> np.ndarray:
         return self.A
 

@@ -2,7 +2,8 @@
 FGMRES; Sec. 2.1: the K-cycle solves each coarse system by a few FGMRES
 iterations; Tab. 1: restart length 10 and tolerance 1e-10 outside, length 5,
 2 restart cycles and tolerance 1e-1 in the K-cycle) and the coarsest-level
-solve by odd-even preconditioned GMRES to relative accuracy eps (Sec. 3).
+solve by odd-even preconditioned GMRES to relative accuracy eps (Sec. 3);
+and CGNR, the paper's comparison method (Sec. 4).
 
 The oracle takes the plainest route: Arnoldi with modified Gram-Schmidt and,
 at every step, the small least-squares problem min || beta e1 - H y || solved
@@ -82,6 +83,43 @@ def fgmres(A, b, M, m, max_cycles, tol, x0=None, check_true_residual=False, stat
         stats["iters"] = stats.get("iters", 0) + iters
         stats["converged"] = converged
         stats["history"] = history
+    return x
+
+
+def cgnr(A, AH, b, tol, max_iter, x0=None, stats=None):
+    """CGNR, the Krylov method the paper compares against (Sec. 4, Tab. 5;
+    its iteration count is the conditioning indicator of Tab. 2): conjugate
+    gradients applied to A^H A x = A^H b, carried with the residual
+    r = b - A x.  Textbook CG on the normal equations: search direction p,
+    step alpha = ||A^H r||^2 / ||A p||^2, x += alpha p, r -= alpha A p,
+    beta = ||A^H r_new||^2 / ||A^H r_old||^2, p = A^H r_new + beta p.
+    Stops when ||r|| <= tol ||b|| or after max_iter iterations; ``AH``
+    applies A^H.  Returns x (stats: iterations, residual history)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - A(x)
+    target = tol * norm(b)
+    z = AH(r)
+    p = z.copy()
+    gam = vdot(z, z).real
+    history = [norm(r)]
+    iters = 0
+    while history[-1] > target and iters < max_iter:
+        w = A(p)
+        alpha = gam / vdot(w, w).real
+        x = x + alpha * p
+        r = r - alpha * w
+        iters += 1
+        history.append(norm(r))
+        if history[-1] <= target:
+            break
+        z = AH(r)
+        gam_new = vdot(z, z).real
+        p = z + (gam_new / gam) * p
+        gam = gam_new
+    if stats is not None:
+        stats["iters"] = iters
+        stats["history"] = history
+        stats["converged"] = history[-1] <= target
     return x
 
 

@@ -6,7 +6,7 @@ import workloads as W
 from oracle.aggregation import Aggregation
 from oracle.dirac import WilsonClover
 from oracle.galerkin import galerkin
-from oracle.krylov import OddEvenCoarsest, fgmres
+from oracle.krylov import OddEvenCoarsest, cgnr, fgmres
 from oracle.lattice import parity, shape
 from oracle.stencil import dense_matrix
 
@@ -102,3 +102,59 @@ def test_odd_even_reaches_eps(rng):
     x = cs.solve(b)
     # the Schur residual reached eps; the full residual is of the same order
     assert np.linalg.norm(b - Dc.apply(x)) <= 0.5 * np.linalg.norm(b)
+
+
+def test_cgnr_scaled_unitary_one_step(rng):
+    """A = c Q with Q unitary: A^H A = |c|^2 I, so CG on the normal equations
+    ends after one step with the exact solution."""
+    n = 30
+    Q, _ = np.linalg.qr(_rand(rng, (n, n)))
+    A = (2.0 - 0.5j) * Q
+    b = _rand(rng, n)
+    st = {}
+    x = cgnr(lambda v: A @ v, lambda v: A.conj().T @ v, b, 1e-12, 50, stats=st)
+    assert st["iters"] == 1
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-12)
+
+
+def test_cgnr_dense_and_monotone(rng):
+    """CGNR minimises ||b - A x|| over the growing Krylov space of A^H A:
+    the residual never increases, and the result is numpy's solution."""
+    n = 50
+    A = np.eye(n) * 2 + 0.4 * _rand(rng, (n, n)) / np.sqrt(n)
+    b = _rand(rng, n)
+    st = {}
+    x = cgnr(lambda v: A @ v, lambda v: A.conj().T @ v, b, 1e-11, 500, stats=st)
+    h = np.array(st["history"])
+    assert st["converged"]
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-12))
+    assert np.linalg.norm(b - A @ x) <= 1e-11 * np.linalg.norm(b)
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-9)
+
+
+def test_cgnr_finite_termination(rng):
+    """In exact arithmetic CG on an n x n system ends within n steps."""
+    n = 12
+    A = np.diag(np.linspace(1.0, 3.0, n)) + 0.2 * _rand(rng, (n, n))
+    b = _rand(rng, n)
+    st = {}
+    cgnr(lambda v: A @ v, lambda v: A.conj().T @ v, b, 1e-10, 200, stats=st)
+    assert st["converged"] and st["iters"] <= n + 3
+
+
+def test_cgnr_wilson_clover_gamma5_adjoint(rng):
+    """On a 2^4 clover lattice: D^H applied as Gamma5 D Gamma5 gives the same
+    CGNR iterates as the dense conjugate transpose, and the solution of the
+    dense system."""
+    dims = (2, 2, 2, 2)
+    op = WilsonClover(W.links(dims, 0.5, 77), -0.2, 1.0)
+    M = dense_matrix(op)
+    b = W.gaussian_spinor(dims, 78)
+    s1, s2 = {}, {}
+    x1 = cgnr(op.apply, op.apply_dagger, b, 1e-10, 2000, stats=s1)
+    x2 = cgnr(lambda v: (M @ v.reshape(-1)).reshape(v.shape),
+              lambda v: (M.conj().T @ v.reshape(-1)).reshape(v.shape), b, 1e-10, 2000, stats=s2)
+    assert s1["iters"] == s2["iters"]
+    assert np.allclose(x1, x2, atol=1e-11)
+    ref = np.linalg.solve(M, b.reshape(-1)).reshape(b.shape)
+    assert np.linalg.norm(x1 - ref) <= 1e-8 * np.linalg.norm(ref)

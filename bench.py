@@ -181,6 +181,20 @@ def main():
         diff = torch.linalg.vector_norm(z - z_mixed) / torch.linalg.vector_norm(z)
         plain["rel_diff_vs_mixed_solution"] = float(diff)
 
+    # CGNR in FP64 (the paper's comparison method, Sec. 4) on the same system
+    cg = None
+    if not args.no_plain:
+        zc = torch.zeros_like(bd)
+        torch.cuda.synchronize()
+        t = time.time()
+        rc, cst = dd.cgnr(ctx, bd.reshape(1, -1), zc.reshape(1, -1), tol=cfg["tol"], max_iter=100000)
+        torch.cuda.synchronize()
+        t_cg = time.time() - t
+        cg = dict(time_to_solution_s=round(t_cg, 4), iterations=cst[0]["outer_iters"],
+                  true_relres=cst[0]["true_relres"], status=rc,
+                  speedup_mixed_vs_cgnr=round(t_cg / (ms / 1000.0), 2))
+        log(f"[bench] CGNR FP64: {cst[0]['outer_iters']} its, {t_cg:.3f}s")
+
     # the 12 spin-colour point sources on the same lattice: one batch through
     # the mixed-precision solver, against the plain FP64 method solving them
     # one at a time
@@ -366,6 +380,7 @@ def main():
         "true_relres": stats[-1]["true_relres"],
         "kcycle_iters": stats[-1]["kcycle_iters"],
         "coarsest_iters": stats[-1]["coarsest_iters"],
+        "cgnr_fp64": cg,
         "plain_fp64": plain,
         "fp16_storage": half,
         "batched_point_sources": batched,
@@ -704,6 +719,16 @@ def uneven_workload(args, dd, W, np, torch):
             log(f"[bench] plain FP64 lattice {j}: setup {su[-1]:.2f}s, solve {per[-1]:.3f}s rc={rc}, its {its[-1]}")
         plain = dict(total_s=round(sum(per), 4), per_system_s=[round(x, 4) for x in per], outer_iters=its,
                      status=stat, setup_s=su)
+    # CGNR iteration counts: the conditioning indicator of the paper's Tab. 2
+    cgn = None
+    if not args.no_plain:
+        cgn = dict(iterations=[], seconds=[])
+        for j in range(n):
+            zs[j].zero_()
+            rc, st = dd.cgnr(ctxs[j], bs[j], zs[j], tol=1e-10, max_iter=20000)
+            cgn["iterations"].append(st[0]["outer_iters"])
+            cgn["seconds"].append(round(st[0]["seconds"], 3))
+            log(f"[bench] CGNR lattice {j}: {st[0]['outer_iters']} its, {st[0]['seconds']:.2f}s rc={rc}")
     ms = 1000.0 * float(np.mean(ktimes[args.warmup:] or ktimes))
     line = {
         "metric": METRIC,
@@ -727,6 +752,7 @@ def uneven_workload(args, dd, W, np, torch):
         "vcycle": vres,
         "vcycle_graph_captured": gres,
         "plain_fp64": plain,
+        "cgnr_fp64": cgn,
         "speedup_vs_plain_fp64": round(plain["total_s"] / (ms / 1000.0), 3) if plain else None,
     }
     print(json.dumps(line), flush=True)

@@ -272,6 +272,22 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
 int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void* const* z, const int* nrhs,
                      ddamg_solve_stats* stats, void* stream);
 
+/* CGNR, the Krylov method the paper compares against (Sec. 4, Tab. 5; its
+ * iteration count is the conditioning indicator of Tab. 2): conjugate
+ * gradients on D^H D z = D^H b with the residual r = b - D z, all in double
+ * precision, D^H applied as Gamma5 D Gamma5.  b, z: device pointers to nrhs
+ * canonical complex128 fine fields of the context's lattice; z holds the
+ * initial guess on entry and the solution on return.  Stops a system when
+ * ||b - D z|| <= tol ||b|| (the recursive residual, confirmed by the
+ * recomputed one) or after max_iter iterations.  Right-hand sides advance
+ * in batches of up to 16 with their own scalars.  stats (host, may be NULL)
+ * receives one record per right-hand side (outer_iters = CG iterations,
+ * true_relres, seconds of its batch).  Synchronous; work buffers are
+ * allocated per call.  Returns DDAMG_ENOCONV / DDAMG_ENONFINITE if any
+ * system did. */
+int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int max_iter,
+               ddamg_solve_stats* stats, void* stream);
+
 /* Export the orthonormalised interpolation basis of level `level` as
  * ntv[level] canonical complex128 fields of that level ([N][V_l][d_l]), and
  * the coarse operator D_{level} (level >= 1) in the canonical coarse layout. */

@@ -8,6 +8,7 @@
 #include <thread>
 #include <vector>
 
+#include "cgnr.h"
 #include "solver.h"
 
 using namespace ddamg;
@@ -501,6 +502,43 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
   for (int i = 0; i < n; ++i)
     if (worst[i] != DDAMG_OK && w == DDAMG_OK) w = worst[i];
   return report_worst(w);
+}
+
+int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int max_iter,
+               ddamg_solve_stats* stats, void* stream) {
+  int worst = DDAMG_OK;
+  int rc = guarded([&] {
+    DD_REQUIRE(ctx && ctx->c, "null context");
+    DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
+    DD_REQUIRE(tol > 0 && max_iter >= 0, "tol must be > 0 and max_iter >= 0");
+    Context& c = *ctx->c;
+    hipStream_t s = as_stream(stream);
+    const long long n = c.g.V * 12;
+    const int bmax = std::min(nrhs, 16);
+    DevArray<double2> nb_, nx_;
+    nb_.alloc((size_t)n * bmax);
+    nx_.alloc((size_t)n * bmax);
+    std::vector<ddamg_solve_stats> st(bmax);
+    for (int r0 = 0; r0 < nrhs; r0 += bmax) {
+      const int nb = std::min(bmax, nrhs - r0);
+      auto t0 = std::chrono::steady_clock::now();
+      fine_to_native<double>(c.g, static_cast<const double2*>(b) + r0 * n, nb_.p, nb, s);
+      fine_to_native<double>(c.g, static_cast<const double2*>(z) + r0 * n, nx_.p, nb, s);
+      cgnr(c, nb_.p, nx_.p, nb, tol, max_iter, st.data(), s);
+      fine_from_native<double>(c.g, nx_.p, static_cast<double2*>(z) + r0 * n, nb, s);
+      DD_CHECK_HIP(hipStreamSynchronize(s));
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int r = 0; r < nb; ++r) {
+        st[r].seconds = secs;
+        if (stats) stats[r0 + r] = st[r];
+        if (st[r].status != DDAMG_OK && worst == DDAMG_OK) worst = st[r].status;
+      }
+    }
+  });
+  if (rc != DDAMG_OK) return rc;
+  if (worst == DDAMG_ENOCONV) g_err = "CGNR reached max_iter before tol";
+  if (worst == DDAMG_ENONFINITE) g_err = "non-finite value in b or in a residual";
+  return worst;
 }
 
 int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream) {

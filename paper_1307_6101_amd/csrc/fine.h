@@ -92,5 +92,9 @@ void to_half(const double2* in, __half2* out, long long n, hipStream_t s);
 void encode_sites(const FineGeom& g, const float2* in, __half2* half, float* scale, double2* dec, int nb,
                   hipStream_t s);
 
+// out = Gamma5 in for nb native fine fields (spins 3 and 4, components
+// 6..11, change sign; in == out allowed)
+void gamma5(const FineGeom& g, const double2* in, double2* out, int nb, hipStream_t s);
+
 
 }  // namespace ddamg

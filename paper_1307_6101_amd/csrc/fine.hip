@@ -542,6 +542,25 @@ __global__ void k_to_half(const double2* __restrict__ in, __half2* __restrict__ 
     out[i] = __floats2half2_rn((float)in[i].x, (float)in[i].y);
 }
 
+__global__ void k_gamma5(const double2* in, double2* out, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+    // native layout [block][component][16 sites]: component (i / 16) % 12
+    const int c = (int)((i >> 4) % 12);
+    const double2 v = in[i];
+    out[i] = c < 6 ? v : make_double2(-v.x, -v.y);
+  }
+}
+
+void gamma5(const FineGeom& g, const double2* in, double2* out, int nb, hipStream_t s) {
+  const long long n = (long long)g.nblk * 192 * nb;
+  long long gr = (n + 255) / 256;
+  if (gr > 8192) gr = 8192;
+  if (gr < 1) gr = 1;
+  k_gamma5<<<(unsigned)gr, 256, 0, s>>>(in, out, n);
+  DD_LAUNCH_CHECK();
+}
+
 void to_half(const double2* in, __half2* out, long long n, hipStream_t s) {
   long long g = (n + 255) / 256;
   if (g > 4096) g = 4096;

@@ -97,6 +97,7 @@ _SIGS = {
     "ddamg_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveStats), _P]),
     "ddamg_solve_many": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                               ctypes.POINTER(_I), ctypes.POINTER(SolveStats), _P]),
+    "ddamg_cgnr": (_I, [_P, _P, _P, _I, ctypes.c_double, _I, ctypes.POINTER(SolveStats), _P]),
     "ddamg_export_interpolation": (_I, [_P, _I, _P, _P]),
     "ddamg_export_coarse_op": (_I, [_P, _I, _P, _P]),
     "ddamg_import_test_vectors": (_I, [_P, _I, _P, _P]),
@@ -267,6 +268,17 @@ def solve_many(hiers, bs, zs, nrhs=None):
     if rc not in (OK, ENOCONV, ENONFINITE):
         _check(rc)
     return rc, [s.as_dict() for s in stats[:sum(nrhs)]]
+
+
+def cgnr(ctx, b, z, nrhs=1, tol=1e-10, max_iter=100000):
+    """CGNR in FP64 on the context's operator; returns (status, [stats
+    dicts]), outer_iters holding the CG iteration count.  ENOCONV /
+    ENONFINITE are returned, other failures raise."""
+    stats = (SolveStats * nrhs)()
+    rc = load_library().ddamg_cgnr(ctx.handle, _ptr(b), _ptr(z), nrhs, tol, max_iter, stats, _stream())
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _check(rc)
+    return rc, [s.as_dict() for s in stats]
 
 
 def export_interpolation(hier, level, out):

@@ -595,7 +595,8 @@ def uneven_workload(args, dd, W, np, torch):
     three-level hierarchy (FP32 preconditioner, FP64 outer FGMRES, one
     complex Gaussian right-hand side).  A step solves all eight with
     ddamg_solve_many (concurrently, one stream per hierarchy) using the
-    K-cycle.  Also timed: the same eight one after another; the V-cycle,
+    K-cycle, after the autotuner has chosen each hierarchy's level-1 SAP
+    block shape.  Also timed: the same eight one after another; the V-cycle,
     host-driven and graph-captured (coarsest GMRES with device-side scalars
     and a fixed launch sequence); the plain FP64 method one after another."""
     dev = torch.device("cuda:0")
@@ -673,9 +674,18 @@ def uneven_workload(args, dd, W, np, torch):
                     coarsest_iters=[x["coarsest_iters"] for x in st],
                     max_true_relres=max(x["true_relres"] for x in st))
 
-    def run_set(name, prec, cycle, graph, reps):
+    def run_set(name, prec, cycle, graph, reps, tune=False):
         hs, su = build_set(prec, cycle, graph)
         log(f"[bench] {name}: setup {su}")
+        tuned = None
+        if tune:
+            t_untuned, _, st0 = together(hs)
+            log(f"[bench] {name}, together before tuning: {t_untuned:.3f}s")
+            t = time.time()
+            choice = [dd.tune(H, b, nrhs=1) for H, b in zip(hs, bs)]
+            tuned = dict(search_s=round(time.time() - t, 2), together_before_s=round(t_untuned, 4),
+                         sap_block_level1=[c["sap_block_l"][0] for c in choice])
+            log(f"[bench] {name}: tuned in {tuned['search_s']}s, level-1 SAP blocks {tuned['sap_block_level1']}")
         times, st = [], None
         for i in range(reps):
             tt, rc, st = together(hs)
@@ -688,13 +698,15 @@ def uneven_workload(args, dd, W, np, torch):
         out = dict(setup_s=su, together_s=round(float(np.mean(times[-max(1, reps - 1):])), 4),
                    one_after_another_s=round(sum(per), 4), per_system_alone_s=[round(x, 4) for x in per],
                    **summary(st))
+        if tuned:
+            out["autotuned"] = tuned
         del hs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         return out, times
 
     reps = args.warmup + args.steps
-    kres, ktimes = run_set("mixed K-cycle", dd.F32, "K", False, reps)
+    kres, ktimes = run_set("mixed K-cycle", dd.F32, "K", False, reps, tune=True)
     vres, _ = run_set("mixed V-cycle", dd.F32, "V", False, 2)
     gres, _ = run_set("mixed V-cycle, graph-captured", dd.F32, "V", True, 3)
     gres["coarsest_budget"] = {"restart": GRAPH_COARSE[0], "cycles": GRAPH_COARSE[1]}

@@ -272,6 +272,38 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
 int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void* const* z, const int* nrhs,
                      ddamg_solve_stats* stats, void* stream);
 
+/* Change the SAP block shape of coarse level `level` (1 .. levels-2, the
+ * smoothed coarse levels) for the solves from now on; the hierarchy (test
+ * vectors, P, D_c), built with the earlier shape, is kept.  The shape must
+ * tile the level with an even block count per direction (Sec. 2).  Not
+ * stream-ordered: waits for the device. */
+int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]);
+/* Change params.batch (1..32) for the solves from now on. */
+int ddamg_set_batch(ddamg_hier hier, int batch);
+
+typedef struct {
+  int sap_block_l[3][4];   /* chosen SAP block of coarse levels 1..3 (rows
+                              beyond levels-2 are 0) */
+  int batch;               /* chosen batch size */
+  double seconds;          /* solve time measured for the choice */
+  int from_cache;          /* 1: read from the cache, no measurement */
+} ddamg_tune_result;
+
+/* Autotuner.  Times complete solves of the nrhs canonical complex128
+ * right-hand sides b (device) with every candidate SAP block shape of each
+ * smoothed coarse level (equal extents in x, y, z and a free extent in t,
+ * dividing the level with an even count per direction, block volume 8..512;
+ * one level after the other), then, for nrhs > 1, every batch size up to
+ * min(nrhs, 32); keeps the fastest choice that converges (best of two
+ * timed solves after a warm-up) and applies it to the hierarchy.  With a
+ * cache file (may be NULL) the choice is looked up first under a key made
+ * of the device architecture, lattice, precisions, levels, aggregates,
+ * test-vector counts, cycle and nrhs, and stored there after a search
+ * (a JSON object, one entry per line).  Synchronous; allocates a work
+ * field of nrhs fine fields.  out (host, may be NULL) receives the choice. */
+int ddamg_tune(ddamg_hier hier, const void* b, int nrhs, const char* cache_path, ddamg_tune_result* out,
+               void* stream);
+
 /* CGNR, the Krylov method the paper compares against (Sec. 4, Tab. 5; its
  * iteration count is the conditioning indicator of Tab. 2): conjugate
  * gradients on D^H D z = D^H b with the residual r = b - D z, all in double

@@ -10,6 +10,7 @@
 
 #include "cgnr.h"
 #include "solver.h"
+#include "tune.h"
 
 using namespace ddamg;
 
@@ -502,6 +503,105 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
   for (int i = 0; i < n; ++i)
     if (worst[i] != DDAMG_OK && w == DDAMG_OK) w = worst[i];
   return report_worst(w);
+}
+
+int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(block != nullptr, "null block shape");
+    H.set_sap_block(level, block);
+  });
+}
+
+int ddamg_set_batch(ddamg_hier hier, int batch) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(batch >= 1 && batch <= NBMAX, "batch must be 1..32");
+    H.p.batch = batch;
+  });
+}
+
+int ddamg_tune(ddamg_hier hier, const void* b, int nrhs, const char* cache_path, ddamg_tune_result* out,
+               void* stream) {
+  return guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(b && nrhs >= 1, "bad argument");
+    const std::string path = cache_path ? cache_path : "";
+    const std::string key = tune_key(H, nrhs);
+    TuneChoice best;
+    auto apply = [&](const TuneChoice& c) {
+      for (int l = 1; l <= H.L - 2; ++l) H.set_sap_block(l, c.sap[l - 1]);
+      if (c.batch >= 1) H.p.batch = c.batch;
+    };
+    auto current = [&]() {
+      TuneChoice c;
+      for (int l = 1; l <= H.L - 2; ++l)
+        for (int mu = 0; mu < 4; ++mu) c.sap[l - 1][mu] = H.lv[l].cg.sap[mu];
+      c.batch = H.p.batch;
+      return c;
+    };
+    bool cached = !path.empty() && tune_cache_lookup(path, key, best);
+    if (!cached) {
+      hipStream_t s = as_stream(stream);
+      const long long n = H.lv[0].n;
+      DevArray<double2> z;
+      z.alloc((size_t)n * nrhs);
+      // best of two timed solves after a warm-up one; a solve that does not
+      // converge does not count
+      auto measure = [&]() {
+        double t = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+          vzero<double>(z.p, n * nrhs, s);
+          DD_CHECK_HIP(hipStreamSynchronize(s));
+          const auto t0 = std::chrono::steady_clock::now();
+          const int w = solve_batches(H, b, z.p, nrhs, nullptr, s);
+          const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          if (w != DDAMG_OK) return 1e300;
+          if (rep > 0) t = std::min(t, dt);
+        }
+        return t;
+      };
+      best = current();
+      best.batch = std::min(best.batch, nrhs);   // the same grouping, stated as used
+      H.p.batch = best.batch;
+      best.seconds = measure();
+      for (int l = 1; l <= H.L - 2; ++l) {
+        for (const auto& cand : sap_candidates(H, l)) {
+          TuneChoice c = best;
+          for (int mu = 0; mu < 4; ++mu) c.sap[l - 1][mu] = cand[mu];
+          try {
+            apply(c);
+          } catch (const Error&) {
+            apply(best);
+            continue;
+          }
+          c.seconds = measure();
+          if (c.seconds < best.seconds) best = c;
+        }
+        apply(best);
+      }
+      if (nrhs > 1) {
+        for (int bt : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+          if (bt > nrhs || bt == best.batch) continue;
+          TuneChoice c = best;
+          c.batch = bt;
+          apply(c);
+          c.seconds = measure();
+          if (c.seconds < best.seconds) best = c;
+        }
+      }
+      DD_REQUIRE(best.seconds < 1e299, "no candidate configuration converged");
+      if (!path.empty()) tune_cache_store(path, key, best);
+    }
+    apply(best);
+    if (out) {
+      for (int l = 0; l < 3; ++l)
+        for (int mu = 0; mu < 4; ++mu) out->sap_block_l[l][mu] = best.sap[l][mu];
+      out->batch = H.p.batch;
+      out->seconds = best.seconds;
+      out->from_cache = cached ? 1 : 0;
+    }
+  });
 }
 
 int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int max_iter,

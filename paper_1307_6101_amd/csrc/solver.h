@@ -212,6 +212,9 @@ struct Hierarchy {
   // from32: the FP32 test vectors are the current ones
   void build_level(int l, bool from32);
   template <typename T> void alloc_work(int cap);
+  // replace the SAP block shape of coarse level l (1 <= l <= L-2) for the
+  // solves from now on (the setup already done is kept)
+  void set_sap_block(int l, const int blk[4]);
 
   Hierarchy() = default;
   Hierarchy(const Hierarchy&) = delete;

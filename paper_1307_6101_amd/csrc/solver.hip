@@ -1031,6 +1031,31 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(d <= 64, "coarsest dof per site must be <= 64");
 }
 
+void Hierarchy::set_sap_block(int l, const int blk[4]) {
+  DD_REQUIRE(l >= 1 && l <= L - 2, "only the coarse levels 1..L-2 are smoothed by SAP");
+  ddamg_params q = p;
+  for (int mu = 0; mu < 4; ++mu) q.sap_block_l[l - 1][mu] = blk[mu];
+  validate_params(*ctx, q);
+  LevelStore& S = lv[l];
+  int sap[4];
+  sap_block_of(q, l, sap);
+  CoarseGeom g = make_coarse_geom(S.dims, S.d, sap);
+  S.cg.sap[0] = g.sap[0], S.cg.sap[1] = g.sap[1], S.cg.sap[2] = g.sap[2], S.cg.sap[3] = g.sap[3];
+  S.cg.nblk = g.nblk;
+  S.cg.bs = g.bs;
+  S.cg.blk_sites = std::move(g.blk_sites);
+  S.cg.site_blk = std::move(g.site_blk);
+  S.cg.site_pos = std::move(g.site_pos);
+  S.cg.inmask = std::move(g.inmask);
+  S.c_blk_sites.upload(S.cg.blk_sites, s);
+  S.c_site_blk.upload(S.cg.site_blk, s);
+  S.c_site_pos.upload(S.cg.site_pos, s);
+  S.c_inmask.upload(S.cg.inmask, s);
+  DD_CHECK_HIP(hipStreamSynchronize(s));
+  p = q;
+  ++gen;
+}
+
 Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2* tvc,
                             const double2* tv_extra, hipStream_t s) {
   DD_REQUIRE(ctx && pp && tvc, "null argument");

@@ -75,6 +75,15 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("sap_block_l", (ctypes.c_int * 4) * 3),
+        ("batch", ctypes.c_int),
+        ("seconds", ctypes.c_double),
+        ("from_cache", ctypes.c_int),
+    ]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
@@ -97,6 +106,9 @@ _SIGS = {
     "ddamg_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveStats), _P]),
     "ddamg_solve_many": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                               ctypes.POINTER(_I), ctypes.POINTER(SolveStats), _P]),
+    "ddamg_set_sap_block": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int * 4)]),
+    "ddamg_set_batch": (_I, [_P, _I]),
+    "ddamg_tune": (_I, [_P, _P, _I, ctypes.c_char_p, ctypes.POINTER(TuneResult), _P]),
     "ddamg_cgnr": (_I, [_P, _P, _P, _I, ctypes.c_double, _I, ctypes.POINTER(SolveStats), _P]),
     "ddamg_export_interpolation": (_I, [_P, _I, _P, _P]),
     "ddamg_export_coarse_op": (_I, [_P, _I, _P, _P]),
@@ -268,6 +280,24 @@ def solve_many(hiers, bs, zs, nrhs=None):
     if rc not in (OK, ENOCONV, ENONFINITE):
         _check(rc)
     return rc, [s.as_dict() for s in stats[:sum(nrhs)]]
+
+
+def set_sap_block(hier, level, block):
+    _check(load_library().ddamg_set_sap_block(hier.handle, level, ctypes.byref((ctypes.c_int * 4)(*block))))
+
+
+def set_batch(hier, batch):
+    _check(load_library().ddamg_set_batch(hier.handle, batch))
+
+
+def tune(hier, b, nrhs=1, cache=None):
+    """Autotune the coarse SAP block shapes and the batch size by timing
+    solves of b (applied to the hierarchy); returns a dict of the choice."""
+    r = TuneResult()
+    path = None if cache is None else os.fspath(cache).encode()
+    _check(load_library().ddamg_tune(hier.handle, _ptr(b), nrhs, path, ctypes.byref(r), _stream()))
+    return dict(sap_block_l=[list(row) for row in r.sap_block_l], batch=r.batch, seconds=r.seconds,
+                from_cache=bool(r.from_cache))
 
 
 def cgnr(ctx, b, z, nrhs=1, tol=1e-10, max_iter=100000):

@@ -49,6 +49,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_eps), offsetof(ddamg_params, kc_tol),
          offsetof(ddamg_params, tol), offsetof(ddamg_params, cycle));
   printf("%zu %zu\n", offsetof(ddamg_solve_stats, true_relres), offsetof(ddamg_solve_stats, seconds));
+  printf("%zu %zu %zu %zu\n", sizeof(ddamg_tune_result), offsetof(ddamg_tune_result, batch),
+         offsetof(ddamg_tune_result, seconds), offsetof(ddamg_tune_result, from_cache));
   printf("%zu %zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
          offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions),
          offsetof(ddamg_params, graph));
@@ -69,11 +71,15 @@ int main(void) {
     assert vals[6] == dd.Params.cycle.offset
     assert vals[7] == dd.SolveStats.true_relres.offset
     assert vals[8] == dd.SolveStats.seconds.offset
-    assert vals[9] == dd.Params.half_storage.offset
-    assert vals[10] == dd.Params.batch.offset
-    assert vals[11] == dd.Params.sap_block_l.offset
-    assert vals[12] == dd.Params.half_directions.offset
-    assert vals[13] == dd.Params.graph.offset
+    assert vals[9] == ctypes.sizeof(dd.TuneResult)
+    assert vals[10] == dd.TuneResult.batch.offset
+    assert vals[11] == dd.TuneResult.seconds.offset
+    assert vals[12] == dd.TuneResult.from_cache.offset
+    assert vals[13] == dd.Params.half_storage.offset
+    assert vals[14] == dd.Params.batch.offset
+    assert vals[15] == dd.Params.sap_block_l.offset
+    assert vals[16] == dd.Params.half_directions.offset
+    assert vals[17] == dd.Params.graph.offset
 
 
 def test_params_default_is_table1(dd):

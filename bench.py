@@ -148,6 +148,20 @@ def main():
             raise RuntimeError(f"solve failed rc={rc} {st}")
         return st[0]
 
+    # the autotuner picks the level-1 SAP block shape (timed solves; every
+    # hierarchy below is tuned the same way, the plain FP64 one included)
+    def tune(H, rhs, nrhs=1):
+        one_solve(H) if nrhs == 1 else None
+        t = time.time()
+        r = dd.tune(H, rhs, nrhs=nrhs)
+        return dict(sap_block_level1=r["sap_block_l"][0], batch=r["batch"], search_s=round(time.time() - t, 3))
+
+    one_solve(H32)
+    t_untuned = float(np.median([one_solve(H32)["seconds"] for _ in range(3)]))
+    tuned32 = tune(H32, bd.reshape(1, -1))
+    tuned32["untuned_time_to_solution_s"] = round(t_untuned, 4)
+    log(f"[bench] autotuned: {tuned32}")
+
     for i in range(args.warmup):
         st = one_solve(H32)
         log(f"[bench] warmup {i}: {st['outer_iters']} its, {st['seconds']:.3f}s")
@@ -169,6 +183,8 @@ def main():
     if not args.no_plain:
         H64, t_setup64 = setup(dd.F64)
         log(f"[bench] plain FP64 setup {t_setup64:.2f}s")
+        tuned64 = tune(H64, bd.reshape(1, -1))
+        log(f"[bench] plain FP64 autotuned: {tuned64}")
         one_solve(H64)
         torch.cuda.synchronize()
         t = time.time()
@@ -176,7 +192,7 @@ def main():
         torch.cuda.synchronize()
         t_plain = (time.time() - t) / len(pst)
         plain = dict(time_to_solution_s=t_plain, setup_s=t_setup64,
-                     outer_iters=pst[-1]["outer_iters"], true_relres=pst[-1]["true_relres"])
+                     outer_iters=pst[-1]["outer_iters"], true_relres=pst[-1]["true_relres"], autotuned=tuned64)
         log(f"[bench] plain FP64 solve {t_plain:.3f}s, {pst[-1]['outer_iters']} its")
         diff = torch.linalg.vector_norm(z - z_mixed) / torch.linalg.vector_norm(z)
         plain["rel_diff_vs_mixed_solution"] = float(diff)
@@ -213,6 +229,8 @@ def main():
                 raise RuntimeError(f"batched solve failed rc={rc}")
             return time.time() - t, st
 
+        tuned_b = tune(H32, bps, BATCH_RHS)
+        log(f"[bench] 12 point sources autotuned: {tuned_b}")
         batch_solve(H32, BATCH_RHS)
         t_b, st_b = batch_solve(H32, BATCH_RHS)
         log(f"[bench] 12 point sources, one mixed batch: {t_b:.3f}s "
@@ -220,11 +238,12 @@ def main():
         batched = dict(rhs=BATCH_RHS, sources="12 spin-colour point sources at x = 0",
                        mixed_batch_s=round(t_b, 4), mixed_per_rhs_s=round(t_b / BATCH_RHS, 5),
                        outer_iters=[x["outer_iters"] for x in st_b],
-                       max_true_relres=max(x["true_relres"] for x in st_b))
+                       max_true_relres=max(x["true_relres"] for x in st_b), autotuned=tuned_b)
         if not args.no_plain:
             p1 = params(dd.F64)
             p1.batch = 1
             H64b = dd.build_hierarchy(ctx, p1, tvd)
+            tune(H64b, bps[:1], 1)
             t_p, st_p = batch_solve(H64b, BATCH_RHS)
             log(f"[bench] 12 point sources, plain FP64 one at a time: {t_p:.3f}s")
             batched.update(plain_fp64_one_at_a_time_s=round(t_p, 4),
@@ -239,6 +258,7 @@ def main():
     if not args.no_half:
         H16, t_setup16 = setup(dd.F32, half=True)
         log(f"[bench] FP16-storage setup {t_setup16:.2f}s")
+        tune(H16, bd.reshape(1, -1))
         one_solve(H16)
         torch.cuda.synchronize()
         t = time.time()
@@ -253,6 +273,7 @@ def main():
         pd = params(dd.F32, True)
         pd.half_directions = 1
         Hd = dd.build_hierarchy(ctx, pd, tvd)
+        tune(Hd, bd.reshape(1, -1))
         one_solve(Hd)
         torch.cuda.synchronize()
         t = time.time()
@@ -376,6 +397,7 @@ def main():
                    "parallelism": "1 GPU"},
         "time_to_solution_s": round(ms / 1000.0, 4),
         "setup_s": round(t_setup32, 3),
+        "autotuned": tuned32,
         "outer_iters": mean_its,
         "true_relres": stats[-1]["true_relres"],
         "kcycle_iters": stats[-1]["kcycle_iters"],

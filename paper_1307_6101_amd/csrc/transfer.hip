@@ -419,6 +419,20 @@ struct GalFineGeom {
   int agg[4];
 };
 
+// Galerkin grids: workgroup bid of 8 * ceil(nagg / 8) * ncol handles
+// (aggregate A, column col) such that the ncol columns of an aggregate run
+// one after another on one XCD (workgroup i is dispatched to XCD i mod 8),
+// whose L2 then serves the aggregate's links, clover and rows of P to all
+// of them.  Returns false for the padding workgroups.
+__device__ inline bool agg_col_xcd(int bid, int nagg, int ncol, int& A, int& col) {
+  const int apx = (nagg + 7) / 8;
+  const int j = bid >> 3;
+  A = (bid & 7) * apx + j / ncol;
+  col = j % ncol;
+  return A < nagg;
+}
+inline unsigned agg_col_grid(int nagg, int ncol) { return 8u * (unsigned)((nagg + 7) / 8) * (unsigned)ncol; }
+
 template <int MU, bool FWD>
 __device__ inline void gal_hop(const FineOpView<double>& op, const double2* __restrict__ Pk, int sigma,
                                int blk, int loc, double2 acc[12]) {
@@ -445,11 +459,12 @@ __device__ inline void gal_hops_inside(const FineOpView<double>& op, const doubl
 }
 
 __global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int* __restrict__ members,
-                                                       int nbpa, int N, FineOpView<double> op,
+                                                       int nbpa, int N, int nagg, FineOpView<double> op,
                                                        const double2* __restrict__ P, long long fstride,
                                                        double2* __restrict__ Dc) {
   __shared__ double red[4 * NMAX * 4];
-  const int A = blockIdx.x, col = blockIdx.y;
+  int A, col;
+  if (!agg_col_xcd(blockIdx.x, nagg, 2 * N, A, col)) return;
   const int sigma = col / N, k = col % N;
   const int t = threadIdx.x;
   const int blk = members[A * nbpa + (t >> 4)], loc = t & 15;
@@ -523,9 +538,8 @@ void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int 
   DD_REQUIRE(N <= NMAX, "too many test vectors");
   GalFineGeom gg;
   for (int mu = 0; mu < 4; ++mu) { gg.nb[mu] = g.nb[mu]; gg.agg[mu] = a.agg[mu]; }
-  dim3 grid(a.nagg, 2 * N);
-  k_galerkin_fine<<<grid, 256, 0, s>>>(gg, ad.members, a.asz / 16, N, op, P, (long long)g.nblk * 192,
-                                       Dc);
+  k_galerkin_fine<<<agg_col_grid(a.nagg, 2 * N), 256, 0, s>>>(gg, ad.members, a.asz / 16, N, a.nagg, op, P,
+                                                              (long long)g.nblk * 192, Dc);
   DD_LAUNCH_CHECK();
 }
 
@@ -544,13 +558,14 @@ __device__ inline void colmajor_row_rng(const double2* M, const double2* u, int 
   for (int j = j0; j < j1; ++j) cfma(acc, M[(size_t)j * d + i], u[j]);
 }
 
-__global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N,
+__global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N, int nagg,
                                   CoarseOpView<double> op, const double2* __restrict__ P,
                                   long long fstride, double2* __restrict__ Dc) {
   extern __shared__ unsigned char smem_raw[];
   double* red = reinterpret_cast<double*>(smem_raw);
   const int d = op.d, h = d / 2;
-  const int A = blockIdx.x, col = blockIdx.y;
+  int A, col;
+  if (!agg_col_xcd(blockIdx.x, nagg, 2 * N, A, col)) return;
   const int sigma = col / N, k = col % N;
   const int j0 = sigma * h, j1 = j0 + h;
   const int t = threadIdx.x;
@@ -612,8 +627,8 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   for (int mu = 0; mu < 4; ++mu) { gg.dims[mu] = cg.dims[mu]; gg.agg[mu] = a.agg[mu]; }
   const int wg = 64 * ((rows + 63) / 64);
   const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(double);
-  dim3 grid(a.nagg, 2 * N);
-  k_galerkin_coarse<<<grid, wg, sm, s>>>(gg, ad.members, a.asz, N, op, P, (long long)cg.V * cg.d, Dc);
+  k_galerkin_coarse<<<agg_col_grid(a.nagg, 2 * N), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
+                                                                 (long long)cg.V * cg.d, Dc);
   DD_LAUNCH_CHECK();
 }
 

@@ -292,11 +292,15 @@ void prolong_coarse(const AggTables& a, const AggDev& ad, int d, int N, long lon
 constexpr int NMAX = 32;   // max test vectors per level
 constexpr int EPT = 8;     // max elements per thread
 
+// Element e of the restriction of a field to (aggregate A, chirality sigma):
+// the order is free (the result does not depend on it) and is chosen so that
+// consecutive elements are consecutive in memory.
 struct FineMap {
   const int* members;
   int nbpa;
   __device__ long long operator()(int A, int sigma, int e) const {
-    const int ts = e / 6, c = 6 * sigma + e % 6;
+    const int asz = nbpa * 16;
+    const int c = 6 * sigma + e / asz, ts = e % asz;
     const int blk = members[A * nbpa + (ts >> 4)];
     return ((long long)blk * 12 + c) * 16 + (ts & 15);
   }
@@ -311,77 +315,129 @@ struct CoarseMap {
   }
 };
 
-// sum over the workgroup of nv (<= 2*NMAX) doubles held in v[]; lds >= 16*2*NMAX
-__device__ inline void wg_sum_n(double (&v)[2 * NMAX], int nv, double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-  for (int j = 0; j < 2 * NMAX; ++j)
-    if (j < nv) {
-      double s = wave_sum(v[j]);
-      if (lane == 0) lds[wave * 2 * NMAX + j] = s;
-    }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 2 * NMAX; ++j)
-    if (j < nv) {
-      double s = 0;
-      for (int w = 0; w < nw; ++w) s += lds[w * 2 * NMAX + j];
-      v[j] = s;
-    }
-  __syncthreads();
+// Orthonormalisation of the N test vectors restricted to (aggregate,
+// chirality): one workgroup per pair, Cholesky QR applied twice.  A pass
+// forms the Gram matrix G = V^H V (chunks of the vectors staged in LDS,
+// one upper-triangle entry per thread), factors G = R^H R (R upper
+// triangular, positive diagonal), and writes V R^-1.  The Q factor with
+// positive diagonal R is unique, so this is the Gram-Schmidt result of the
+// paper's construction up to rounding; the second pass restores
+// orthogonality to working precision.  A vector that depends on the
+// earlier ones (zero pivot) gives a zero column, as Gram-Schmidt does.
+constexpr int ORTH_CHUNK = 16;    // elements per LDS chunk of the Gram pass
+constexpr int ORTH_APPLY = 64;    // elements per LDS chunk of the V R^-1 pass
+
+__device__ inline void orth_pair(int p, int N, int& i, int& j) {
+  // p -> (i, j), i <= j, row by row of the upper triangle
+  i = 0;
+  int row = N;
+  while (p >= row) {
+    p -= row;
+    --row;
+    ++i;
+  }
+  j = i + p;
 }
 
 template <class Map>
 __global__ void __launch_bounds__(256) k_orth(Map map, int m, int N, long long fstride,
                                               const double2* __restrict__ tv, double2* __restrict__ P) {
-  __shared__ double lds[16 * 2 * NMAX];
+  __shared__ double2 chunk[NMAX * ORTH_APPLY];
+  __shared__ double2 R[NMAX * NMAX];   // Gram matrix, then R (upper triangle)
+  __shared__ double2 X[NMAX * NMAX];   // R^-1 (upper triangle)
+  __shared__ int dep[NMAX];
   const int A = blockIdx.x >> 1, sigma = blockIdx.x & 1;
-  long long off[EPT];
+  const int t = threadIdx.x;
+  const int npairs = N * (N + 1) / 2;
+  constexpr int PPT = (NMAX * (NMAX + 1) / 2 + 255) / 256;
+  for (int pass = 0; pass < 2; ++pass) {
+    const double2* src = pass == 0 ? tv : P;
+    // Gram matrix
+    double2 acc[PPT];
+    int pi[PPT], pj[PPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * blockDim.x;
-    off[q] = e < m ? map(A, sigma, e) : -1;
-  }
-  for (int k = 0; k < N; ++k) {
-    double2 w[EPT];
+    for (int r = 0; r < PPT; ++r) {
+      acc[r] = czero<double>();
+      pi[r] = pj[r] = 0;
+      if (t + 256 * r < npairs) orth_pair(t + 256 * r, N, pi[r], pj[r]);
+    }
+    for (int e0 = 0; e0 < m; e0 += ORTH_CHUNK) {
+      for (int idx = t; idx < N * ORTH_CHUNK; idx += 256) {
+        const int j = idx / ORTH_CHUNK, e = e0 + idx % ORTH_CHUNK;
+        chunk[idx] = e < m ? src[j * fstride + map(A, sigma, e)] : czero<double>();
+      }
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) w[q] = off[q] >= 0 ? tv[k * fstride + off[q]] : czero<double>();
-    for (int pass = 0; pass < 2 && k > 0; ++pass) {
-      double h[2 * NMAX];
+      for (int r = 0; r < PPT; ++r)
+        if (t + 256 * r < npairs) {
+          const double2* a = chunk + pi[r] * ORTH_CHUNK;
+          const double2* b = chunk + pj[r] * ORTH_CHUNK;
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) {
-        h[2 * j] = 0;
-        h[2 * j + 1] = 0;
-        if (j < k) {
+          for (int q = 0; q < ORTH_CHUNK; ++q) cjfma(acc[r], a[q], b[q]);
+        }
+      __syncthreads();
+    }
 #pragma unroll
-          for (int q = 0; q < EPT; ++q)
-            if (off[q] >= 0) {
-              const double2 p = P[j * fstride + off[q]];
-              h[2 * j] += p.x * w[q].x + p.y * w[q].y;
-              h[2 * j + 1] += p.x * w[q].y - p.y * w[q].x;
-            }
+    for (int r = 0; r < PPT; ++r)
+      if (t + 256 * r < npairs) R[pi[r] * NMAX + pj[r]] = acc[r];
+    __syncthreads();
+    // Cholesky G = R^H R in place (upper triangle): thread j < N owns
+    // column j; step k fixes row k
+    for (int k = 0; k < N; ++k) {
+      if (t == k) {
+        double dk = R[k * NMAX + k].x;
+        for (int i = 0; i < k; ++i) {
+          const double2 r = R[i * NMAX + k];
+          dk -= r.x * r.x + r.y * r.y;
+        }
+        const double gkk = R[k * NMAX + k].x;
+        const bool zero = !(gkk > 0.0) || !(dk > 1e-28 * gkk);
+        dep[k] = zero ? 1 : 0;
+        R[k * NMAX + k] = make_double2(zero ? 0.0 : sqrt(dk), 0.0);
+      }
+      __syncthreads();
+      if (t > k && t < N) {
+        double2 g = R[k * NMAX + t];
+        for (int i = 0; i < k; ++i) g = csub(g, cjmul(R[i * NMAX + k], R[i * NMAX + t]));
+        const double rkk = R[k * NMAX + k].x;
+        R[k * NMAX + t] = rkk > 0.0 ? cscale(g, 1.0 / rkk) : czero<double>();
+      }
+      __syncthreads();
+    }
+    // X = R^-1: thread j < N solves column j (zero rows and columns for
+    // dependent vectors)
+    if (t < N) {
+      const int j = t;
+      for (int i = 0; i < N; ++i) X[i * NMAX + j] = czero<double>();
+      if (!dep[j]) {
+        X[j * NMAX + j] = make_double2(1.0 / R[j * NMAX + j].x, 0.0);
+        for (int i = j - 1; i >= 0; --i) {
+          if (dep[i]) continue;
+          double2 sacc = czero<double>();
+          for (int k = i + 1; k <= j; ++k) cfma(sacc, R[i * NMAX + k], X[k * NMAX + j]);
+          X[i * NMAX + j] = cscale(sacc, -1.0 / R[i * NMAX + i].x);
         }
       }
-      wg_sum_n(h, 2 * k, lds);
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j)
-        if (j < k) {
-          const double2 hj = mk<double>(h[2 * j], h[2 * j + 1]);
-#pragma unroll
-          for (int q = 0; q < EPT; ++q)
-            if (off[q] >= 0) w[q] = csub(w[q], cmul(hj, P[j * fstride + off[q]]));
-        }
     }
-    double nn[2 * NMAX];
-    nn[0] = 0;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) nn[0] += w[q].x * w[q].x + w[q].y * w[q].y;
-    wg_sum_n(nn, 1, lds);
-    const double inv = nn[0] > 0 ? 1.0 / sqrt(nn[0]) : 0.0;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q)
-      if (off[q] >= 0) P[k * fstride + off[q]] = cscale(w[q], inv);
+    __syncthreads();
+    // P = V X, chunks of ORTH_APPLY elements staged in LDS (the whole
+    // chunk is read before any of it is written, so the second pass may
+    // work in place); thread t forms outputs (element, column) t, t+256, ...
+    for (int e0 = 0; e0 < m; e0 += ORTH_APPLY) {
+      for (int idx = t; idx < N * ORTH_APPLY; idx += 256) {
+        const int j = idx / ORTH_APPLY, e = e0 + idx % ORTH_APPLY;
+        chunk[idx] = e < m ? src[j * fstride + map(A, sigma, e)] : czero<double>();
+      }
+      __syncthreads();
+      for (int idx = t; idx < N * ORTH_APPLY; idx += 256) {
+        const int j = idx / ORTH_APPLY, q = idx % ORTH_APPLY, e = e0 + q;
+        if (e >= m) continue;
+        double2 o = czero<double>();
+        for (int i = 0; i <= j; ++i) cfma(o, chunk[i * ORTH_APPLY + q], X[i * NMAX + j]);
+        P[j * fstride + map(A, sigma, e)] = o;
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -570,14 +570,19 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int
       y[c].x -= 0.5 * acc[c].x;
       y[c].y -= 0.5 * acc[c].y;
     }
+    // a face part is nonzero only on the aggregate's face sites: the other
+    // threads skip the loads of the rows of P and contribute zeros
+    const bool live = tau == 0 || !fin[tau - 1];
     for (int kp = 0; kp < N; ++kp) {
-      double2 w[12];
-      load_spinor<double>(P + kp * fstride, blk, loc, w);
       double2 p0 = czero<double>(), p1 = czero<double>();
+      if (live) {
+        double2 w[12];
+        load_spinor<double>(P + kp * fstride, blk, loc, w);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        cjfma(p0, w[c], y[c]);
-        cjfma(p1, w[6 + c], y[6 + c]);
+        for (int c = 0; c < 6; ++c) {
+          cjfma(p0, w[c], y[c]);
+          cjfma(p1, w[6 + c], y[6 + c]);
+        }
       }
       stash4<double>(red, N, kp, p0.x, p0.y, p1.x, p1.y);
     }

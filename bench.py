@@ -538,8 +538,9 @@ def big_workload(args, name, cfg, dd, W, np, torch):
 
 
 def kernels_only(args, cfg, dd, W, np, torch):
-    """Stencil launches in FP32 and FP64 plus a 1 GiB device copy (the
-    reference for scaling FETCH_SIZE / WRITE_SIZE counters)."""
+    """Stencil launches in FP32 and FP64, FP32 SAP sweeps, the matrix-core
+    coarse operator on 12 fields, and a 1 GiB device copy (the reference for
+    scaling FETCH_SIZE / WRITE_SIZE counters)."""
     dims = tuple(int(x) for x in args.lattice.split(",")) if args.lattice else cfg["dims"]
     V = int(np.prod(dims))
     dev = torch.device("cuda:0")
@@ -571,6 +572,40 @@ def kernels_only(args, cfg, dd, W, np, torch):
                      "algorithmic_bytes": nbytes}
         log(f"[bench] {name}: {t * 1e6:.1f} us, {nbytes / t / 1e9:.0f} GB/s")
         del x, y
+    # one SAP sweep (both colours, FP32) on a single field, and the coarse
+    # operator of a 20-vector two-level hierarchy on 12 fields (matrix cores)
+    p = dd.params_default(2)
+    p.ntv[0] = 20
+    p.n_inv = 0
+    p.precond_prec = dd.F32
+    tv = torch.from_numpy(W.test_vectors(dims, 12, 20, cfg["seed_tv"])).to(dev)
+    H = dd.build_hierarchy(ctx, p, tv)
+    del tv
+    x = torch.zeros(V * 12, dtype=torch.complex64, device=dev)
+    dd.to_native(ctx, None, 0, bd, x, prec=dd.F32)
+    zf = torch.zeros_like(x)
+    ldims, dof = dd.level_info(H, 1)
+    Vc = int(np.prod(ldims))
+    xc = torch.randn((BATCH_RHS, Vc * dof), dtype=torch.complex64, device=dev)
+    yc = torch.zeros_like(xc)
+    for name, fn, nbytes in (
+            ("sap_sweep_f32", lambda: dd.sap_smooth(H, 0, x, zf, 1, prec=dd.F32, layout=dd.NATIVE),
+             SAP_REALS_PER_SITE * 4 * V),
+            ("coarse_apply_mfma_f32_x12",
+             lambda: dd.apply_Dc(H, 1, xc, yc, nrhs=BATCH_RHS, prec=dd.F32, layout=dd.NATIVE),
+             Vc * (9 * dof * dof + 2 * BATCH_RHS * dof) * 8)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1000.0 / args.kernel_reps
+        out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
+        log(f"[bench] {name}: {t * 1e6:.1f} us, {nbytes / t / 1e9:.0f} GB/s")
+    del H
     # reference copy of known size: 1 GiB read + 1 GiB written
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)

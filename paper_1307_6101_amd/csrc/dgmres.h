@@ -32,6 +32,8 @@ struct DevGmres {
   double2* coef = nullptr;       // [NBMAX][KMAX]
   double* scale = nullptr;       // [NBMAX]
   long long* iters = nullptr;    // [NBMAX] iterations, accumulated
+  int* flag = nullptr;           // device alias of a coherent host word: set by
+                                 // gm_begin / gm_step / gm_solve (see below)
   BArg arg() const {
     BArg a;
     a.inl = 0;
@@ -45,16 +47,17 @@ struct DevGmres {
 void gm_reset(const DevGmres& d, int nb, hipStream_t s);
 // start of a restart cycle from the norms ||r_r||^2 in res[r][0]: first
 // cycle sets the targets tol * ||b_r||; scale[r] = 1 / ||r_r|| (0 for
-// systems that are done)
+// systems that are done); flag = some system is active
 void gm_begin(const DevGmres& d, int m, int nb, double tol, int first, hipStream_t s);
 // after the first Gram-Schmidt pass of step j (res = <V_i, w>, <w, w>):
 // decide the second pass, coef = its coefficients (zero where none)
 void gm_cgs1(const DevGmres& d, int j, int nb, hipStream_t s);
 // after the second pass: Hessenberg column, Givens rotation, stopping test;
-// coef / scale = the update w += V c and V_{j+1} = w / h_{j+1,j}
+// coef / scale = the update w += V c and V_{j+1} = w / h_{j+1,j}; flag =
+// some system is still live
 void gm_step(const DevGmres& d, int j, int m, int nb, hipStream_t s);
 // end of a cycle: coef = y = R^-1 g of every active system (zero beyond its
-// last step)
+// last step); flag = some system needs another cycle
 void gm_solve(const DevGmres& d, int m, int nb, hipStream_t s);
 
 }  // namespace ddamg

@@ -20,9 +20,15 @@ __global__ void k_gm_reset(long long* iters, int nb) {
   if (r < nb) iters[r] = 0;
 }
 
-__global__ void k_gm_begin(DevGmres d, int m, int nb, double tol, int first) {
-  const int r = threadIdx.x;
-  if (r >= nb) return;
+// lane 0 stores whether any lane's predicate holds; called once by every
+// lane of the wavefront, outside divergent code
+__device__ inline void set_flag(int* flag, bool pred) {
+  const unsigned long long any = __ballot(pred);
+  if (threadIdx.x == 0) *flag = any != 0ull;
+}
+
+// the per-system bodies return the lane's part of the flag
+__device__ inline bool gm_begin_body(DevGmres& d, int r, int m, double tol, int first) {
   GmSys& S = d.sys[r];
   const double beta = sqrt(fmax(d.res[(size_t)r * (KMAX + 1)].x, 0.0));
   if (first) {
@@ -38,6 +44,13 @@ __global__ void k_gm_begin(DevGmres d, int m, int nb, double tol, int first) {
   for (int i = 0; i <= m; ++i) S.g[i] = make_double2(0.0, 0.0);
   S.g[0] = make_double2(S.active ? beta : 0.0, 0.0);
   d.scale[r] = S.active ? 1.0 / beta : 0.0;
+  return S.active;
+}
+
+__global__ void k_gm_begin(DevGmres d, int m, int nb, double tol, int first) {
+  const int r = threadIdx.x;
+  const bool live = r < nb ? gm_begin_body(d, r, m, tol, first) : false;
+  set_flag(d.flag, live);
 }
 
 __global__ void k_gm_cgs1(DevGmres d, int j, int nb) {
@@ -57,15 +70,13 @@ __global__ void k_gm_cgs1(DevGmres d, int j, int nb) {
   for (int i = 0; i <= j; ++i) d.coef[(size_t)r * KMAX + i] = again ? cneg(h[i]) : make_double2(0.0, 0.0);
 }
 
-__global__ void k_gm_step(DevGmres d, int j, int m, int nb) {
-  const int r = threadIdx.x;
-  if (r >= nb) return;
+__device__ inline bool gm_step_body(DevGmres& d, int r, int j, int m) {
   GmSys& S = d.sys[r];
   double2* cf = d.coef + (size_t)r * KMAX;
   if (!S.live) {
     for (int i = 0; i <= j; ++i) cf[i] = make_double2(0.0, 0.0);
     d.scale[r] = 0.0;
-    return;
+    return false;
   }
   const double2* h2 = d.res + (size_t)r * (KMAX + 1);
   double proj = 0;
@@ -122,21 +133,34 @@ __global__ void k_gm_step(DevGmres d, int j, int m, int nb) {
     S.conv = 1;
   }
   d.scale[r] = S.live ? 1.0 / hn : 0.0;
+  return S.live;
 }
 
-__global__ void k_gm_solve(DevGmres d, int m, int nb) {
+__global__ void k_gm_step(DevGmres d, int j, int m, int nb) {
   const int r = threadIdx.x;
-  if (r >= nb) return;
+  const bool live = r < nb ? gm_step_body(d, r, j, m) : false;
+  set_flag(d.flag, live);
+}
+
+__device__ inline bool gm_solve_body(DevGmres& d, int r, int m) {
   GmSys& S = d.sys[r];
+  const bool again = S.active && !S.conv;
   double2* y = d.coef + (size_t)r * KMAX;
   for (int i = 0; i < m; ++i) y[i] = make_double2(0.0, 0.0);
-  if (!S.active || S.jend == 0) return;
+  if (!S.active || S.jend == 0) return again;
   const double2* H = S.H;
   for (int i = S.jend - 1; i >= 0; --i) {
     double2 acc = S.g[i];
     for (int k = i + 1; k < S.jend; ++k) acc = csub(acc, cmul(H[(size_t)i * m + k], y[k]));
     y[i] = cdiv(acc, H[(size_t)i * m + i]);
   }
+  return again;
+}
+
+__global__ void k_gm_solve(DevGmres d, int m, int nb) {
+  const int r = threadIdx.x;
+  const bool again = r < nb ? gm_solve_body(d, r, m) : false;
+  set_flag(d.flag, again);
 }
 
 }  // namespace

@@ -147,7 +147,10 @@ struct Hierarchy {
   DevArray<double2> gm_res, gm_coef;
   DevArray<double> gm_scale;
   DevArray<long long> gm_iters;
+  int* gm_flag_host = nullptr;     // coherent pinned word, written by the kernels
+  int* gm_flag_dev = nullptr;
   bool dev_scalars = false;
+  int pred_steps = 4;              // steps the last polled device-scalar GMRES cycle needed
   long long gen = 0;
   struct PreGraph {
     hipGraphExec_t exec = nullptr;
@@ -179,11 +182,13 @@ struct Hierarchy {
   // every system keeps its own Krylov scalars and stopping test, so the
   // result for each equals that of a solve on its own.
   template <typename T> void cycle(int l, const C<T>* b, C<T>* z, int nb = 1);
-  template <typename T> void coarsest_solve(const C<T>* b, C<T>* z, int nb);
-  // the same with the GMRES scalars on the device (fixed launch sequence)
-  template <typename T> void coarsest_solve_dev(const C<T>* b, C<T>* z, int nb);
+  // Coarsest solve (odd-even reduced GMRES) with the GMRES scalars on the
+  // device: poll > 0 reads the device's liveness flag every poll steps and
+  // at each restart (a host round trip each) and stops there when no
+  // system is left; poll = 0 issues the fixed launch sequence (graph capture)
+  template <typename T> void coarsest_solve(const C<T>* b, C<T>* z, int nb, int poll);
   template <typename T, typename Op>
-  void gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb);
+  void gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb, int poll);
   // level-0 cycle of the batch, work<T>(0).bin -> work<T>(0).x, by replaying
   // the captured graph (captured on first use after an eager run)
   template <typename T> void apply_pre_graph(int nb);
@@ -222,6 +227,7 @@ struct Hierarchy {
   ~Hierarchy() {
     drop_graphs();
     if (own_s) (void)hipStreamDestroy(own_s);
+    if (gm_flag_host) (void)hipHostFree(gm_flag_host);
   }
 };
 

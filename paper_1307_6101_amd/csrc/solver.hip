@@ -63,6 +63,12 @@ template <typename T, typename F> void Hierarchy::interp(int l, F&& f) const {
 
 static inline double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
 
+// polled mode of the device-scalar GMRES: the first read of the liveness
+// flag comes after the number of steps the previous solve of the level
+// needed (a read costs a host round trip, a step past convergence a few
+// launches), then one read per step
+constexpr int COARSE_POLL = 1;
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -405,36 +411,6 @@ template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out, int nb) {
   });
 }
 
-template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z, int nb) {
-  const int c = L - 1;
-  const LevelStore& L_ = lv[c];
-  Work<T>& W = work<T>(c);
-  const long long n = L_.n;
-  if (!L_.cg.bipartite) {
-    fgmres<T>(
-        c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); }, [](const C<T>*, C<T>*) {}, false, b, z,
-        p.coarse_restart, p.coarse_max_restarts, p.coarse_eps, nb, cs_it.data());
-    return;
-  }
-  const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
-  // u_e = D_ee^-1 b_e
-  vzero<T>(W.t1.p, n * nb, s);
-  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, b, W.t1.p, s, nb);
-  // rhs_o = b_o - D_oe u_e (zero on even sites)
-  vzero<T>(W.t2.p, n * nb, s);
-  coarse_op<T>(c, [&](const auto& op) {
-    coarse_site_apply(op, L_.c_odd.p, no, T(1), b, T(0), nullptr, T(-1), W.t1.p, W.t2.p, s, nb);
-  });
-  fgmres<T>(
-      c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o, nb); }, [](const C<T>*, C<T>*) {}, false, W.t2.p, z,
-      p.coarse_restart, p.coarse_max_restarts, p.coarse_eps, nb, cs_it.data());
-  // z_e = D_ee^-1 (b_e - D_eo z_o)
-  coarse_op<T>(c, [&](const auto& op) {
-    coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s, nb);
-  });
-  site_matvec<T>(einv<T>(L_), L_.c_even.p, ne, L_.d, L_.n, W.t1.p, z, s, nb);
-}
-
 // ---------------------------------------------------------------------------
 // GMRES(m) from x = 0 with the scalars on the device: the host-driven
 // fgmres above (unpreconditioned) as a fixed sequence of launches
@@ -446,6 +422,8 @@ DevGmres Hierarchy::gm() {
     gm_coef.alloc((size_t)NBMAX * KMAX);
     gm_scale.alloc(NBMAX);
     gm_iters.alloc(NBMAX);
+    DD_CHECK_HIP(hipHostMalloc(&gm_flag_host, sizeof(int), hipHostMallocCoherent));
+    DD_CHECK_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&gm_flag_dev), gm_flag_host, 0));
     ++gen;
   }
   DevGmres d;
@@ -454,11 +432,13 @@ DevGmres Hierarchy::gm() {
   d.coef = gm_coef.p;
   d.scale = gm_scale.p;
   d.iters = gm_iters.p;
+  d.flag = gm_flag_dev;
   return d;
 }
 
 template <typename T, typename Op>
-void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb) {
+void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb,
+                          int poll) {
   Work<T>& W = work<T>(l);
   const long long n = lv[l].n, vs = (long long)nb * n;
   DD_REQUIRE(m <= W.m && nb <= W.cap, "Krylov basis too short for the batch");
@@ -467,10 +447,16 @@ void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycle
   C<T>* V = W.V.p;
   C<T>* w = W.w.p;
   vzero<T>(x, vs, s);
+  // the liveness flag, read after the stream has drained
+  auto flag_set = [&]() {
+    DD_CHECK_HIP(hipStreamSynchronize(s));
+    return *static_cast<volatile int*>(gm_flag_host) != 0;
+  };
   for (int c = 0; c < cycles; ++c) {
     // r = b (first cycle) or b - A x: its norm starts the cycle
     const C<T>* r0 = b;
     if (c > 0) {
+      if (poll > 0 && !flag_set()) break;   // no system needs another cycle
       op(x, w);
       vbmy<T>(b, w, vs, s);
       r0 = w;
@@ -478,20 +464,33 @@ void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycle
     red->bdots<T>(nullptr, r0, 0, 0, const_cast<C<T>*>(r0), n, nb, s, d.res);
     gm_begin(d, m, nb, tol, c == 0, s);
     bscale<T>(a, r0, V, n, nb, s);
+    int steps = 0, polls = 0;
+    const int first_poll = std::max(poll, pred_steps);
     for (int j = 0; j < m; ++j) {
       op(V + (size_t)j * vs, w);
       red->bdots<T>(nullptr, V, vs, j + 1, w, n, nb, s, d.res);
       gm_cgs1(d, j, nb, s);
       red->bdots<T>(&a, V, vs, j + 1, w, n, nb, s, d.res);
       gm_step(d, j, m, nb, s);
+      steps = j + 1;
       if (j + 1 < m) blincomb<T, T>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+      if (poll > 0 && j + 1 < m && j + 1 >= first_poll) {
+        ++polls;
+        if (!flag_set()) break;
+      }
+    }
+    if (poll > 0) {
+      // next time the first read comes one step earlier if it already found
+      // every system done, else at the step where they were
+      pred_steps = polls <= 1 ? std::max(1, steps - 1) : steps;
     }
     gm_solve(d, m, nb, s);
-    blincomb<T, T>(a, m, V, vs, x, n, nb, nullptr, s);
+    // only the basis vectors written in this cycle
+    blincomb<T, T>(a, steps, V, vs, x, n, nb, nullptr, s);
   }
 }
 
-template <typename T> void Hierarchy::coarsest_solve_dev(const C<T>* b, C<T>* z, int nb) {
+template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z, int nb, int poll) {
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
   Work<T>& W = work<T>(c);
@@ -499,7 +498,7 @@ template <typename T> void Hierarchy::coarsest_solve_dev(const C<T>* b, C<T>* z,
   if (!L_.cg.bipartite) {
     gmres_dev<T>(
         c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); }, b, z, p.coarse_restart,
-        p.coarse_max_restarts, p.coarse_eps, nb);
+        p.coarse_max_restarts, p.coarse_eps, nb, poll);
     return;
   }
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
@@ -511,7 +510,7 @@ template <typename T> void Hierarchy::coarsest_solve_dev(const C<T>* b, C<T>* z,
   });
   gmres_dev<T>(
       c, [&](const C<T>* a, C<T>* o) { schur<T>(a, o, nb); }, W.t2.p, z, p.coarse_restart,
-      p.coarse_max_restarts, p.coarse_eps, nb);
+      p.coarse_max_restarts, p.coarse_eps, nb, poll);
   coarse_op<T>(c, [&](const auto& op) {
     coarse_site_apply(op, L_.c_even.p, ne, T(1), b, T(0), nullptr, T(-1), z, W.t1.p, s, nb);
   });
@@ -592,8 +591,9 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
     restrict_to<T>(l, b, Wc.bin.p, nb);
   }
   if (l + 1 == L - 1) {
-    if (dev_scalars) coarsest_solve_dev<T>(Wc.bin.p, Wc.z.p, nb);
-    else coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb);
+    // under graph capture the fixed launch sequence, else the liveness
+    // flag is read every COARSE_POLL steps
+    coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb, dev_scalars ? 0 : COARSE_POLL);
   } else if (p.cycle == DDAMG_KCYCLE) {
     const int c = l + 1;
     fgmres<T>(
@@ -630,7 +630,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
   C<T>* Z = outerZ<T>(*this).p;
   // FP16 directions with per-site scales (FP16 storage, FP32 cycle)
   const bool zh = std::is_same<T, float>::value && p.half_directions == 1;
-  if (p.graph) gm_reset(gm(), nb, s);
+  gm_reset(gm(), nb, s);
   double2* w = ow.p;
   std::vector<double> bnorm, beta, target(nb), scale(nb);
   bnorms<double>(*red, b, n, nb, bnorm, s);
@@ -769,7 +769,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     st[r].status = status[r];
     st[r].true_relres = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
   }
-  if (p.graph) {
+  {
     std::vector<long long> it(nb);
     DD_CHECK_HIP(hipMemcpyAsync(it.data(), gm_iters.p, sizeof(long long) * nb, hipMemcpyDeviceToHost, s));
     DD_CHECK_HIP(hipStreamSynchronize(s));

@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-half", action="store_true",
                     help="skip the FP16-operator-storage variant of the mixed solve")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default SAP blocks and batch size (no autotuner search)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
@@ -151,6 +153,8 @@ def main():
     # the autotuner picks the level-1 SAP block shape (timed solves; every
     # hierarchy below is tuned the same way, the plain FP64 one included)
     def tune(H, rhs, nrhs=1):
+        if args.no_tune:
+            return None
         one_solve(H) if nrhs == 1 else None
         t = time.time()
         r = dd.tune(H, rhs, nrhs=nrhs)
@@ -159,7 +163,8 @@ def main():
     one_solve(H32)
     t_untuned = float(np.median([one_solve(H32)["seconds"] for _ in range(3)]))
     tuned32 = tune(H32, bd.reshape(1, -1))
-    tuned32["untuned_time_to_solution_s"] = round(t_untuned, 4)
+    if tuned32 is not None:
+        tuned32["untuned_time_to_solution_s"] = round(t_untuned, 4)
     log(f"[bench] autotuned: {tuned32}")
 
     for i in range(args.warmup):

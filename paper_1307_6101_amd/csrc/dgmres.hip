@@ -40,8 +40,8 @@ __device__ inline bool gm_begin_body(DevGmres& d, int r, int m, double tol, int 
   S.conv = 0;
   S.live = S.active;
   S.jend = 0;
-  for (int i = 0; i < (m + 1) * m; ++i) S.H[i] = make_double2(0.0, 0.0);
-  for (int i = 0; i <= m; ++i) S.g[i] = make_double2(0.0, 0.0);
+  // step j writes rows 0..j+1 of Hessenberg column j and g[j+1], so nothing
+  // of an earlier cycle is read again
   S.g[0] = make_double2(S.active ? beta : 0.0, 0.0);
   d.scale[r] = S.active ? 1.0 / beta : 0.0;
   return S.active;

@@ -37,6 +37,10 @@ METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU
 BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"
 FOUR_LEVEL_WORKLOAD = "clover48x96_4lvl"
 UNEVEN_WORKLOAD = "uneven8_3lvl"
+SCAN_WORKLOAD = "m0_scan_16x32"
+# bare masses of the scan on the 16^3x32 lattice (eps 0.5: the critical mass
+# estimated on 4^4 is about -0.49)
+SCAN_M0 = (-0.30, -0.35, -0.40, -0.43, -0.45, -0.46)
 # coarsest GMRES of the graph-captured V-cycle: restart length, cycles (a
 # fixed launch sequence, steps after convergence doing nothing)
 GRAPH_COARSE = (8, 1)
@@ -67,10 +71,12 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD,
+                                                      SCAN_WORKLOAD],
                     help="the bench workload (default), the 32^3x64 lattice with the 12 point sources "
                          "solved in one batch, the 48^3x96 four-level lattice, or the uneven batch of eight "
-                         "lattices (four 16^4, two 24^3x48, two 32^3x64) solved concurrently")
+                         "lattices (four 16^4, two 24^3x48, two 32^3x64) solved concurrently, or the bare-mass "
+                         "scan towards criticality on the 16^3x32 lattice (two and three levels against CGNR)")
     ap.add_argument("--lattice", default=None,
                     help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
@@ -101,6 +107,9 @@ def main():
         return
     if args.workload == UNEVEN_WORKLOAD:
         uneven_workload(args, dd, W, np, torch)
+        return
+    if args.workload == SCAN_WORKLOAD:
+        scan_workload(args, cfg, dd, W, np, torch)
         return
     if args.workload != WORKLOAD:
         big_workload(args, args.workload, W.CONFIGS[args.workload], dd, W, np, torch)
@@ -828,6 +837,91 @@ def uneven_workload(args, dd, W, np, torch):
         "plain_fp64": plain,
         "cgnr_fp64": cgn,
         "speedup_vs_plain_fp64": round(plain["total_s"] / (ms / 1000.0), 3) if plain else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def scan_workload(args, cfg, dd, W, np, torch):
+    """Critical slowing down on synthetic links: the 16^3x32 workload's links
+    (eps 0.5) with the bare mass m0 moved towards the critical value; for
+    each m0 the mixed-precision three-level and two-level solves (setup and
+    solve times, outer iterations) against FP64 CGNR (iterations, time), as
+    the paper does on its ensembles (m0 scans, 2 vs 3 levels, comparison
+    with CGNR).  A step is one pass over the masses; `value` is the
+    three-level solves per second over the scan."""
+    dims = cfg["dims"]
+    dev = torch.device("cuda:0")
+    U = torch.from_numpy(W.links(dims, cfg["eps"], cfg["seed_links"])).to(dev)
+    b = torch.from_numpy(W.gaussian_spinor(dims, cfg["seed_rhs"])).unsqueeze(0).to(dev)
+    tv = torch.from_numpy(W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])).to(dev)
+    z = torch.zeros_like(b)
+    log(f"[bench] workload {SCAN_WORKLOAD} dims={dims} m0={SCAN_M0}")
+
+    def params(levels):
+        p = dd.params_default(levels)
+        for l in range(levels - 1):
+            for mu in range(4):
+                p.agg[l][mu] = cfg["agg"][l][mu]
+            p.ntv[l] = cfg["ntv"][l]
+        p.nu = cfg["nu"]
+        p.precond_prec = dd.F32
+        return p
+
+    def timed_solve(H):
+        z.zero_()
+        torch.cuda.synchronize()
+        t = time.time()
+        rc, st = dd.solve(H, b, z)
+        torch.cuda.synchronize()
+        return time.time() - t, rc, st[0]
+
+    rows, t3 = [], []
+    for m0 in SCAN_M0:
+        ctx = dd.create(dims, m0, cfg["csw"], U)
+        row = {"m0": m0}
+        for levels in (3, 2):
+            torch.cuda.synchronize()
+            t = time.time()
+            H = dd.build_hierarchy(ctx, params(levels), tv)
+            torch.cuda.synchronize()
+            t_setup = time.time() - t
+            timed_solve(H)
+            ts = [timed_solve(H) for _ in range(max(1, args.steps))]
+            t_solve = min(x[0] for x in ts)
+            rc, st = ts[-1][1], ts[-1][2]
+            row[f"{levels}lvl"] = dict(setup_s=round(t_setup, 3), solve_s=round(t_solve, 4),
+                                        outer_iters=st["outer_iters"], status=rc,
+                                        true_relres=st["true_relres"])
+            if levels == 3:
+                t3.append(t_solve)
+            del H
+        zc = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t = time.time()
+        rc, cst = dd.cgnr(ctx, b, zc, tol=cfg["tol"], max_iter=200000)
+        torch.cuda.synchronize()
+        row["cgnr"] = dict(iterations=cst[0]["outer_iters"], solve_s=round(time.time() - t, 3), status=rc)
+        rows.append(row)
+        log(f"[bench] m0={m0}: 3 levels {row['3lvl']}, 2 levels {row['2lvl']}, CGNR {row['cgnr']}")
+        del ctx
+    ms = 1000.0 * float(np.mean(t3))
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner, f64 outer",
+        "data": "synthetic (seeded SU(3) links exp(i eps H), Gaussian rhs)",
+        "config": {"workload": f"16^3x32 Wilson-clover, eps=0.5, c_sw=1, m0 scan {list(SCAN_M0)}, "
+                               "3 and 2 levels against FP64 CGNR, tol 1e-10",
+                   "parallelism": "1 GPU"},
+        "scan": rows,
     }
     print(json.dumps(line), flush=True)
 

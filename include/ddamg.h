@@ -68,7 +68,8 @@ enum {
 
 enum { DDAMG_F64 = 0, DDAMG_F32 = 1 };            /* arithmetic precision */
 enum { DDAMG_CANONICAL = 0, DDAMG_NATIVE = 1 };   /* vector layout */
-enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1 };      /* Alg. 2 / Alg. 1 */
+enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1, DDAMG_WCYCLE = 2 };  /* Alg. 2 / Alg. 1 / Alg. 1 with
+                                                                 two coarse cycles per level */
 
 typedef struct ddamg_ctx_s* ddamg_ctx;    /* one lattice operator D */
 typedef struct ddamg_hier_s* ddamg_hier;  /* a multilevel hierarchy for D */
@@ -98,7 +99,10 @@ typedef struct {
   double tol;                 /* outer relative residual (1e-10) */
   int max_restarts;           /* outer restart cycles before DDAMG_ENOCONV */
   int precond_prec;           /* DDAMG_F32 (mixed) or DDAMG_F64 (plain) */
-  int cycle;                  /* DDAMG_KCYCLE or DDAMG_VCYCLE */
+  int cycle;                  /* DDAMG_KCYCLE, DDAMG_VCYCLE, or DDAMG_WCYCLE: on an
+                                 intermediate level the coarse system gets two
+                                 cycles, the second on the residual of the
+                                 first (a fixed count, like the V-cycle) */
   int half_storage;           /* 0: the preconditioner's operator data (fine
                                  links and clover, every P_l, every coarse D_l)
                                  are stored at precond_prec.  1: stored as IEEE
@@ -145,7 +149,7 @@ typedef struct {
                                  coarse_eps changing nothing, so results equal
                                  those of the host-driven solve up to
                                  rounding while costing the full launch
-                                 count.  Needs the V-cycle when levels >= 3
+                                 count.  Needs the V- or W-cycle when levels >= 3
                                  (the K-cycle's stopping tests are data
                                  dependent).  0 (default): host-driven. */
 } ddamg_params;

@@ -57,7 +57,9 @@ class Hierarchy:
 
     # -- Alg. 1 / Alg. 2 -----------------------------------------------------
     def cycle(self, l, b, record=None):
-        """One application of the level-l cycle to b (K-cycle unless V)."""
+        """One application of the level-l cycle to b: K-cycle (Alg. 2), V-cycle
+        (Alg. 1) or W-cycle (Alg. 1 with two level-(l+1) cycles, the second
+        on the residual of the first)."""
         op = self.ops[l]
         z = np.zeros_like(b)
         z = self.smooth(l, b, z, self.p["mu"])
@@ -73,6 +75,10 @@ class Hierarchy:
                         lambda v: self.cycle(l + 1, v, record),
                         self.p["kc_len"], self.p["kc_restarts"], self.p["kc_tol"], stats=st)
             self.counters["kcycle_iters"] += st.get("iters", 0)
+        elif self.cycle_type == "W":
+            # two cycles on level l+1, the second on the residual of the first
+            zc = self.cycle(l + 1, bc, record)
+            zc = zc + self.cycle(l + 1, bc - self.ops[l + 1].apply(zc), record)
         else:
             zc = self.cycle(l + 1, bc, record)
         if record is not None:

@@ -22,6 +22,8 @@ template <typename T> void vzero(C<T>* x, long long n, hipStream_t s);
 template <typename TA, typename TB> void vcopy(const C<TA>* x, C<TB>* y, long long n, hipStream_t s);
 // y = b - y
 template <typename T> void vbmy(const C<T>* b, C<T>* y, long long n, hipStream_t s);
+// y += x
+template <typename T> void vadd(const C<T>* x, C<T>* y, long long n, hipStream_t s);
 
 // Batches: nb systems advance together; field r of a batched vector w sits
 // at w + r*n, basis vector j of system r at V + j*vstride + r*n.

@@ -22,6 +22,11 @@ __global__ void k_bmy(const C<T>* __restrict__ b, C<T>* __restrict__ y, long lon
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   for (; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = csub(b[i], y[i]);
 }
+template <typename T>
+__global__ void k_add(const C<T>* __restrict__ x, C<T>* __restrict__ y, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = cadd(y[i], x[i]);
+}
 static unsigned grid_for(long long n) {
   long long g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -39,6 +44,10 @@ template <typename TA, typename TB> void vcopy(const C<TA>* x, C<TB>* y, long lo
 }
 template <typename T> void vbmy(const C<T>* b, C<T>* y, long long n, hipStream_t s) {
   k_bmy<T><<<grid_for(n), 256, 0, s>>>(b, y, n);
+  DD_LAUNCH_CHECK();
+}
+template <typename T> void vadd(const C<T>* x, C<T>* y, long long n, hipStream_t s) {
+  k_add<T><<<grid_for(n), 256, 0, s>>>(x, y, n);
   DD_LAUNCH_CHECK();
 }
 // ---------------------------------------------------------------------------
@@ -327,6 +336,7 @@ Reducer::~Reducer() {
 #define DD_INST(T)                                                                            \
   template void vzero<T>(C<T>*, long long, hipStream_t);                                     \
   template void vbmy<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
+  template void vadd<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
   template void Reducer::bdots<T>(const BArg*, const C<T>*, long long, int, C<T>*, long long, int, \
                                   hipStream_t, double2*);                                      \
   template void blincomb<T, T>(const BArg&, int, const C<T>*, long long, C<T>*, long long, int, C<T>*, \

@@ -591,8 +591,8 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
     restrict_to<T>(l, b, Wc.bin.p, nb);
   }
   if (l + 1 == L - 1) {
-    // under graph capture the fixed launch sequence, else the liveness
-    // flag is read every COARSE_POLL steps
+    // under graph capture the fixed launch sequence, else with the host
+    // reading the device's liveness flag
     coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb, dev_scalars ? 0 : COARSE_POLL);
   } else if (p.cycle == DDAMG_KCYCLE) {
     const int c = l + 1;
@@ -600,6 +600,14 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
         c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); },
         [&](const C<T>* a, C<T>* o) { cycle<T>(c, a, o, nb); }, true, Wc.bin.p, Wc.z.p, p.kc_len,
         p.kc_restarts, p.kc_tol, nb, kc_it.data());
+  } else if (p.cycle == DDAMG_WCYCLE) {
+    // two cycles on level l+1, the second on the residual of the first
+    const long long nc = lv[l + 1].n;
+    cycle<T>(l + 1, Wc.bin.p, Wc.z.p, nb);
+    apply<T>(l + 1, Wc.z.p, Wc.x.p, nb);
+    vbmy<T>(Wc.bin.p, Wc.x.p, nc * nb, s);
+    cycle<T>(l + 1, Wc.x.p, Wc.w.p, nb);
+    vadd<T>(Wc.w.p, Wc.z.p, nc * nb, s);
   } else {
     cycle<T>(l + 1, Wc.bin.p, Wc.z.p, nb);
   }
@@ -981,7 +989,7 @@ void sap_block_of(const ddamg_params& p, int l, int out[4]) {
 void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.levels >= 2 && p.levels <= 4, "levels must be 2..4");
   DD_REQUIRE(p.precond_prec == DDAMG_F32 || p.precond_prec == DDAMG_F64, "bad precond_prec");
-  DD_REQUIRE(p.cycle == DDAMG_KCYCLE || p.cycle == DDAMG_VCYCLE, "bad cycle");
+  DD_REQUIRE(p.cycle == DDAMG_KCYCLE || p.cycle == DDAMG_VCYCLE || p.cycle == DDAMG_WCYCLE, "bad cycle");
   DD_REQUIRE(p.half_storage == 0 || p.half_storage == 1, "half_storage must be 0 or 1");
   DD_REQUIRE(p.half_storage == 0 || p.precond_prec == DDAMG_F32,
              "FP16 operator storage needs the FP32 preconditioner");
@@ -989,8 +997,8 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.half_directions == 0 || p.precond_prec == DDAMG_F32,
              "FP16 directions need the FP32 preconditioner");
   DD_REQUIRE(p.graph == 0 || p.graph == 1, "graph must be 0 or 1");
-  DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle == DDAMG_VCYCLE,
-             "a graph-captured preconditioner needs the V-cycle (levels >= 3)");
+  DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle != DDAMG_KCYCLE,
+             "a graph-captured preconditioner needs the V- or W-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
   DD_REQUIRE(p.nkv >= 1 && p.nkv <= KMAX - 1, "nkv out of range");
   DD_REQUIRE(p.kc_len >= 1 && p.kc_len <= KMAX - 1 && p.kc_restarts >= 1, "bad K-cycle length");

@@ -22,7 +22,7 @@ std::string tune_key(const Hierarchy& H, int nrhs) {
     << "|" << (p.precond_prec == DDAMG_F64 ? "f64" : (p.half_storage ? "f16" : "f32")) << "|L" << p.levels;
   for (int l = 0; l < p.levels - 1; ++l)
     k << "|a" << p.agg[l][0] << "." << p.agg[l][1] << "." << p.agg[l][2] << "." << p.agg[l][3] << "n" << p.ntv[l];
-  k << "|" << (p.cycle == DDAMG_VCYCLE ? "V" : "K") << (p.graph ? "g" : "") << "|nrhs" << nrhs;
+  k << "|" << (p.cycle == DDAMG_VCYCLE ? "V" : p.cycle == DDAMG_WCYCLE ? "W" : "K") << (p.graph ? "g" : "") << "|nrhs" << nrhs;
   return k.str();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libddamg.so")
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 CANONICAL, NATIVE = 0, 1
-KCYCLE, VCYCLE = 0, 1
+KCYCLE, VCYCLE, WCYCLE = 0, 1, 2
 
 
 class DDAMGError(RuntimeError):

@@ -54,7 +54,7 @@ def to_params(dd, p, prec=None, cycle="K", half=False, half_dirs=False):
     P.nkv, P.tol = p["nkv"], p["tol"]
     P.max_restarts = p.get("max_restarts", 100)
     P.precond_prec = dd.F64 if prec is None else prec
-    P.cycle = dd.KCYCLE if cycle == "K" else dd.VCYCLE
+    P.cycle = {"K": dd.KCYCLE, "V": dd.VCYCLE, "W": dd.WCYCLE}[cycle]
     P.half_storage = 1 if half else 0
     P.half_directions = 1 if half_dirs else 0
     return P

@@ -87,7 +87,7 @@ def three_level():
                  m0=-0.3)
 
 
-@pytest.mark.parametrize("cycle", ["K", "V"])
+@pytest.mark.parametrize("cycle", ["K", "V", "W"])
 def test_three_level_solve_known_solution(three_level, cycle):
     """b = D z* for a Gaussian z*; report ||z - z*|| / ||z*|| (Sec. 3.4)."""
     H, op = three_level
@@ -150,3 +150,26 @@ def test_per_level_sap_blocks(rng):
     f = W.gaussian_spinor(dims, 79)
     assert np.array_equal(H1.smooth(0, f, np.zeros_like(f), 1),
                           sap_sweep(op, f, np.zeros_like(f), (2, 2, 2, 2), base["mr_iters"]))
+
+
+def test_w_cycle_equals_v_cycle_for_exact_coarse_correction(rng):
+    """Without smoothing on level 1 and with an exact coarsest solve, the
+    level-1 cycle is P (P^H D_1 P)^-1 P^H, whose second application to the
+    residual of the first adds nothing (Galerkin orthogonality): the W-cycle
+    then equals the V-cycle.  With smoothing the two differ."""
+    H, op = _hier((8, 8, 8, 8), [(2, 2, 2, 2), (2, 2, 2, 2)], [4, 4], 3, 601, n_inv=1, m0=-0.3,
+                  coarse_eps=1e-14, coarse_restart=60, coarse_max_restarts=20)
+    b = W.gaussian_spinor(op.dims, 602)
+    H.p["mu"] = 0
+    H.p["nu"] = 0
+    H.cycle_type = "V"
+    zv = H.cycle(0, b)
+    H.cycle_type = "W"
+    zw = H.cycle(0, b)
+    assert norm(zw - zv) <= 1e-10 * norm(zv)
+    H.p["nu"] = 2
+    H.cycle_type = "V"
+    zv = H.cycle(0, b)
+    H.cycle_type = "W"
+    zw = H.cycle(0, b)
+    assert norm(zw - zv) > 1e-6 * norm(zv)

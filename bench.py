@@ -847,8 +847,9 @@ def scan_workload(args, cfg, dd, W, np, torch):
     each m0 the mixed-precision three-level and two-level solves (setup and
     solve times, outer iterations) against FP64 CGNR (iterations, time), as
     the paper does on its ensembles (m0 scans, 2 vs 3 levels, comparison
-    with CGNR).  A step is one pass over the masses; `value` is the
-    three-level solves per second over the scan."""
+    with CGNR), and the three-level K-cycle against the V- and W-cycles.  A
+    step is one pass over the masses; `value` is the three-level K-cycle
+    solves per second over the scan."""
     dims = cfg["dims"]
     dev = torch.device("cuda:0")
     U = torch.from_numpy(W.links(dims, cfg["eps"], cfg["seed_links"])).to(dev)
@@ -857,7 +858,7 @@ def scan_workload(args, cfg, dd, W, np, torch):
     z = torch.zeros_like(b)
     log(f"[bench] workload {SCAN_WORKLOAD} dims={dims} m0={SCAN_M0}")
 
-    def params(levels):
+    def params(levels, cycle=None):
         p = dd.params_default(levels)
         for l in range(levels - 1):
             for mu in range(4):
@@ -865,6 +866,8 @@ def scan_workload(args, cfg, dd, W, np, torch):
             p.ntv[l] = cfg["ntv"][l]
         p.nu = cfg["nu"]
         p.precond_prec = dd.F32
+        if cycle is not None:
+            p.cycle = cycle
         return p
 
     def timed_solve(H):
@@ -879,20 +882,20 @@ def scan_workload(args, cfg, dd, W, np, torch):
     for m0 in SCAN_M0:
         ctx = dd.create(dims, m0, cfg["csw"], U)
         row = {"m0": m0}
-        for levels in (3, 2):
+        for levels, cyc, key in ((3, None, "3lvl"), (2, None, "2lvl"), (3, dd.VCYCLE, "3lvl_vcycle"),
+                                 (3, dd.WCYCLE, "3lvl_wcycle")):
             torch.cuda.synchronize()
             t = time.time()
-            H = dd.build_hierarchy(ctx, params(levels), tv)
+            H = dd.build_hierarchy(ctx, params(levels, cyc), tv)
             torch.cuda.synchronize()
             t_setup = time.time() - t
             timed_solve(H)
             ts = [timed_solve(H) for _ in range(max(1, args.steps))]
             t_solve = min(x[0] for x in ts)
             rc, st = ts[-1][1], ts[-1][2]
-            row[f"{levels}lvl"] = dict(setup_s=round(t_setup, 3), solve_s=round(t_solve, 4),
-                                        outer_iters=st["outer_iters"], status=rc,
-                                        true_relres=st["true_relres"])
-            if levels == 3:
+            row[key] = dict(setup_s=round(t_setup, 3), solve_s=round(t_solve, 4),
+                            outer_iters=st["outer_iters"], status=rc, true_relres=st["true_relres"])
+            if key == "3lvl":
                 t3.append(t_solve)
             del H
         zc = torch.zeros_like(b)
@@ -902,7 +905,8 @@ def scan_workload(args, cfg, dd, W, np, torch):
         torch.cuda.synchronize()
         row["cgnr"] = dict(iterations=cst[0]["outer_iters"], solve_s=round(time.time() - t, 3), status=rc)
         rows.append(row)
-        log(f"[bench] m0={m0}: 3 levels {row['3lvl']}, 2 levels {row['2lvl']}, CGNR {row['cgnr']}")
+        log(f"[bench] m0={m0}: " + ", ".join(f"{k} {v.get('outer_iters', v.get('iterations'))} its "
+                                               f"{v['solve_s']}s" for k, v in row.items() if k != "m0"))
         del ctx
     ms = 1000.0 * float(np.mean(t3))
     line = {
@@ -919,7 +923,7 @@ def scan_workload(args, cfg, dd, W, np, torch):
         "dtype": "f32 preconditioner, f64 outer",
         "data": "synthetic (seeded SU(3) links exp(i eps H), Gaussian rhs)",
         "config": {"workload": f"16^3x32 Wilson-clover, eps=0.5, c_sw=1, m0 scan {list(SCAN_M0)}, "
-                               "3 and 2 levels against FP64 CGNR, tol 1e-10",
+                               "3 levels (K-, V-, W-cycle) and 2 levels against FP64 CGNR, tol 1e-10",
                    "parallelism": "1 GPU"},
         "scan": rows,
     }

@@ -148,3 +148,54 @@ class WilsonClover:
             Uc = dagger(shift(self.U[..., mu, :, :], mu, -1))
             s = self._pm[mu][1]
         return (-0.5 * np.einsum("st,...ab->...satb", s, Uc)).reshape(lat + (12, 12))
+
+
+def apply_at_sites(U: np.ndarray, m0: float, csw: float, psi: np.ndarray, sites) -> np.ndarray:
+    """(D psi)(x) at the given sites only, each written out from the
+    operator's definition (Sec. 1, eq. (1)) with its own index arithmetic:
+    the four leaves of every (mu, nu) plane at x, the clover term, the mass
+    term and the eight hops.  For checks of large lattices on sampled sites.
+    ``sites`` holds (x, y, z, t) tuples; psi has shape (T, Z, Y, X, 12);
+    returns (len(sites), 12)."""
+    T, Z, Y, X = U.shape[:4]
+    ext = (X, Y, Z, T)
+
+    def at(c):
+        return (c[3] % T, c[2] % Z, c[1] % Y, c[0] % X)
+
+    def link(c, mu):
+        return U[at(c) + (mu,)]
+
+    def step(c, mu, k):
+        c = list(c)
+        c[mu] += k
+        return c
+
+    def h(m):
+        return m.conj().T
+
+    out = np.zeros((len(sites), 12), dtype=np.complex128)
+    for n, x in enumerate(sites):
+        x = [int(v) % e for v, e in zip(x, ext)]
+        p = psi[at(x)].reshape(4, 3)
+        o = (m0 + 4.0) * p
+        if csw != 0.0:
+            for mu in range(4):
+                for nu in range(4):
+                    if mu == nu:
+                        continue
+                    xm, xn = step(x, mu, -1), step(x, nu, -1)
+                    q = (link(x, mu) @ link(step(x, mu, 1), nu) @ h(link(step(x, nu, 1), mu)) @ h(link(x, nu))
+                         + link(x, nu) @ h(link(step(xm, nu, 1), mu)) @ h(link(xm, nu)) @ link(xm, mu)
+                         + h(link(xm, mu)) @ h(link(step(xm, nu, -1), nu)) @ link(step(xm, nu, -1), mu)
+                         @ link(xn, nu)
+                         + h(link(xn, nu)) @ link(xn, mu) @ link(step(xn, mu, 1), nu) @ h(link(x, mu)))
+                    f = q - h(q)
+                    o = o - (csw / 32.0) * (GAMMA[mu] @ GAMMA[nu]) @ p @ f.T
+        for mu in range(4):
+            fwd = psi[at(step(x, mu, 1))].reshape(4, 3)
+            bwd = psi[at(step(x, mu, -1))].reshape(4, 3)
+            o = o - 0.5 * ((np.eye(4) - GAMMA[mu]) @ fwd @ link(x, mu).T
+                           + (np.eye(4) + GAMMA[mu]) @ bwd @ h(link(step(x, mu, -1), mu)).T)
+        out[n] = o.reshape(12)
+    return out

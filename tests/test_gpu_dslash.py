@@ -86,6 +86,33 @@ def test_apply_D_full_size_16x32(dd):
         assert e <= tol
 
 
+@pytest.mark.parametrize("name", ["clover32x64_3lvl_12rhs"])
+def test_apply_D_sampled_full_size(dd, name):
+    """The 32^3x64 workload's operator on three fields in one launch (the
+    batched launch of its 12-source solves), FP64 and FP32, checked on 64
+    sampled sites per field against the oracle's site-by-site evaluation
+    (the whole-lattice oracle is too slow at 2.1 M sites)."""
+    from oracle.dirac import apply_at_sites
+    cfg = W.CONFIGS[name]
+    dims = cfg["dims"]
+    say(f"apply_D sampled full-size {dims}")
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    psi = W.gaussian_spinor(dims, cfg["seed_rhs"], nrhs=3)
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+    rng = np.random.Generator(np.random.PCG64(2024))
+    sites = [tuple(int(rng.integers(0, e)) for e in dims) for _ in range(64)]
+    refs = [apply_at_sites(U, cfg["m0"], cfg["csw"], psi[r], sites) for r in range(3)]
+    for prec, tol in ((dd.F64, 1e-13), (dd.F32, 1e-5)):
+        out = empty(psi.shape)
+        dd.apply_D(ctx, dev(psi), out, nrhs=3, prec=prec)
+        o = host(out)
+        for r in range(3):
+            got = np.array([o[r, t, z, y, x] for (x, y, z, t) in sites])
+            e = relerr(got, refs[r])
+            say(f"  prec={prec} field {r}: sampled relerr={e:.3e}")
+            assert e <= tol
+
+
 def test_bad_arguments_raise(dd):
     dims = (4, 4, 4, 4)
     U = W.links(dims, 0.5, 9)

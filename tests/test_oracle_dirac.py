@@ -149,3 +149,18 @@ def test_links_are_su3():
     I = np.eye(3)
     assert np.max(np.abs(dagger(U) @ U - I)) < 1e-14
     assert np.max(np.abs(np.linalg.det(U) - 1)) < 1e-14
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_apply_at_sites_matches_full_apply(csw, rng):
+    """The site-by-site evaluation (used on sampled sites of large lattices)
+    against the whole-lattice operator, on every site of a 4x4x4x6 lattice."""
+    from oracle.dirac import apply_at_sites
+    dims = (4, 4, 4, 6)
+    U = W.links(dims, 0.6, 97)
+    psi = W.gaussian_spinor(dims, 98)
+    full = WilsonClover(U, -0.3, csw).apply(psi)
+    sites = [(x, y, z, t) for t in range(6) for z in range(4) for y in range(4) for x in range(4)]
+    got = apply_at_sites(U, -0.3, csw, psi, sites)
+    ref = np.array([full[t, z, y, x] for (x, y, z, t) in sites])
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))

@@ -32,7 +32,10 @@
  *                has local index (x&1)+2(y&1)+4(z&1)+8(t&1) in block
  *                (x/2,y/2,z/2,t/2); blocks are numbered tile-major: a tile is
  *                the 2x2x2x2 blocks of one 4^4 brick (block bits in the same
- *                order inside the tile), tiles lexicographic (x fastest)
+ *                order inside the tile); tiles in a Morton-like order: level
+ *                by level, each direction whose remaining tile count is even
+ *                gives one binary digit (finest level first, x lowest), the
+ *                rest lexicographic (x fastest)
  *   level-l field (l >= 1) [nrhs][V_l][2N] (canonical order)
  *   Use ddamg_to_native / ddamg_from_native to convert.
  * Levels are numbered from 0 (the fine lattice; the paper's level 1).

@@ -32,20 +32,70 @@ struct FineGeom {
 
 FineGeom make_fine_geom(const int dims[4]);
 
+// Block numbering.  The 2^4 blocks form 4^4 tiles of 2x2x2x2 blocks
+// (block = 16 * tile + index in the tile); tiles are numbered in a
+// Morton-like order: level by level, every direction whose remaining tile
+// count is even contributes one binary digit (finest level first), and what
+// is left (odd counts) is numbered lexicographically.  Consecutive tiles
+// thus form compact 4-D regions in all directions, so the workgroups that
+// run one after another on an XCD share their faces in its L2.
+__host__ __device__ inline int tile_encode(const int nt[4], const int tc[4]) {
+  int c[4] = {tc[0], tc[1], tc[2], tc[3]}, rem[4] = {nt[0], nt[1], nt[2], nt[3]};
+  int idx = 0, mult = 1;
+  for (;;) {
+    int f[4], prod = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      f[mu] = (rem[mu] % 2 == 0) ? 2 : 1;
+      prod *= f[mu];
+    }
+    if (prod == 1) break;
+    const int digit = (c[0] % f[0]) + f[0] * ((c[1] % f[1]) + f[1] * ((c[2] % f[2]) + f[2] * (c[3] % f[3])));
+    idx += digit * mult;
+    mult *= prod;
+    for (int mu = 0; mu < 4; ++mu) {
+      c[mu] /= f[mu];
+      rem[mu] /= f[mu];
+    }
+  }
+  return idx + mult * (c[0] + rem[0] * (c[1] + rem[1] * (c[2] + rem[2] * c[3])));
+}
+__host__ __device__ inline void tile_decode(const int nt[4], int tile, int tc[4]) {
+  int rem[4] = {nt[0], nt[1], nt[2], nt[3]}, scale[4] = {1, 1, 1, 1};
+  for (int mu = 0; mu < 4; ++mu) tc[mu] = 0;
+  for (;;) {
+    int f[4], prod = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      f[mu] = (rem[mu] % 2 == 0) ? 2 : 1;
+      prod *= f[mu];
+    }
+    if (prod == 1) break;
+    int digit = tile % prod;
+    tile /= prod;
+    for (int mu = 0; mu < 4; ++mu) {
+      tc[mu] += (digit % f[mu]) * scale[mu];
+      digit /= f[mu];
+      scale[mu] *= f[mu];
+      rem[mu] /= f[mu];
+    }
+  }
+  for (int mu = 0; mu < 4; ++mu) {
+    tc[mu] += (tile % rem[mu]) * scale[mu];
+    tile /= rem[mu];
+  }
+}
 // block number of the block with coordinates b (block grid nb) and back
 __host__ __device__ inline int block_encode(const int nb[4], const int b[4]) {
   const int it = (b[0] & 1) | ((b[1] & 1) << 1) | ((b[2] & 1) << 2) | ((b[3] & 1) << 3);
-  const int tile = (b[0] >> 1) + (nb[0] >> 1) * ((b[1] >> 1) + (nb[1] >> 1) * ((b[2] >> 1) + (nb[2] >> 1) * (b[3] >> 1)));
-  return tile * 16 + it;
+  const int nt[4] = {nb[0] >> 1, nb[1] >> 1, nb[2] >> 1, nb[3] >> 1};
+  const int tc[4] = {b[0] >> 1, b[1] >> 1, b[2] >> 1, b[3] >> 1};
+  return tile_encode(nt, tc) * 16 + it;
 }
 __host__ __device__ inline void block_decode(const int nb[4], int blk, int b[4]) {
   const int it = blk & 15;
-  int tile = blk >> 4;
-  for (int mu = 0; mu < 4; ++mu) {
-    const int nt = nb[mu] >> 1;
-    b[mu] = 2 * (tile % nt) + ((it >> mu) & 1);
-    tile /= nt;
-  }
+  const int nt[4] = {nb[0] >> 1, nb[1] >> 1, nb[2] >> 1, nb[3] >> 1};
+  int tc[4];
+  tile_decode(nt, blk >> 4, tc);
+  for (int mu = 0; mu < 4; ++mu) b[mu] = 2 * tc[mu] + ((it >> mu) & 1);
 }
 // host tables: nbr_blk[blk*8 + 2*mu + (0 fwd | 1 bwd)], colour lists
 void fine_tables(const FineGeom& g, int* nbr_blk, int* colour_blocks /* [2][nblk/2] */);

@@ -31,7 +31,7 @@ BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-
 # HBM traffic per launch of the FP32 stencil on the bench lattice, from the
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in
 # profiles/dslash_clover16x32_counters.md (null once the kernel changes)
-DSLASH_F32_TRAFFIC_BYTES = 129.69e6
+DSLASH_F32_TRAFFIC_BYTES = 128.25e6
 WORKLOAD = "clover16x32_3lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
 BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"

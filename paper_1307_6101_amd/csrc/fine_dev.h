@@ -101,29 +101,31 @@ __device__ inline void load_link(const S* __restrict__ U, int blk, int loc, int 
 // out = A(x) v for the packed clover of one site (both chiralities); get(e)
 // returns entry e = 0..35 as C<T>: per chirality 3 packed real diagonal
 // pairs, then the 15 upper off-diagonal entries row by row
+// one chirality block h of the clover: o = A_h w (6 components each)
+template <typename T, typename G>
+__device__ inline void clover_block(int h, G&& get, const C<T>* w, C<T>* o) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const C<T> d = get(h * 18 + k);
+    o[2 * k] = cscale(w[2 * k], d.x);
+    o[2 * k + 1] = cscale(w[2 * k + 1], d.y);
+  }
+  int e = 3;
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 6; ++b) {
+      const C<T> m = get(h * 18 + e);
+      ++e;
+      cfma(o[a], m, w[b]);
+      cjfma(o[b], m, w[a]);
+    }
+}
+
 template <typename T, typename G>
 __device__ inline void clover_mul(G&& get, const C<T> v[12], C<T> out[12]) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const C<T>* w = v + 6 * h;
-    C<T>* o = out + 6 * h;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const C<T> d = get(h * 18 + k);
-      o[2 * k] = cscale(w[2 * k], d.x);
-      o[2 * k + 1] = cscale(w[2 * k + 1], d.y);
-    }
-    int e = 3;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-      for (int b = a + 1; b < 6; ++b) {
-        const C<T> m = get(h * 18 + e);
-        ++e;
-        cfma(o[a], m, w[b]);
-        cjfma(o[b], m, w[a]);
-      }
-  }
+  for (int h = 0; h < 2; ++h) clover_block<T>(h, get, v + 6 * h, out + 6 * h);
 }
 
 template <typename T, typename S = C<T>>

@@ -489,29 +489,64 @@ __device__ inline bool agg_col_xcd(int bid, int nagg, int ncol, int& A, int& col
 }
 inline unsigned agg_col_grid(int nagg, int ncol) { return 8u * (unsigned)((nagg + 7) / 8) * (unsigned)ncol; }
 
-template <int MU, bool FWD>
-__device__ inline void gal_hop(const FineOpView<double>& op, const double2* __restrict__ Pk, int sigma,
-                               int blk, int loc, double2 acc[12]) {
+// y += -1/2 * hop of the column restricted to chirality SIGMA: the other
+// spinor half is a compile-time zero (not loaded), and the factor -1/2 is
+// applied to the input so that the hop accumulates straight into y
+template <int MU, bool FWD, int SIGMA>
+__device__ inline void gal_hop(const FineOpView<double>& op, const double2* __restrict__ Pk, int blk, int loc,
+                               double2 y[12]) {
   constexpr int bit = 1 << MU;
   int nb;
   if constexpr (FWD) nb = (loc & bit) ? op.nbr[blk * 8 + 2 * MU] : blk;
   else nb = (loc & bit) ? blk : op.nbr[blk * 8 + 2 * MU + 1];
   double2 psi[12], u[9];
-  load_spinor<double>(Pk, nb, loc ^ bit, psi);
+  const double2* p = Pk + (long long)nb * 192 + (loc ^ bit);
 #pragma unroll
   for (int c = 0; c < 12; ++c)
-    if ((c / 6) != sigma) psi[c] = czero<double>();
+    psi[c] = (c / 6) == SIGMA ? cscale(p[c * 16], -0.5) : czero<double>();
   if constexpr (FWD) load_link<double>(op.U, blk, loc, MU, u);
   else load_link<double>(op.U, nb, loc ^ bit, MU, u);
-  hop_apply<double, MU, FWD>(psi, u, acc);
+  hop_apply<double, MU, FWD>(psi, u, y);
 }
 
-template <int MU>
-__device__ inline void gal_hops_inside(const FineOpView<double>& op, const double2* Pk, int sigma,
-                                       int blk, int loc, const bool* fin, const bool* bin,
-                                       double2 acc[12]) {
-  if (fin[MU]) gal_hop<MU, true>(op, Pk, sigma, blk, loc, acc);
-  if (bin[MU]) gal_hop<MU, false>(op, Pk, sigma, blk, loc, acc);
+template <int MU, int SIGMA>
+__device__ inline void gal_hops_inside(const FineOpView<double>& op, const double2* Pk, int blk, int loc,
+                                       const bool* fin, const bool* bin, double2 y[12]) {
+  if (fin[MU]) gal_hop<MU, true, SIGMA>(op, Pk, blk, loc, y);
+  if (bin[MU]) gal_hop<MU, false, SIGMA>(op, Pk, blk, loc, y);
+}
+
+// part tau of the column (SIGMA, k) at this thread's site: tau = 0 the self
+// part (clover and the hops inside the aggregate), tau = 1 + mu the forward
+// face part across the +mu face
+template <int SIGMA>
+__device__ inline void gal_part(const FineOpView<double>& op, const double2* __restrict__ Pk, int blk, int loc,
+                                const bool* fin, const bool* bin, int tau, double2 y[12]) {
+  if (tau == 0) {
+    // the clover is block diagonal in chirality: only block SIGMA acts
+    double2 u[6];
+    const double2* p = Pk + (long long)blk * 192 + loc + 6 * SIGMA * 16;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) u[c] = p[c * 16];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) y[6 * (1 - SIGMA) + c] = czero<double>();
+    const double2* a = op.A + (long long)blk * 576 + loc;
+    clover_block<double>(SIGMA, [&](int e) { return a[e * 16]; }, u, y + 6 * SIGMA);
+    gal_hops_inside<0, SIGMA>(op, Pk, blk, loc, fin, bin, y);
+    gal_hops_inside<1, SIGMA>(op, Pk, blk, loc, fin, bin, y);
+    gal_hops_inside<2, SIGMA>(op, Pk, blk, loc, fin, bin, y);
+    gal_hops_inside<3, SIGMA>(op, Pk, blk, loc, fin, bin, y);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c] = czero<double>();
+    const int mu = tau - 1;
+    if (!fin[mu]) {
+      if (mu == 0) gal_hop<0, true, SIGMA>(op, Pk, blk, loc, y);
+      else if (mu == 1) gal_hop<1, true, SIGMA>(op, Pk, blk, loc, y);
+      else if (mu == 2) gal_hop<2, true, SIGMA>(op, Pk, blk, loc, y);
+      else gal_hop<3, true, SIGMA>(op, Pk, blk, loc, y);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int* __restrict__ members,
@@ -539,40 +574,15 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(GalFineGeom gg, const int
   }
   const double2* Pk = P + k * fstride;
   const int twoN = 2 * N;
+#pragma unroll 1
   for (int tau = 0; tau < 5; ++tau) {
-    double2 y[12], acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = czero<double>();
-    if (tau == 0) {
-      double2 u[12];
-      load_spinor<double>(Pk, blk, loc, u);
-#pragma unroll
-      for (int c = 0; c < 12; ++c)
-        if ((c / 6) != sigma) u[c] = czero<double>();
-      clover_apply<double>(op.A, blk, loc, u, y);
-      gal_hops_inside<0>(op, Pk, sigma, blk, loc, fin, bin, acc);
-      gal_hops_inside<1>(op, Pk, sigma, blk, loc, fin, bin, acc);
-      gal_hops_inside<2>(op, Pk, sigma, blk, loc, fin, bin, acc);
-      gal_hops_inside<3>(op, Pk, sigma, blk, loc, fin, bin, acc);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) y[c] = czero<double>();
-      const int mu = tau - 1;
-      if (!fin[mu]) {
-        if (mu == 0) gal_hop<0, true>(op, Pk, sigma, blk, loc, acc);
-        else if (mu == 1) gal_hop<1, true>(op, Pk, sigma, blk, loc, acc);
-        else if (mu == 2) gal_hop<2, true>(op, Pk, sigma, blk, loc, acc);
-        else gal_hop<3, true>(op, Pk, sigma, blk, loc, acc);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      y[c].x -= 0.5 * acc[c].x;
-      y[c].y -= 0.5 * acc[c].y;
-    }
+    double2 y[12];
+    if (sigma == 0) gal_part<0>(op, Pk, blk, loc, fin, bin, tau, y);
+    else gal_part<1>(op, Pk, blk, loc, fin, bin, tau, y);
     // a face part is nonzero only on the aggregate's face sites: the other
     // threads skip the loads of the rows of P and contribute zeros
     const bool live = tau == 0 || !fin[tau - 1];
+#pragma unroll 2
     for (int kp = 0; kp < N; ++kp) {
       double2 p0 = czero<double>(), p1 = czero<double>();
       if (live) {

@@ -615,18 +615,29 @@ void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int 
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin, coarse level: grid (aggregate, column), one thread per
-// (site of the aggregate, row i of level l).
+// Galerkin, coarse level: grid (aggregate, group of columns), one thread
+// per (site of the aggregate, row i of level l).
 // ---------------------------------------------------------------------------
 struct GalCoarseGeom {
   int dims[4];
   int agg[4];
 };
 
-// row i of a column-major block times u restricted to the columns [j0, j1)
-__device__ inline void colmajor_row_rng(const double2* M, const double2* u, int i, int d, int j0, int j1,
-                                        double2& acc) {
-  for (int j = j0; j < j1; ++j) cfma(acc, M[(size_t)j * d + i], u[j]);
+
+// KG consecutive columns (same chirality half) per workgroup: each operator
+// entry loaded is applied to all of them
+constexpr int GAL_KG = 4;
+
+// row i of a column-major block times the KG columns' vectors at site nb,
+// restricted to the components [j0, j1)
+__device__ inline void colmajor_row_kg(const double2* M, const double2* P, long long fstride, long long nb,
+                                       int k0, int nk, int i, int d, int j0, int j1, double2 (&y)[GAL_KG]) {
+  for (int j = j0; j < j1; ++j) {
+    const double2 m = M[(size_t)j * d + i];
+#pragma unroll
+    for (int g = 0; g < GAL_KG; ++g)
+      if (g < nk) cfma(y[g], m, P[(k0 + g) * fstride + nb * d + j]);
+  }
 }
 
 __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N, int nagg,
@@ -635,9 +646,11 @@ __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ memb
   extern __shared__ unsigned char smem_raw[];
   double* red = reinterpret_cast<double*>(smem_raw);
   const int d = op.d, h = d / 2;
-  int A, col;
-  if (!agg_col_xcd(blockIdx.x, nagg, 2 * N, A, col)) return;
-  const int sigma = col / N, k = col % N;
+  const int ngs = (N + GAL_KG - 1) / GAL_KG;   // column groups per chirality
+  int A, grp;
+  if (!agg_col_xcd(blockIdx.x, nagg, 2 * ngs, A, grp)) return;
+  const int sigma = grp / ngs, k0 = (grp % ngs) * GAL_KG;
+  const int nk = min(GAL_KG, N - k0);
   const int j0 = sigma * h, j1 = j0 + h;
   const int t = threadIdx.x;
   const bool valid = t < asz * d;
@@ -655,37 +668,38 @@ __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ memb
     }
   }
   const size_t bsz = (size_t)d * d;
-  const double2* Pk = P + k * fstride;
   const double2* Kx = op.K + (size_t)site * 9 * bsz;
   const int* nb9 = op.nbr9 + (size_t)site * 9;
   const int twoN = 2 * N;
   for (int tau = 0; tau < 5; ++tau) {
-    double2 y = czero<double>();
+    double2 y[GAL_KG];
+#pragma unroll
+    for (int g = 0; g < GAL_KG; ++g) y[g] = czero<double>();
     if (valid) {
       if (tau == 0) {
-        colmajor_row_rng(Kx, Pk + (size_t)site * d, i, d, j0, j1, y);
+        colmajor_row_kg(Kx, P, fstride, site, k0, nk, i, d, j0, j1, y);
         for (int mu = 0; mu < 4; ++mu) {
-          if (fin[mu])
-            colmajor_row_rng(Kx + (1 + mu) * bsz, Pk + (size_t)nb9[1 + mu] * d, i, d, j0, j1, y);
-          if (bin[mu])
-            colmajor_row_rng(Kx + (5 + mu) * bsz, Pk + (size_t)nb9[5 + mu] * d, i, d, j0, j1, y);
+          if (fin[mu]) colmajor_row_kg(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
+          if (bin[mu]) colmajor_row_kg(Kx + (5 + mu) * bsz, P, fstride, nb9[5 + mu], k0, nk, i, d, j0, j1, y);
         }
       } else {
         const int mu = tau - 1;
-        if (!fin[mu])
-          colmajor_row_rng(Kx + (1 + mu) * bsz, Pk + (size_t)nb9[1 + mu] * d, i, d, j0, j1, y);
+        if (!fin[mu]) colmajor_row_kg(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
       }
     }
     const bool up = i < h;
-    for (int kp = 0; kp < N; ++kp) {
-      double2 p = czero<double>();
-      if (valid) cjfma(p, P[kp * fstride + (size_t)site * d + i], y);
-      stash4<double>(red, N, kp, up ? p.x : 0.0, up ? p.y : 0.0, up ? 0.0 : p.x, up ? 0.0 : p.y);
+    for (int g = 0; g < nk; ++g) {
+      for (int kp = 0; kp < N; ++kp) {
+        double2 p = czero<double>();
+        if (valid) cjfma(p, P[kp * fstride + (size_t)site * d + i], y[g]);
+        stash4<double>(red, N, kp, up ? p.x : 0.0, up ? p.y : 0.0, up ? 0.0 : p.x, up ? 0.0 : p.y);
+      }
+      __syncthreads();
+      const int col = sigma * N + k0 + g;
+      if (t < twoN)
+        Dc[(((long long)A * 5 + tau) * twoN + t) * twoN + col] = collect<double>(red, N, t / N, t % N);
+      __syncthreads();
     }
-    __syncthreads();
-    if (t < twoN)
-      Dc[(((long long)A * 5 + tau) * twoN + t) * twoN + col] = collect<double>(red, N, t / N, t % N);
-    __syncthreads();
   }
 }
 
@@ -698,8 +712,9 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   for (int mu = 0; mu < 4; ++mu) { gg.dims[mu] = cg.dims[mu]; gg.agg[mu] = a.agg[mu]; }
   const int wg = 64 * ((rows + 63) / 64);
   const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(double);
-  k_galerkin_coarse<<<agg_col_grid(a.nagg, 2 * N), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
-                                                                 (long long)cg.V * cg.d, Dc);
+  const int ngs = (N + GAL_KG - 1) / GAL_KG;
+  k_galerkin_coarse<<<agg_col_grid(a.nagg, 2 * ngs), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
+                                                                   (long long)cg.V * cg.d, Dc);
   DD_LAUNCH_CHECK();
 }
 

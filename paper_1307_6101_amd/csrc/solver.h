@@ -183,9 +183,10 @@ struct Hierarchy {
   // result for each equals that of a solve on its own.
   template <typename T> void cycle(int l, const C<T>* b, C<T>* z, int nb = 1);
   // Coarsest solve (odd-even reduced GMRES) with the GMRES scalars on the
-  // device: poll > 0 reads the device's liveness flag every poll steps and
-  // at each restart (a host round trip each) and stops there when no
-  // system is left; poll = 0 issues the fixed launch sequence (graph capture)
+  // device: with poll > 0 the host reads the device's liveness flag (a
+  // round trip each) first after max(poll, pred_steps) steps, then every
+  // step, and at each restart, and stops when no system is left; poll = 0
+  // issues the fixed launch sequence (graph capture)
   template <typename T> void coarsest_solve(const C<T>* b, C<T>* z, int nb, int poll);
   template <typename T, typename Op>
   void gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycles, double tol, int nb, int poll);

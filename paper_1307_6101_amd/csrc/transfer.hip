@@ -625,21 +625,24 @@ struct GalCoarseGeom {
 
 
 // KG consecutive columns (same chirality half) per workgroup: each operator
-// entry loaded is applied to all of them
-constexpr int GAL_KG = 4;
+// entry loaded is applied to all of them (KG = 4 where the level has
+// aggregates enough to keep the device busy with a quarter of the
+// workgroups, else 1)
 
 // row i of a column-major block times the KG columns' vectors at site nb,
 // restricted to the components [j0, j1)
+template <int KG>
 __device__ inline void colmajor_row_kg(const double2* M, const double2* P, long long fstride, long long nb,
-                                       int k0, int nk, int i, int d, int j0, int j1, double2 (&y)[GAL_KG]) {
+                                       int k0, int nk, int i, int d, int j0, int j1, double2 (&y)[KG]) {
   for (int j = j0; j < j1; ++j) {
     const double2 m = M[(size_t)j * d + i];
 #pragma unroll
-    for (int g = 0; g < GAL_KG; ++g)
+    for (int g = 0; g < KG; ++g)
       if (g < nk) cfma(y[g], m, P[(k0 + g) * fstride + nb * d + j]);
   }
 }
 
+template <int GAL_KG>
 __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ members, int asz, int N, int nagg,
                                   CoarseOpView<double> op, const double2* __restrict__ P,
                                   long long fstride, double2* __restrict__ Dc) {
@@ -677,14 +680,14 @@ __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ memb
     for (int g = 0; g < GAL_KG; ++g) y[g] = czero<double>();
     if (valid) {
       if (tau == 0) {
-        colmajor_row_kg(Kx, P, fstride, site, k0, nk, i, d, j0, j1, y);
+        colmajor_row_kg<GAL_KG>(Kx, P, fstride, site, k0, nk, i, d, j0, j1, y);
         for (int mu = 0; mu < 4; ++mu) {
-          if (fin[mu]) colmajor_row_kg(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
-          if (bin[mu]) colmajor_row_kg(Kx + (5 + mu) * bsz, P, fstride, nb9[5 + mu], k0, nk, i, d, j0, j1, y);
+          if (fin[mu]) colmajor_row_kg<GAL_KG>(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
+          if (bin[mu]) colmajor_row_kg<GAL_KG>(Kx + (5 + mu) * bsz, P, fstride, nb9[5 + mu], k0, nk, i, d, j0, j1, y);
         }
       } else {
         const int mu = tau - 1;
-        if (!fin[mu]) colmajor_row_kg(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
+        if (!fin[mu]) colmajor_row_kg<GAL_KG>(Kx + (1 + mu) * bsz, P, fstride, nb9[1 + mu], k0, nk, i, d, j0, j1, y);
       }
     }
     const bool up = i < h;
@@ -712,9 +715,14 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   for (int mu = 0; mu < 4; ++mu) { gg.dims[mu] = cg.dims[mu]; gg.agg[mu] = a.agg[mu]; }
   const int wg = 64 * ((rows + 63) / 64);
   const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(double);
-  const int ngs = (N + GAL_KG - 1) / GAL_KG;
-  k_galerkin_coarse<<<agg_col_grid(a.nagg, 2 * ngs), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
-                                                                   (long long)cg.V * cg.d, Dc);
+  if ((long long)a.nagg * 2 * ((N + 3) / 4) >= 2048) {
+    const int ngs = (N + 3) / 4;
+    k_galerkin_coarse<4><<<agg_col_grid(a.nagg, 2 * ngs), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
+                                                                       (long long)cg.V * cg.d, Dc);
+  } else {
+    k_galerkin_coarse<1><<<agg_col_grid(a.nagg, 2 * N), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
+                                                                     (long long)cg.V * cg.d, Dc);
+  }
   DD_LAUNCH_CHECK();
 }
 

@@ -155,6 +155,17 @@ typedef struct {
                                  count.  Needs the V- or W-cycle when levels >= 3
                                  (the K-cycle's stopping tests are data
                                  dependent).  0 (default): host-driven. */
+  int coarse_dense;           /* 1 (default): on a coarsest level whose
+                                 odd-even Schur system S = D_oo - D_oe
+                                 D_ee^-1 D_eo (Sec. 3.3) is small (at most
+                                 2048 unknowns and at most twice the entries
+                                 of the level's sparse blocks) the setup forms
+                                 S as a dense matrix (FP64, with an FP32 copy
+                                 that the FP32 and FP16-storage solves use)
+                                 and the coarsest GMRES applies it with one
+                                 launch instead of the three-launch sparse
+                                 product; results agree up to rounding.
+                                 0: always the sparse product. */
 } ddamg_params;
 
 typedef struct {

@@ -211,6 +211,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->batch = 16;
   p->half_directions = 0;
   p->graph = 0;
+  p->coarse_dense = 1;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {

@@ -92,6 +92,19 @@ void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsite
 template <typename T>
 void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n, const C<T>* in, C<T>* out,
                  hipStream_t s, int nb = 1);
+// Dense Schur complement S = D_oo - D_oe D_ee^-1 D_eo of a small bipartite
+// coarsest level (odd-even reduction), row-major [m][m] over the m = n_odd * d
+// odd-site components; oidx[i] is the level-vector index of component i,
+// eidx[i] the index of an even-site component (the two counts are equal).
+// out = S in on the odd components and 0 on the even ones; nb fields n apart
+template <typename T>
+void dense_schur_apply(const C<T>* S, int m, const int* oidx, const int* eidx, long long n, const C<T>* in,
+                       C<T>* out, hipStream_t s, int nb = 1);
+// nbc level vectors n apart, vector r the unit vector of odd component j0 + r
+void schur_unit_cols(double2* e, long long n, int nbc, const int* oidx, int j0, hipStream_t s);
+// columns j0 .. j0 + nbc - 1 of S from the odd components of nbc level vectors
+void schur_gather_cols(const double2* cols, long long n, int nbc, const int* oidx, int m, int j0, double2* S,
+                       hipStream_t s);
 // inverses of the self blocks (taken from the FP64 [V][5][d][d] Galerkin
 // output) of `sites`, FP64 Gauss-Jordan with partial pivoting; written
 // column-major, [nsites][d][d]

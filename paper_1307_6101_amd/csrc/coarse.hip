@@ -646,12 +646,90 @@ void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n
   DD_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// dense Schur complement of a small coarsest level: one wavefront per row,
+// lanes striding over the row (contiguous) and the odd components of the
+// input (an index table, cached), four rows per workgroup
+// ---------------------------------------------------------------------------
+template <typename T, int RB>
+__global__ void __launch_bounds__(256) k_dense_schur(const C<T>* __restrict__ S, int m,
+                                                     const int* __restrict__ oidx, const int* __restrict__ eidx,
+                                                     const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                     long long n) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= m) return;   // wavefront-uniform: no wavefront is split
+  const long long off = (long long)blockIdx.y * RB * n;
+  in += off;
+  out += off;
+  const C<T>* row = S + (size_t)i * m;
+  C<T> acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = czero<T>();
+  for (int j = lane; j < m; j += 64) {
+    const C<T> a = row[j];
+    const int o = oidx[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) cfma(acc[r], a, in[r * n + o]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const T re = wave_sum(acc[r].x), im = wave_sum(acc[r].y);
+    if (lane == 0) {
+      out[r * n + oidx[i]] = mk<T>(re, im);
+      out[r * n + eidx[i]] = czero<T>();
+    }
+  }
+}
+
+template <typename T>
+void dense_schur_apply(const C<T>* S, int m, const int* oidx, const int* eidx, long long n, const C<T>* in,
+                       C<T>* out, hipStream_t s, int nb) {
+  DD_REQUIRE(m >= 1 && (long long)m <= n, "bad dense Schur shape");
+  rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
+    constexpr int RB = decltype(rb)::value;
+    k_dense_schur<T, RB><<<dim3((m + 3) / 4, nc), 256, 0, s>>>(S, m, oidx, eidx, in + first * n, out + first * n,
+                                                              n);
+  });
+  DD_LAUNCH_CHECK();
+}
+
+__global__ void k_schur_unit_cols(double2* __restrict__ e, long long n, int nbc, const int* __restrict__ oidx,
+                                  int j0) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nbc) return;
+  const int r = (int)(t / n);
+  const long long k = t - (long long)r * n;
+  e[t] = make_double2(k == oidx[j0 + r] ? 1.0 : 0.0, 0.0);
+}
+
+void schur_unit_cols(double2* e, long long n, int nbc, const int* oidx, int j0, hipStream_t s) {
+  const long long tot = n * nbc;
+  k_schur_unit_cols<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(e, n, nbc, oidx, j0);
+  DD_LAUNCH_CHECK();
+}
+
+__global__ void k_schur_gather_cols(const double2* __restrict__ cols, long long n, int nbc,
+                                    const int* __restrict__ oidx, int m, int j0, double2* __restrict__ S) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m * nbc) return;
+  const int i = (int)(t / nbc), r = (int)(t % nbc);
+  S[(size_t)i * m + j0 + r] = cols[r * n + oidx[i]];
+}
+
+void schur_gather_cols(const double2* cols, long long n, int nbc, const int* oidx, int m, int j0, double2* S,
+                       hipStream_t s) {
+  const long long tot = (long long)m * nbc;
+  k_schur_gather_cols<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(cols, n, nbc, oidx, m, j0, S);
+  DD_LAUNCH_CHECK();
+}
+
 // Gauss-Jordan inversion of the self block of every listed site, FP64.
 __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __restrict__ sites, int d,
                                double2* __restrict__ inv) {
   extern __shared__ unsigned char smem_raw[];
   double2* a = reinterpret_cast<double2*>(smem_raw);     // [d][2d]
   __shared__ int piv;
+  __shared__ double2 fcol[64];   // the pivot column's multipliers of one step
   const int k = blockIdx.x, site = sites[k];
   const int w = 2 * d;
   const double2* S = D5 + (size_t)site * 5 * d * d;
@@ -684,13 +762,14 @@ __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __rest
     const double2 pinv = mk<double>(p.x / pn, -p.y / pn);
     __syncthreads();
     for (int c = threadIdx.x; c < w; c += blockDim.x) a[col * w + c] = cmul(a[col * w + c], pinv);
+    // every row's multiplier is read before any row is updated: the update
+    // of row r overwrites a[r][col], which the other elements of the row
+    // still need (a row spans several wavefronts and loop trips)
+    for (int r = threadIdx.x; r < d; r += blockDim.x) fcol[r] = a[r * w + col];
     __syncthreads();
     for (int e = threadIdx.x; e < d * w; e += blockDim.x) {
       const int r = e / w, c = e % w;
-      if (r != col) {
-        const double2 f = a[r * w + col];
-        a[e] = csub(a[e], cmul(f, a[col * w + c]));
-      }
+      if (r != col) a[e] = csub(a[e], cmul(fcol[r], a[col * w + c]));
     }
     __syncthreads();
   }
@@ -703,6 +782,7 @@ __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __rest
 
 void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv,
                         hipStream_t s) {
+  DD_REQUIRE(d >= 1 && d <= 64, "self-block inversion supports at most 64 components per site");
   const size_t sm = (size_t)d * 2 * d * sizeof(double2);
   DD_CHECK_HIP(hipFuncSetAttribute((const void*)k_self_inverse,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
@@ -743,6 +823,10 @@ DD_INST(double, double2)
 DD_INST(float, float2)
 DD_INST(float, __half2)
 #undef DD_INST
+template void dense_schur_apply<double>(const double2*, int, const int*, const int*, long long, const double2*,
+                                        double2*, hipStream_t, int);
+template void dense_schur_apply<float>(const float2*, int, const int*, const int*, long long, const float2*,
+                                       float2*, hipStream_t, int);
 template void site_matvec<double>(const double2*, const int*, int, int, long long, const double2*, double2*,
                                   hipStream_t, int);
 template void site_matvec<float>(const float2*, const int*, int, int, long long, const float2*, float2*,

@@ -93,6 +93,13 @@ struct LevelStore {
   DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
   DevArray<float2> K32, Einv32;
   DevArray<__half2> K16;
+  // dense Schur complement of a small coarsest level (sm = its order, 0 when
+  // the sparse product is used): FP64 master, FP32 copy, index tables
+  int sm = 0;
+  std::vector<int> s_oidx_h, s_eidx_h;
+  DevArray<int> s_oidx, s_eidx;
+  DevArray<double2> S64;
+  DevArray<float2> S32;
   // coarse SAP work buffers (rho, q ping-pong; per-site inner products),
   // sized for the largest batch seen
   DevArray<double2> sr64, sq64;
@@ -217,6 +224,9 @@ struct Hierarchy {
   // construct P_l (FP64 orthonormalisation) and D_{l+1} (FP64 Galerkin);
   // from32: the FP32 test vectors are the current ones
   void build_level(int l, bool from32);
+  // the dense Schur complement of coarsest level c, column by column from
+  // unit vectors through the sparse FP64 product
+  void build_dense_schur(int c);
   template <typename T> void alloc_work(int cap);
   // replace the SAP block shape of coarse level l (1 <= l <= L-2) for the
   // solves from now on (the setup already done is kept)

@@ -69,6 +69,10 @@ static inline double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
 // launches), then one read per step
 constexpr int COARSE_POLL = 1;
 
+// largest coarsest Schur system (unknowns) stored as a dense matrix: 2048^2
+// complex entries are 64 MiB in FP64 and 32 MiB in FP32
+constexpr long long DENSE_SCHUR_MAX = 2048;
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -400,6 +404,13 @@ template <> const C<float>* einv<float>(const LevelStore& L_) { return L_.Einv32
 template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out, int nb) {
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
+  if (L_.sm > 0) {
+    const C<T>* S;
+    if constexpr (std::is_same<T, double>::value) S = L_.S64.p;
+    else S = L_.S32.p;
+    dense_schur_apply<T>(S, L_.sm, L_.s_oidx.p, L_.s_eidx.p, L_.n, v, out, s, nb);
+    return;
+  }
   Work<T>& W = work<T>(c);
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
   // t3_e = D_eo v_o ; t4_e = D_ee^-1 t3_e ; out_o = D_oo v_o - D_oe t4_e
@@ -882,7 +893,33 @@ void Hierarchy::build_level(int l, bool from32) {
     const int ne = (int)Cc.cg.even.size();
     self_block_inverse(Cc.D64.p, Cc.c_even.p, ne, Cc.d, Cc.Einv64.p, s);
     if (Cc.Einv32.p) vcopy<double, float>(Cc.Einv64.p, Cc.Einv32.p, (long long)ne * Cc.d * Cc.d, s);
+    if (Cc.sm > 0) build_dense_schur(l + 1);
   }
+  DD_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void Hierarchy::build_dense_schur(int c) {
+  LevelStore& C_ = lv[c];
+  const int m = C_.sm, ne = (int)C_.cg.even.size(), no = (int)C_.cg.odd.size(), d = C_.d;
+  const long long n = C_.n;
+  constexpr int chunk = NBMAX;
+  DevArray<double2> e, t3, t4, o;
+  e.alloc((size_t)n * chunk);
+  t3.alloc((size_t)n * chunk);
+  t4.alloc((size_t)n * chunk);
+  o.alloc((size_t)n * chunk);
+  const CoarseOpView<double> op = C_.cview<double>();
+  for (int j0 = 0; j0 < m; j0 += chunk) {
+    const int nbc = std::min(chunk, m - j0);
+    schur_unit_cols(e.p, n, nbc, C_.s_oidx.p, j0, s);
+    // the sparse product of schur(): D_eo, D_ee^-1, then D_oo - D_oe
+    coarse_site_apply(op, C_.c_even.p, ne, 0.0, nullptr, 0.0, nullptr, 1.0, e.p, t3.p, s, nbc);
+    site_matvec<double>(C_.Einv64.p, C_.c_even.p, ne, d, n, t3.p, t4.p, s, nbc);
+    coarse_site_apply(op, C_.c_odd.p, no, 0.0, nullptr, 1.0, e.p, -1.0, t4.p, o.p, s, nbc);
+    schur_gather_cols(o.p, n, nbc, C_.s_oidx.p, m, j0, C_.S64.p, s);
+  }
+  vcopy<double, float>(C_.S64.p, C_.S32.p, (long long)m * m, s);
+  // the temporaries are freed on return: drain the stream first
   DD_CHECK_HIP(hipStreamSynchronize(s));
 }
 
@@ -997,6 +1034,7 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.half_directions == 0 || p.precond_prec == DDAMG_F32,
              "FP16 directions need the FP32 preconditioner");
   DD_REQUIRE(p.graph == 0 || p.graph == 1, "graph must be 0 or 1");
+  DD_REQUIRE(p.coarse_dense == 0 || p.coarse_dense == 1, "coarse_dense must be 0 or 1");
   DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle != DDAMG_KCYCLE,
              "a graph-captured preconditioner needs the V- or W-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
@@ -1108,6 +1146,23 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       if (l == L - 1 && S.cg.bipartite) {
         S.Einv64.alloc(S.cg.even.size() * (size_t)d * d);
         S.Einv32.alloc(S.cg.even.size() * (size_t)d * d);
+        // a dense Schur complement where it is small: at most DENSE_SCHUR_MAX
+        // unknowns and at most twice the entries of the sparse blocks
+        const long long m = (long long)S.cg.odd.size() * d, sparse = S.V * 9LL * d * d;
+        if (p.coarse_dense && S.cg.odd.size() == S.cg.even.size() && m <= DENSE_SCHUR_MAX && m * m <= 2 * sparse) {
+          S.sm = (int)m;
+          S.s_oidx_h.resize(m);
+          S.s_eidx_h.resize(m);
+          for (size_t k = 0; k < S.cg.odd.size(); ++k)
+            for (int a = 0; a < d; ++a) {
+              S.s_oidx_h[k * d + a] = S.cg.odd[k] * d + a;
+              S.s_eidx_h[k * d + a] = S.cg.even[k] * d + a;
+            }
+          S.s_oidx.upload(S.s_oidx_h, s);
+          S.s_eidx.upload(S.s_eidx_h, s);
+          S.S64.alloc((size_t)m * m);
+          S.S32.alloc((size_t)m * m);
+        }
       }
     }
     if (l < L - 1) {

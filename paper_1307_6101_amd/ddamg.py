@@ -57,6 +57,7 @@ class Params(ctypes.Structure):
         ("sap_block_l", (ctypes.c_int * 4) * 3),
         ("half_directions", ctypes.c_int),
         ("graph", ctypes.c_int),
+        ("coarse_dense", ctypes.c_int),
     ]
 
 

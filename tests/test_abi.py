@@ -54,6 +54,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
          offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions),
          offsetof(ddamg_params, graph));
+  printf("%zu\n", offsetof(ddamg_params, coarse_dense));
   return 0;
 }
 ''')
@@ -80,6 +81,7 @@ int main(void) {
     assert vals[15] == dd.Params.sap_block_l.offset
     assert vals[16] == dd.Params.half_directions.offset
     assert vals[17] == dd.Params.graph.offset
+    assert vals[18] == dd.Params.coarse_dense.offset
 
 
 def test_params_default_is_table1(dd):

@@ -157,7 +157,7 @@ typedef struct {
                                  dependent).  0 (default): host-driven. */
   int coarse_dense;           /* 1 (default): on a coarsest level whose
                                  odd-even Schur system S = D_oo - D_oe
-                                 D_ee^-1 D_eo (Sec. 3.3) is small (at most
+                                 D_ee^-1 D_eo (Sec. 3) is small (at most
                                  2048 unknowns and at most twice the entries
                                  of the level's sparse blocks) the setup forms
                                  S as a dense matrix (FP64, with an FP32 copy

@@ -92,7 +92,7 @@ void coarse_site_apply(const CoarseOpView<T, S>& op, const int* sites, int nsite
 template <typename T>
 void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n, const C<T>* in, C<T>* out,
                  hipStream_t s, int nb = 1);
-// Dense Schur complement S = D_oo - D_oe D_ee^-1 D_eo of a small bipartite
+// Dense Schur complement S = D_oo - D_oe D_ee^-1 D_eo (Sec. 3) of a small bipartite
 // coarsest level (odd-even reduction), row-major [m][m] over the m = n_odd * d
 // odd-site components; oidx[i] is the level-vector index of component i,
 // eidx[i] the index of an even-site component (the two counts are equal).

@@ -647,29 +647,38 @@ void site_matvec(const C<T>* M, const int* sites, int nsites, int d, long long n
 }
 
 // ---------------------------------------------------------------------------
-// dense Schur complement of a small coarsest level: one wavefront per row,
-// lanes striding over the row (contiguous) and the odd components of the
-// input (an index table, cached), four rows per workgroup
+// dense Schur complement of a small coarsest level: the workgroup first
+// stages the odd components of its RB input fields in LDS (one gather through
+// the index table), then each wavefront takes one row, its lanes striding
+// over the row (contiguous) against the staged input; four rows per
+// workgroup
 // ---------------------------------------------------------------------------
 template <typename T, int RB>
 __global__ void __launch_bounds__(256) k_dense_schur(const C<T>* __restrict__ S, int m,
                                                      const int* __restrict__ oidx, const int* __restrict__ eidx,
                                                      const C<T>* __restrict__ in, C<T>* __restrict__ out,
                                                      long long n) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= m) return;   // wavefront-uniform: no wavefront is split
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* vs = reinterpret_cast<C<T>*>(smem_raw);   // [RB][m]
   const long long off = (long long)blockIdx.y * RB * n;
   in += off;
   out += off;
+  for (int e = threadIdx.x; e < RB * m; e += blockDim.x) {
+    const int r = e / m, j = e - r * m;
+    vs[e] = in[r * n + oidx[j]];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= m) return;   // after the only barrier; wavefront-uniform
   const C<T>* row = S + (size_t)i * m;
   C<T> acc[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) acc[r] = czero<T>();
+#pragma unroll 4
   for (int j = lane; j < m; j += 64) {
     const C<T> a = row[j];
-    const int o = oidx[j];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) cfma(acc[r], a, in[r * n + o]);
+    for (int r = 0; r < RB; ++r) cfma(acc[r], a, vs[r * m + j]);
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
@@ -681,14 +690,17 @@ __global__ void __launch_bounds__(256) k_dense_schur(const C<T>* __restrict__ S,
   }
 }
 
+// the staged input is RB * m elements: at most 64 KiB for m <= 2048 (FP32
+// with four fields, FP64 with two), within the default dynamic LDS limit
 template <typename T>
 void dense_schur_apply(const C<T>* S, int m, const int* oidx, const int* eidx, long long n, const C<T>* in,
                        C<T>* out, hipStream_t s, int nb) {
-  DD_REQUIRE(m >= 1 && (long long)m <= n, "bad dense Schur shape");
+  DD_REQUIRE(m >= 1 && (long long)m <= n && m <= 2048, "bad dense Schur shape");
   rhs_chunks<T>(nb, [&](auto rb, int first, int nc) {
     constexpr int RB = decltype(rb)::value;
-    k_dense_schur<T, RB><<<dim3((m + 3) / 4, nc), 256, 0, s>>>(S, m, oidx, eidx, in + first * n, out + first * n,
-                                                              n);
+    const size_t sm = (size_t)RB * m * sizeof(C<T>);
+    k_dense_schur<T, RB><<<dim3((m + 3) / 4, nc), 256, sm, s>>>(S, m, oidx, eidx, in + first * n,
+                                                               out + first * n, n);
   });
   DD_LAUNCH_CHECK();
 }

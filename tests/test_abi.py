@@ -95,6 +95,8 @@ def test_params_default_is_table1(dd):
     assert p.coarse_eps == 5e-2 and p.kc_tol == 1e-1 and p.tol == 1e-10
     assert p.precond_prec == dd.F32 and p.cycle == dd.KCYCLE
     assert p.half_storage == 0 and p.batch == 16 and p.half_directions == 0
+    # beyond Tab. 1: host-driven coarsest GMRES, dense Schur product where small
+    assert p.graph == 0 and p.coarse_dense == 1
 
 
 def test_host_validation_rejects_bad_lattice(dd):

@@ -20,8 +20,11 @@ Modules
   multigrid   hierarchy, K-cycle / V-cycle, setup phases, outer solve
 
 Parity pins: every function is checked in tests/test_oracle_*.py against a
-closed form, an invariant or a dense brute-force computation.  The
-adaptive setup's test vectors have no such pin: "parity unpinned" for
-``multigrid.initial_setup`` / ``multigrid.iterative_setup`` beyond the
-invariants they must satisfy (orthonormal P, gamma5-symmetric D_c).
+closed form, an invariant or a dense brute-force computation.  The setup
+phases (``multigrid.initial_setup``, ``multigrid.iterative_setup``) and the
+three-level K-, V- and W-cycles are pinned by dense closed forms with exact
+block solves in place of MR (the smoother is then linear) and an exact
+coarsest solve (tests/test_oracle_setup.py).  The test-vector values of a
+setup with MR block solves have no unique value; the GPU library is compared
+with the oracle there through exported and imported interpolation bases.
 """

@@ -48,11 +48,19 @@ class Hierarchy:
             agg = self.p["agg"][l]
             dims = tuple(d // a for d, a in zip(dims, agg))
         self.counters = {"coarsest_iters": 0, "kcycle_iters": 0}
+        # Optional replacement of the SAP block solves: a callable
+        # (level, operator, block shape) -> block solver for sap_sweep.  The
+        # tests pass exact dense block inverses, which make the smoother a
+        # linear map with a closed form; None keeps the MR block solves.
+        self.block_solver_factory = None
 
     # -- smoothing ---------------------------------------------------------
     def smooth(self, l, b, z, n):
+        bs = None
+        if self.block_solver_factory is not None and n > 0:
+            bs = self.block_solver_factory(l, self.ops[l], self.blocks[l])
         for _ in range(n):
-            z = sap_sweep(self.ops[l], b, z, self.blocks[l], self.p["mr_iters"])
+            z = sap_sweep(self.ops[l], b, z, self.blocks[l], self.p["mr_iters"], block_solver=bs)
         return z
 
     # -- Alg. 1 / Alg. 2 -----------------------------------------------------

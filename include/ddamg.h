@@ -166,6 +166,14 @@ typedef struct {
                                  launch instead of the three-launch sparse
                                  product; results agree up to rounding.
                                  0: always the sparse product. */
+  int galerkin_cols;          /* columns of P a workgroup of the coarse
+                                 Galerkin product D_{l+1} = P_l^H D_l P_l
+                                 (l >= 1) applies each loaded operator entry
+                                 to: 1 or 4; 0 (default) takes 4 where the
+                                 level has aggregates enough to fill the
+                                 device with a quarter of the workgroups,
+                                 else 1.  The result is the same up to
+                                 rounding either way. */
 } ddamg_params;
 
 typedef struct {

@@ -9,26 +9,19 @@
 #include <vector>
 
 #include "cgnr.h"
+#include "handles.h"
 #include "solver.h"
 #include "tune.h"
 
 using namespace ddamg;
 
-struct ddamg_ctx_s {
-  std::unique_ptr<Context> c;
-};
-struct ddamg_hier_s {
-  std::unique_ptr<Hierarchy> h;
-  ddamg_ctx_s* owner;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-template <typename F> int guarded(F&& f) {
+int ddamg::guarded_call(void (*f)(void*), void* arg) {
   try {
-    f();
+    f(arg);
     g_err.clear();
     return DDAMG_OK;
   } catch (const Error& e) {
@@ -42,6 +35,8 @@ template <typename F> int guarded(F&& f) {
     return DDAMG_EHIP;
   }
 }
+
+namespace {
 
 void check_prec(int prec) { DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32, "prec must be DDAMG_F64 or DDAMG_F32"); }
 void check_layout(int layout) {
@@ -212,6 +207,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->half_directions = 0;
   p->graph = 0;
   p->coarse_dense = 1;
+  p->galerkin_cols = 0;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {

@@ -885,7 +885,7 @@ void Hierarchy::build_level(int l, bool from32) {
   if (F.P16.p) to_half(F.P64.p, F.P16.p, (long long)N * n, s);
   // Galerkin in FP64
   if (l == 0) galerkin_fine(ctx->g, F.at, F.ad(), N, ctx->view<double>(), F.P64.p, Cc.D64.p, s);
-  else galerkin_coarse(F.cg, F.at, F.ad(), N, F.cview<double>(), F.P64.p, Cc.D64.p, s);
+  else galerkin_coarse(F.cg, F.at, F.ad(), N, F.cview<double>(), F.P64.p, Cc.D64.p, s, p.galerkin_cols);
   expand_coarse<double2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K64.p, s);
   if (Cc.K32.p) expand_coarse<float2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K32.p, s);
   if (Cc.K16.p) expand_coarse<__half2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K16.p, s);
@@ -1035,6 +1035,8 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
              "FP16 directions need the FP32 preconditioner");
   DD_REQUIRE(p.graph == 0 || p.graph == 1, "graph must be 0 or 1");
   DD_REQUIRE(p.coarse_dense == 0 || p.coarse_dense == 1, "coarse_dense must be 0 or 1");
+  DD_REQUIRE(p.galerkin_cols == 0 || p.galerkin_cols == 1 || p.galerkin_cols == 4,
+             "galerkin_cols must be 0, 1 or 4");
   DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle != DDAMG_KCYCLE,
              "a graph-captured preconditioner needs the V- or W-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");

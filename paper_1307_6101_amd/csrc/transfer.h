@@ -61,7 +61,11 @@ void orthonormalise_coarse(const AggTables& a, const AggDev& ad, int d, int N, l
 // Galerkin D_{l+1} = P^H D_l P in FP64: self and forward blocks, [nagg][5][2N][2N]
 void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
                    const FineOpView<double>& op, const double2* P, double2* Dc, hipStream_t s);
+// cols: operator entries applied to 1 or 4 columns per workgroup (0: four
+// where the level has aggregates enough to fill the device with a quarter
+// of the workgroups, else one)
 void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad, int N,
-                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s);
+                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s,
+                     int cols = 0);
 
 }  // namespace ddamg

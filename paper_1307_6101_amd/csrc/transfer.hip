@@ -707,7 +707,7 @@ __global__ void k_galerkin_coarse(GalCoarseGeom gg, const int* __restrict__ memb
 }
 
 void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad, int N,
-                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s) {
+                     const CoarseOpView<double>& op, const double2* P, double2* Dc, hipStream_t s, int cols) {
   const int rows = a.asz * cg.d;
   DD_REQUIRE(rows <= 1024, "coarse aggregate too large for one workgroup");
   DD_REQUIRE(N <= NMAX, "too many test vectors");
@@ -715,7 +715,8 @@ void galerkin_coarse(const CoarseGeom& cg, const AggTables& a, const AggDev& ad,
   for (int mu = 0; mu < 4; ++mu) { gg.dims[mu] = cg.dims[mu]; gg.agg[mu] = a.agg[mu]; }
   const int wg = 64 * ((rows + 63) / 64);
   const size_t sm = (size_t)(wg / 64) * N * 4 * sizeof(double);
-  if ((long long)a.nagg * 2 * ((N + 3) / 4) >= 2048) {
+  const bool four = cols == 4 || (cols == 0 && (long long)a.nagg * 2 * ((N + 3) / 4) >= 2048);
+  if (four) {
     const int ngs = (N + 3) / 4;
     k_galerkin_coarse<4><<<agg_col_grid(a.nagg, 2 * ngs), wg, sm, s>>>(gg, ad.members, a.asz, N, a.nagg, op, P,
                                                                        (long long)cg.V * cg.d, Dc);

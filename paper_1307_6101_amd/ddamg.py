@@ -58,6 +58,7 @@ class Params(ctypes.Structure):
         ("half_directions", ctypes.c_int),
         ("graph", ctypes.c_int),
         ("coarse_dense", ctypes.c_int),
+        ("galerkin_cols", ctypes.c_int),
     ]
 
 

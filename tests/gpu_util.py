@@ -28,6 +28,34 @@ def empty(shape_, dtype=torch.complex128):
     return torch.zeros(shape_, dtype=dtype, device="cuda")
 
 
+def fields_on_device(dims, dof, n, seed):
+    """gaussian_field(dims, dof, seed, nrhs=n) built on the device one field
+    at a time (one field of host memory for the largest lattices)."""
+    import workloads as W
+    out = torch.empty((n,) + shape(dims) + (dof,), dtype=torch.complex128, device="cuda")
+    for k, f in enumerate(W.gaussian_fields_iter(dims, dof, n, seed)):
+        out[k].copy_(torch.from_numpy(f))
+    return out
+
+
+def sampled_residual(U, m0, csw, b_at, z, sites):
+    """(sqrt(V) * rms over the sampled sites of |b - D z|, an estimate of
+    ||b - D z||; the largest |b - D z| of a sampled site, a lower bound of
+    it), with D the oracle's site-by-site operator; b_at(site) gives b at a
+    site (x, y, z, t), z is the host solution field."""
+    from oracle.dirac import apply_at_sites
+    dz = apply_at_sites(U, m0, csw, z, sites)
+    r = np.array([b_at(s) for s in sites]) - dz
+    V = int(np.prod(U.shape[:4]))
+    return (float(np.sqrt(np.mean(np.sum(np.abs(r) ** 2, axis=1)) * V)),
+            float(np.max(np.linalg.norm(r, axis=1))))
+
+
+def sample_sites(dims, n, seed, extra=()):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return list(extra) + [tuple(int(rng.integers(0, e)) for e in dims) for _ in range(n)]
+
+
 def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 

@@ -54,7 +54,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
          offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions),
          offsetof(ddamg_params, graph));
-  printf("%zu\n", offsetof(ddamg_params, coarse_dense));
+  printf("%zu %zu\n", offsetof(ddamg_params, coarse_dense), offsetof(ddamg_params, galerkin_cols));
   return 0;
 }
 ''')
@@ -82,6 +82,7 @@ int main(void) {
     assert vals[16] == dd.Params.half_directions.offset
     assert vals[17] == dd.Params.graph.offset
     assert vals[18] == dd.Params.coarse_dense.offset
+    assert vals[19] == dd.Params.galerkin_cols.offset
 
 
 def test_params_default_is_table1(dd):

@@ -29,3 +29,15 @@ def test_defaults_match_table1():
     assert big["agg"][0] == tuple(int(x) for x in g["agg_level1"].split(","))
     assert big["agg"][1] == tuple(int(x) for x in g["agg_coarser"].split(","))
     assert big["ntv"][0] == int(g["ntv"])
+
+
+def test_input_generators_chunked_and_parallel_agree():
+    """The streaming field generator and the multi-process link generator
+    give the same values as the one-shot generators."""
+    import numpy as np
+    import workloads as W
+    dims = (4, 4, 4, 8)
+    full = W.test_vectors(dims, 12, 3, 99)
+    parts = np.stack(list(W.gaussian_fields_iter(dims, 12, 3, 99)))
+    assert np.array_equal(full, parts)
+    assert np.array_equal(W.links(dims, 0.5, 98, workers=1), W.links(dims, 0.5, 98, workers=3))

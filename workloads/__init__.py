@@ -19,6 +19,8 @@ Conventions shared by everything in this repository:
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 BASE_SEED = 13076101
@@ -51,16 +53,93 @@ def su3_exp(h: np.ndarray, eps: float) -> np.ndarray:
     return np.einsum("...ab,...b,...cb->...ac", W, ph, W.conj())
 
 
-def links(dims, eps: float, seed: int) -> np.ndarray:
+def _links_from_normals(h: np.ndarray, eps: float) -> np.ndarray:
+    H = np.einsum("...a,aij->...ij", h, _GELL_MANN) / 2.0
+    return su3_exp(H, eps)
+
+
+# Lattices with at least this many links are exponentiated by a pool of
+# worker processes (each matrix is exponentiated on its own, so the result
+# is the same bit for bit as in one process).
+PARALLEL_LINKS = 1 << 22
+
+
+def links(dims, eps: float, seed: int, workers: int | None = None) -> np.ndarray:
     """Gauge links U_mu(x) = exp(i eps H), H = sum_a h_a lambda_a / 2, h_a ~ N(0,1).
 
     The normals are drawn in canonical site order, then direction, with 8 per
-    link.  Returns complex128 of shape (T, Z, Y, X, 4, 3, 3).
+    link.  Returns complex128 of shape (T, Z, Y, X, 4, 3, 3).  ``workers``
+    (default: up to 16 where the lattice has PARALLEL_LINKS links or more,
+    else 1) processes share the exponentials.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     h = rng.standard_normal(_shape(dims) + (4, 8))
-    H = np.einsum("...a,aij->...ij", h, _GELL_MANN) / 2.0
-    return su3_exp(H, eps)
+    nlinks = h.size // 8
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if nlinks >= PARALLEL_LINKS else 1
+    if workers <= 1:
+        return _links_from_normals(h, eps)
+    return _parallel_links(h, eps, workers)
+
+
+def _links_worker(argv):
+    """Child-process entry: exponentiate links lo..hi of the memory-mapped
+    normals file into the memory-mapped links file."""
+    hpath, upath = argv[0], argv[1]
+    n, lo, hi = int(argv[2]), int(argv[3]), int(argv[4])
+    eps = float(argv[5])
+    h = np.memmap(hpath, dtype=np.float64, mode="r", shape=(n, 8))
+    u = np.memmap(upath, dtype=np.complex128, mode="r+", shape=(n, 3, 3))
+    step = 1 << 16
+    for a in range(lo, hi, step):
+        b = min(hi, a + step)
+        u[a:b] = _links_from_normals(np.asarray(h[a:b]), eps)
+    u.flush()
+    del h, u
+
+
+def _parallel_links(h: np.ndarray, eps: float, workers: int) -> np.ndarray:
+    """The exponentials of _links_from_normals shared by `workers` child
+    processes (each started as a fresh interpreter running _links_worker on
+    one slice) through two memory-mapped files in a private temporary
+    directory (in memory where /dev/shm exists), removed afterwards.  A
+    failing child raises here."""
+    import shutil
+    import subprocess
+    import sys
+    import tempfile
+    shape = h.shape[:-1] + (3, 3)
+    n = h.size // 8
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, sys.argv[1]); import workloads; "
+            "workloads._links_worker(sys.argv[2:])")
+    tmp = tempfile.mkdtemp(prefix="ddamg_links_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    procs = []
+    try:
+        hpath, upath = os.path.join(tmp, "h"), os.path.join(tmp, "u")
+        hm = np.memmap(hpath, dtype=np.float64, mode="w+", shape=(n, 8))
+        hm[:] = h.reshape(n, 8)
+        hm.flush()
+        del hm
+        um = np.memmap(upath, dtype=np.complex128, mode="w+", shape=(n, 3, 3))
+        del um
+        cuts = np.linspace(0, n, workers + 1).astype(np.int64)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        for k in range(workers):
+            procs.append(subprocess.Popen(
+                [sys.executable, "-c", code, root, hpath, upath, str(n), str(int(cuts[k])),
+                 str(int(cuts[k + 1])), repr(float(eps))], env=env))
+        rcs = [p.wait(timeout=1800) for p in procs]
+        if any(rcs):
+            raise RuntimeError(f"link exponentiation workers failed: exit codes {rcs}")
+        out = np.array(np.memmap(upath, dtype=np.complex128, mode="r", shape=(n, 3, 3))).reshape(shape)
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+        shutil.rmtree(tmp, ignore_errors=True)
+    return out
 
 
 def random_su3(dims, seed: int, eps: float = np.pi) -> np.ndarray:
@@ -97,6 +176,16 @@ def point_sources(dims) -> np.ndarray:
 def test_vectors(dims, dof: int, n: int, seed: int) -> np.ndarray:
     """The n random initial test vectors of the setup, shape (n, T, Z, Y, X, dof)."""
     return gaussian_field(dims, dof, seed, nrhs=n)
+
+
+def gaussian_fields_iter(dims, dof: int, n: int, seed: int):
+    """The n fields of gaussian_field(dims, dof, seed, nrhs=n) one at a time
+    (the same values: the normals are drawn in the same order), so that large
+    lattices need one field of host memory instead of n."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for _ in range(n):
+        g = rng.standard_normal(_shape(dims) + (dof, 2))
+        yield g[..., 0] + 1j * g[..., 1]
 
 
 # --------------------------------------------------------------------------

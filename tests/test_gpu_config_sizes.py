@@ -1,0 +1,216 @@
+"""The 16^3x32, 32^3x64, uneven-batch and 48^3x96 workloads at their own
+sizes and parameters (Tab. 1 defaults where they say nothing: n_inv = 6,
+nu = 5, 3 MR steps, K-cycle 5 / 2 / 1e-1, coarsest 5e-2, outer 1e-10),
+certified by the FP64 oracle:
+
+* 16^3x32, three levels, N = 20 / 20: the plain FP64 and the mixed solve of
+  b = D z* for a Gaussian z* (the error protocol of Sec. 3.4), the residual
+  recomputed by the oracle's whole-lattice operator and the error against
+  z*; one K-cycle of the FP64 hierarchy against the oracle's cycle on the
+  GPU's bases;
+* 32^3x64, three levels, the 12 spin-colour point sources in one batch on
+  FP16-stored operators: every source's residual, and the oracle's
+  site-by-site residual on sampled sites (the origin and its neighbours
+  among them);
+* the eight lattices of the uneven batch (four 16^4, two 24^3x48, two
+  32^3x64) solved concurrently: the oracle's sampled residual of each;
+* 48^3x96, four levels, N = 20 / 20 / 28 (8 fresh level-2 vectors), 3^4
+  SAP blocks on level 2: level shapes, the solve and its sampled residual.
+
+The whole-lattice oracle is too slow beyond 16^3x32, so the larger lattices
+are certified by the solver's own FP64 residual together with the oracle's
+residual at sampled sites (sqrt(V) times their rms estimates ||b - D z||,
+and no sampled site may exceed the bound)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.dirac import WilsonClover
+from oracle.krylov import norm
+from oracle.lattice import shape
+from tests.gpu_util import (dev, empty, fields_on_device, host, oracle_from_gpu, relerr, sample_sites,
+                            sampled_residual, say, to_params)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    from paper_1307_6101_amd import ddamg
+    ddamg.load_library()
+    return ddamg
+
+
+def _nbrs(x):
+    out = [tuple(x)]
+    for mu in range(4):
+        for s in (1, -1):
+            y = list(x)
+            y[mu] += s
+            out.append(tuple(y))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 16^3 x 32
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c2(dd):
+    cfg = W.CONFIGS["clover16x32_3lvl"]
+    dims = cfg["dims"]
+    say(f"16^3x32 workload: inputs and oracle operator")
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    op = WilsonClover(U, cfg["m0"], cfg["csw"])
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+    tv = W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    return dict(cfg=cfg, dims=dims, op=op, ctx=ctx, tv=tv, H={})
+
+
+def _c2_hier(dd, c, prec):
+    if prec not in c["H"]:
+        say(f"  setup prec={prec}")
+        c["H"][prec] = dd.build_hierarchy(c["ctx"], to_params(dd, c["cfg"], prec), dev(c["tv"]))
+    return c["H"][prec]
+
+
+@pytest.mark.timeout(600)
+def test_c2_solves_certified_by_oracle(dd, c2):
+    op, dims = c2["op"], c2["dims"]
+    zstar = W.gaussian_spinor(dims, c2["cfg"]["seed_rhs"] + 50)
+    b = op.apply(zstar)
+    sols = {}
+    for name, prec in (("plain FP64", dd.F64), ("mixed", dd.F32)):
+        H = _c2_hier(dd, c2, prec)
+        z = empty(b.shape)
+        rc, st = dd.solve(H, dev(b), z)
+        zz = host(z)
+        res = norm(b - op.apply(zz)) / norm(b)
+        err = norm(zz - zstar) / norm(zstar)
+        say(f"  {name}: rc={rc} its={st[0]['outer_iters']} gpu relres={st[0]['true_relres']:.2e} "
+            f"oracle relres={res:.2e} error vs z*={err:.2e}")
+        assert rc == dd.OK and st[0]["true_relres"] <= 1e-10 and res <= 1e-10
+        assert err < 1e-8
+        sols[name] = zz
+    assert relerr(sols["mixed"], sols["plain FP64"]) < 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_c2_one_cycle_parity(dd, c2):
+    H = _c2_hier(dd, c2, dd.F64)
+    say("  oracle hierarchy on the GPU's bases (N = 20 / 20)")
+    OH = oracle_from_gpu(dd, H, c2["op"], c2["cfg"])
+    b = W.gaussian_spinor(c2["dims"], 1601)
+    z = empty(b.shape)
+    dd.precondition(H, dev(b), z)
+    say("  oracle cycle")
+    e = relerr(host(z), OH.cycle(0, b))
+    say(f"  one K-cycle relerr {e:.2e}")
+    assert e < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# 32^3 x 64, 12 point sources
+# ---------------------------------------------------------------------------
+@pytest.mark.timeout(600)
+def test_c3_twelve_point_sources(dd):
+    cfg = W.CONFIGS["clover32x64_3lvl_12rhs"]
+    dims = cfg["dims"]
+    say("32^3x64 workload: inputs")
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+    tv = fields_on_device(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    say("  setup (FP32 preconditioner, FP16 storage)")
+    H = dd.build_hierarchy(ctx, to_params(dd, cfg, dd.F32, half=True), tv)
+    del tv
+    b = W.point_sources(dims)
+    z = empty(b.shape)
+    say("  solve of the 12 sources in one batch")
+    rc, st = dd.solve(H, dev(b), z, nrhs=12)
+    say(f"  rc={rc} its={[x['outer_iters'] for x in st]}")
+    assert rc == dd.OK
+    zz = host(z)
+    sites = sample_sites(dims, 48, 3201, extra=_nbrs((0, 0, 0, 0)))
+    for r in range(12):
+        assert st[r]["true_relres"] <= 1e-10
+
+        def b_at(s, r=r):
+            return b[r][tuple(v % e for v, e in zip(s, dims))[::-1]]
+
+        est, mx = sampled_residual(U, cfg["m0"], cfg["csw"], b_at, zz[r], sites)
+        say(f"  source {r}: gpu relres {st[r]['true_relres']:.2e}, oracle sampled estimate {est:.2e}, "
+            f"max site {mx:.2e}")
+        assert mx <= 1e-10 and est <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# the uneven batch of eight lattices
+# ---------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_c4_uneven_batch_of_eight(dd):
+    hs, bs, zs, keep = [], [], [], []
+    for j in range(len(W.UNEVEN_BATCH)):
+        cfg = W.uneven_batch_config(j)
+        dims = cfg["dims"]
+        say(f"  lattice {j}: {dims} eps={cfg['eps']} m0={cfg['m0']}")
+        U = W.links(dims, cfg["eps"], cfg["seed_links"])
+        ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+        tv = fields_on_device(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+        H = dd.build_hierarchy(ctx, to_params(dd, cfg, dd.F32, cycle=cfg["cycle"]), tv)
+        del tv
+        b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+        hs.append(H)
+        bs.append(dev(b))
+        zs.append(empty(b.shape))
+        keep.append((cfg, U, b, ctx))
+    rc, st = dd.solve_many(hs, bs, zs)
+    say(f"  solve_many rc={rc} its={[x['outer_iters'] for x in st]}")
+    assert rc == dd.OK
+    for j, (cfg, U, b, _) in enumerate(keep):
+        dims = cfg["dims"]
+        assert st[j]["true_relres"] <= 1e-10
+        zz = host(zs[j])
+        sites = sample_sites(dims, 24, 4100 + j)
+        est, mx = sampled_residual(U, cfg["m0"], cfg["csw"],
+                                   lambda s: b[tuple(v % e for v, e in zip(s, dims))[::-1]], zz, sites)
+        say(f"  lattice {j}: gpu relres {st[j]['true_relres']:.2e}, oracle sampled estimate "
+            f"{est / norm(b):.2e}")
+        assert mx <= 1e-10 * norm(b) and est <= 1e-9 * norm(b)
+
+
+# ---------------------------------------------------------------------------
+# 48^3 x 96, four levels
+# ---------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_c5_four_level(dd):
+    cfg = W.CONFIGS["clover48x96_4lvl"]
+    dims = cfg["dims"]
+    say("48^3x96 workload: links")
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+    say("  test vectors")
+    tv = fields_on_device(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    d2 = 2 * cfg["ntv"][1]
+    cd2 = tuple(x // (a1 * a2) for x, a1, a2 in zip(dims, cfg["agg"][0], cfg["agg"][1]))
+    extra = dev(W.test_vectors(cd2, d2, cfg["ntv"][2] - cfg["ntv"][1], cfg["seed_tv"] + 7))
+    say("  setup (FP32 preconditioner, FP16 storage)")
+    P = to_params(dd, cfg, dd.F32, half=True)
+    P.batch = 8
+    H = dd.build_hierarchy(ctx, P, tv, extra)
+    del tv
+    assert dd.level_info(H, 1) == ((12, 12, 12, 24), 40)
+    assert dd.level_info(H, 2) == ((6, 6, 6, 12), 40)
+    assert dd.level_info(H, 3) == ((3, 3, 3, 6), 56)
+    b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+    z = empty(b.shape)
+    say("  solve")
+    rc, st = dd.solve(H, dev(b), z)
+    say(f"  rc={rc} {st[0]}")
+    assert rc == dd.OK and st[0]["true_relres"] <= 1e-10
+    zz = host(z)
+    del z
+    sites = sample_sites(dims, 48, 4801)
+    est, mx = sampled_residual(U, cfg["m0"], cfg["csw"],
+                               lambda s: b[tuple(v % e for v, e in zip(s, dims))[::-1]], zz, sites)
+    say(f"  oracle sampled estimate {est / norm(b):.2e}, max site {mx / norm(b):.2e} (relative to ||b||)")
+    assert mx <= 1e-10 * norm(b) and est <= 1e-9 * norm(b)

@@ -213,6 +213,21 @@ void ddamg_destroy(ddamg_ctx ctx);
 int ddamg_apply_D(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, int layout,
                   void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as ddamg_apply_D with DDAMG_CANONICAL, but the native staging
+ * fields live in a fixed array of DDAMG_NOALLOC_SCRATCH_BYTES bytes in the
+ * library's device data (one per GPU, held until the process ends) instead
+ * of memory the library allocates.  No call allocates.  in/out: device
+ * pointers to nrhs canonical complex128 spinors, caller-owned, distinct.
+ * EINVAL when 2 * nrhs * V * 12 * (16 bytes for F64, 8 for F32) exceeds
+ * DDAMG_NOALLOC_SCRATCH_BYTES.  Every call on a GPU uses that GPU's one
+ * array, whatever the context: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  The
+ * staging is fully overwritten by each call (nothing needs clearing). */
+#define DDAMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ddamg_apply_D_noalloc(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, void* stream);
+
 /* Canonical complex128 <-> native (at prec) conversion of nrhs fields of
  * level `level` (level 0 needs only ctx; level >= 1 needs hier, else pass
  * NULL). */

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libddamg.so")
 
-SOURCES = ["fine.hip", "coarse.hip", "transfer.hip", "blas.hip", "dgmres.hip", "solver.hip", "cgnr.hip", "tune.hip", "capi.hip"]
+SOURCES = ["fine.hip", "coarse.hip", "transfer.hip", "blas.hip", "dgmres.hip", "solver.hip", "cgnr.hip", "tune.hip", "capi.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

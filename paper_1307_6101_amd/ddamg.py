@@ -95,6 +95,7 @@ _SIGS = {
     "ddamg_create": (_I, [ctypes.POINTER(Lattice), _P, _P, ctypes.POINTER(_P)]),
     "ddamg_destroy": (None, [_P]),
     "ddamg_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _P]),
+    "ddamg_apply_D_noalloc": (_I, [_P, _P, _P, _I, _I, _P]),
     "ddamg_to_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
     "ddamg_from_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
     "ddamg_build_hierarchy": (_I, [_P, ctypes.POINTER(Params), _P, _P, _P, ctypes.POINTER(_P)]),
@@ -211,6 +212,15 @@ def build_hierarchy(ctx, params, tv, tv_extra=None) -> Hierarchy:
 
 def apply_D(ctx, inp, out, nrhs=1, prec=F64, layout=CANONICAL):
     _check(load_library().ddamg_apply_D(ctx.handle, _ptr(inp), _ptr(out), nrhs, prec, layout, _stream()))
+
+
+def apply_D_noalloc(ctx, inp, out, nrhs=1, prec=F64):
+    """ddamg_apply_D_noalloc: canonical out = D inp through the library's
+    fixed device staging array (no allocation)."""
+    _check(load_library().ddamg_apply_D_noalloc(ctx.handle, _ptr(inp), _ptr(out), nrhs, prec, _stream()))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def to_native(ctx, hier, level, inp, out, nrhs=1, prec=F64):

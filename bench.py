@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the DD-alpha-AMG hot path on one MI355X.
 
-A step is one complete solve of D z = b to relative residual 1e-10 (outer
-FP64 FGMRES, FP32 K-cycle preconditioner, three levels) on the 16^3x32
-Wilson-clover workload (eps 0.5, m0 -0.4, c_sw 1, one complex Gaussian
-right-hand side), with the hierarchy built beforehand (setup timed
-separately) and b resident in HBM.  `value` is solves per second.
+A step is one complete solve of D z = b to relative residual 1e-10 on the
+48^3x96 four-level Wilson-clover workload (aggregates 4^4, 2^4, 2^4; N = 20 /
+20 / 28; c_sw 1, eps 0.55, m0 -0.43; one complex Gaussian right-hand side):
+outer FP64 FGMRES, FP32 K-cycle preconditioner on FP16-stored operator data,
+the hierarchy built beforehand (setup timed separately) and b resident in
+HBM.  `value` is solves per second.
 
-Also reported on the same inputs: the plain FP64 GPU solve (everything FP64,
-no batching) for the time-to-solution comparison, the setup times, the
-Wilson-clover stencil's achieved bandwidth (HIP events around launches on the
-library's stream) against the HBM roofline, and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+Also reported on the same inputs: the plain FP64 GPU solve (everything FP64)
+for the time-to-solution comparison, the setup times, the solve's error
+measured by the FP64 oracle (its site-by-site operator on sampled sites), two
+and three levels against four on the same lattice, CGNR, the SAP colour
+pass (the solve's dominant kernel) and the Wilson-clover stencil against the
+HBM roofline (HIP events around launches on the stream the library uses),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads (--workload): the 16^3x32 three-level lattice with its
+batched, FP16 and CGNR variants; the 32^3x64 lattice with the 12 point
+sources in one batch; the uneven batch of eight lattices; the bare-mass scan.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,6 +32,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+T_START = time.time()
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-colour sources)
@@ -32,7 +40,12 @@ BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in
 # profiles/dslash_clover16x32_counters.md (null once the kernel changes)
 DSLASH_F32_TRAFFIC_BYTES = 128.25e6
+# HBM traffic per launch of the SAP colour pass on FP16-stored links and
+# clover on the 48^3x96 lattice, from the FETCH_SIZE / WRITE_SIZE counter
+# runs summarised in profiles/ (None until taken for the current kernel)
+SAP_F16_PASS_TRAFFIC_BYTES = 6.241e9
 WORKLOAD = "clover16x32_3lvl"
+HEADLINE = "clover48x96_4lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
 BATCH_WORKLOAD = "clover32x64_3lvl_12rhs"
 FOUR_LEVEL_WORKLOAD = "clover48x96_4lvl"
@@ -71,12 +84,19 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the Wilson-clover stencil loops and a reference copy of known size "
                          "(for hardware-counter runs)")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD,
+    ap.add_argument("--profile-window", type=float, nargs=2, default=None, metavar=("START", "DURATION"),
+                    help="after the warmup, wait until START seconds after the bench started and solve "
+                         "repeatedly for DURATION seconds (for a rocprofv3 --collection-period window that "
+                         "holds nothing but solves)")
+    ap.add_argument("--no-levels", action="store_true",
+                    help="skip the two- and three-level comparison on the headline lattice")
+    ap.add_argument("--workload", default=HEADLINE, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD,
                                                       SCAN_WORKLOAD],
-                    help="the bench workload (default), the 32^3x64 lattice with the 12 point sources "
-                         "solved in one batch, the 48^3x96 four-level lattice, or the uneven batch of eight "
-                         "lattices (four 16^4, two 24^3x48, two 32^3x64) solved concurrently, or the bare-mass "
-                         "scan towards criticality on the 16^3x32 lattice (two and three levels against CGNR)")
+                    help="the 48^3x96 four-level lattice (default), the 16^3x32 three-level lattice with "
+                         "its batched and FP16 variants, the 32^3x64 lattice with the 12 point sources "
+                         "solved in one batch, the uneven batch of eight lattices (four 16^4, two 24^3x48, "
+                         "two 32^3x64) solved concurrently, or the bare-mass scan towards criticality on the "
+                         "16^3x32 lattice (two and three levels against CGNR)")
     ap.add_argument("--lattice", default=None,
                     help="X,Y,Z,T lattice for --kernels-only (default: the bench workload's)")
     return ap.parse_args()
@@ -103,7 +123,10 @@ def main():
 
     cfg = W.CONFIGS[WORKLOAD]
     if args.kernels_only:
-        kernels_only(args, cfg, dd, W, np, torch)
+        kernels_only(args, W.CONFIGS[args.workload], dd, W, np, torch)
+        return
+    if args.workload == HEADLINE:
+        headline_workload(args, dd, W, np, torch)
         return
     if args.workload == UNEVEN_WORKLOAD:
         uneven_workload(args, dd, W, np, torch)
@@ -430,6 +453,334 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def fill_params(dd, cfg, prec, half=False, batch=None, levels=None):
+    """ddamg_params of a workload (Tab. 1 defaults otherwise); `levels` keeps
+    only the first levels of its hierarchy."""
+    L = cfg["levels"] if levels is None else levels
+    p = dd.params_default(L)
+    for l, a in enumerate(cfg["agg"][:L - 1]):
+        for mu in range(4):
+            p.agg[l][mu] = a[mu]
+    for l, n in enumerate(cfg["ntv"][:L - 1]):
+        p.ntv[l] = n
+    for l, blk in enumerate(cfg.get("sap_blocks", [])[1:L - 1]):
+        for mu in range(4):
+            p.sap_block_l[l][mu] = blk[mu]
+    p.nu = cfg["nu"]
+    p.precond_prec = prec
+    p.half_storage = 1 if half else 0
+    if batch is not None:
+        p.batch = batch
+    return p
+
+
+def device_fields(torch, W, dims, dof, n, seed):
+    """W.gaussian_field(dims, dof, seed, nrhs=n) built on the device one
+    field at a time (host memory for one field)."""
+    X, Y, Z, T = dims
+    out = torch.empty((n, T, Z, Y, X, dof), dtype=torch.complex128, device="cuda")
+    for k, f in enumerate(W.gaussian_fields_iter(dims, dof, n, seed)):
+        out[k].copy_(torch.from_numpy(f))
+    return out
+
+
+def time_launches(torch, fn, reps):
+    """Mean seconds per call of fn (after one untimed call), from HIP events
+    recorded on torch's current stream, which the binding passes to the
+    library: the events bracket exactly the launches of the timed calls."""
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1000.0 / reps
+
+
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def headline_workload(args, dd, W, np, torch):
+    """The 48^3x96 four-level workload (the default bench line)."""
+    name = HEADLINE
+    cfg = W.CONFIGS[name]
+    dims = cfg["dims"]
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {name} dims={dims} V={V}")
+    t0 = time.time()
+    U = W.links(dims, cfg["eps"], cfg["seed_links"])
+    log(f"[bench] links in {time.time() - t0:.1f}s")
+    ctx = dd.create(dims, cfg["m0"], cfg["csw"], torch.from_numpy(U).to(dev))
+    tvd = device_fields(torch, W, dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+    log(f"[bench] test vectors in {time.time() - t0:.1f}s")
+    # fresh random vectors for level 2, which has more test vectors than level 1
+    d2 = 2 * cfg["ntv"][1]
+    cd2 = tuple(x // (a1 * a2) for x, a1, a2 in zip(dims, cfg["agg"][0], cfg["agg"][1]))
+    extra = torch.from_numpy(W.test_vectors(cd2, d2, cfg["ntv"][2] - cfg["ntv"][1], cfg["seed_tv"] + 7)).to(dev)
+    b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+    bd = torch.from_numpy(b).to(dev).unsqueeze(0)
+    z = torch.zeros_like(bd)
+    log(f"[bench] inputs in {time.time() - t0:.1f}s")
+
+    def build(prec, half, levels=None):
+        torch.cuda.synchronize()
+        t = time.time()
+        H = dd.build_hierarchy(ctx, fill_params(dd, cfg, prec, half, batch=8, levels=levels), tvd,
+                               extra if (levels or cfg["levels"]) == 4 else None)
+        torch.cuda.synchronize()
+        return H, time.time() - t
+
+    def one_solve(H):
+        z.zero_()
+        rc, st = dd.solve(H, bd, z)
+        if rc != dd.OK:
+            raise RuntimeError(f"solve failed rc={rc} {st}")
+        return st[0]
+
+    H, t_setup = build(dd.F32, True)
+    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
+    for i in range(args.warmup):
+        st = one_solve(H)
+        log(f"[bench] warmup {i}: {st['outer_iters']} its, {st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    if args.profile_window is not None:
+        start, dur = args.profile_window
+        while time.time() - T_START < start:
+            time.sleep(0.05)
+        n = 0
+        while time.time() - T_START < start + dur:
+            one_solve(H)
+            n += 1
+        log(f"[bench] profile window: {n} solves from {start:.0f}s to {time.time() - T_START:.1f}s")
+    t = time.time()
+    stats = []
+    for i in range(args.steps):
+        st = one_solve(H)
+        stats.append(st)
+        log(f"[bench] step {i}: {st['outer_iters']} its, relres {st['true_relres']:.2e}, {st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.time() - t) / args.steps
+    zz = z[0].cpu().numpy()
+
+    # the solve's error measured by the FP64 oracle: its site-by-site
+    # operator (its own index arithmetic and clover leaves) on sampled sites;
+    # sqrt(V) times the rms residual there estimates ||b - D z||
+    from oracle.dirac import apply_at_sites
+    rng = np.random.Generator(np.random.PCG64(4811))
+    sites = [tuple(int(rng.integers(0, e)) for e in dims) for _ in range(64)]
+    dz = apply_at_sites(U, cfg["m0"], cfg["csw"], zz, sites)
+    r = np.array([b[s[3], s[2], s[1], s[0]] for s in sites]) - dz
+    bnorm = float(np.linalg.norm(b))
+    oracle_est = float(np.sqrt(np.mean(np.sum(np.abs(r) ** 2, axis=1)) * V)) / bnorm
+    oracle_max = float(np.max(np.linalg.norm(r, axis=1))) / bnorm
+    log(f"[bench] oracle residual on 64 sampled sites: estimate {oracle_est:.2e}, largest site {oracle_max:.2e}")
+    del zz
+
+    # kernels of the solve, timed with events on the stream the library uses
+    kern = {}
+    nat32 = torch.zeros(V * 12, dtype=torch.complex64, device=dev)
+    dd.to_native(ctx, None, 0, bd, nat32, prec=dd.F32)
+    zs = torch.zeros_like(nat32)
+    out32 = torch.zeros_like(nat32)
+    reps = args.kernel_reps
+    t_sap = time_launches(torch, lambda: dd.sap_smooth(H, 0, nat32, zs, 1, prec=dd.F32, layout=dd.NATIVE), reps)
+    # one colour pass handles half the sites: b, z in, z out at FP32 and the
+    # links and clover at FP16, per site of the lattice and sweep
+    sweep_bytes = (SAP_SPINOR_REALS_PER_SITE * 4 + (SAP_REALS_PER_SITE - SAP_SPINOR_REALS_PER_SITE) * 2) * V
+    kern["sap_colour_pass_f16store"] = dict(seconds=t_sap / 2, algorithmic_bytes=sweep_bytes / 2,
+                                            gbs=sweep_bytes / t_sap / 1e9)
+    t_d16 = time_launches(torch, lambda: dd.apply_Dc(H, 0, nat32, out32, prec=dd.F32, layout=dd.NATIVE), reps)
+    d16 = (DPSI_SPINOR_REALS_PER_SITE * 4 + (DPSI_REALS_PER_SITE - DPSI_SPINOR_REALS_PER_SITE) * 2) * V
+    kern["dslash_f16store"] = dict(seconds=t_d16, algorithmic_bytes=d16, gbs=d16 / t_d16 / 1e9)
+    t_d32 = time_launches(torch, lambda: dd.apply_D(ctx, nat32, out32, prec=dd.F32, layout=dd.NATIVE), reps)
+    kern["dslash_f32"] = dict(seconds=t_d32, algorithmic_bytes=DPSI_REALS_PER_SITE * 4 * V,
+                              gbs=DPSI_REALS_PER_SITE * 4 * V / t_d32 / 1e9)
+    del nat32, zs, out32
+    nat64 = torch.zeros(V * 12, dtype=torch.complex128, device=dev)
+    out64 = torch.zeros_like(nat64)
+    dd.to_native(ctx, None, 0, bd, nat64, prec=dd.F64)
+    t_d64 = time_launches(torch, lambda: dd.apply_D(ctx, nat64, out64, prec=dd.F64, layout=dd.NATIVE), reps)
+    kern["dslash_f64"] = dict(seconds=t_d64, algorithmic_bytes=DPSI_REALS_PER_SITE * 8 * V,
+                              gbs=DPSI_REALS_PER_SITE * 8 * V / t_d64 / 1e9)
+    del nat64, out64
+    # level-1 coarse operator (12^3x24 sites, 40 components, FP16-stored):
+    # one field per launch, and 12 fields on the matrix cores
+    (cdims, cd) = dd.level_info(H, 1)
+    cV = int(np.prod(cdims))
+    cin = torch.randn((BATCH_RHS, cV * cd), dtype=torch.complex64, device=dev)
+    cout = torch.zeros_like(cin)
+    t_c1 = time_launches(torch, lambda: dd.apply_Dc(H, 1, cin[0], cout[0], prec=dd.F32, layout=dd.NATIVE), reps)
+    cbytes = (9 * cd * cd * 4 + 2 * cd * 8) * cV
+    kern["coarse_apply_f16store_x1"] = dict(seconds=t_c1, algorithmic_bytes=cbytes, gbs=cbytes / t_c1 / 1e9)
+    t_cb = time_launches(torch, lambda: dd.apply_Dc(H, 1, cin, cout, nrhs=BATCH_RHS, prec=dd.F32,
+                                                    layout=dd.NATIVE), reps)
+    flops = 9 * cd * cd * 8 * BATCH_RHS * cV
+    cbb = (9 * cd * cd * 4 + 2 * BATCH_RHS * cd * 8) * cV
+    kern[f"coarse_apply_mfma_f16store_x{BATCH_RHS}"] = dict(
+        seconds=t_cb, algorithmic_bytes=cbb, gbs=cbb / t_cb / 1e9, tflops=flops / t_cb / 1e12,
+        mfma_frac=flops / t_cb / 1e12 / MFMA_F32_PEAK_TFLOPS)
+    del cin, cout
+    for k, v in kern.items():
+        ext = f", {v['tflops']:.1f} TFLOP/s" if "tflops" in v else ""
+        log(f"[bench] {k}: {v['seconds'] * 1e6:.1f} us, {v['gbs']:.0f} GB/s{ext}")
+    mixed = dict(outer_iters=[s["outer_iters"] for s in stats][-1], true_relres=stats[-1]["true_relres"],
+                 kcycle_iters=stats[-1]["kcycle_iters"], coarsest_iters=stats[-1]["coarsest_iters"])
+    del H
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    # fewer levels on the same lattice (mixed, FP16 storage), one solve each
+    levels_cmp = None
+    if not args.no_levels:
+        levels_cmp = {"4": dict(setup_s=round(t_setup, 3), solve_s=round(ms / 1000.0, 4),
+                                outer_iters=mixed["outer_iters"])}
+        for L in (3, 2):
+            Hl, t_l = build(dd.F32, True, levels=L)
+            one_solve(Hl)
+            torch.cuda.synchronize()
+            tl = time.time()
+            st = one_solve(Hl)
+            torch.cuda.synchronize()
+            tl = time.time() - tl
+            levels_cmp[str(L)] = dict(setup_s=round(t_l, 3), solve_s=round(tl, 4), outer_iters=st["outer_iters"],
+                                      kcycle_iters=st["kcycle_iters"], coarsest_iters=st["coarsest_iters"])
+            log(f"[bench] {L} levels: setup {t_l:.2f}s, solve {tl:.3f}s, {st['outer_iters']} its, "
+                f"{st['coarsest_iters']} coarsest its")
+            del Hl
+            torch.cuda.empty_cache()
+
+    # plain FP64 GPU method on the same inputs
+    plain = None
+    if not args.no_plain:
+        H64, t_setup64 = build(dd.F64, False)
+        one_solve(H64)
+        torch.cuda.synchronize()
+        tp = time.time()
+        pst = one_solve(H64)
+        torch.cuda.synchronize()
+        tp = time.time() - tp
+        plain = dict(time_to_solution_s=round(tp, 4), setup_s=round(t_setup64, 3), outer_iters=pst["outer_iters"],
+                     true_relres=pst["true_relres"])
+        log(f"[bench] plain FP64: setup {t_setup64:.2f}s, solve {tp:.3f}s, {pst['outer_iters']} its")
+        del H64
+        torch.cuda.empty_cache()
+        # CGNR (the paper's comparison method, Sec. 4; the conditioning indicator)
+        zc = torch.zeros_like(bd)
+        torch.cuda.synchronize()
+        tc = time.time()
+        rc, cst = dd.cgnr(ctx, bd, zc, tol=cfg["tol"], max_iter=100000)
+        torch.cuda.synchronize()
+        tc = time.time() - tc
+        plain["cgnr"] = dict(time_s=round(tc, 4), iterations=cst[0]["outer_iters"], true_relres=cst[0]["true_relres"],
+                             status=rc)
+        log(f"[bench] CGNR FP64: {cst[0]['outer_iters']} its, {tc:.3f}s")
+
+    dom = kern["sap_colour_pass_f16store"]
+    roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": SAP_F16_PASS_TRAFFIC_BYTES,
+                "kernel": "k_sap_colour<float, __half2> (one SAP colour pass, FP32 arithmetic on FP16 "
+                          "links and clover)",
+                "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
+                "us_per_launch": round(dom["seconds"] * 1e6, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_headline(cfg, U, b, mixed["outer_iters"], V, ms / 1000.0)
+
+    aggs = ", ".join("x".join(str(a) for a in ag) for ag in cfg["agg"])
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner on f16-stored operators, f64 outer",
+        "data": "synthetic (seeded SU(3) links exp(i eps H), one complex Gaussian rhs)",
+        "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-clover, {cfg['levels']} levels "
+                               f"(aggregates {aggs}, N={cfg['ntv']}, level-2 SAP blocks 3^4), c_sw={cfg['csw']}, "
+                               f"eps={cfg['eps']}, m0={cfg['m0']}, 1 rhs, tol 1e-10",
+                   "parallelism": "1 GPU"},
+        "time_to_solution_s": round(ms / 1000.0, 4),
+        "setup_s": round(t_setup, 3),
+        **mixed,
+        "oracle_sampled_relres": oracle_est,
+        "oracle_sampled_max_site_relres": oracle_max,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
+        "levels_2_3_4": levels_cmp,
+        "kernels": {k: dict({"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)},
+                            **({"TFLOP/s": round(v["tflops"], 2), "mfma_frac": round(v["mfma_frac"], 4)}
+                               if "tflops" in v else {})) for k, v in kern.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_headline(cfg, U, b, outer_iters, V, gpu_solve_s):
+    """The FP64 numpy oracle, unmodified, timed on a bounded sample of the
+    headline workload: the 16^3x32 corner of its lattice (its links and
+    right-hand side, closed periodically) carries one outer iteration's
+    fine-level work (nu = 5 SAP sweeps, one Wilson-clover apply, P^H and P
+    with N = 20), scaled to the whole lattice (x V / V_sample) and solve
+    (x outer iterations of the GPU run).  The three coarse levels and the
+    setup are left out: an upper bound on the oracle's solves per second."""
+    import numpy as np
+
+    import workloads as W
+    from oracle.aggregation import Aggregation
+    from oracle.dirac import WilsonClover
+    from oracle.sap import sap_sweep
+    sd = (16, 16, 16, 32)
+    Us = np.ascontiguousarray(U[:sd[3], :sd[2], :sd[1], :sd[0]])
+    bs = np.ascontiguousarray(b[:sd[3], :sd[2], :sd[1], :sd[0]])
+    Vs = int(np.prod(sd))
+    op = WilsonClover(Us, cfg["m0"], cfg["csw"])
+    agg = Aggregation(sd, cfg["agg"][0], W.test_vectors(sd, 12, cfg["ntv"][0], cfg["seed_tv"]))
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t = time.time()
+    zc = agg.restrict(bs)
+    zf = agg.prolong(zc)
+    for _ in range(cfg["nu"]):
+        zf = sap_sweep(op, bs, zf, (2, 2, 2, 2), cfg["mr_iters"])
+    op.apply(zf)
+    wall = time.time() - t
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, int(round(cpu_s / wall)))
+    per_solve = wall * (V / Vs) * outer_iters
+    model, nproc = cpu_info()
+    log(f"[bench] oracle sample {wall:.1f}s wall, {cpu_s:.1f}s cpu; scaled {per_solve:.0f}s per solve")
+    return {"value": round(1.0 / per_solve, 8), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"one outer iteration's fine-level work (P^H, P with N=20, 5 SAP sweeps, 1 Dpsi; FP64 "
+                      f"numpy) on the 16^3x32 corner of the 48^3x96 lattice took {wall:.2f}s; x{V // Vs} "
+                      f"volume, x{outer_iters} outer iterations; coarse levels and setup excluded (upper bound)",
+            "host": {"cpu_model": model, "nproc": nproc},
+            "core_minutes_per_solve": round(per_solve * cores / 60.0, 2),
+            "gpu_speedup": round(per_solve / gpu_solve_s, 1),
+            "paper_context": "Tab. 5: 3-level DD-alpha-AMG 160 core-minutes (128 Nehalem cores, 64^4 BMW-c "
+                             "ensemble, 75.2 s), CGNR 111,446 core-minutes"}
+
 def big_workload(args, name, cfg, dd, W, np, torch):
     """The larger lattices, run on request: a step is one solve with the
     FP32 preconditioner on FP16-stored operator data.  On the 32^3x64
@@ -552,9 +903,11 @@ def big_workload(args, name, cfg, dd, W, np, torch):
 
 
 def kernels_only(args, cfg, dd, W, np, torch):
-    """Stencil launches in FP32 and FP64, FP32 SAP sweeps, the matrix-core
-    coarse operator on 12 fields, and a 1 GiB device copy (the reference for
-    scaling FETCH_SIZE / WRITE_SIZE counters)."""
+    """The fine kernels alone, for hardware-counter runs: the Wilson-clover
+    stencil in FP32 and FP64, one SAP sweep (two colour passes) on FP16-stored
+    links and clover and one in FP32, each from a cheap two-level hierarchy
+    (the fine smoother reads only the fine operator), and a 1 GiB device copy
+    (the reference for scaling FETCH_SIZE / WRITE_SIZE counters)."""
     dims = tuple(int(x) for x in args.lattice.split(",")) if args.lattice else cfg["dims"]
     V = int(np.prod(dims))
     dev = torch.device("cuda:0")
@@ -566,60 +919,34 @@ def kernels_only(args, cfg, dd, W, np, torch):
     del U
     bd = torch.from_numpy(b).to(dev)
     out = {}
-    stream = torch.cuda.current_stream()
     for name, prec, cdt, bpr in (("dslash_f32", dd.F32, torch.complex64, 4),
                                  ("dslash_f64", dd.F64, torch.complex128, 8)):
         x = torch.zeros(V * 12, dtype=cdt, device=dev)
         y = torch.zeros_like(x)
         dd.to_native(ctx, None, 0, bd, x, prec=prec)
-        dd.apply_D(ctx, x, y, prec=prec, layout=dd.NATIVE)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.kernel_reps):
-            dd.apply_D(ctx, x, y, prec=prec, layout=dd.NATIVE)
-        e1.record(stream)
-        e1.synchronize()
-        t = e0.elapsed_time(e1) / 1000.0 / args.kernel_reps
+        t = time_launches(torch, lambda: dd.apply_D(ctx, x, y, prec=prec, layout=dd.NATIVE), args.kernel_reps)
         nbytes = DPSI_REALS_PER_SITE * bpr * V
-        out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1),
-                     "algorithmic_bytes": nbytes}
+        out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
         log(f"[bench] {name}: {t * 1e6:.1f} us, {nbytes / t / 1e9:.0f} GB/s")
         del x, y
-    # one SAP sweep (both colours, FP32) on a single field, and the coarse
-    # operator of a 20-vector two-level hierarchy on 12 fields (matrix cores)
-    p = dd.params_default(2)
-    p.ntv[0] = 20
-    p.n_inv = 0
-    p.precond_prec = dd.F32
-    tv = torch.from_numpy(W.test_vectors(dims, 12, 20, cfg["seed_tv"])).to(dev)
-    H = dd.build_hierarchy(ctx, p, tv)
-    del tv
+    tv = device_fields(torch, W, dims, 12, 2, cfg["seed_tv"])
     x = torch.zeros(V * 12, dtype=torch.complex64, device=dev)
     dd.to_native(ctx, None, 0, bd, x, prec=dd.F32)
     zf = torch.zeros_like(x)
-    ldims, dof = dd.level_info(H, 1)
-    Vc = int(np.prod(ldims))
-    xc = torch.randn((BATCH_RHS, Vc * dof), dtype=torch.complex64, device=dev)
-    yc = torch.zeros_like(xc)
-    for name, fn, nbytes in (
-            ("sap_sweep_f32", lambda: dd.sap_smooth(H, 0, x, zf, 1, prec=dd.F32, layout=dd.NATIVE),
-             SAP_REALS_PER_SITE * 4 * V),
-            ("coarse_apply_mfma_f32_x12",
-             lambda: dd.apply_Dc(H, 1, xc, yc, nrhs=BATCH_RHS, prec=dd.F32, layout=dd.NATIVE),
-             Vc * (9 * dof * dof + 2 * BATCH_RHS * dof) * 8)):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.kernel_reps):
-            fn()
-        e1.record(stream)
-        e1.synchronize()
-        t = e0.elapsed_time(e1) / 1000.0 / args.kernel_reps
+    for name, half in (("sap_colour_pass_f16store", True), ("sap_colour_pass_f32", False)):
+        p = dd.params_default(2)
+        p.ntv[0] = 2
+        p.n_inv = 0
+        p.precond_prec = dd.F32
+        p.half_storage = 1 if half else 0
+        H = dd.build_hierarchy(ctx, p, tv)
+        t = time_launches(torch, lambda: dd.sap_smooth(H, 0, x, zf, 1, prec=dd.F32, layout=dd.NATIVE),
+                          args.kernel_reps) / 2
+        nbytes = ((SAP_SPINOR_REALS_PER_SITE * 4 + (SAP_REALS_PER_SITE - SAP_SPINOR_REALS_PER_SITE) * 2) * V / 2
+                  if half else SAP_REALS_PER_SITE * 4 * V / 2)
         out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
-        log(f"[bench] {name}: {t * 1e6:.1f} us, {nbytes / t / 1e9:.0f} GB/s")
-    del H
+        log(f"[bench] {name}: {t * 1e6:.1f} us per colour pass, {nbytes / t / 1e9:.0f} GB/s")
+        del H
     # reference copy of known size: 1 GiB read + 1 GiB written
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)

@@ -106,6 +106,22 @@ template <int WIDTH, typename T> __device__ inline T group_sum(T v) {
   return v;
 }
 
+// Sum over each group of 16 lanes (a DPP row), left in every lane: swaps
+// within pairs and quads, then the half-row and row mirrors, each a data
+// parallel move folded into the add (no LDS round trip).
+template <int CTRL> __device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float row_sum16(float v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return v;
+}
+template <typename T> __device__ inline T sum16(T v) { return group_sum<16>(v); }
+template <> __device__ inline float sum16<float>(float v) { return row_sum16(v); }
+
 inline unsigned nblocks(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // Batches of nb right-hand sides are cut into launches that give every

@@ -380,46 +380,97 @@ void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s
 // ---------------------------------------------------------------------------
 // SAP colour pass.  One thread per site, 16 lanes per 2^4 block, 16 blocks
 // per workgroup; a batch of fields runs one field per workgroup with the
-// XCD-aware batch mapping.  r = b - D z with the full operator, then mr_iters minimal
-// residual steps on the Dirichlet block operator D_i (self term + the four
-// in-block hops, partner spinors exchanged through LDS), z += x.  The four
-// in-block links of a site are read once into registers, in their stored
-// precision, and reused by every MR step.
+// XCD-aware batch mapping.  r = b - D z with the full operator (the blocks'
+// z staged in LDS: the in-block neighbours come from there, the others from
+// memory), then mr_iters minimal residual steps on the Dirichlet block
+// operator D_i (self term + the four in-block hops, partner spinors
+// exchanged through LDS, block sums of the step sizes by DPP row moves),
+// z += x.  The four in-block links of a site are read once into registers,
+// in their stored precision and as the site applies them (U for the lower
+// site of a pair, U^H for the upper one), so that forward and backward
+// in-block hops run the same instructions; with FP16 storage the clover is
+// kept in LDS for the pass.
 // ---------------------------------------------------------------------------
+// The in-block hop of direction MU: forward (the lower site of the pair,
+// link U) or backward (the upper site, U^H), with the link passed as the site
+// applies it; the backward hop's projection phases are the forward ones times
+// -1 (sg), so every lane runs the same instructions.
 template <typename T, typename S, int MU>
 __device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, const C<T> (&u)[9],
                                    C<T> acc[12]) {
+  using P = Proj<MU>;
   constexpr int bit = 1 << MU;
-  C<T> psi[12];
+  constexpr int c0 = (4 - P::K0) & 3, c1 = (4 - P::K1) & 3;
+  const T sg = (loc & bit) ? T(-1) : T(1);
+  C<T> h[6];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
-  if (loc & bit) hop_apply<T, MU, false>(psi, u, acc);
-  else hop_apply<T, MU, true>(psi, u, acc);
+  for (int a = 0; a < 3; ++a) {
+    const C<T> p0 = rs[a * 256 + (t ^ bit)], p1 = rs[(3 + a) * 256 + (t ^ bit)];
+    const C<T> q0 = mul_ik<P::K0>(rs[(P::J0 * 3 + a) * 256 + (t ^ bit)]);
+    const C<T> q1 = mul_ik<P::K1>(rs[(P::J1 * 3 + a) * 256 + (t ^ bit)]);
+    h[a] = mk<T>(fma(sg, q0.x, p0.x), fma(sg, q0.y, p0.y));
+    h[3 + a] = mk<T>(fma(sg, q1.x, p1.x), fma(sg, q1.y, p1.y));
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C<T> v = cmul(u[a * 3], h[s * 3]);
+      cfma(v, u[a * 3 + 1], h[s * 3 + 1]);
+      cfma(v, u[a * 3 + 2], h[s * 3 + 2]);
+      acc[s * 3 + a] = cadd(acc[s * 3 + a], v);
+      const int j = s ? P::J1 : P::J0;
+      const C<T> w = s ? mul_ik<c1>(v) : mul_ik<c0>(v);
+      acc[j * 3 + a] = mk<T>(fma(sg, w.x, acc[j * 3 + a].x), fma(sg, w.y, acc[j * 3 + a].y));
+    }
 }
 
 // The site's in-block links: kept in registers across the MR steps (FP32
 // and FP16 storage) or read again at every step (FP64, where registers do
 // not suffice).  The clover is read at every step: keeping it too (144 more
 // registers in FP32) leaves one wavefront per SIMD and was measured slower.
+// The link of in-block direction mu as the site applies it: the link
+// joining loc and loc ^ (1 << mu) belongs to the lower site, which applies
+// U; the upper site applies U^H (the transposed entries, conjugated).
+template <typename T, typename S>
+__device__ inline void oriented_link(const S* __restrict__ U, int blk, int loc, int mu, C<T> (&u)[9]) {
+  const bool up = (loc >> mu) & 1;
+  const S* p = U + (long long)blk * 576 + mu * 144 + (loc & ~(1 << mu));
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const C<T> v = ldc<T, S>(p[(up ? b * 3 + a : a * 3 + b) * 16]);
+      u[a * 3 + b] = up ? cconj(v) : v;
+    }
+}
+
 template <typename T, typename S, bool KEEP> struct BlockOp {
   S ul[KEEP ? 4 : 1][9];
   __device__ void load(const FineOpView<T, S>& op, int blk, int loc, bool valid) {
     if constexpr (KEEP) {
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {
-        // the link joining loc and loc ^ (1 << mu) belongs to the lower site
+        const bool up = (loc >> mu) & 1;
         const S* p = op.U + (long long)blk * 576 + mu * 144 + (loc & ~(1 << mu));
 #pragma unroll
-        for (int k = 0; k < 9; ++k) ul[mu][k] = valid ? p[k * 16] : szero<S>();
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            S v = p[(up ? b * 3 + a : a * 3 + b) * 16];
+            if (up) v.y = -v.y;
+            ul[mu][a * 3 + b] = v;
+          }
       }
     }
   }
+  // the link as this site applies it (U or U^H)
   __device__ void link(const FineOpView<T, S>& op, int blk, int loc, int mu, C<T> (&u)[9]) const {
     if constexpr (KEEP) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) u[k] = ldc<T, S>(ul[mu][k]);
     } else {
-      load_link<T, S>(op.U, blk, loc & ~(1 << mu), mu, u);
+      oriented_link<T, S>(op.U, blk, loc, mu, u);
     }
   }
   __device__ void clover(const FineOpView<T, S>& op, int blk, int loc, const C<T> v[12], C<T> out[12]) const {
@@ -427,12 +478,64 @@ template <typename T, typename S, bool KEEP> struct BlockOp {
   }
 };
 
+// Whether a colour pass keeps each site's clover in LDS (one private slot
+// per thread, [36][256] entries of the stored type) for its MR steps instead
+// of reading it from memory at every step: for FP16 storage the slots take
+// 36 KiB of a workgroup's LDS, which leaves the kernel's occupancy (set by
+// its registers) unchanged; in FP32 they would take 72 KiB and halve it.
+template <typename S> struct ClLds : std::false_type {};
+template <> struct ClLds<__half2> : std::true_type {};
+
+// Completes the arithmetic that produces acc before the statements that
+// follow (empty asm statements that read and write it), so that the next
+// direction's loads are not all issued ahead of it: hoisting the eight hops'
+// loads would need more registers than the colour pass can hold at two
+// wavefronts per SIMD.
+template <typename T> __device__ inline void pin12(C<T> (&acc)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[c].x), "+v"(acc[c].y));
+}
+
+// The hops of direction MU in the residual of a SAP block site, whose
+// block's current z is staged in LDS (rs, [12][256], the site at column t):
+// of the two neighbours in direction MU one lies in the block and is read
+// from LDS, the other from memory.
+template <typename T, typename S, int MU>
+__device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const C<T>* __restrict__ in, const C<T>* rs, int t,
+                                   int blk, int loc, const Nbr8& nb8, C<T> (&acc)[12]) {
+  constexpr int bit = 1 << MU;
+  const bool up = loc & bit;   // the forward neighbour is outside the block
+  C<T> psi[12], u[9];
+  // forward: psi(x+mu), U_mu(x)
+  if (up) {
+    load_spinor<T>(in, nb8.v[2 * MU], loc ^ bit, psi);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
+  }
+  load_link<T, S>(op.U, blk, loc, MU, u);
+  hop_apply<T, MU, true>(psi, u, acc);
+  // backward: psi(x-mu), U_mu(x-mu)^H
+  const int nb = up ? blk : nb8.v[2 * MU + 1];
+  if (up) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
+  } else {
+    load_spinor<T>(in, nb, loc ^ bit, psi);
+  }
+  load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
+  hop_apply<T, MU, false>(psi, u, acc);
+  pin12<T>(acc);
+}
+
 // one workgroup per (chunk of 16 blocks, field of the batch), gx chunks
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
                                                     int ncb, int mr_iters, const C<T>* __restrict__ b,
                                                     C<T>* __restrict__ z, int nb, long long fs, int gx) {
   __shared__ C<T> rs[12 * 256];
+  constexpr bool CL = ClLds<S>::value;
+  __shared__ S cl[CL ? 36 * 256 : 1];
   const int t = threadIdx.x;
   int xw, rw;
   xcd_slab_rhs(blockIdx.x, gx, nb, xw, rw);
@@ -446,16 +549,49 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
   BlockOp<T, S, KEEP> bop;
   {
     C<T> rho[12], x[12];
+    if constexpr (CL) {
+      // the site's clover into its private LDS slot (read once per pass)
+      const S* pa = op.A + (long long)blk * 576 + loc;
+#pragma unroll
+      for (int e = 0; e < 36; ++e) cl[e * 256 + t] = pa[e * 16];
+    }
+    // the block's z in LDS: in-block neighbours and the site itself come
+    // from there, the other neighbours from memory
+    {
+      C<T> zz[12];
+      if (valid) load_spinor<T>(z, blk, loc, zz);
+      else
+#pragma unroll
+        for (int c = 0; c < 12; ++c) zz[c] = czero<T>();
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rs[c * 256 + t] = zz[c];
+    }
+    __syncthreads();
     if (valid) {
-      C<T> dz[12], bb[12];
-      dslash_site<T, S>(op, z, blk, loc, dz);
+      const Nbr8 nb8 = load_nbr8(op.nbr, blk);
+      C<T> acc[12], zz[12], dz[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
+      sap_hops_mu<T, S, 0>(op, z, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, 1>(op, z, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, 2>(op, z, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, 3>(op, z, rs, t, blk, loc, nb8, acc);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) zz[c] = rs[c * 256 + t];
+      if constexpr (CL) clover_mul<T>([&](int e) { return ldc<T, S>(cl[e * 256 + t]); }, zz, dz);
+      else clover_apply<T, S>(op.A, blk, loc, zz, dz);
+      C<T> bb[12];
       load_spinor<T>(b, blk, loc, bb);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) rho[c] = csub(bb[c], dz[c]);
+      for (int c = 0; c < 12; ++c) {
+        rho[c].x = bb[c].x - dz[c].x + T(0.5) * acc[c].x;
+        rho[c].y = bb[c].y - dz[c].y + T(0.5) * acc[c].y;
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
     }
+    __syncthreads();   // rs is rewritten by the first MR step
     // the block operator is read after the residual, which needs the registers
     bop.load(op, blk, loc, valid);
 #pragma unroll
@@ -479,7 +615,8 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
         bop.link(op, blk, loc, 3, u);
         inblock_hop<T, S, 3>(rs, t, loc, u, acc);
       }
-      bop.clover(op, blk, loc, rho, q);
+      if constexpr (CL) clover_mul<T>([&](int e) { return ldc<T, S>(cl[e * 256 + t]); }, rho, q);
+      else bop.clover(op, blk, loc, rho, q);
       T qr_re = 0, qr_im = 0, qq = 0;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -489,10 +626,11 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
         qr_im += q[c].x * rho[c].y - q[c].y * rho[c].x;
         qq += q[c].x * q[c].x + q[c].y * q[c].y;
       }
-      qr_re = group_sum<16>(qr_re);
-      qr_im = group_sum<16>(qr_im);
-      qq = group_sum<16>(qq);
-      C<T> alpha = qq > T(0) ? mk<T>(qr_re / qq, qr_im / qq) : czero<T>();
+      qr_re = sum16<T>(qr_re);
+      qr_im = sum16<T>(qr_im);
+      qq = sum16<T>(qq);
+      const T iq = qq > T(0) ? T(1) / qq : T(0);
+      const C<T> alpha = mk<T>(qr_re * iq, qr_im * iq);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         cfma(x[c], alpha, rho[c]);
@@ -508,6 +646,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
     }
   }
 }
+
 
 template <typename T, typename S>
 void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,

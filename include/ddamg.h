@@ -69,7 +69,12 @@ enum {
   DDAMG_EUNSUPPORTED = -6   /* valid request this build does not implement */
 };
 
-enum { DDAMG_F64 = 0, DDAMG_F32 = 1 };            /* arithmetic precision */
+/* Precision of a call.  F64 and F32: arithmetic (and storage) precision.
+ * F16: IEEE binary16 storage of the operator data (links, clover, P_l, D_l)
+ * with FP32 arithmetic and FP32 native vectors (Sec. 3 runs the
+ * preconditioner in single precision; the half-precision storage is this
+ * library's); on a hierarchy it needs half_storage = 1. */
+enum { DDAMG_F64 = 0, DDAMG_F32 = 1, DDAMG_F16 = 2 };
 enum { DDAMG_CANONICAL = 0, DDAMG_NATIVE = 1 };   /* vector layout */
 enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1, DDAMG_WCYCLE = 2 };  /* Alg. 2 / Alg. 1 / Alg. 1 with
                                                                  two coarse cycles per level */
@@ -174,6 +179,13 @@ typedef struct {
                                  device with a quarter of the workgroups,
                                  else 1.  The result is the same up to
                                  rounding either way. */
+  int profile_levels;         /* 1: ddamg_solve records GPU events where
+                                 the work moves between levels and reports
+                                 the time consumed on each level (the
+                                 per-level times of the paper's Tab. 4) in
+                                 ddamg_solve_stats.t_level_s; costs a few
+                                 microseconds per level change.  Not with
+                                 graph = 1 (the times stay 0).  0: off. */
 } ddamg_params;
 
 typedef struct {
@@ -184,6 +196,23 @@ typedef struct {
   long long coarsest_iters;   /* GMRES iterations on the coarsest level */
   double true_relres;         /* ||b - D z|| / ||b||, recomputed in FP64 */
   double seconds;             /* wall time of the call */
+  double err_vs_ref;          /* ||z - z_ref|| / ||z_ref|| in FP64 for
+                                 ddamg_solve_ex with a reference solution
+                                 (Sec. 3.4 reports the error against a known
+                                 solution), else -1 */
+  double t_setup_s;           /* wall time of the hierarchy's setup */
+  double t_level_s[4];        /* GPU time consumed on level 0..3 during the
+                                 solve of this record's batch (with
+                                 params.profile_levels), else 0 */
+  double bytes;               /* algorithmic bytes of the batch's solve: the
+                                 compulsory traffic of every operator, smoother,
+                                 transfer and Krylov vector operation counted
+                                 from their per-site sizes (an estimate, not
+                                 a measurement) */
+  double flops;               /* algorithmic flops of the batch's solve,
+                                 counted the same way */
+  int coarsest_dense;         /* order of the dense Schur matrix of the
+                                 coarsest level (0: sparse product) */
 } ddamg_solve_stats;
 
 /* Fill p with the defaults of Tab. 1 for `levels` levels (agg 4^4 then 2^4,
@@ -291,6 +320,14 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
  * right-hand side did (a non-finite inner residual fails the whole batch). */
 int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
                 void* stream);
+
+/* ddamg_solve with a reference solution (the error protocol of Sec. 3.4:
+ * b = D z_ref for a known z_ref): z_ref (device, nrhs canonical complex128
+ * fields, or NULL) gives stats[r].err_vs_ref = ||z_r - z_ref_r|| /
+ * ||z_ref_r||, computed in FP64 on the device after the solve.  Otherwise
+ * identical to ddamg_solve. */
+int ddamg_solve_ex(ddamg_hier hier, const void* b, void* z, int nrhs, const void* z_ref,
+                   ddamg_solve_stats* stats, void* stream);
 
 /* Independent systems on different lattices (an uneven batch: the sizes,
  * links, masses and hierarchy parameters of the n hierarchies may all

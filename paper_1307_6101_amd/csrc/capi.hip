@@ -38,7 +38,15 @@ int ddamg::guarded_call(void (*f)(void*), void* arg) {
 
 namespace {
 
-void check_prec(int prec) { DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32, "prec must be DDAMG_F64 or DDAMG_F32"); }
+void check_prec(int prec) {
+  DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32 || prec == DDAMG_F16,
+             "prec must be DDAMG_F64, DDAMG_F32 or DDAMG_F16");
+}
+// DDAMG_F16 on a hierarchy: its FP32 level operations read the FP16 copies
+// of the operator data, which exist when it was built with half_storage
+void check_half(const Hierarchy& H, int prec) {
+  DD_REQUIRE(prec != DDAMG_F16 || H.half, "DDAMG_F16 needs a hierarchy built with half_storage = 1");
+}
 void check_layout(int layout) {
   DD_REQUIRE(layout == DDAMG_CANONICAL || layout == DDAMG_NATIVE, "layout must be DDAMG_CANONICAL or DDAMG_NATIVE");
 }
@@ -70,10 +78,17 @@ void from_nat(Context& c, int l, long long n, int nrhs, const C<T>* in, double2*
 // Every entry point hands the whole batch of nrhs fields to one batched
 // call; with the canonical layout the batch is converted through scratch
 // fields first.
-template <typename T>
+template <typename T, bool HALF = false>
 void apply_D_impl(Context& c, const void* in, void* out, int nrhs, int layout, hipStream_t s) {
   const long long n = c.g.V * 12;
-  const auto op = c.view<T>();
+  const auto op = [&] {
+    if constexpr (HALF) {
+      c.make_half(s);
+      return c.view16();
+    } else {
+      return c.view<T>();
+    }
+  }();
   if (layout == DDAMG_NATIVE) {
     dslash<T>(op, static_cast<const C<T>*>(in), static_cast<C<T>*>(out), s, nrhs);
   } else {
@@ -208,6 +223,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->graph = 0;
   p->coarse_dense = 1;
   p->galerkin_cols = 0;
+  p->profile_levels = 0;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {
@@ -231,6 +247,7 @@ int ddamg_apply_D(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, 
     check_prec(prec);
     check_layout(layout);
     if (prec == DDAMG_F64) apply_D_impl<double>(*ctx->c, in, out, nrhs, layout, as_stream(stream));
+    else if (prec == DDAMG_F16) apply_D_impl<float, true>(*ctx->c, in, out, nrhs, layout, as_stream(stream));
     else apply_D_impl<float>(*ctx->c, in, out, nrhs, layout, as_stream(stream));
   });
 }
@@ -309,6 +326,7 @@ int ddamg_apply_Dc(ddamg_hier hier, int level, const void* in, void* out, int nr
     check_prec(prec);
     check_layout(layout);
     H.s = as_stream(stream);
+    check_half(H, prec);
     if (prec == DDAMG_F64) apply_Dc_impl<double>(H, level, in, out, nrhs, layout);
     else apply_Dc_impl<float>(H, level, in, out, nrhs, layout);
   });
@@ -323,6 +341,7 @@ int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, i
     check_prec(prec);
     check_layout(layout);
     H.s = as_stream(stream);
+    check_half(H, prec);
     if (prec == DDAMG_F64) restrict_impl<double>(H, level, fine, coarse, nrhs, layout);
     else restrict_impl<float>(H, level, fine, coarse, nrhs, layout);
   });
@@ -337,6 +356,7 @@ int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, in
     check_prec(prec);
     check_layout(layout);
     H.s = as_stream(stream);
+    check_half(H, prec);
     if (prec == DDAMG_F64) prolong_impl<double>(H, level, coarse, fine, nrhs, layout);
     else prolong_impl<float>(H, level, coarse, fine, nrhs, layout);
   });
@@ -351,6 +371,7 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
     check_prec(prec);
     check_layout(layout);
     H.s = as_stream(stream);
+    check_half(H, prec);
     if (prec == DDAMG_F64) sap_impl<double>(H, level, b, z, nsweeps, nrhs, layout);
     else sap_impl<float>(H, level, b, z, nsweeps, nrhs, layout);
   });
@@ -373,7 +394,8 @@ namespace {
 // time; fills stats (per system) and returns the worst per-system outcome
 // (DDAMG_OK, DDAMG_ENOCONV or DDAMG_ENONFINITE).  Failures of the library
 // itself throw.
-int solve_batches(Hierarchy& H, const void* b, void* z, int nrhs, ddamg_solve_stats* stats, hipStream_t s) {
+int solve_batches(Hierarchy& H, const void* b, void* z, int nrhs, ddamg_solve_stats* stats, hipStream_t s,
+                  const void* z_ref = nullptr) {
   int worst = DDAMG_OK;
   if (H.p.graph && (!H.own_s || s != H.own_s)) {
     // graphs are captured on the hierarchy's own stream (the caller's may be
@@ -399,17 +421,38 @@ int solve_batches(Hierarchy& H, const void* b, void* z, int nrhs, ddamg_solve_st
     for (auto& e : st) std::memset(&e, 0, sizeof(e));
     std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
     std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
+    H.m_bytes = H.m_flops = 0;
+    H.lt_begin();
     fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b) + r0 * n, H.ob.p, nb, H.s);
     fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z) + r0 * n, H.ox.p, nb, H.s);
     if (H.p.precond_prec == DDAMG_F64) H.outer<double>(H.ob.p, H.ox.p, st.data(), nb);
     else H.outer<float>(H.ob.p, H.ox.p, st.data(), nb);
     fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z) + r0 * n, nb, H.s);
+    double tl[4];
+    H.lt_end(tl);
+    // the error against the reference solution, in FP64 on the device
+    std::vector<double> err(nb, -1.0);
+    if (z_ref) {
+      const double2* zr = static_cast<const double2*>(z_ref) + r0 * n;
+      std::vector<double> dn, rn;
+      vcopy<double, double>(zr, H.ow.p, n * nb, H.s);
+      vbmy<double>(static_cast<const double2*>(z) + r0 * n, H.ow.p, n * nb, H.s);
+      bnorms<double>(*H.red, H.ow.p, n, nb, dn, H.s);
+      bnorms<double>(*H.red, zr, n, nb, rn, H.s);
+      for (int r = 0; r < nb; ++r) err[r] = rn[r] > 0 ? dn[r] / rn[r] : dn[r];
+    }
     DD_CHECK_HIP(hipStreamSynchronize(H.s));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int r = 0; r < nb; ++r) {
       st[r].kcycle_iters = H.kc_it[r];
       st[r].coarsest_iters = H.cs_it[r];
       st[r].seconds = secs;
+      st[r].err_vs_ref = err[r];
+      st[r].t_setup_s = H.t_setup;
+      for (int k = 0; k < 4; ++k) st[r].t_level_s[k] = tl[k];
+      st[r].bytes = H.m_bytes;
+      st[r].flops = H.m_flops;
+      st[r].coarsest_dense = H.lv[H.L - 1].sm;
       if (stats) stats[r0 + r] = st[r];
       if (st[r].status != DDAMG_OK && worst == DDAMG_OK) worst = st[r].status;
     }
@@ -432,6 +475,19 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
     Hierarchy& H = H_(hier);
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     worst = solve_batches(H, b, z, nrhs, stats, as_stream(stream));
+  });
+  if (rc != DDAMG_OK) return rc;
+  return report_worst(worst);
+}
+
+int ddamg_solve_ex(ddamg_hier hier, const void* b, void* z, int nrhs, const void* z_ref,
+                   ddamg_solve_stats* stats, void* stream) {
+  int worst = DDAMG_OK;
+  int rc = guarded([&] {
+    Hierarchy& H = H_(hier);
+    DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
+    DD_REQUIRE(z_ref != z && z_ref != b, "z_ref must not alias b or z");
+    worst = solve_batches(H, b, z, nrhs, stats, as_stream(stream), z_ref);
   });
   if (rc != DDAMG_OK) return rc;
   return report_worst(worst);

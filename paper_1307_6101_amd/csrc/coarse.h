@@ -108,7 +108,8 @@ void schur_gather_cols(const double2* cols, long long n, int nbc, const int* oid
 // inverses of the self blocks (taken from the FP64 [V][5][d][d] Galerkin
 // output) of `sites`, FP64 Gauss-Jordan with partial pivoting; written
 // column-major, [nsites][d][d]
-void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv,
+// *flag (device) is set to 1 when a pivot is zero or not finite
+void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv, int* flag,
                         hipStream_t s);
 
 // canonical copy [V][9][d][d] row-major (self, +x..+t, -x..-t) of the FP64

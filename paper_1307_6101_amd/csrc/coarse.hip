@@ -737,7 +737,7 @@ void schur_gather_cols(const double2* cols, long long n, int nbc, const int* oid
 
 // Gauss-Jordan inversion of the self block of every listed site, FP64.
 __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __restrict__ sites, int d,
-                               double2* __restrict__ inv) {
+                               double2* __restrict__ inv, int* __restrict__ flag) {
   extern __shared__ unsigned char smem_raw[];
   double2* a = reinterpret_cast<double2*>(smem_raw);     // [d][2d]
   __shared__ int piv;
@@ -771,6 +771,7 @@ __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __rest
     __syncthreads();
     const double2 p = a[col * w + col];
     const double pn = p.x * p.x + p.y * p.y;
+    if (threadIdx.x == 0 && !(pn > 0.0 && pn < INFINITY)) *flag = 1;   // singular or non-finite block
     const double2 pinv = mk<double>(p.x / pn, -p.y / pn);
     __syncthreads();
     for (int c = threadIdx.x; c < w; c += blockDim.x) a[col * w + c] = cmul(a[col * w + c], pinv);
@@ -792,13 +793,13 @@ __global__ void k_self_inverse(const double2* __restrict__ D5, const int* __rest
   }
 }
 
-void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv,
+void self_block_inverse(const double2* D, const int* sites, int nsites, int d, double2* inv, int* flag,
                         hipStream_t s) {
   DD_REQUIRE(d >= 1 && d <= 64, "self-block inversion supports at most 64 components per site");
   const size_t sm = (size_t)d * 2 * d * sizeof(double2);
   DD_CHECK_HIP(hipFuncSetAttribute((const void*)k_self_inverse,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
-  k_self_inverse<<<nsites, 256, sm, s>>>(D, sites, d, inv);
+  k_self_inverse<<<nsites, 256, sm, s>>>(D, sites, d, inv, flag);
   DD_LAUNCH_CHECK();
 }
 

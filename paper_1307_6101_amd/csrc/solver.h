@@ -147,6 +147,30 @@ struct Hierarchy {
   int ocap = 0;                    // batch capacity of the outer solver's buffers
   std::vector<long long> kc_it, cs_it;   // per system of the batch: K-cycle / coarsest iterations
   const double2* tv_extra = nullptr;
+  DevArray<int> setup_flags;       // [0] dependent test vectors, [1] singular coarsest self block
+  double t_setup = 0;              // wall time of the setup
+  // Algorithmic bytes and flops of the level operations since the last
+  // reset: each operation adds what its definition must move and compute
+  // (per-site sizes of its vectors and operator data, at the precision and
+  // storage it runs with); an estimate of the compulsory work, not a
+  // measurement.
+  double m_bytes = 0, m_flops = 0;
+  void meter(double bytes, double flops) { m_bytes += bytes; m_flops += flops; }
+  // bytes per stored complex number of the operator data read by precision T
+  template <typename T> double op_bytes() const { return sizeof(T) == 8 ? 16.0 : (half ? 4.0 : 8.0); }
+  // GPU time per level (params.profile_levels): an event is recorded on the
+  // stream wherever the work moves from one level to another (lt_push on
+  // entering a level, lt_pop on returning), and the time between two marks
+  // is charged to the level current after the first
+  std::vector<std::pair<hipEvent_t, int>> lt_marks;
+  std::vector<hipEvent_t> lt_pool;
+  std::vector<int> lt_stack;
+  bool lt_on = false;
+  void lt_mark(int level);
+  void lt_push(int l);
+  void lt_pop();
+  void lt_begin();
+  void lt_end(double out[4]);
   // device-side GMRES scalars (graph mode) and the captured preconditioner
   // graphs, one per (precision, batch size); `gen` counts reallocations of
   // the buffers a graph has baked in
@@ -236,11 +260,17 @@ struct Hierarchy {
   Hierarchy(const Hierarchy&) = delete;
   Hierarchy& operator=(const Hierarchy&) = delete;
   ~Hierarchy() {
+    for (auto& m : lt_marks) lt_pool.push_back(m.first);
+    for (hipEvent_t e : lt_pool) (void)hipEventDestroy(e);
     drop_graphs();
     if (own_s) (void)hipStreamDestroy(own_s);
     if (gm_flag_host) (void)hipHostFree(gm_flag_host);
   }
 };
+
+// out[r] = ||v_r|| (FP64 sum) for nb fields of n complex numbers each
+template <typename T>
+void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector<double>& out, hipStream_t s);
 
 Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s);
 Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* p, const double2* tv,

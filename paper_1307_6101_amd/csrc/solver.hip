@@ -114,9 +114,60 @@ void Context::make_half(hipStream_t s) {
 // ---------------------------------------------------------------------------
 // level operations
 // ---------------------------------------------------------------------------
+void Hierarchy::lt_mark(int level) {
+  hipEvent_t e = nullptr;
+  if (lt_pool.empty()) {
+    DD_CHECK_HIP(hipEventCreate(&e));
+  } else {
+    e = lt_pool.back();
+    lt_pool.pop_back();
+  }
+  lt_marks.emplace_back(e, level);
+  DD_CHECK_HIP(hipEventRecord(e, s));
+}
+void Hierarchy::lt_push(int l) {
+  if (!lt_on) return;
+  lt_stack.push_back(l);
+  lt_mark(l);
+}
+void Hierarchy::lt_pop() {
+  if (!lt_on) return;
+  lt_stack.pop_back();
+  lt_mark(lt_stack.empty() ? 0 : lt_stack.back());
+}
+void Hierarchy::lt_begin() {
+  lt_on = p.profile_levels == 1 && !p.graph;
+  for (auto& m : lt_marks) lt_pool.push_back(m.first);
+  lt_marks.clear();
+  lt_stack.assign(1, 0);
+  if (lt_on) lt_mark(0);
+}
+void Hierarchy::lt_end(double out[4]) {
+  for (int k = 0; k < 4; ++k) out[k] = 0;
+  if (!lt_on) return;
+  lt_mark(0);
+  DD_CHECK_HIP(hipEventSynchronize(lt_marks.back().first));
+  for (size_t i = 0; i + 1 < lt_marks.size(); ++i) {
+    float ms = 0;
+    DD_CHECK_HIP(hipEventElapsedTime(&ms, lt_marks[i].first, lt_marks[i + 1].first));
+    out[std::min(lt_marks[i].second, 3)] += ms * 1e-3;
+  }
+  for (auto& m : lt_marks) lt_pool.push_back(m.first);
+  lt_marks.clear();
+  lt_on = false;
+}
+
 template <typename T> void Hierarchy::apply(int l, const C<T>* in, C<T>* out, int nb) {
-  if (l == 0) fine_op<T>([&](const auto& op) { dslash(op, in, out, s, nb); });
-  else coarse_op<T>(l, [&](const auto& op) { coarse_apply(op, in, out, s, nb); });
+  const double V = (double)lv[l].V, vz = sizeof(C<T>), ob = op_bytes<T>();
+  if (l == 0) {
+    // spinor in and out (24 complex), four links and the clover (72 complex)
+    meter(V * (24 * vz * nb + 72 * ob), 1870.0 * V * nb);
+    fine_op<T>([&](const auto& op) { dslash(op, in, out, s, nb); });
+  } else {
+    const double d = lv[l].d;
+    meter(V * (9 * d * d * ob + 2 * d * vz * nb), 72.0 * d * d * V * nb);
+    coarse_op<T>(l, [&](const auto& op) { coarse_apply(op, in, out, s, nb); });
+  }
 }
 
 // coarse SAP work buffers of level l for a batch of nb (grown on demand)
@@ -148,6 +199,19 @@ template <> const void* sap_scratch_base<double>(const LevelStore& L_) { return 
 template <> const void* sap_scratch_base<float>(const LevelStore& L_) { return L_.sr32.p; }
 
 template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsweeps, int nb) {
+  {
+    const double V = (double)lv[l].V, vz = sizeof(C<T>), ob = op_bytes<T>();
+    if (l == 0) {
+      // per sweep: b, z in, z out (36 complex per site and field), links and
+      // clover (72 complex); residual + mr_iters block-MR steps
+      meter(nsweeps * V * (36 * vz * nb + 72 * ob), nsweeps * (1870.0 + p.mr_iters * 2280.0) * V * nb);
+    } else {
+      // per sweep about 1 + mr_iters applications of the level operator
+      const double d = lv[l].d;
+      meter(nsweeps * (1.0 + p.mr_iters) * V * (9 * d * d * ob + 2 * d * vz * nb),
+            nsweeps * (1.0 + p.mr_iters) * 72.0 * d * d * V * nb);
+    }
+  }
   for (int it = 0; it < nsweeps; ++it)
     for (int col = 0; col < 2; ++col) {
       if (l == 0) {
@@ -166,6 +230,8 @@ template <typename T> void Hierarchy::sap(int l, const C<T>* b, C<T>* z, int nsw
 
 template <typename T> void Hierarchy::restrict_to(int l, const C<T>* fine, C<T>* coarse, int nb) {
   const LevelStore& L_ = lv[l];
+  meter(L_.N * (double)L_.n * op_bytes<T>() + ((double)L_.n + 2.0 * L_.N * lv[l + 1].V) * sizeof(C<T>) * nb,
+        8.0 * L_.N * (double)L_.n * nb);
   interp<T>(l, [&](const auto* P_) {
     if (l == 0) restrict_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, fine, coarse, s, nb);
     else restrict_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, fine, coarse, s, nb);
@@ -174,6 +240,8 @@ template <typename T> void Hierarchy::restrict_to(int l, const C<T>* fine, C<T>*
 
 template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T>* fine, int nb) {
   const LevelStore& L_ = lv[l];
+  meter(L_.N * (double)L_.n * op_bytes<T>() + (2.0 * L_.n + 2.0 * L_.N * lv[l + 1].V) * sizeof(C<T>) * nb,
+        8.0 * L_.N * (double)L_.n * nb);
   interp<T>(l, [&](const auto* P_) {
     if (l == 0) prolong_fine<T>(ctx->g, L_.at, L_.ad(), L_.N, P_, coarse, fine, s, nb);
     else prolong_coarse<T>(L_.at, L_.ad(), L_.d, L_.N, L_.V, P_, coarse, fine, s, nb);
@@ -190,7 +258,7 @@ template <typename T> void Hierarchy::prolong_add(int l, const C<T>* coarse, C<T
 // ---------------------------------------------------------------------------
 // norms ||v_r|| of a batch
 template <typename T>
-static void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector<double>& out, hipStream_t s) {
+void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector<double>& out, hipStream_t s) {
   red.bdots<T>(nullptr, v, 0, 0, const_cast<C<T>*>(v), n, nb, s);
   std::vector<cd> r(nb);
   red.bfetch(1, nb, r.data(), s);
@@ -214,6 +282,9 @@ void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, i
                         const std::vector<char>& live, std::vector<cd>& h, std::vector<double>& hn,
                         std::vector<cd>& cf) {
   const int k1 = j + 2;
+  // the inner products read V_0..V_j and w; the update reads them again and
+  // writes the next basis vector
+  meter((2.0 * k1 + 1) * n * sizeof(C<T>) * nb, 16.0 * k1 * n * nb);
   std::vector<cd> h1((size_t)nb * k1), h2((size_t)nb * k1), c1((size_t)nb * KMAX, cd(0));
   red->bdots<T>(nullptr, V, vstride, j + 1, w, n, nb, s);
   red->bfetch(k1, nb, h1.data(), s);
@@ -408,11 +479,18 @@ template <typename T> void Hierarchy::schur(const C<T>* v, C<T>* out, int nb) {
     const C<T>* S;
     if constexpr (std::is_same<T, double>::value) S = L_.S64.p;
     else S = L_.S32.p;
+    meter((double)L_.sm * L_.sm * sizeof(C<T>) + 2.0 * L_.sm * sizeof(C<T>) * nb, 8.0 * L_.sm * L_.sm * nb);
     dense_schur_apply<T>(S, L_.sm, L_.s_oidx.p, L_.s_eidx.p, L_.n, v, out, s, nb);
     return;
   }
   Work<T>& W = work<T>(c);
   const int ne = (int)L_.cg.even.size(), no = (int)L_.cg.odd.size();
+  {
+    // two half-lattice sweeps of the stencil and the even self-block inverses
+    const double d = L_.d;
+    meter(L_.V * (9 * d * d * op_bytes<T>() + 4 * d * sizeof(C<T>) * nb) + ne * d * d * sizeof(C<T>),
+          (72.0 + 8.0) * d * d * L_.V * nb);
+  }
   // t3_e = D_eo v_o ; t4_e = D_ee^-1 t3_e ; out_o = D_oo v_o - D_oe t4_e
   coarse_op<T>(c, [&](const auto& op) {
     coarse_site_apply(op, L_.c_even.p, ne, T(0), nullptr, T(0), nullptr, T(1), v, W.t3.p, s, nb);
@@ -588,6 +666,7 @@ template <typename T> void Hierarchy::apply_pre_graph(int nb) {
 // the level-l cycle (Alg. 1; Alg. 2 replaces the recursive call by FGMRES)
 // ---------------------------------------------------------------------------
 template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int nb) {
+  lt_push(l);
   Work<T>& W = work<T>(l);
   Work<T>& Wc = work<T>(l + 1);
   DD_REQUIRE(nb <= W.cap && nb <= Wc.cap, "batch larger than the work buffers");
@@ -604,19 +683,25 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
   if (l + 1 == L - 1) {
     // under graph capture the fixed launch sequence, else with the host
     // reading the device's liveness flag
+    lt_push(l + 1);
     coarsest_solve<T>(Wc.bin.p, Wc.z.p, nb, dev_scalars ? 0 : COARSE_POLL);
+    lt_pop();
   } else if (p.cycle == DDAMG_KCYCLE) {
     const int c = l + 1;
+    lt_push(c);
     fgmres<T>(
         c, [&](const C<T>* a, C<T>* o) { apply<T>(c, a, o, nb); },
         [&](const C<T>* a, C<T>* o) { cycle<T>(c, a, o, nb); }, true, Wc.bin.p, Wc.z.p, p.kc_len,
         p.kc_restarts, p.kc_tol, nb, kc_it.data());
+    lt_pop();
   } else if (p.cycle == DDAMG_WCYCLE) {
     // two cycles on level l+1, the second on the residual of the first
     const long long nc = lv[l + 1].n;
     cycle<T>(l + 1, Wc.bin.p, Wc.z.p, nb);
+    lt_push(l + 1);
     apply<T>(l + 1, Wc.z.p, Wc.x.p, nb);
     vbmy<T>(Wc.bin.p, Wc.x.p, nc * nb, s);
+    lt_pop();
     cycle<T>(l + 1, Wc.x.p, Wc.w.p, nb);
     vadd<T>(Wc.w.p, Wc.z.p, nc * nb, s);
   } else {
@@ -629,6 +714,7 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
   }
   prolong_add<T>(l, Wc.z.p, z, nb);
   if (p.nu > 0) sap<T>(l, b, z, p.nu, nb);
+  lt_pop();
 }
 
 // ---------------------------------------------------------------------------
@@ -645,6 +731,11 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
   const int m = p.nkv;
   ensure_batch<T>(nb);
   const FineOpView<double> D = ctx->view<double>();
+  // the FP64 operator of the outer iteration (residuals and Arnoldi)
+  const auto applyD64 = [&](const double2* in, double2* out) {
+    meter((double)ctx->g.V * (24 * 16.0 * nb + 72 * 16.0), 1870.0 * ctx->g.V * nb);
+    dslash<double>(D, in, out, s, nb);
+  };
   double2* V = oV.p;
   C<T>* Z = outerZ<T>(*this).p;
   // FP16 directions with per-site scales (FP16 storage, FP32 cycle)
@@ -670,7 +761,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     bscale_host<double>(*red, keep, x, x, n, nb, s);
   }
   // r = b - D x
-  dslash<double>(D, x, w, s, nb);
+  applyD64(x, w);
   vbmy<double>(b, w, vs, s);
   bnorms<double>(*red, w, n, nb, beta, s);
   for (int r = 0; r < nb; ++r) {
@@ -705,30 +796,30 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
         if (zh) {
           encode_sites(ctx->g, reinterpret_cast<const float2*>(W0.x.p), oZ16.p + (size_t)j * vs,
                        oZs.p + (size_t)j * nb * ctx->g.V, ot.p, nb, s);
-          dslash<double>(D, ot.p, w, s, nb);
+          applyD64(ot.p, w);
         } else if constexpr (std::is_same<T, double>::value) {
           vcopy<double, double>(W0.x.p, Zj, vs, s);
-          dslash<double>(D, Zj, w, s, nb);
+          applyD64(Zj, w);
         } else {
           vcopy<T, T>(W0.x.p, Zj, vs, s);
           vcopy<T, double>(W0.x.p, ot.p, vs, s);
-          dslash<double>(D, ot.p, w, s, nb);
+          applyD64(ot.p, w);
         }
       } else if constexpr (std::is_same<T, double>::value) {
         cycle<double>(0, Vj, Zj, nb);
-        dslash<double>(D, Zj, w, s, nb);
+        applyD64(Zj, w);
       } else if (zh) {
         vcopy<double, T>(Vj, W0.bin.p, vs, s);
         cycle<T>(0, W0.bin.p, W0.x.p, nb);
         // the stored direction is the FP16 one: D is applied to its decoded value
         encode_sites(ctx->g, reinterpret_cast<const float2*>(W0.x.p), oZ16.p + (size_t)j * vs,
                      oZs.p + (size_t)j * nb * ctx->g.V, ot.p, nb, s);
-        dslash<double>(D, ot.p, w, s, nb);
+        applyD64(ot.p, w);
       } else {
         vcopy<double, T>(Vj, W0.bin.p, vs, s);
         cycle<T>(0, W0.bin.p, Zj, nb);
         vcopy<T, double>(Zj, ot.p, vs, s);
-        dslash<double>(D, ot.p, w, s, nb);
+        applyD64(ot.p, w);
       }
       arnoldi<double>(V, vs, n, nb, j, w, live, h, hn, cf);
       bool still = false;
@@ -770,7 +861,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       else blincomb<double, T>(a, kmax, Z, vs, x, n, nb, nullptr, s);
     }
     // true residuals in FP64
-    dslash<double>(D, x, w, s, nb);
+    applyD64(x, w);
     vbmy<double>(b, w, vs, s);
     bnorms<double>(*red, w, n, nb, beta, s);
     for (int r = 0; r < nb; ++r) {
@@ -879,8 +970,10 @@ void Hierarchy::build_level(int l, bool from32) {
   // the FP64 test vectors (for an FP32 setup: their FP64 copy) feed the
   // orthonormalisation, which writes P in FP64
   if (from32) vcopy<float, double>(F.tv32.p, F.tv64.p, (long long)N * n, s);
-  if (l == 0) orthonormalise_fine(ctx->g, F.at, F.ad(), N, F.tv64.p, F.P64.p, s);
-  else orthonormalise_coarse(F.at, F.ad(), F.d, N, F.V, F.tv64.p, F.P64.p, s);
+  if (!setup_flags.p) setup_flags.alloc(2);
+  DD_CHECK_HIP(hipMemsetAsync(setup_flags.p, 0, 2 * sizeof(int), s));
+  if (l == 0) orthonormalise_fine(ctx->g, F.at, F.ad(), N, F.tv64.p, F.P64.p, setup_flags.p, s);
+  else orthonormalise_coarse(F.at, F.ad(), F.d, N, F.V, F.tv64.p, F.P64.p, setup_flags.p, s);
   if (F.P32.p) vcopy<double, float>(F.P64.p, F.P32.p, (long long)N * n, s);
   if (F.P16.p) to_half(F.P64.p, F.P16.p, (long long)N * n, s);
   // Galerkin in FP64
@@ -891,11 +984,17 @@ void Hierarchy::build_level(int l, bool from32) {
   if (Cc.K16.p) expand_coarse<__half2>(Cc.D64.p, Cc.c_nbr9.p, (int)Cc.V, Cc.d, Cc.K16.p, s);
   if (l + 1 == L - 1 && Cc.cg.bipartite) {
     const int ne = (int)Cc.cg.even.size();
-    self_block_inverse(Cc.D64.p, Cc.c_even.p, ne, Cc.d, Cc.Einv64.p, s);
+    self_block_inverse(Cc.D64.p, Cc.c_even.p, ne, Cc.d, Cc.Einv64.p, setup_flags.p + 1, s);
     if (Cc.Einv32.p) vcopy<double, float>(Cc.Einv64.p, Cc.Einv32.p, (long long)ne * Cc.d * Cc.d, s);
     if (Cc.sm > 0) build_dense_schur(l + 1);
   }
+  int fl[2] = {0, 0};
+  DD_CHECK_HIP(hipMemcpyAsync(fl, setup_flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
   DD_CHECK_HIP(hipStreamSynchronize(s));
+  DD_REQUIRE(!fl[0], "the test vectors of level " + std::to_string(l) +
+                         " are linearly dependent on an aggregate to within rounding (Gram ratio below 1e-12): "
+                         "P cannot be orthonormalised accurately");
+  DD_REQUIRE(!fl[1], "an even-site self block of the coarsest level is singular or not finite");
 }
 
 void Hierarchy::build_dense_schur(int c) {
@@ -1037,6 +1136,7 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.coarse_dense == 0 || p.coarse_dense == 1, "coarse_dense must be 0 or 1");
   DD_REQUIRE(p.galerkin_cols == 0 || p.galerkin_cols == 1 || p.galerkin_cols == 4,
              "galerkin_cols must be 0, 1 or 4");
+  DD_REQUIRE(p.profile_levels == 0 || p.profile_levels == 1, "profile_levels must be 0 or 1");
   DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle != DDAMG_KCYCLE,
              "a graph-captured preconditioner needs the V- or W-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
@@ -1185,6 +1285,7 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
   int cap = 1;
   for (int l = 0; l < L - 1; ++l) cap = std::max(cap, p.ntv[l]);
   cap = std::min(cap, p.batch);
+  const auto t0 = std::chrono::steady_clock::now();
   if (p.precond_prec == DDAMG_F32) {
     H->ensure_work<float>(cap);
     H->setup<float>(tvc);
@@ -1192,11 +1293,14 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
     H->ensure_work<double>(cap);
     H->setup<double>(tvc);
   }
+  DD_CHECK_HIP(hipStreamSynchronize(s));
+  H->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   H->tv_extra = nullptr;
   return H.release();
 }
 
 // explicit instantiations used by the C ABI
+template void bnorms<double>(Reducer&, const C<double>*, long long, int, std::vector<double>&, hipStream_t);
 template void Hierarchy::apply<double>(int, const C<double>*, C<double>*, int);
 template void Hierarchy::apply<float>(int, const C<float>*, C<float>*, int);
 template void Hierarchy::sap<double>(int, const C<double>*, C<double>*, int, int);

@@ -52,11 +52,13 @@ void prolong_coarse(const AggTables& a, const AggDev& ad, int d, int N, long lon
 
 // orthonormalise the N test-vector fields tv (FP64, layout of level l) per
 // (aggregate, chirality) in index order (Gram-Schmidt with one
-// re-orthogonalisation pass); result written to P.
+// re-orthogonalisation pass); result written to P.  *flag (device) is set
+// to 1 where a vector is dependent on the earlier ones of its aggregate to
+// within the rounding level of the Gram matrix.
 void orthonormalise_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
-                         const double2* tv, double2* P, hipStream_t s);
+                         const double2* tv, double2* P, int* flag, hipStream_t s);
 void orthonormalise_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                           const double2* tv, double2* P, hipStream_t s);
+                           const double2* tv, double2* P, int* flag, hipStream_t s);
 
 // Galerkin D_{l+1} = P^H D_l P in FP64: self and forward blocks, [nagg][5][2N][2N]
 void galerkin_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,

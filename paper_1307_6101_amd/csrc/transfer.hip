@@ -341,7 +341,8 @@ __device__ inline void orth_pair(int p, int N, int& i, int& j) {
 
 template <class Map>
 __global__ void __launch_bounds__(256) k_orth(Map map, int m, int N, long long fstride,
-                                              const double2* __restrict__ tv, double2* __restrict__ P) {
+                                              const double2* __restrict__ tv, double2* __restrict__ P,
+                                              int* __restrict__ flag) {
   __shared__ double2 chunk[NMAX * ORTH_APPLY];
   __shared__ double2 R[NMAX * NMAX];   // Gram matrix, then R (upper triangle)
   __shared__ double2 X[NMAX * NMAX];   // R^-1 (upper triangle)
@@ -391,6 +392,10 @@ __global__ void __launch_bounds__(256) k_orth(Map map, int m, int N, long long f
           dk -= r.x * r.x + r.y * r.y;
         }
         const double gkk = R[k * NMAX + k].x;
+        // a column whose part orthogonal to the earlier ones is below the
+        // rounding level of the Gram matrix (relative 1e-12) cannot be
+        // orthonormalised accurately from it: reported to the host
+        if (!(dk > 1e-12 * gkk)) *flag = 1;
         const bool zero = !(gkk > 0.0) || !(dk > 1e-28 * gkk);
         dep[k] = zero ? 1 : 0;
         R[k * NMAX + k] = make_double2(zero ? 0.0 : sqrt(dk), 0.0);
@@ -442,23 +447,23 @@ __global__ void __launch_bounds__(256) k_orth(Map map, int m, int N, long long f
 }
 
 void orthonormalise_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N,
-                         const double2* tv, double2* P, hipStream_t s) {
+                         const double2* tv, double2* P, int* flag, hipStream_t s) {
   const int m = a.asz * 6;
   DD_REQUIRE(N <= NMAX, "too many test vectors");
   DD_REQUIRE(N <= m, "more test vectors than the aggregate dimension");
   DD_REQUIRE(m <= 256 * EPT, "aggregate too large");
   k_orth<FineMap><<<2 * a.nagg, 256, 0, s>>>(FineMap{ad.members, a.asz / 16}, m, N,
-                                            (long long)g.nblk * 192, tv, P);
+                                            (long long)g.nblk * 192, tv, P, flag);
   DD_LAUNCH_CHECK();
 }
 
 void orthonormalise_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
-                           const double2* tv, double2* P, hipStream_t s) {
+                           const double2* tv, double2* P, int* flag, hipStream_t s) {
   const int m = a.asz * (d / 2);
   DD_REQUIRE(N <= NMAX, "too many test vectors");
   DD_REQUIRE(N <= m, "more test vectors than the aggregate dimension");
   DD_REQUIRE(m <= 256 * EPT, "aggregate too large");
-  k_orth<CoarseMap><<<2 * a.nagg, 256, 0, s>>>(CoarseMap{ad.members, a.asz, d}, m, N, V * d, tv, P);
+  k_orth<CoarseMap><<<2 * a.nagg, 256, 0, s>>>(CoarseMap{ad.members, a.asz, d}, m, N, V * d, tv, P, flag);
   DD_LAUNCH_CHECK();
 }
 

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddamg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-F64, F32 = 0, 1
+F64, F32, F16 = 0, 1, 2
 CANONICAL, NATIVE = 0, 1
 KCYCLE, VCYCLE, WCYCLE = 0, 1, 2
 
@@ -59,6 +59,7 @@ class Params(ctypes.Structure):
         ("graph", ctypes.c_int),
         ("coarse_dense", ctypes.c_int),
         ("galerkin_cols", ctypes.c_int),
+        ("profile_levels", ctypes.c_int),
     ]
 
 
@@ -71,10 +72,18 @@ class SolveStats(ctypes.Structure):
         ("coarsest_iters", ctypes.c_longlong),
         ("true_relres", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("err_vs_ref", ctypes.c_double),
+        ("t_setup_s", ctypes.c_double),
+        ("t_level_s", ctypes.c_double * 4),
+        ("bytes", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("coarsest_dense", ctypes.c_int),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["t_level_s"] = list(self.t_level_s)
+        return d
 
 
 class TuneResult(ctypes.Structure):
@@ -107,6 +116,7 @@ _SIGS = {
     "ddamg_sap_smooth": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P]),
     "ddamg_precondition": (_I, [_P, _P, _P, _I, _I, _P]),
     "ddamg_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveStats), _P]),
+    "ddamg_solve_ex": (_I, [_P, _P, _P, _I, _P, ctypes.POINTER(SolveStats), _P]),
     "ddamg_solve_many": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                               ctypes.POINTER(_I), ctypes.POINTER(SolveStats), _P]),
     "ddamg_set_sap_block": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int * 4)]),
@@ -269,6 +279,16 @@ def solve(hier, b, z, nrhs=1):
     ENOCONV / ENONFINITE are returned, other failures raise."""
     stats = (SolveStats * nrhs)()
     rc = load_library().ddamg_solve(hier.handle, _ptr(b), _ptr(z), nrhs, stats, _stream())
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _check(rc)
+    return rc, [s.as_dict() for s in stats]
+
+
+def solve_ex(hier, b, z, z_ref=None, nrhs=1):
+    """ddamg_solve_ex: solve D z = b and, with z_ref, report each system's
+    error ||z - z_ref|| / ||z_ref||; returns (status, [stats dicts])."""
+    stats = (SolveStats * nrhs)()
+    rc = load_library().ddamg_solve_ex(hier.handle, _ptr(b), _ptr(z), nrhs, _ptr(z_ref), stats, _stream())
     if rc not in (OK, ENOCONV, ENONFINITE):
         _check(rc)
     return rc, [s.as_dict() for s in stats]

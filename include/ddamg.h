@@ -40,9 +40,13 @@
  *   Use ddamg_to_native / ddamg_from_native to convert.
  * Levels are numbered from 0 (the fine lattice; the paper's level 1).
  * Memory.  Every pointer argument named in/out/b/z/links/tv is a DEVICE
- *   pointer owned by the caller; the library never frees it.  The handles own
- *   the library's device memory (operators, interpolations, Krylov bases) and
- *   free it on destroy.
+ *   pointer owned by the caller; the library never frees it.  Handles made by
+ *   ddamg_create / ddamg_build_hierarchy own the library's device memory
+ *   (operators, interpolations, Krylov bases) and free it on destroy.
+ *   Handles made by ddamg_create_ws / ddamg_build_hierarchy_ws instead carve
+ *   all their device memory out of a caller-owned workspace, whose size
+ *   ddamg_workspace_bytes returns; they own only small host state (pinned
+ *   staging words, events, captured graphs).
  * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
  *   on it and return without waiting, except ddamg_create,
  *   ddamg_build_hierarchy and ddamg_solve, which return when done.
@@ -233,6 +237,34 @@ const char* ddamg_version(void);
  * kept in FP64 and FP32 next to the links.  EINVAL unless every extent is a
  * positive multiple of 4. */
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out);
+
+/* Workspace sizes for caller-owned device memory.  *ctx_bytes (if non-NULL)
+ * receives the bytes a context on `lat` made by ddamg_create_ws keeps: the
+ * links and clover term in FP64 and FP32 (Sec. 1 eq. (1)), their FP16 copies
+ * when params is non-NULL with half_storage = 1, the neighbour tables, and
+ * scratch for canonical-layout ddamg_apply_D calls of up to nrhs_max fields.
+ * *hier_bytes (if non-NULL; needs params) receives the bytes a hierarchy built
+ * with these params by ddamg_build_hierarchy_ws keeps: P_l, D_{l+1} and the
+ * test vectors of every level (Sec. 2), the setup's work (Alg. 3 and 4), and
+ * the work of solves, preconditioner and canonical-layout level calls at the
+ * hierarchy's precision on batches of up to nrhs_max right-hand sides (the
+ * outer FGMRES bases of Sec. 3, the K-cycle bases of Alg. 2, the coarsest
+ * GMRES basis, SAP scratch).  The count runs the same allocation sequence
+ * as the build, against a counter, so it is exact; it needs no GPU.  EINVAL
+ * for an invalid lattice or params, or nrhs_max < 1. */
+int ddamg_workspace_bytes(const ddamg_lattice* lat, const ddamg_params* params, int nrhs_max,
+                          size_t* ctx_bytes, size_t* hier_bytes);
+
+/* ddamg_create with all device memory carved out of `workspace` (a device
+ * pointer aligned to 256 bytes, ws_bytes long, owned by the caller, which must
+ * keep it allocated until ddamg_destroy has returned).  params (nullable) and
+ * nrhs_max must be those given to ddamg_workspace_bytes; EINVAL if ws_bytes is
+ * below its *ctx_bytes.  Calls that need more than was counted (ddamg_cgnr's
+ * vectors, ddamg_apply_D on more than nrhs_max fields in canonical layout)
+ * take it from the rest of the workspace and fail with ENOMEM when it runs
+ * out. */
+int ddamg_create_ws(const ddamg_lattice* lat, const void* links, const ddamg_params* params, int nrhs_max,
+                    void* workspace, size_t ws_bytes, void* stream, ddamg_ctx* out);
 void ddamg_destroy(ddamg_ctx ctx);
 
 /* out = D in for nrhs fine fields (eq. (1)), computed at `prec`.  With
@@ -278,6 +310,19 @@ int ddamg_from_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in,
  * dimension. */
 int ddamg_build_hierarchy(ddamg_ctx ctx, const ddamg_params* params, const void* tv,
                           const void* tv_extra, void* stream, ddamg_hier* out);
+
+/* ddamg_build_hierarchy with all of the hierarchy's device memory carved out
+ * of `workspace` (device, 256-byte aligned, ws_bytes long, caller-owned and
+ * kept allocated until ddamg_destroy_hierarchy has returned): what
+ * ddamg_workspace_bytes(lattice of ctx, params, nrhs_max) counts in
+ * *hier_bytes, all of it allocated before the setup starts, so that solves
+ * and preconditioner calls on up to nrhs_max right-hand sides allocate
+ * nothing.  EINVAL if ws_bytes is below that count.  Work beyond the count
+ * (level calls at the other precision, ddamg_tune's solution vectors, a
+ * larger SAP block set by ddamg_set_sap_block) takes memory from the rest of
+ * the workspace and fails with ENOMEM when it runs out. */
+int ddamg_build_hierarchy_ws(ddamg_ctx ctx, const ddamg_params* params, const void* tv, const void* tv_extra,
+                             int nrhs_max, void* workspace, size_t ws_bytes, void* stream, ddamg_hier* out);
 void ddamg_destroy_hierarchy(ddamg_hier hier);
 
 /* Number of levels, and sites / components per site of level `level`. */

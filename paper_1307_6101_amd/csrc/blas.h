@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "memory.h"
 
 namespace ddamg {
 
@@ -78,13 +79,13 @@ class Reducer {
   BArg upload(const std::vector<std::complex<double>>& c, const std::vector<double>& scale, int nb,
               hipStream_t s);
  private:
-  double* partial_ = nullptr;   // [NBMAX][GMAX][2*(KMAX+1)]
+  DevArray<double> partial_;    // [NBMAX][GMAX][2*(KMAX+1)]
   double2* result_ = nullptr;   // [NBMAX][KMAX+1], device alias of host_
   double2* host_ = nullptr;     // coherent pinned host memory
   // coefficient ring: pinned staging and device slots, an event per slot
   static constexpr int NSLOT = 64;
   unsigned char* cstage_ = nullptr;
-  unsigned char* cdev_ = nullptr;
+  DevArray<unsigned char> cdev_;
   hipEvent_t cev_[NSLOT] = {};
   bool cev_used_[NSLOT] = {};
   int cslot_ = 0;

@@ -257,10 +257,10 @@ void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>
   double* out = reinterpret_cast<double*>(dev_out ? dev_out : result_);
   static const BArg none{};
   BDotsLaunch<T, 0>::go(k, (unsigned)g, one ? RED_BS_ONE : RED_BS, nb, s, a ? *a : none, a ? 1 : 0, V, vstride,
-                        w, n, g == 1 ? out : partial_);
+                        w, n, g == 1 ? out : partial_.p);
   DD_LAUNCH_CHECK();
   if (g > 1) {
-    k_bdots_pass2<<<nb, 256, 0, s>>>(partial_, (int)g, 2 * (k + 1), out);
+    k_bdots_pass2<<<nb, 256, 0, s>>>(partial_.p, (int)g, 2 * (k + 1), out);
     DD_LAUNCH_CHECK();
   }
 }
@@ -297,7 +297,7 @@ BArg Reducer::upload(const std::vector<std::complex<double>>& c, const std::vect
   // the staging slot is free once the copy that last used it has run
   if (cev_used_[k]) DD_CHECK_HIP(hipEventSynchronize(cev_[k]));
   unsigned char* hst = cstage_ + (size_t)k * slot;
-  unsigned char* dvc = cdev_ + (size_t)k * slot;
+  unsigned char* dvc = cdev_.p + (size_t)k * slot;
   double* hs = reinterpret_cast<double*>(hst);
   double2* hc = reinterpret_cast<double2*>(hst + sbytes);
   for (int r = 0; r < nb; ++r) {
@@ -313,24 +313,24 @@ BArg Reducer::upload(const std::vector<std::complex<double>>& c, const std::vect
 }
 
 Reducer::Reducer() {
-  DD_CHECK_HIP(hipMalloc(&partial_, sizeof(double) * NBMAX * GMAX * 2 * (KMAX + 1)));
+  partial_.alloc((size_t)NBMAX * GMAX * 2 * (KMAX + 1));
+  const size_t slot = sizeof(double2) * KMAX * NBMAX + sizeof(double) * NBMAX;
+  cdev_.alloc(slot * NSLOT);
+  // sizing a workspace: the device arrays above are all that is counted
+  if (counting_only()) return;
   // the final sums are written by the kernels straight into coherent pinned
   // host memory: after the stream synchronisation the host reads them with
   // no copy in between
   DD_CHECK_HIP(hipHostMalloc(&host_, sizeof(double2) * NBMAX * (KMAX + 1), hipHostMallocCoherent));
   DD_CHECK_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&result_), host_, 0));
-  const size_t slot = sizeof(double2) * KMAX * NBMAX + sizeof(double) * NBMAX;
   DD_CHECK_HIP(hipHostMalloc(&cstage_, slot * NSLOT, hipHostMallocDefault));
-  DD_CHECK_HIP(hipMalloc(&cdev_, slot * NSLOT));
   for (int k = 0; k < NSLOT; ++k) DD_CHECK_HIP(hipEventCreateWithFlags(&cev_[k], hipEventDisableTiming));
 }
 Reducer::~Reducer() {
   for (int k = 0; k < NSLOT; ++k)
     if (cev_[k]) (void)hipEventDestroy(cev_[k]);
-  (void)hipFree(partial_);
-  (void)hipHostFree(host_);
-  (void)hipHostFree(cstage_);
-  (void)hipFree(cdev_);
+  if (host_) (void)hipHostFree(host_);
+  if (cstage_) (void)hipHostFree(cstage_);
 }
 
 #define DD_INST(T)                                                                            \

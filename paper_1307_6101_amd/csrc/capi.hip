@@ -51,17 +51,21 @@ void check_layout(int layout) {
   DD_REQUIRE(layout == DDAMG_CANONICAL || layout == DDAMG_NATIVE, "layout must be DDAMG_CANONICAL or DDAMG_NATIVE");
 }
 
-template <typename T> DevArray<C<T>>& ctx_scratch(Context& c, int which);
-template <> DevArray<C<double>>& ctx_scratch<double>(Context& c, int w) { return w ? c.s64b : c.s64a; }
-template <> DevArray<C<float>>& ctx_scratch<float>(Context& c, int w) { return w ? c.s32b : c.s32a; }
-template <typename T> DevArray<C<T>>& hier_scratch(Hierarchy& h, int which);
-template <> DevArray<C<double>>& hier_scratch<double>(Hierarchy& h, int w) { return w ? h.sc64b : h.sc64a; }
-template <> DevArray<C<float>>& hier_scratch<float>(Hierarchy& h, int w) { return w ? h.sc32b : h.sc32a; }
-
-template <typename E> E* ensure(DevArray<E>& a, size_t n) {
-  if (a.n < n) a.alloc(n);
-  return a.p;
+// scratch for canonical-layout calls: n complex numbers of precision T in a
+// raw array of FP64 elements that both precisions share
+// (grown by allocating the new array first, so that a failed growth leaves
+// the old one in place)
+template <typename T> C<T>* scratch(DevArray<double2>& a, size_t n) {
+  const size_t need = (n * sizeof(C<T>) + sizeof(double2) - 1) / sizeof(double2);
+  if (a.n < need) {
+    DevArray<double2> t;
+    t.alloc(need);
+    a = std::move(t);
+  }
+  return reinterpret_cast<C<T>*>(a.p);
 }
+template <typename T> C<T>* ctx_scratch(Context& c, int w, size_t n) { return scratch<T>(w ? c.s64b : c.s64a, n); }
+template <typename T> C<T>* hier_scratch(Hierarchy& h, int w, size_t n) { return scratch<T>(w ? h.sc64b : h.sc64a, n); }
 
 // canonical complex128 <-> native at T for nrhs level-l fields (n complex each)
 template <typename T>
@@ -92,8 +96,8 @@ void apply_D_impl(Context& c, const void* in, void* out, int nrhs, int layout, h
   if (layout == DDAMG_NATIVE) {
     dslash<T>(op, static_cast<const C<T>*>(in), static_cast<C<T>*>(out), s, nrhs);
   } else {
-    C<T>* a = ensure(ctx_scratch<T>(c, 0), n * nrhs);
-    C<T>* b = ensure(ctx_scratch<T>(c, 1), n * nrhs);
+    C<T>* a = ctx_scratch<T>(c, 0, n * nrhs);
+    C<T>* b = ctx_scratch<T>(c, 1, n * nrhs);
     to_nat<T>(c, 0, n, nrhs, static_cast<const double2*>(in), a, s);
     dslash<T>(op, a, b, s, nrhs);
     from_nat<T>(c, 0, n, nrhs, b, static_cast<double2*>(out), s);
@@ -111,8 +115,8 @@ void apply_Dc_impl(Hierarchy& H, int level, const void* in, void* out, int nrhs,
   if (layout == DDAMG_NATIVE) {
     H.apply<T>(level, static_cast<const C<T>*>(in), static_cast<C<T>*>(out), nrhs);
   } else {
-    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nrhs);
-    C<T>* b = ensure(hier_scratch<T>(H, 1), n * nrhs);
+    C<T>* a = hier_scratch<T>(H, 0, n * nrhs);
+    C<T>* b = hier_scratch<T>(H, 1, n * nrhs);
     to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(in), a, H.s);
     H.apply<T>(level, a, b, nrhs);
     from_nat<T>(*H.ctx, level, n, nrhs, b, static_cast<double2*>(out), H.s);
@@ -125,8 +129,8 @@ void restrict_impl(Hierarchy& H, int level, const void* fine, void* coarse, int 
   if (layout == DDAMG_NATIVE) {
     H.restrict_to<T>(level, static_cast<const C<T>*>(fine), static_cast<C<T>*>(coarse), nrhs);
   } else {
-    C<T>* a = ensure(hier_scratch<T>(H, 0), nf * nrhs);
-    C<T>* b = ensure(hier_scratch<T>(H, 1), nf * nrhs);
+    C<T>* a = hier_scratch<T>(H, 0, nf * nrhs);
+    C<T>* b = hier_scratch<T>(H, 1, nf * nrhs);
     to_nat<T>(*H.ctx, level, nf, nrhs, static_cast<const double2*>(fine), a, H.s);
     H.restrict_to<T>(level, a, b, nrhs);
     from_nat<T>(*H.ctx, level + 1, nc, nrhs, b, static_cast<double2*>(coarse), H.s);
@@ -139,8 +143,8 @@ void prolong_impl(Hierarchy& H, int level, const void* coarse, void* fine, int n
   if (layout == DDAMG_NATIVE) {
     H.prolong_add<T>(level, static_cast<const C<T>*>(coarse), static_cast<C<T>*>(fine), nrhs);
   } else {
-    C<T>* a = ensure(hier_scratch<T>(H, 0), nf * nrhs);
-    C<T>* b = ensure(hier_scratch<T>(H, 1), nf * nrhs);
+    C<T>* a = hier_scratch<T>(H, 0, nf * nrhs);
+    C<T>* b = hier_scratch<T>(H, 1, nf * nrhs);
     to_nat<T>(*H.ctx, level, nf, nrhs, static_cast<const double2*>(fine), a, H.s);
     to_nat<T>(*H.ctx, level + 1, nc, nrhs, static_cast<const double2*>(coarse), b, H.s);
     H.prolong_add<T>(level, b, a, nrhs);
@@ -154,8 +158,8 @@ void sap_impl(Hierarchy& H, int level, const void* b, void* z, int nsweeps, int 
   if (layout == DDAMG_NATIVE) {
     H.sap<T>(level, static_cast<const C<T>*>(b), static_cast<C<T>*>(z), nsweeps, nrhs);
   } else {
-    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nrhs);
-    C<T>* c = ensure(hier_scratch<T>(H, 1), n * nrhs);
+    C<T>* a = hier_scratch<T>(H, 0, n * nrhs);
+    C<T>* c = hier_scratch<T>(H, 1, n * nrhs);
     to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(b), a, H.s);
     to_nat<T>(*H.ctx, level, n, nrhs, static_cast<const double2*>(z), c, H.s);
     H.sap<T>(level, a, c, nsweeps, nrhs);
@@ -173,12 +177,12 @@ void precondition_impl(Hierarchy& H, const void* b, void* z, int nrhs, int layou
     std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
     std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
     // the cycle writes z before reading b's copy; b must stay intact
-    C<T>* a = ensure(hier_scratch<T>(H, 0), n * nb);
+    C<T>* a = hier_scratch<T>(H, 0, n * nb);
     if (layout == DDAMG_NATIVE) {
       vcopy<T, T>(static_cast<const C<T>*>(b) + r0 * n, a, n * nb, H.s);
       H.cycle<T>(0, a, static_cast<C<T>*>(z) + r0 * n, nb);
     } else {
-      C<T>* c = ensure(hier_scratch<T>(H, 1), n * nb);
+      C<T>* c = hier_scratch<T>(H, 1, n * nb);
       to_nat<T>(*H.ctx, 0, n, nb, static_cast<const double2*>(b) + r0 * n, a, H.s);
       H.cycle<T>(0, a, c, nb);
       from_nat<T>(*H.ctx, 0, n, nb, c, static_cast<double2*>(z) + r0 * n, H.s);
@@ -238,10 +242,46 @@ int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddam
 
 void ddamg_destroy(ddamg_ctx ctx) { delete ctx; }
 
+int ddamg_workspace_bytes(const ddamg_lattice* lat, const ddamg_params* params, int nrhs_max,
+                          size_t* ctx_bytes, size_t* hier_bytes) {
+  return guarded([&] {
+    DD_REQUIRE(ctx_bytes || hier_bytes, "no output");
+    workspace_bytes(lat, params, nrhs_max, ctx_bytes, hier_bytes);
+  });
+}
+
+// the caller's workspace for a handle, checked against what the handle's
+// layout counts
+static std::unique_ptr<Workspace> caller_workspace(void* workspace, size_t ws_bytes, size_t need) {
+  DD_REQUIRE(workspace != nullptr, "null workspace");
+  DD_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % Workspace::ALIGN == 0,
+             "the workspace must be aligned to 256 bytes");
+  DD_REQUIRE(ws_bytes >= need, "the workspace holds " + std::to_string(ws_bytes) + " bytes; " +
+                                   std::to_string(need) + " are needed");
+  return std::unique_ptr<Workspace>(new Workspace(workspace, ws_bytes));
+}
+
+int ddamg_create_ws(const ddamg_lattice* lat, const void* links, const ddamg_params* params, int nrhs_max,
+                    void* workspace, size_t ws_bytes, void* stream, ddamg_ctx* out) {
+  return guarded([&] {
+    DD_REQUIRE(out != nullptr, "null output handle");
+    *out = nullptr;
+    size_t need = 0;
+    workspace_bytes(lat, params, nrhs_max, &need, nullptr);
+    const bool half = params && params->half_storage == 1;
+    std::unique_ptr<ddamg_ctx_s> h(new ddamg_ctx_s);
+    h->c.reset(create_context(lat, static_cast<const double2*>(links), as_stream(stream),
+                              caller_workspace(workspace, ws_bytes, need), half, nrhs_max));
+    *out = h.release();
+  });
+}
+
+
 int ddamg_apply_D(ddamg_ctx ctx, const void* in, void* out, int nrhs, int prec, int layout,
                   void* stream) {
   return guarded([&] {
     DD_REQUIRE(ctx && ctx->c, "null context");
+    const WorkspaceScope wsc(ctx->c->ws.get());
     DD_REQUIRE(in && out && in != out, "in/out must be distinct device pointers");
     DD_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     check_prec(prec);
@@ -308,9 +348,32 @@ int ddamg_build_hierarchy(ddamg_ctx ctx, const ddamg_params* params, const void*
 
 void ddamg_destroy_hierarchy(ddamg_hier hier) { delete hier; }
 
+int ddamg_build_hierarchy_ws(ddamg_ctx ctx, const ddamg_params* params, const void* tv, const void* tv_extra,
+                             int nrhs_max, void* workspace, size_t ws_bytes, void* stream, ddamg_hier* out) {
+  return guarded([&] {
+    DD_REQUIRE(ctx && ctx->c, "null context");
+    DD_REQUIRE(out != nullptr && params != nullptr, "null argument");
+    *out = nullptr;
+    ddamg_lattice lat{};
+    for (int mu = 0; mu < 4; ++mu) lat.dims[mu] = ctx->c->g.dims[mu];
+    lat.m0 = ctx->c->m0;
+    lat.csw = ctx->c->csw;
+    size_t need = 0;
+    workspace_bytes(&lat, params, nrhs_max, nullptr, &need);
+    std::unique_ptr<ddamg_hier_s> h(new ddamg_hier_s);
+    h->owner = ctx;
+    h->h.reset(create_hierarchy(ctx->c.get(), params, static_cast<const double2*>(tv),
+                                static_cast<const double2*>(tv_extra), as_stream(stream),
+                                caller_workspace(workspace, ws_bytes, need), nrhs_max));
+    *out = h.release();
+  });
+}
+
+
 int ddamg_level_info(ddamg_hier hier, int level, int dims_out[4], int* dof_out) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L, "level out of range");
     if (dims_out) for (int mu = 0; mu < 4; ++mu) dims_out[mu] = H.lv[level].dims[mu];
     if (dof_out) *dof_out = H.lv[level].d;
@@ -321,6 +384,7 @@ int ddamg_apply_Dc(ddamg_hier hier, int level, const void* in, void* out, int nr
                    int layout, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L, "level out of range");
     DD_REQUIRE(in && out && in != out && nrhs >= 1, "bad argument");
     check_prec(prec);
@@ -336,6 +400,7 @@ int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, i
                    int layout, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
     check_prec(prec);
@@ -351,6 +416,7 @@ int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, in
                   int layout, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
     check_prec(prec);
@@ -366,6 +432,7 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
                      int prec, int layout, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "SAP is defined on levels 0..L-2");
     DD_REQUIRE(b && z && b != z && nrhs >= 1 && nsweeps >= 0, "bad argument");
     check_prec(prec);
@@ -380,6 +447,7 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
 int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int layout, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     check_layout(layout);
     H.s = as_stream(stream);
@@ -473,6 +541,7 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
   int worst = DDAMG_OK;
   int rc = guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     worst = solve_batches(H, b, z, nrhs, stats, as_stream(stream));
   });
@@ -485,6 +554,7 @@ int ddamg_solve_ex(ddamg_hier hier, const void* b, void* z, int nrhs, const void
   int worst = DDAMG_OK;
   int rc = guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     DD_REQUIRE(z_ref != z && z_ref != b, "z_ref must not alias b or z");
     worst = solve_batches(H, b, z, nrhs, stats, as_stream(stream), z_ref);
@@ -534,6 +604,7 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
       th.t.emplace_back([&, i] {
         try {
           Hierarchy& H = H_(hiers[i]);
+          const WorkspaceScope wsc(H.ws.get());
           DD_CHECK_HIP(hipSetDevice(dev));
           worst[i] = solve_batches(H, b[i], z[i], nrhs[i], stats ? stats + off[i] : nullptr, H.own_s);
         } catch (const Error& e) {
@@ -561,6 +632,7 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
 int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(block != nullptr, "null block shape");
     H.set_sap_block(level, block);
   });
@@ -569,6 +641,7 @@ int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]) {
 int ddamg_set_batch(ddamg_hier hier, int batch) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(batch >= 1 && batch <= NBMAX, "batch must be 1..32");
     H.p.batch = batch;
   });
@@ -578,6 +651,7 @@ int ddamg_tune(ddamg_hier hier, const void* b, int nrhs, const char* cache_path,
                void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(b && nrhs >= 1, "bad argument");
     const std::string path = cache_path ? cache_path : "";
     const std::string key = tune_key(H, nrhs);
@@ -665,6 +739,7 @@ int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int 
     DD_REQUIRE(b && z && b != z && nrhs >= 1, "bad argument");
     DD_REQUIRE(tol > 0 && max_iter >= 0, "tol must be > 0 and max_iter >= 0");
     Context& c = *ctx->c;
+    const WorkspaceScope wsc(c.ws.get());
     hipStream_t s = as_stream(stream);
     const long long n = c.g.V * 12;
     const int bmax = std::min(nrhs, 16);
@@ -697,6 +772,7 @@ int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int 
 int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(out != nullptr, "null output");
     hipStream_t s = as_stream(stream);
@@ -709,6 +785,7 @@ int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stre
 int ddamg_export_coarse_op(ddamg_hier hier, int level, void* out, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 1 && level < H.L, "level out of range (coarse levels are 1..L-1)");
     DD_REQUIRE(out != nullptr, "null output");
     export_coarse(H.lv[level].cview<double>(), static_cast<double2*>(out), as_stream(stream));
@@ -718,6 +795,7 @@ int ddamg_export_coarse_op(ddamg_hier hier, int level, void* out, void* stream) 
 int ddamg_import_test_vectors(ddamg_hier hier, int level, const void* tv, void* stream) {
   return guarded([&] {
     Hierarchy& H = H_(hier);
+    const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(tv != nullptr, "null test vectors");
     H.s = as_stream(stream);

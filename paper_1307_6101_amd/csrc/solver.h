@@ -15,55 +15,24 @@
 #include "coarse.h"
 #include "dgmres.h"
 #include "fine.h"
+#include "memory.h"
 #include "transfer.h"
 
 namespace ddamg {
 
-// RAII device array
-template <typename E>
-struct DevArray {
-  E* p = nullptr;
-  size_t n = 0;
-  DevArray() = default;
-  DevArray(const DevArray&) = delete;
-  DevArray& operator=(const DevArray&) = delete;
-  DevArray(DevArray&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
-  DevArray& operator=(DevArray&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
-    return *this;
-  }
-  ~DevArray() { release(); }
-  void alloc(size_t count) {
-    release();
-    if (count == 0) return;
-    if (hipMalloc(&p, count * sizeof(E)) != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      throw Error(DDAMG_ENOMEM, "device allocation of " + std::to_string(count * sizeof(E)) + " bytes failed");
-    }
-    n = count;
-  }
-  void upload(const std::vector<E>& v, hipStream_t s) {
-    alloc(v.size());
-    if (!v.empty())
-      DD_CHECK_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s));
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-};
-
 struct Context {
+  // the caller's workspace the arrays below are carved from (nullptr: each
+  // is a hipMalloc of its own); declared first so that it outlives them
+  std::unique_ptr<Workspace> ws;
   FineGeom g;
   double m0 = 0, csw = 0;
   DevArray<double2> U64, A64;
   DevArray<float2> U32, A32;
   DevArray<__half2> U16, A16;     // FP16 storage, made on first request
+  bool half_ready = false;
   DevArray<int> nbr, cblk;
-  DevArray<double2> s64a, s64b;   // scratch for canonical-layout calls
-  DevArray<float2> s32a, s32b;
+  // scratch for canonical-layout calls, raw bytes shared by both precisions
+  DevArray<double2> s64a, s64b;
   template <typename T> FineOpView<T> view() const;
   FineOpView<float, __half2> view16() const { return {U16.p, A16.p, nbr.p, g.nblk}; }
   void make_half(hipStream_t s);
@@ -123,6 +92,9 @@ struct LevelStore {
 };
 
 struct Hierarchy {
+  // the caller's workspace (see Context::ws); declared first
+  std::unique_ptr<Workspace> ws;
+  int nrhs_max = 0;                // batches the workspace was sized for (0: no workspace)
   Context* ctx = nullptr;
   ddamg_params p{};
   int L = 0;
@@ -134,8 +106,8 @@ struct Hierarchy {
   DevArray<float2> oZ32;
   DevArray<__half2> oZ16;          // FP16 directions with per-site scales (FP16 storage)
   DevArray<float> oZs;
-  DevArray<double2> sc64a, sc64b;   // scratch for canonical-layout calls
-  DevArray<float2> sc32a, sc32b;
+  DevArray<double2> sc64a, sc64b;   // scratch for canonical-layout calls (raw bytes, both precisions)
+  DevArray<double2> ds_e, ds_t3, ds_t4, ds_o;   // dense Schur construction, kept with a workspace
   std::unique_ptr<Reducer> red;
   hipStream_t s = nullptr;
   hipStream_t own_s = nullptr;     // the hierarchy's own stream (concurrent solves), made on first use
@@ -252,6 +224,13 @@ struct Hierarchy {
   // unit vectors through the sparse FP64 product
   void build_dense_schur(int c);
   template <typename T> void alloc_work(int cap);
+  // the level structure: geometry, index tables and the arrays of the
+  // operators, interpolations and test vectors (no kernels: it also runs
+  // against a counting workspace)
+  void layout();
+  // with a workspace: everything a setup and the solves of batches of up to
+  // nrhs right-hand sides grow on demand otherwise, allocated up front
+  void reserve(int nrhs);
   // replace the SAP block shape of coarse level l (1 <= l <= L-2) for the
   // solves from now on (the setup already done is kept)
   void set_sap_block(int l, const int blk[4]);
@@ -272,9 +251,18 @@ struct Hierarchy {
 template <typename T>
 void bnorms(Reducer& red, const C<T>* v, long long n, int nb, std::vector<double>& out, hipStream_t s);
 
-Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s);
+// ws: the caller's workspace (nullptr: the library allocates); half and
+// nrhs_max size what a workspace reserves up front (the FP16 operator
+// copies, canonical-layout scratch for nrhs_max fields)
+Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s,
+                        std::unique_ptr<Workspace> ws = nullptr, bool half = false, int nrhs_max = 0);
 Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* p, const double2* tv,
-                            const double2* tv_extra, hipStream_t s);
+                            const double2* tv_extra, hipStream_t s,
+                            std::unique_ptr<Workspace> ws = nullptr, int nrhs_max = 0);
+// device bytes of a context and, with params, of a hierarchy on it, as the
+// workspace entry points allocate them
+void workspace_bytes(const ddamg_lattice* lat, const ddamg_params* p, int nrhs_max, size_t* ctx_bytes,
+                     size_t* hier_bytes);
 void validate_params(const Context& ctx, const ddamg_params& p);
 void sap_block_of(const ddamg_params& p, int l, int out[4]);
 

@@ -76,39 +76,71 @@ constexpr long long DENSE_SCHUR_MAX = 2048;
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
-Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s) {
-  DD_REQUIRE(lat != nullptr && links != nullptr, "null lattice or links");
+static void check_lattice(const ddamg_lattice* lat) {
+  DD_REQUIRE(lat != nullptr, "null lattice");
   for (int mu = 0; mu < 4; ++mu)
     DD_REQUIRE(lat->dims[mu] >= 4 && lat->dims[mu] % 4 == 0,
                "every lattice extent must be a positive multiple of 4");
   DD_REQUIRE(std::isfinite(lat->m0) && std::isfinite(lat->csw), "non-finite m0 or csw");
-  std::unique_ptr<Context> c(new Context);
-  c->g = make_fine_geom(lat->dims);
-  c->m0 = lat->m0;
-  c->csw = lat->csw;
-  const FineGeom& g = c->g;
+}
+
+// geometry, neighbour tables and the operator arrays of a context (no
+// kernels); with a workspace also the FP16 copies and the canonical-layout
+// scratch that would otherwise be made on first use
+static void context_layout(Context& c, const ddamg_lattice* lat, bool half, int nrhs_max, hipStream_t s) {
+  c.g = make_fine_geom(lat->dims);
+  c.m0 = lat->m0;
+  c.csw = lat->csw;
+  const FineGeom& g = c.g;
   std::vector<int> nbr((size_t)g.nblk * 8), cblk(g.nblk);
   fine_tables(g, nbr.data(), cblk.data());
-  c->nbr.upload(nbr, s);
-  c->cblk.upload(cblk, s);
-  c->U64.alloc((size_t)g.V * 36);
-  c->U32.alloc((size_t)g.V * 36);
-  c->A64.alloc((size_t)g.V * 36);
-  c->A32.alloc((size_t)g.V * 36);
+  c.nbr.upload(nbr, s);
+  c.cblk.upload(cblk, s);
+  c.U64.alloc((size_t)g.V * 36);
+  c.U32.alloc((size_t)g.V * 36);
+  c.A64.alloc((size_t)g.V * 36);
+  c.A32.alloc((size_t)g.V * 36);
+  if (current_workspace()) {
+    if (half) {
+      c.U16.alloc((size_t)g.V * 36);
+      c.A16.alloc((size_t)g.V * 36);
+    }
+    if (nrhs_max > 0) {
+      c.s64a.alloc((size_t)g.V * 12 * nrhs_max);
+      c.s64b.alloc((size_t)g.V * 12 * nrhs_max);
+    }
+  }
+}
+
+Context* create_context(const ddamg_lattice* lat, const double2* links, hipStream_t s,
+                        std::unique_ptr<Workspace> ws, bool half, int nrhs_max) {
+  check_lattice(lat);
+  DD_REQUIRE(links != nullptr, "null links");
+  std::unique_ptr<Context> c(new Context);
+  c->ws = std::move(ws);
+  const WorkspaceScope scope(c->ws.get());
+  context_layout(*c, lat, half, nrhs_max, s);
+  const FineGeom& g = c->g;
   links_to_native<double>(g, links, c->U64.p, s);
   links_to_native<float>(g, links, c->U32.p, s);
   clover_build(g, links, lat->m0, lat->csw, c->A64.p, s);
   vcopy<double, float>(c->A64.p, c->A32.p, (long long)g.V * 36, s);
+  if (c->U16.p) c->make_half(s);
   DD_CHECK_HIP(hipStreamSynchronize(s));
   return c.release();
 }
 
 void Context::make_half(hipStream_t s) {
-  if (U16.p) return;
-  U16.alloc((size_t)g.V * 36);
-  A16.alloc((size_t)g.V * 36);
+  if (half_ready) return;
+  // the copies belong to the context: from its workspace, if it has one
+  const WorkspaceScope scope(ws.get());
+  if (!U16.p) {
+    U16.alloc((size_t)g.V * 36);
+    A16.alloc((size_t)g.V * 36);
+  }
   to_half(U64.p, U16.p, (long long)g.V * 36, s);
   to_half(A64.p, A16.p, (long long)g.V * 36, s);
+  half_ready = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -511,9 +543,11 @@ DevGmres Hierarchy::gm() {
     gm_coef.alloc((size_t)NBMAX * KMAX);
     gm_scale.alloc(NBMAX);
     gm_iters.alloc(NBMAX);
+    ++gen;
+  }
+  if (!gm_flag_host && !counting_only()) {
     DD_CHECK_HIP(hipHostMalloc(&gm_flag_host, sizeof(int), hipHostMallocCoherent));
     DD_CHECK_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&gm_flag_dev), gm_flag_host, 0));
-    ++gen;
   }
   DevGmres d;
   d.sys = gm_sys.p;
@@ -1002,11 +1036,15 @@ void Hierarchy::build_dense_schur(int c) {
   const int m = C_.sm, ne = (int)C_.cg.even.size(), no = (int)C_.cg.odd.size(), d = C_.d;
   const long long n = C_.n;
   constexpr int chunk = NBMAX;
-  DevArray<double2> e, t3, t4, o;
-  e.alloc((size_t)n * chunk);
-  t3.alloc((size_t)n * chunk);
-  t4.alloc((size_t)n * chunk);
-  o.alloc((size_t)n * chunk);
+  // temporaries: kept with a workspace (reserved up front), freed otherwise
+  DevArray<double2> &e = ds_e, &t3 = ds_t3, &t4 = ds_t4, &o = ds_o;
+  const size_t need = (size_t)n * chunk;
+  if (e.n < need) {
+    e.alloc(need);
+    t3.alloc(need);
+    t4.alloc(need);
+    o.alloc(need);
+  }
   const CoarseOpView<double> op = C_.cview<double>();
   for (int j0 = 0; j0 < m; j0 += chunk) {
     const int nbc = std::min(chunk, m - j0);
@@ -1018,8 +1056,11 @@ void Hierarchy::build_dense_schur(int c) {
     schur_gather_cols(o.p, n, nbc, C_.s_oidx.p, m, j0, C_.S64.p, s);
   }
   vcopy<double, float>(C_.S64.p, C_.S32.p, (long long)m * m, s);
-  // the temporaries are freed on return: drain the stream first
-  DD_CHECK_HIP(hipStreamSynchronize(s));
+  if (!ws) {
+    // freeing them waits for the stream to drain
+    DD_CHECK_HIP(hipStreamSynchronize(s));
+    e.release(), t3.release(), t4.release(), o.release();
+  }
 }
 
 // The N test vectors of a level form a batch: Alg. 3 smooths each of them
@@ -1204,27 +1245,13 @@ void Hierarchy::set_sap_block(int l, const int blk[4]) {
   ++gen;
 }
 
-Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2* tvc,
-                            const double2* tv_extra, hipStream_t s) {
-  DD_REQUIRE(ctx && pp && tvc, "null argument");
-  validate_params(*ctx, *pp);
-  std::unique_ptr<Hierarchy> H(new Hierarchy);
-  H->ctx = ctx;
-  H->p = *pp;
-  H->L = pp->levels;
-  H->s = s;
-  H->tv_extra = tv_extra;
-  H->red.reset(new Reducer);
-  H->half = pp->half_storage == 1;
-  const ddamg_params& p = H->p;
-  if (H->half) ctx->make_half(s);
-  const int L = H->L;
-  H->lv.resize(L);
+void Hierarchy::layout() {
+  lv.resize(L);
   int dims[4];
   for (int mu = 0; mu < 4; ++mu) dims[mu] = ctx->g.dims[mu];
   int d = 12;
   for (int l = 0; l < L; ++l) {
-    LevelStore& S = H->lv[l];
+    LevelStore& S = lv[l];
     S.fine = l == 0;
     for (int mu = 0; mu < 4; ++mu) S.dims[mu] = dims[mu];
     S.d = d;
@@ -1243,8 +1270,8 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.c_odd.upload(S.cg.odd, s);
       S.D64.alloc((size_t)S.V * 5 * d * d);
       S.K64.alloc((size_t)S.V * 9 * d * d);
-      if (!H->half) S.K32.alloc((size_t)S.V * 9 * d * d);
-      if (H->half) S.K16.alloc((size_t)S.V * 9 * d * d);
+      if (!half) S.K32.alloc((size_t)S.V * 9 * d * d);
+      if (half) S.K16.alloc((size_t)S.V * 9 * d * d);
       if (l == L - 1 && S.cg.bipartite) {
         S.Einv64.alloc(S.cg.even.size() * (size_t)d * d);
         S.Einv32.alloc(S.cg.even.size() * (size_t)d * d);
@@ -1273,20 +1300,72 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
       S.a_members.upload(S.at.members, s);
       S.a_member_agg.upload(S.at.member_agg, s);
       S.P64.alloc((size_t)S.N * S.n);
-      if (!H->half) S.P32.alloc((size_t)S.N * S.n);
-      if (H->half) S.P16.alloc((size_t)S.N * S.n);
+      if (!half) S.P32.alloc((size_t)S.N * S.n);
+      if (half) S.P16.alloc((size_t)S.N * S.n);
       S.tv64.alloc((size_t)S.N * S.n);
       if (p.precond_prec == DDAMG_F32) S.tv32.alloc((size_t)S.N * S.n);
       for (int mu = 0; mu < 4; ++mu) dims[mu] = S.at.cdims[mu];
       d = 2 * S.N;
     }
   }
-  // setup batches: the test vectors of a level, at most `batch` at once
+  red.reset(new Reducer);
+}
+
+// the batch the setup runs its test vectors in: at most `batch` at once
+static int setup_batch(const ddamg_params& p) {
   int cap = 1;
-  for (int l = 0; l < L - 1; ++l) cap = std::max(cap, p.ntv[l]);
-  cap = std::min(cap, p.batch);
+  for (int l = 0; l < p.levels - 1; ++l) cap = std::max(cap, p.ntv[l]);
+  return std::min(cap, p.batch);
+}
+
+void Hierarchy::reserve(int nrhs) {
+  nrhs_max = nrhs;
+  const int solve = std::min(nrhs, p.batch), cap = std::max(setup_batch(p), solve);
+  auto at = [&](auto zero) {
+    using T = decltype(zero);
+    ensure_work<T>(cap);
+    ensure_batch<T>(solve);
+    for (int l = 1; l <= L - 2; ++l) sap_scratch<T>(lv[l], cap);
+  };
+  if (p.precond_prec == DDAMG_F32) at(0.f);
+  else at(0.0);
+  gm();
+  setup_flags.alloc(2);
+  // canonical-layout level calls and the preconditioner call: two fields of
+  // the finest level per right-hand side at the hierarchy's precision
+  const size_t c2 = p.precond_prec == DDAMG_F32 ? 2 : 1;
+  sc64a.alloc(((size_t)lv[0].n * nrhs + c2 - 1) / c2);
+  sc64b.alloc(((size_t)lv[0].n * nrhs + c2 - 1) / c2);
+  const LevelStore& Lc = lv[L - 1];
+  if (Lc.sm > 0) {
+    const size_t nc = (size_t)Lc.n * NBMAX;
+    ds_e.alloc(nc);
+    ds_t3.alloc(nc);
+    ds_t4.alloc(nc);
+    ds_o.alloc(nc);
+  }
+}
+
+Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2* tvc,
+                            const double2* tv_extra, hipStream_t s, std::unique_ptr<Workspace> ws,
+                            int nrhs_max) {
+  DD_REQUIRE(ctx && pp && tvc, "null argument");
+  validate_params(*ctx, *pp);
+  std::unique_ptr<Hierarchy> H(new Hierarchy);
+  H->ws = std::move(ws);
+  H->ctx = ctx;
+  H->p = *pp;
+  H->L = pp->levels;
+  H->s = s;
+  H->tv_extra = tv_extra;
+  H->half = pp->half_storage == 1;
+  if (H->half) ctx->make_half(s);
+  const WorkspaceScope scope(H->ws.get());
+  H->layout();
+  if (H->ws) H->reserve(nrhs_max);
+  const int cap = setup_batch(H->p);
   const auto t0 = std::chrono::steady_clock::now();
-  if (p.precond_prec == DDAMG_F32) {
+  if (H->p.precond_prec == DDAMG_F32) {
     H->ensure_work<float>(cap);
     H->setup<float>(tvc);
   } else {
@@ -1297,6 +1376,36 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
   H->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   H->tv_extra = nullptr;
   return H.release();
+}
+
+void workspace_bytes(const ddamg_lattice* lat, const ddamg_params* pp, int nrhs_max, size_t* ctx_bytes,
+                     size_t* hier_bytes) {
+  check_lattice(lat);
+  DD_REQUIRE(nrhs_max >= 1 && nrhs_max <= 1 << 20, "nrhs_max must be >= 1");
+  const bool half = pp && pp->half_storage == 1;
+  // the counters outlive the arrays that report back to them
+  Workspace count_ctx, count;
+  Context c;
+  {
+    const WorkspaceScope scope(&count_ctx);
+    context_layout(c, lat, half, nrhs_max, nullptr);
+    if (ctx_bytes) *ctx_bytes = count_ctx.peak();
+  }
+  if (!hier_bytes) return;
+  *hier_bytes = 0;
+  if (!pp) return;
+  validate_params(c, *pp);
+  {
+    const WorkspaceScope scope(&count);
+    Hierarchy H;
+    H.ctx = &c;
+    H.p = *pp;
+    H.L = pp->levels;
+    H.half = half;
+    H.layout();
+    H.reserve(nrhs_max);
+  }
+  *hier_bytes = count.peak();
 }
 
 // explicit instantiations used by the C ABI

@@ -102,12 +102,18 @@ _SIGS = {
     "ddamg_last_error": (ctypes.c_char_p, []),
     "ddamg_version": (ctypes.c_char_p, []),
     "ddamg_create": (_I, [ctypes.POINTER(Lattice), _P, _P, ctypes.POINTER(_P)]),
+    "ddamg_workspace_bytes": (_I, [ctypes.POINTER(Lattice), ctypes.POINTER(Params), _I,
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "ddamg_create_ws": (_I, [ctypes.POINTER(Lattice), _P, ctypes.POINTER(Params), _I, _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(_P)]),
     "ddamg_destroy": (None, [_P]),
     "ddamg_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _P]),
     "ddamg_apply_D_noalloc": (_I, [_P, _P, _P, _I, _I, _P]),
     "ddamg_to_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
     "ddamg_from_native": (_I, [_P, _P, _I, _P, _P, _I, _I, _P]),
     "ddamg_build_hierarchy": (_I, [_P, ctypes.POINTER(Params), _P, _P, _P, ctypes.POINTER(_P)]),
+    "ddamg_build_hierarchy_ws": (_I, [_P, ctypes.POINTER(Params), _P, _P, _I, _P, ctypes.c_size_t, _P,
+                                      ctypes.POINTER(_P)]),
     "ddamg_destroy_hierarchy": (None, [_P]),
     "ddamg_level_info": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int * 4), ctypes.POINTER(_I)]),
     "ddamg_apply_Dc": (_I, [_P, _I, _P, _P, _I, _I, _I, _P]),
@@ -177,16 +183,44 @@ def params_default(levels: int) -> Params:
     return p
 
 
-class Context:
-    """Handle of one lattice operator D (ddamg_create / ddamg_destroy)."""
+def _ws(t):
+    """A workspace tensor: contiguous device bytes."""
+    if t.dtype != torch.uint8:
+        raise ValueError("a workspace is a torch.uint8 device tensor")
+    return _ptr(t), ctypes.c_size_t(t.numel())
 
-    def __init__(self, dims, m0, csw, links):
+
+def workspace_bytes(dims, m0, csw, params=None, nrhs_max=1):
+    """(context bytes, hierarchy bytes) of ddamg_workspace_bytes; the second
+    is 0 without params."""
+    lib = load_library()
+    lat = Lattice((ctypes.c_int * 4)(*dims), float(m0), float(csw))
+    cb, hb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(lib.ddamg_workspace_bytes(ctypes.byref(lat), ctypes.byref(params) if params is not None else None,
+                                     int(nrhs_max), ctypes.byref(cb), ctypes.byref(hb)))
+    return cb.value, hb.value
+
+
+class Context:
+    """Handle of one lattice operator D (ddamg_create / ddamg_destroy); with
+    `workspace` (a torch.uint8 device tensor) ddamg_create_ws, which keeps
+    all of the handle's device memory in that tensor (held here until the
+    handle is destroyed)."""
+
+    def __init__(self, dims, m0, csw, links, workspace=None, params=None, nrhs_max=1):
         lib = load_library()
         lat = Lattice((ctypes.c_int * 4)(*dims), float(m0), float(csw))
         h = ctypes.c_void_p()
-        _check(lib.ddamg_create(ctypes.byref(lat), _ptr(links), _stream(), ctypes.byref(h)))
+        if workspace is None:
+            _check(lib.ddamg_create(ctypes.byref(lat), _ptr(links), _stream(), ctypes.byref(h)))
+        else:
+            wp, wn = _ws(workspace)
+            _check(lib.ddamg_create_ws(ctypes.byref(lat), _ptr(links),
+                                       ctypes.byref(params) if params is not None else None, int(nrhs_max),
+                                       wp, wn, _stream(), ctypes.byref(h)))
         self.handle = h
         self.dims = tuple(dims)
+        self.workspace = workspace
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -195,16 +229,23 @@ class Context:
 
 
 class Hierarchy:
-    """Handle of a multilevel hierarchy (ddamg_build_hierarchy / destroy)."""
+    """Handle of a multilevel hierarchy (ddamg_build_hierarchy / destroy);
+    with `workspace` ddamg_build_hierarchy_ws (see Context)."""
 
-    def __init__(self, ctx: Context, params: Params, tv, tv_extra=None):
+    def __init__(self, ctx: Context, params: Params, tv, tv_extra=None, workspace=None, nrhs_max=1):
         lib = load_library()
         h = ctypes.c_void_p()
-        _check(lib.ddamg_build_hierarchy(ctx.handle, ctypes.byref(params), _ptr(tv), _ptr(tv_extra),
-                                         _stream(), ctypes.byref(h)))
+        if workspace is None:
+            _check(lib.ddamg_build_hierarchy(ctx.handle, ctypes.byref(params), _ptr(tv), _ptr(tv_extra),
+                                             _stream(), ctypes.byref(h)))
+        else:
+            wp, wn = _ws(workspace)
+            _check(lib.ddamg_build_hierarchy_ws(ctx.handle, ctypes.byref(params), _ptr(tv), _ptr(tv_extra),
+                                                int(nrhs_max), wp, wn, _stream(), ctypes.byref(h)))
         self.handle = h
         self.ctx = ctx
         self.params = params
+        self.workspace = workspace
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -218,6 +259,14 @@ def create(dims, m0, csw, links) -> Context:
 
 def build_hierarchy(ctx, params, tv, tv_extra=None) -> Hierarchy:
     return Hierarchy(ctx, params, tv, tv_extra)
+
+
+def create_ws(dims, m0, csw, links, workspace, params=None, nrhs_max=1) -> Context:
+    return Context(dims, m0, csw, links, workspace=workspace, params=params, nrhs_max=nrhs_max)
+
+
+def build_hierarchy_ws(ctx, params, tv, workspace, nrhs_max=1, tv_extra=None) -> Hierarchy:
+    return Hierarchy(ctx, params, tv, tv_extra, workspace=workspace, nrhs_max=nrhs_max)
 
 
 def apply_D(ctx, inp, out, nrhs=1, prec=F64, layout=CANONICAL):

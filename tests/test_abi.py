@@ -151,3 +151,66 @@ def test_solve_many_validation(dd):
     assert b"twice" in lib.ddamg_last_error()
     assert lib.ddamg_solve_many(1, one, bz, bz, n1, None, None) == dd.EINVAL
     assert lib.ddamg_solve_many(1, one, bz, zz, (ctypes.c_int * 1)(0), None, None) == dd.EINVAL
+
+
+def _round(b):
+    return (b + 255) // 256 * 256
+
+
+def test_workspace_bytes_counts_the_layout(dd):
+    """The workspace query runs the handles' allocation sequence against a
+    counter on the host: it needs no GPU, and its totals follow the array
+    sizes of the layout exactly."""
+    dims = (16, 16, 16, 16)
+    V = 16 ** 4
+    c1, h0 = dd.workspace_bytes(dims, -0.3, 1.0, None, 1)
+    assert h0 == 0
+    # links and clover in FP64 and FP32, neighbour tables, two scratch fields
+    ops = 2 * _round(V * 36 * 16) + 2 * _round(V * 36 * 8)
+    scr = 2 * _round(V * 12 * 16)
+    tables = _round(V // 16 * 8 * 4) + _round(V // 16 * 4)
+    assert c1 == ops + scr + tables
+    c3, _ = dd.workspace_bytes(dims, -0.3, 1.0, None, 3)
+    assert c3 - c1 == 2 * (_round(3 * V * 12 * 16) - _round(V * 12 * 16))
+    p = dd.params_default(3)
+    p.ntv[0], p.ntv[1] = 8, 8
+    p.agg[1][:] = [2, 2, 2, 2]
+    c_nohalf, h1 = dd.workspace_bytes(dims, -0.3, 1.0, p, 1)
+    assert c_nohalf == c1
+    # at least P_0, P_1 (FP64 + FP32), the test vectors (FP64 + FP32) and
+    # the coarse operators (five FP64 blocks, nine in FP64 and FP32)
+    n0, V1, d1 = V * 12, V // 256, 16
+    n1 = V1 * d1
+    V2, d2 = V1 // 16, 16
+    lower = (8 * n0 + 8 * n1) * (16 + 8) * 2 + (V1 * d1 * d1 + V2 * d2 * d2) * (5 * 16 + 9 * 24)
+    assert h1 > lower
+    _, h4 = dd.workspace_bytes(dims, -0.3, 1.0, p, 4)
+    assert h4 > h1
+    p.half_storage = 1
+    c_half, h1h = dd.workspace_bytes(dims, -0.3, 1.0, p, 1)
+    assert c_half - c1 == 2 * _round(V * 36 * 4)
+    assert h1h < h1      # FP16 copies of P and D_c in place of the FP32 ones
+
+
+def test_workspace_validation_on_host(dd):
+    lib = dd.load_library()
+    lat = dd.Lattice((ctypes.c_int * 4)(8, 8, 8, 8), -0.3, 1.0)
+    cb = ctypes.c_size_t(0)
+    assert lib.ddamg_workspace_bytes(ctypes.byref(lat), None, 0, ctypes.byref(cb), None) == dd.EINVAL
+    p = dd.params_default(2)
+    p.agg[0][:] = [3, 4, 4, 4]
+    hb = ctypes.c_size_t(0)
+    assert lib.ddamg_workspace_bytes(ctypes.byref(lat), ctypes.byref(p), 1, ctypes.byref(cb),
+                                     ctypes.byref(hb)) == dd.EINVAL
+    # a workspace smaller than the count, or misaligned, is refused before any device work
+    need, _ = dd.workspace_bytes((8, 8, 8, 8), -0.3, 1.0, None, 1)
+    h = ctypes.c_void_p()
+    rc = lib.ddamg_create_ws(ctypes.byref(lat), ctypes.c_void_p(256), None, 1, ctypes.c_void_p(1 << 20),
+                             ctypes.c_size_t(need - 1), None, ctypes.byref(h))
+    assert rc == dd.EINVAL and b"needed" in lib.ddamg_last_error()
+    rc = lib.ddamg_create_ws(ctypes.byref(lat), ctypes.c_void_p(256), None, 1, ctypes.c_void_p((1 << 20) + 64),
+                             ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert rc == dd.EINVAL and b"aligned" in lib.ddamg_last_error()
+    assert lib.ddamg_build_hierarchy_ws(None, ctypes.byref(p), ctypes.c_void_p(256), None, 1,
+                                        ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30), None,
+                                        ctypes.byref(h)) == dd.EINVAL

@@ -325,7 +325,9 @@ int ddamg_build_hierarchy_ws(ddamg_ctx ctx, const ddamg_params* params, const vo
                              int nrhs_max, void* workspace, size_t ws_bytes, void* stream, ddamg_hier* out);
 void ddamg_destroy_hierarchy(ddamg_hier hier);
 
-/* Number of levels, and sites / components per site of level `level`. */
+/* Lattice extents and components per site of level `level` (Sec. 2: level
+ * l+1 has one site per aggregate of level l and 2 N_l components, the two
+ * chirality halves of the N_l test vectors). */
 int ddamg_level_info(ddamg_hier hier, int level, int dims_out[4], int* dof_out);
 
 /* out = D_level in for nrhs level-`level` fields (level >= 1: the Galerkin
@@ -352,8 +354,9 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
 int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int layout,
                        void* stream);
 
-/* Solve D z = b for nrhs canonical complex128 right-hand sides with FGMRES
- * (restart nkv, double precision) preconditioned by the cycle, to
+/* Solve D z = b (Sec. 1 eq. (1)) for nrhs canonical complex128 right-hand
+ * sides with FGMRES (restart nkv, double precision) preconditioned by the
+ * cycle computed in single precision (Sec. 3, opening paragraph), to
  * ||b - D z|| <= tol ||b|| (checked on the recomputed residual).  z holds the
  * initial guess on entry (zeros for none) and the solution on return.
  * The right-hand sides go through in batches of params.batch: every launch
@@ -374,7 +377,8 @@ int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_s
 int ddamg_solve_ex(ddamg_hier hier, const void* b, void* z, int nrhs, const void* z_ref,
                    ddamg_solve_stats* stats, void* stream);
 
-/* Independent systems on different lattices (an uneven batch: the sizes,
+/* ddamg_solve (Sec. 1 eq. (1), Sec. 3) for several independent systems on
+ * different lattices (an uneven batch: the sizes,
  * links, masses and hierarchy parameters of the n hierarchies may all
  * differ), solved concurrently.  System i is ddamg_solve(hiers[i], b[i],
  * z[i], nrhs[i], ...) with the same arguments, layout, ownership and result:
@@ -396,12 +400,15 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
                      ddamg_solve_stats* stats, void* stream);
 
 /* Change the SAP block shape of coarse level `level` (1 .. levels-2, the
+ * coarse levels smoothed by SAP; Tab. 1's default is 2^4 blocks on every
+ * level, Sec. 2 only requires a red-black block decomposition)
  * smoothed coarse levels) for the solves from now on; the hierarchy (test
  * vectors, P, D_c), built with the earlier shape, is kept.  The shape must
  * tile the level with an even block count per direction (Sec. 2).  Not
  * stream-ordered: waits for the device. */
 int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]);
-/* Change params.batch (1..32) for the solves from now on. */
+/* Change params.batch (1..32), the number of right-hand sides of ddamg_solve
+ * that advance together, for the solves from now on. */
 int ddamg_set_batch(ddamg_hier hier, int batch);
 
 typedef struct {
@@ -412,7 +419,10 @@ typedef struct {
   int from_cache;          /* 1: read from the cache, no measurement */
 } ddamg_tune_result;
 
-/* Autotuner.  Times complete solves of the nrhs canonical complex128
+/* Autotuner of choices the method leaves open (the coarse-level SAP block
+ * shapes, for which Tab. 1 gives only the default, and the right-hand side
+ * batch).
+ * Times complete solves of the nrhs canonical complex128
  * right-hand sides b (device) with every candidate SAP block shape of each
  * smoothed coarse level (equal extents in x, y, z and a free extent in t,
  * dividing the level with an even count per direction, block volume 8..512;
@@ -443,14 +453,19 @@ int ddamg_tune(ddamg_hier hier, const void* b, int nrhs, const char* cache_path,
 int ddamg_cgnr(ddamg_ctx ctx, const void* b, void* z, int nrhs, double tol, int max_iter,
                ddamg_solve_stats* stats, void* stream);
 
-/* Export the orthonormalised interpolation basis of level `level` as
+/* Export the orthonormalised interpolation basis of level `level` (P_l of
+ * Sec. 2: the test vectors split by chirality on each aggregate and
+ * orthonormalised) as
  * ntv[level] canonical complex128 fields of that level ([N][V_l][d_l]), and
  * the coarse operator D_{level} (level >= 1) in the canonical coarse layout. */
 int ddamg_export_interpolation(ddamg_hier hier, int level, void* out, void* stream);
 int ddamg_export_coarse_op(ddamg_hier hier, int level, void* out, void* stream);
 
 /* Replace the test vectors of level `level` (canonical complex128,
- * [ntv][V_l][d_l]) and rebuild P_level and D_{level+1} from them (FP64). */
+ * [ntv][V_l][d_l]) and rebuild P_level and D_{level+1} = P^H D_level P from
+ * them in FP64 (the construction that ends each setup step of Alg. 3 and
+ * Alg. 4).  EINVAL if the vectors are linearly dependent on an aggregate to
+ * within rounding. */
 int ddamg_import_test_vectors(ddamg_hier hier, int level, const void* tv, void* stream);
 
 #ifdef __cplusplus

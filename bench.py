@@ -54,6 +54,8 @@ SCAN_WORKLOAD = "m0_scan_16x32"
 # bare masses of the scan on the 16^3x32 lattice (eps 0.5: the critical mass
 # estimated on 4^4 is about -0.49)
 SCAN_M0 = (-0.30, -0.35, -0.40, -0.43, -0.45, -0.46)
+# the shorter scan reported next to the default line
+SCAN_M0_SHORT = (-0.30, -0.40, -0.45)
 # coarsest GMRES of the graph-captured V-cycle: restart length, cycles (a
 # fixed launch sequence, steps after convergence doing nothing)
 GRAPH_COARSE = (8, 1)
@@ -90,6 +92,9 @@ def parse():
                          "holds nothing but solves)")
     ap.add_argument("--no-levels", action="store_true",
                     help="skip the two- and three-level comparison on the headline lattice")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the short bare-mass scan (16^3x32, two and three levels against CGNR) "
+                         "reported next to the default line")
     ap.add_argument("--workload", default=HEADLINE, choices=[WORKLOAD, BATCH_WORKLOAD, FOUR_LEVEL_WORKLOAD, UNEVEN_WORKLOAD,
                                                       SCAN_WORKLOAD],
                     help="the 48^3x96 four-level lattice (default), the 16^3x32 three-level lattice with "
@@ -690,6 +695,13 @@ def headline_workload(args, dd, W, np, torch):
                              status=rc)
         log(f"[bench] CGNR FP64: {cst[0]['outer_iters']} its, {tc:.3f}s")
 
+    # the short bare-mass scan towards criticality on the 16^3x32 lattice
+    scan = None
+    if not args.no_scan:
+        rows, _ = m0_scan(W.CONFIGS[WORKLOAD], dd, W, np, torch, SCAN_M0_SHORT,
+                          ((3, None, "3lvl"), (2, None, "2lvl")), 1)
+        scan = {"lattice": "16^3x32, eps=0.5, c_sw=1, tol 1e-10, b = D z*", "rows": rows}
+
     dom = kern["sap_colour_pass_f16store"]
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": SAP_F16_PASS_TRAFFIC_BYTES,
@@ -728,6 +740,7 @@ def headline_workload(args, dd, W, np, torch):
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
         "levels_2_3_4": levels_cmp,
+        "m0_scan_16x32": scan,
         "kernels": {k: dict({"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)},
                             **({"TFLOP/s": round(v["tflops"], 2), "mfma_frac": round(v["mfma_frac"], 4)}
                                if "tflops" in v else {})) for k, v in kern.items()},
@@ -1168,25 +1181,21 @@ def uneven_workload(args, dd, W, np, torch):
     print(json.dumps(line), flush=True)
 
 
-def scan_workload(args, cfg, dd, W, np, torch):
+def m0_scan(cfg, dd, W, np, torch, masses, variants, reps):
     """Critical slowing down on synthetic links: the 16^3x32 workload's links
     (eps 0.5) with the bare mass m0 moved towards the critical value; for
-    each m0 the mixed-precision three-level and two-level solves (setup and
-    solve times, outer iterations) against FP64 CGNR (iterations, time), as
-    the paper does on its ensembles (m0 scans, 2 vs 3 levels, comparison
-    with CGNR), and the three-level K-cycle against the V- and W-cycles.  A
-    step is one pass over the masses; `value` is the three-level K-cycle
-    solves per second over the scan."""
+    each m0 the mixed-precision multigrid solves of `variants` (levels,
+    cycle, key) and FP64 CGNR, with b = D z* for a Gaussian z* so that the
+    error ||z - z*|| / ||z*|| is reported next to the residual (the paper's
+    m0 scans, 2 vs 3 levels and comparison with CGNR).  Returns the rows
+    and the mean first-variant solve time."""
     dims = cfg["dims"]
     dev = torch.device("cuda:0")
     U = torch.from_numpy(W.links(dims, cfg["eps"], cfg["seed_links"])).to(dev)
-    # a pre-determined solution z*: b = D z* per mass, the error ||z - z*|| / ||z*||
-    # is reported next to the residual (the paper's error-scaling protocol)
     zstar = torch.from_numpy(W.gaussian_spinor(dims, cfg["seed_rhs"])).unsqueeze(0).to(dev)
     b = torch.zeros_like(zstar)
     tv = torch.from_numpy(W.test_vectors(dims, 12, cfg["ntv"][0], cfg["seed_tv"])).to(dev)
     z = torch.zeros_like(b)
-    log(f"[bench] workload {SCAN_WORKLOAD} dims={dims} m0={SCAN_M0}")
 
     def params(levels, cycle=None):
         p = dd.params_default(levels)
@@ -1208,30 +1217,29 @@ def scan_workload(args, cfg, dd, W, np, torch):
         torch.cuda.synchronize()
         return time.time() - t, rc, st[0]
 
-    rows, t3 = [], []
-    def error():
-        return float(torch.linalg.vector_norm(z - zstar) / torch.linalg.vector_norm(zstar))
+    def error(x):
+        return float(torch.linalg.vector_norm(x - zstar) / torch.linalg.vector_norm(zstar))
 
-    for m0 in SCAN_M0:
+    rows, t_first = [], []
+    for m0 in masses:
         ctx = dd.create(dims, m0, cfg["csw"], U)
         dd.apply_D(ctx, zstar, b, prec=dd.F64)
         row = {"m0": m0}
-        for levels, cyc, key in ((3, None, "3lvl"), (2, None, "2lvl"), (3, dd.VCYCLE, "3lvl_vcycle"),
-                                 (3, dd.WCYCLE, "3lvl_wcycle")):
+        for levels, cyc, key in variants:
             torch.cuda.synchronize()
             t = time.time()
             H = dd.build_hierarchy(ctx, params(levels, cyc), tv)
             torch.cuda.synchronize()
             t_setup = time.time() - t
             timed_solve(H)
-            ts = [timed_solve(H) for _ in range(max(1, args.steps))]
+            ts = [timed_solve(H) for _ in range(max(1, reps))]
             t_solve = min(x[0] for x in ts)
             rc, st = ts[-1][1], ts[-1][2]
             row[key] = dict(setup_s=round(t_setup, 3), solve_s=round(t_solve, 4),
                             outer_iters=st["outer_iters"], status=rc, true_relres=st["true_relres"],
-                            rel_error=error())
-            if key == "3lvl":
-                t3.append(t_solve)
+                            rel_error=error(z))
+            if key == variants[0][2]:
+                t_first.append(t_solve)
             del H
         zc = torch.zeros_like(b)
         torch.cuda.synchronize()
@@ -1239,13 +1247,25 @@ def scan_workload(args, cfg, dd, W, np, torch):
         rc, cst = dd.cgnr(ctx, b, zc, tol=cfg["tol"], max_iter=200000)
         torch.cuda.synchronize()
         row["cgnr"] = dict(iterations=cst[0]["outer_iters"], solve_s=round(time.time() - t, 3), status=rc,
-                           rel_error=float(torch.linalg.vector_norm(zc - zstar) / torch.linalg.vector_norm(zstar)))
+                           rel_error=error(zc))
         rows.append(row)
         log(f"[bench] m0={m0}: " + ", ".join(f"{k} {v.get('outer_iters', v.get('iterations'))} its "
                                                f"{v['solve_s']}s err {v['rel_error']:.1e}"
                                                for k, v in row.items() if k != "m0"))
         del ctx
-    ms = 1000.0 * float(np.mean(t3))
+    return rows, float(np.mean(t_first))
+
+
+def scan_workload(args, cfg, dd, W, np, torch):
+    """The bare-mass scan as a workload of its own: three levels (K-, V- and
+    W-cycle) and two levels against CGNR at every mass of SCAN_M0.  A step is
+    one pass over the masses; `value` is the three-level K-cycle solves per
+    second over the scan."""
+    log(f"[bench] workload {SCAN_WORKLOAD} dims={cfg['dims']} m0={SCAN_M0}")
+    rows, t3 = m0_scan(cfg, dd, W, np, torch, SCAN_M0,
+                       ((3, None, "3lvl"), (2, None, "2lvl"), (3, dd.VCYCLE, "3lvl_vcycle"),
+                        (3, dd.WCYCLE, "3lvl_wcycle")), args.steps)
+    ms = 1000.0 * t3
     line = {
         "metric": METRIC,
         "value": round(1000.0 / ms, 4),

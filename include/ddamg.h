@@ -78,7 +78,12 @@ enum {
  * with FP32 arithmetic and FP32 native vectors (Sec. 3 runs the
  * preconditioner in single precision; the half-precision storage is this
  * library's); on a hierarchy it needs half_storage = 1. */
-enum { DDAMG_F64 = 0, DDAMG_F32 = 1, DDAMG_F16 = 2 };
+/* F16S: F16 with the fine-level spinors too in binary16, one FP32 scale per
+ * site (the storage of params.half_spinors); for ddamg_sap_smooth,
+ * ddamg_restrict and ddamg_prolong on level 0 and ddamg_precondition, in
+ * the canonical layout (the FP16 form exists only inside the library), on a
+ * hierarchy built with half_spinors = 1. */
+enum { DDAMG_F64 = 0, DDAMG_F32 = 1, DDAMG_F16 = 2, DDAMG_F16S = 3 };
 enum { DDAMG_CANONICAL = 0, DDAMG_NATIVE = 1 };   /* vector layout */
 enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1, DDAMG_WCYCLE = 2 };  /* Alg. 2 / Alg. 1 / Alg. 1 with
                                                                  two coarse cycles per level */
@@ -190,6 +195,21 @@ typedef struct {
                                  ddamg_solve_stats.t_level_s; costs a few
                                  microseconds per level change.  Not with
                                  graph = 1 (the times stay 0).  0: off. */
+  int half_spinors;           /* 1: the fine-level vectors of the solve's
+                                 preconditioner (the cycle's right-hand side
+                                 and its result, which the SAP colour passes,
+                                 the restriction and the prolongation read
+                                 and write) are stored in FP16 with one FP32
+                                 scale per site, like half_directions (which
+                                 it implies), and the arithmetic stays FP32.
+                                 The FP16 storage of links and spinors that
+                                 halves the bytes of the smoother (Sec. 3
+                                 puts the whole preconditioner in single
+                                 precision; going to half precision storage
+                                 is this library's).  Needs precond_prec =
+                                 DDAMG_F32, half_storage = 1, mu = 0 and
+                                 graph = 0; the setup keeps FP32 vectors.
+                                 0 (default): FP32 vectors. */
 } ddamg_params;
 
 typedef struct {

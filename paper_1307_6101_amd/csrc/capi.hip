@@ -38,9 +38,17 @@ int ddamg::guarded_call(void (*f)(void*), void* arg) {
 
 namespace {
 
-void check_prec(int prec) {
-  DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32 || prec == DDAMG_F16,
-             "prec must be DDAMG_F64, DDAMG_F32 or DDAMG_F16");
+void check_prec(int prec, bool f16s = false) {
+  DD_REQUIRE(prec == DDAMG_F64 || prec == DDAMG_F32 || prec == DDAMG_F16 || (f16s && prec == DDAMG_F16S),
+             f16s ? "prec must be DDAMG_F64, DDAMG_F32, DDAMG_F16 or DDAMG_F16S"
+                  : "prec must be DDAMG_F64, DDAMG_F32 or DDAMG_F16");
+}
+// DDAMG_F16S: level 0, canonical layout, a hierarchy with FP16 spinors
+void check_f16s(const Hierarchy& H, int prec, int level, int layout) {
+  if (prec != DDAMG_F16S) return;
+  DD_REQUIRE(H.hs, "DDAMG_F16S needs a hierarchy built with half_spinors = 1");
+  DD_REQUIRE(level == 0, "DDAMG_F16S applies to level 0");
+  DD_REQUIRE(layout == DDAMG_CANONICAL, "DDAMG_F16S takes the canonical layout");
 }
 // DDAMG_F16 on a hierarchy: its FP32 level operations read the FP16 copies
 // of the operator data, which exist when it was built with half_storage
@@ -167,6 +175,85 @@ void sap_impl(Hierarchy& H, int level, const void* b, void* z, int nsweeps, int 
   }
 }
 
+// Level calls on FP16 fine spinors (DDAMG_F16S): the canonical FP64 fields
+// are converted to native FP64 and encoded into the hierarchy's FP16
+// buffers, and the results decoded back, a batch of at most params.batch
+// at a time
+template <typename F> void f16s_chunks(Hierarchy& H, int nrhs, F&& f) {
+  const int cap = std::min(nrhs, H.p.batch);
+  H.ensure_work<float>(cap);
+  H.ensure_hs(cap);
+  const long long n = H.lv[0].n;
+  double2* a = hier_scratch<double>(H, 0, n * cap);
+  double2* c = hier_scratch<double>(H, 1, n * cap);
+  for (int r0 = 0; r0 < nrhs; r0 += cap) f(r0, std::min(cap, nrhs - r0), a, c);
+}
+
+void sap_f16s(Hierarchy& H, const void* b, void* z, int nsweeps, int nrhs) {
+  const FineGeom& g = H.ctx->g;
+  const long long n = H.lv[0].n;
+  f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2*) {
+    fine_to_native<double>(g, static_cast<const double2*>(b) + r0 * n, a, nb, H.s);
+    encode_h<double>(g, a, H.h16a.p, H.h16as.p, nb, H.s);
+    fine_to_native<double>(g, static_cast<const double2*>(z) + r0 * n, a, nb, H.s);
+    encode_h<double>(g, a, H.h16b.p, H.h16bs.p, nb, H.s);
+    H.sap_hs(H.h16a.p, H.h16as.p, H.h16b.p, H.h16bs.p, nsweeps, nb);
+    decode_h<double>(g, H.h16b.p, H.h16bs.p, a, nb, H.s);
+    fine_from_native<double>(g, a, static_cast<double2*>(z) + r0 * n, nb, H.s);
+  });
+}
+
+void restrict_f16s(Hierarchy& H, const void* fine, void* coarse, int nrhs) {
+  const FineGeom& g = H.ctx->g;
+  const long long n = H.lv[0].n, nc = H.lv[1].n;
+  f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2* c) {
+    fine_to_native<double>(g, static_cast<const double2*>(fine) + r0 * n, a, nb, H.s);
+    encode_h<double>(g, a, H.h16a.p, H.h16as.p, nb, H.s);
+    float2* cf = reinterpret_cast<float2*>(c);
+    H.restrict_hs(H.h16a.p, H.h16as.p, cf, nb);
+    vcopy<float, double>(cf, static_cast<double2*>(coarse) + r0 * nc, nc * nb, H.s);
+  });
+}
+
+void prolong_f16s(Hierarchy& H, const void* coarse, void* fine, int nrhs) {
+  const FineGeom& g = H.ctx->g;
+  const long long n = H.lv[0].n, nc = H.lv[1].n;
+  f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2* c) {
+    float2* cf = reinterpret_cast<float2*>(c);
+    vcopy<double, float>(static_cast<const double2*>(coarse) + r0 * nc, cf, nc * nb, H.s);
+    H.prolong_hs(cf, H.h16b.p, H.h16bs.p, nb);
+    // fine += the decoded FP16 result
+    decode_h<double>(g, H.h16b.p, H.h16bs.p, a, nb, H.s);
+    fine_from_native<double>(g, a, c, nb, H.s);
+    vadd<double>(c, static_cast<double2*>(fine) + r0 * n, n * nb, H.s);
+  });
+}
+
+// the solve's preconditioner on a hierarchy with FP16 spinors: b encoded,
+// the FP16 cycle, z decoded (T: the precision of native-layout fields)
+template <typename T>
+void precondition_hs(Hierarchy& H, const void* b, void* z, int nrhs, int layout) {
+  const FineGeom& g = H.ctx->g;
+  const long long n = H.lv[0].n;
+  f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2*) {
+    std::fill(H.kc_it.begin(), H.kc_it.end(), 0);
+    std::fill(H.cs_it.begin(), H.cs_it.end(), 0);
+    if (layout == DDAMG_NATIVE) {
+      encode_h<T>(g, static_cast<const C<T>*>(b) + r0 * n, H.h16a.p, H.h16as.p, nb, H.s);
+    } else {
+      fine_to_native<double>(g, static_cast<const double2*>(b) + r0 * n, a, nb, H.s);
+      encode_h<double>(g, a, H.h16a.p, H.h16as.p, nb, H.s);
+    }
+    H.cycle_hs(H.h16a.p, H.h16as.p, H.h16b.p, H.h16bs.p, nb);
+    if (layout == DDAMG_NATIVE) {
+      decode_h<T>(g, H.h16b.p, H.h16bs.p, static_cast<C<T>*>(z) + r0 * n, nb, H.s);
+    } else {
+      decode_h<double>(g, H.h16b.p, H.h16bs.p, a, nb, H.s);
+      fine_from_native<double>(g, a, static_cast<double2*>(z) + r0 * n, nb, H.s);
+    }
+  });
+}
+
 template <typename T>
 void precondition_impl(Hierarchy& H, const void* b, void* z, int nrhs, int layout) {
   const long long n = H.lv[0].n;
@@ -228,6 +315,7 @@ void ddamg_params_default(ddamg_params* p, int levels) {
   p->coarse_dense = 1;
   p->galerkin_cols = 0;
   p->profile_levels = 0;
+  p->half_spinors = 0;
 }
 
 int ddamg_create(const ddamg_lattice* lat, const void* links, void* stream, ddamg_ctx* out) {
@@ -403,11 +491,13 @@ int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, i
     const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
-    check_prec(prec);
+    check_prec(prec, true);
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    if (prec == DDAMG_F64) restrict_impl<double>(H, level, fine, coarse, nrhs, layout);
+    check_f16s(H, prec, level, layout);
+    if (prec == DDAMG_F16S) restrict_f16s(H, fine, coarse, nrhs);
+    else if (prec == DDAMG_F64) restrict_impl<double>(H, level, fine, coarse, nrhs, layout);
     else restrict_impl<float>(H, level, fine, coarse, nrhs, layout);
   });
 }
@@ -419,11 +509,13 @@ int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, in
     const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "level out of range");
     DD_REQUIRE(fine && coarse && nrhs >= 1, "bad argument");
-    check_prec(prec);
+    check_prec(prec, true);
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    if (prec == DDAMG_F64) prolong_impl<double>(H, level, coarse, fine, nrhs, layout);
+    check_f16s(H, prec, level, layout);
+    if (prec == DDAMG_F16S) prolong_f16s(H, coarse, fine, nrhs);
+    else if (prec == DDAMG_F64) prolong_impl<double>(H, level, coarse, fine, nrhs, layout);
     else prolong_impl<float>(H, level, coarse, fine, nrhs, layout);
   });
 }
@@ -435,11 +527,13 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
     const WorkspaceScope wsc(H.ws.get());
     DD_REQUIRE(level >= 0 && level < H.L - 1, "SAP is defined on levels 0..L-2");
     DD_REQUIRE(b && z && b != z && nrhs >= 1 && nsweeps >= 0, "bad argument");
-    check_prec(prec);
+    check_prec(prec, true);
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    if (prec == DDAMG_F64) sap_impl<double>(H, level, b, z, nsweeps, nrhs, layout);
+    check_f16s(H, prec, level, layout);
+    if (prec == DDAMG_F16S) sap_f16s(H, b, z, nsweeps, nrhs);
+    else if (prec == DDAMG_F64) sap_impl<double>(H, level, b, z, nsweeps, nrhs, layout);
     else sap_impl<float>(H, level, b, z, nsweeps, nrhs, layout);
   });
 }
@@ -452,6 +546,7 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
     check_layout(layout);
     H.s = as_stream(stream);
     if (H.p.precond_prec == DDAMG_F64) precondition_impl<double>(H, b, z, nrhs, layout);
+    else if (H.hs) precondition_hs<float>(H, b, z, nrhs, layout);
     else precondition_impl<float>(H, b, z, nrhs, layout);
   });
 }

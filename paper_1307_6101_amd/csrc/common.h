@@ -90,6 +90,12 @@ template <> struct Load<float, float2> {
 template <> struct Load<float, __half2> {
   static __device__ inline float2 f(const __half2& v) { return __half22float2(v); }
 };
+template <> struct Load<double, __half2> {
+  static __device__ inline double2 f(const __half2& v) {
+    const float2 t = __half22float2(v);
+    return make_double2(t.x, t.y);
+  }
+};
 template <typename T, typename S> __device__ inline C<T> ldc(const S& v) { return Load<T, S>::f(v); }
 // zero of a storage type (__half2's default constructor leaves it unset)
 template <typename S> __device__ inline S szero();

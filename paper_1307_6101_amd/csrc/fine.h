@@ -131,6 +131,12 @@ template <typename T, typename S>
 void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour, int mr_iters,
                 const C<T>* b, C<T>* z, hipStream_t s, int nb = 1);
 
+// The same pass with FP16 operator data and FP16 spinors b, z with one FP32
+// scale per site (the layout of encode_sites below; bs, zs the scales); z
+// is re-encoded with each updated site's new scale
+void sap_colour_hs(const FineOpView<float, __half2>& op, const int* colour_blocks, int colour, int mr_iters,
+                   const __half2* b, const float* bs, __half2* z, float* zs, hipStream_t s, int nb = 1);
+
 // FP64 -> FP16 copy of n complex numbers (operator storage)
 void to_half(const double2* in, __half2* out, long long n, hipStream_t s);
 
@@ -141,6 +147,11 @@ void to_half(const double2* in, __half2* out, long long n, hipStream_t s);
 // for).
 void encode_sites(const FineGeom& g, const float2* in, __half2* half, float* scale, double2* dec, int nb,
                   hipStream_t s);
+// native fields at precision T <-> that FP16 form (no decoded copy)
+template <typename T>
+void encode_h(const FineGeom& g, const C<T>* in, __half2* half, float* scale, int nb, hipStream_t s);
+template <typename T>
+void decode_h(const FineGeom& g, const __half2* half, const float* scale, C<T>* out, int nb, hipStream_t s);
 
 // out = Gamma5 in for nb native fine fields (spins 3 and 4, components
 // 6..11, change sign; in == out allowed)

@@ -500,15 +500,15 @@ template <typename T> __device__ inline void pin12(C<T> (&acc)[12]) {
 // block's current z is staged in LDS (rs, [12][256], the site at column t):
 // of the two neighbours in direction MU one lies in the block and is read
 // from LDS, the other from memory.
-template <typename T, typename S, int MU>
-__device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const C<T>* __restrict__ in, const C<T>* rs, int t,
-                                   int blk, int loc, const Nbr8& nb8, C<T> (&acc)[12]) {
+template <typename T, typename S, typename V, int MU>
+__device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const V* __restrict__ in, const float* __restrict__ ins,
+                                   const C<T>* rs, int t, int blk, int loc, const Nbr8& nb8, C<T> (&acc)[12]) {
   constexpr int bit = 1 << MU;
   const bool up = loc & bit;   // the forward neighbour is outside the block
   C<T> psi[12], u[9];
   // forward: psi(x+mu), U_mu(x)
   if (up) {
-    load_spinor<T>(in, nb8.v[2 * MU], loc ^ bit, psi);
+    load_site<T, V>(in, ins, nb8.v[2 * MU], loc ^ bit, psi);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
@@ -521,18 +521,20 @@ __device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const C<T>* __res
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
   } else {
-    load_spinor<T>(in, nb, loc ^ bit, psi);
+    load_site<T, V>(in, ins, nb, loc ^ bit, psi);
   }
   load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
   hop_apply<T, MU, false>(psi, u, acc);
   pin12<T>(acc);
 }
 
-// one workgroup per (chunk of 16 blocks, field of the batch), gx chunks
-template <typename T, typename S>
+// one workgroup per (chunk of 16 blocks, field of the batch), gx chunks;
+// b and z in spinor storage V (bs, zs: their site scales for FP16)
+template <typename T, typename S, typename V>
 __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const int* __restrict__ cblk,
-                                                    int ncb, int mr_iters, const C<T>* __restrict__ b,
-                                                    C<T>* __restrict__ z, int nb, long long fs, int gx) {
+                                                    int ncb, int mr_iters, const V* __restrict__ b,
+                                                    const float* __restrict__ bs, V* __restrict__ z,
+                                                    float* __restrict__ zs, int nb, long long fs, int gx) {
   __shared__ C<T> rs[12 * 256];
   constexpr bool CL = ClLds<S>::value;
   __shared__ S cl[CL ? 36 * 256 : 1];
@@ -541,6 +543,11 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
   xcd_slab_rhs(blockIdx.x, gx, nb, xw, rw);
   b += (long long)rw * fs;
   z += (long long)rw * fs;
+  constexpr bool HS = std::is_same<V, __half2>::value;
+  if constexpr (HS) {
+    bs += (long long)rw * (fs / 12);
+    zs += (long long)rw * (fs / 12);
+  }
   const int jb = xw * 16 + (t >> 4);
   const int loc = t & 15;
   const bool valid = jb < ncb;
@@ -559,7 +566,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
     // from there, the other neighbours from memory
     {
       C<T> zz[12];
-      if (valid) load_spinor<T>(z, blk, loc, zz);
+      if (valid) load_site<T, V>(z, zs, blk, loc, zz);
       else
 #pragma unroll
         for (int c = 0; c < 12; ++c) zz[c] = czero<T>();
@@ -572,16 +579,16 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       C<T> acc[12], zz[12], dz[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-      sap_hops_mu<T, S, 0>(op, z, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, 1>(op, z, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, 2>(op, z, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, 3>(op, z, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, V, 0>(op, z, zs, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, V, 1>(op, z, zs, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, V, 2>(op, z, zs, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, V, 3>(op, z, zs, rs, t, blk, loc, nb8, acc);
 #pragma unroll
       for (int c = 0; c < 12; ++c) zz[c] = rs[c * 256 + t];
       if constexpr (CL) clover_mul<T>([&](int e) { return ldc<T, S>(cl[e * 256 + t]); }, zz, dz);
       else clover_apply<T, S>(op.A, blk, loc, zz, dz);
       C<T> bb[12];
-      load_spinor<T>(b, blk, loc, bb);
+      load_site<T, V>(b, bs, blk, loc, bb);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         rho[c].x = bb[c].x - dz[c].x + T(0.5) * acc[c].x;
@@ -640,9 +647,18 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       __syncthreads();
     }
     if (valid) {
-      C<T>* p = z + (long long)blk * 192 + loc;
+      if constexpr (HS) {
+        // z + x re-encoded with the site's new scale
+        C<T> zz[12];
+        load_site<T, V>(z, zs, blk, loc, zz);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
+        for (int c = 0; c < 12; ++c) zz[c] = cadd(zz[c], x[c]);
+        store_site<T, V>(z, zs, blk, loc, zz);
+      } else {
+        C<T>* p = z + (long long)blk * 192 + loc;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
+      }
     }
   }
 }
@@ -654,8 +670,18 @@ void sap_colour(const FineOpView<T, S>& op, const int* colour_blocks, int colour
   const int ncb = op.nblk / 2;
   const long long fs = (long long)op.nblk * 192;
   const unsigned gx = nblocks(ncb, 16);
-  k_sap_colour<T, S><<<gx * nb, 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, z, nb, fs,
-                                             (int)gx);
+  k_sap_colour<T, S, C<T>><<<gx * nb, 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters, b, nullptr,
+                                                   z, nullptr, nb, fs, (int)gx);
+  DD_LAUNCH_CHECK();
+}
+
+void sap_colour_hs(const FineOpView<float, __half2>& op, const int* colour_blocks, int colour, int mr_iters,
+                   const __half2* b, const float* bs, __half2* z, float* zs, hipStream_t s, int nb) {
+  const int ncb = op.nblk / 2;
+  const long long fs = (long long)op.nblk * 192;
+  const unsigned gx = nblocks(ncb, 16);
+  k_sap_colour<float, __half2, __half2><<<gx * nb, 256, 0, s>>>(op, colour_blocks + colour * ncb, ncb, mr_iters,
+                                                                b, bs, z, zs, nb, fs, (int)gx);
   DD_LAUNCH_CHECK();
 }
 
@@ -739,5 +765,44 @@ void encode_sites(const FineGeom& g, const float2* in, __half2* half, float* sca
   k_encode_sites<<<dim3(nblocks((size_t)g.nblk * 16, 256), nb), 256, 0, s>>>(in, half, scale, dec, g.nblk);
   DD_LAUNCH_CHECK();
 }
+
+template <typename T>
+__global__ void k_encode_h(const C<T>* __restrict__ in, __half2* __restrict__ half, float* __restrict__ scale,
+                           int nblk) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15;
+  if (blk >= nblk) return;
+  const long long fs = (long long)nblk * 192, ss = (long long)nblk * 16, r = blockIdx.y;
+  C<T> v[12];
+  load_spinor<T>(in + r * fs, blk, loc, v);
+  store_site<T, __half2>(half + r * fs, scale + r * ss, blk, loc, v);
+}
+template <typename T>
+__global__ void k_decode_h(const __half2* __restrict__ half, const float* __restrict__ scale, C<T>* __restrict__ out,
+                           int nblk) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15;
+  if (blk >= nblk) return;
+  const long long fs = (long long)nblk * 192, ss = (long long)nblk * 16, r = blockIdx.y;
+  C<T> v[12];
+  load_site<T, __half2>(half + r * fs, scale + r * ss, blk, loc, v);
+  C<T>* o = out + r * fs + (long long)blk * 192 + loc;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) o[c * 16] = v[c];
+}
+template <typename T>
+void encode_h(const FineGeom& g, const C<T>* in, __half2* half, float* scale, int nb, hipStream_t s) {
+  k_encode_h<T><<<dim3(nblocks((size_t)g.nblk * 16, 256), nb), 256, 0, s>>>(in, half, scale, g.nblk);
+  DD_LAUNCH_CHECK();
+}
+template <typename T>
+void decode_h(const FineGeom& g, const __half2* half, const float* scale, C<T>* out, int nb, hipStream_t s) {
+  k_decode_h<T><<<dim3(nblocks((size_t)g.nblk * 16, 256), nb), 256, 0, s>>>(half, scale, out, g.nblk);
+  DD_LAUNCH_CHECK();
+}
+template void encode_h<double>(const FineGeom&, const double2*, __half2*, float*, int, hipStream_t);
+template void encode_h<float>(const FineGeom&, const float2*, __half2*, float*, int, hipStream_t);
+template void decode_h<double>(const FineGeom&, const __half2*, const float*, double2*, int, hipStream_t);
+template void decode_h<float>(const FineGeom&, const __half2*, const float*, float2*, int, hipStream_t);
 
 }  // namespace ddamg

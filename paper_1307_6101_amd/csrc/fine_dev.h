@@ -91,6 +91,42 @@ __device__ inline void load_spinor(const S* __restrict__ f, int blk, int loc, C<
 #pragma unroll
   for (int c = 0; c < 12; ++c) v[c] = ldc<T, S>(p[c * 16]);
 }
+// A fine spinor field of storage V: complex numbers of the arithmetic
+// precision (V = C<T>), or FP16 (V = __half2), each site's 12 components
+// divided by their largest |re|, |im|, which is kept in FP32 per site
+// ([field][nblk * 16], native site order) next to them.  load_site /
+// store_site read and write one site in either form; the scale pointer is
+// not used for V = C<T>.
+template <typename T, typename V>
+__device__ inline void load_site(const V* __restrict__ f, const float* __restrict__ sc, int blk, int loc,
+                                 C<T> v[12]) {
+  load_spinor<T, V>(f, blk, loc, v);
+  if constexpr (std::is_same<V, __half2>::value) {
+    const T m = sc[(long long)blk * 16 + loc];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      v[c].x *= m;
+      v[c].y *= m;
+    }
+  }
+}
+template <typename T, typename V>
+__device__ inline void store_site(V* __restrict__ f, float* __restrict__ sc, int blk, int loc, const C<T> v[12]) {
+  V* p = f + (long long)blk * 192 + loc;
+  if constexpr (std::is_same<V, __half2>::value) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].x), fabsf((float)v[c].y)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    sc[(long long)blk * 16 + loc] = m;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c * 16] = __floats2half2_rn((float)v[c].x * inv, (float)v[c].y * inv);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c * 16] = v[c];
+  }
+}
+
 template <typename T, typename S = C<T>>
 __device__ inline void load_link(const S* __restrict__ U, int blk, int loc, int mu, C<T> u[9]) {
   const S* p = U + (long long)blk * 576 + mu * 144 + loc;

@@ -116,6 +116,14 @@ struct Hierarchy {
   // (live in every enclosing FGMRES), so its record may be overwritten
   std::vector<char> visit;
   bool half = false;               // FP16 operator storage for the FP32 levels
+  // FP16 fine-level spinors of the solve's preconditioner (half_spinors):
+  // two batches of fields [cap][n0] with their site scales [cap][V0], the
+  // cycle's right-hand side (a) and a result for the level calls (b)
+  bool hs = false;
+  int hcap = 0;
+  DevArray<__half2> h16a, h16b;
+  DevArray<float> h16as, h16bs;
+  void ensure_hs(int nb);
   int ocap = 0;                    // batch capacity of the outer solver's buffers
   std::vector<long long> kc_it, cs_it;   // per system of the batch: K-cycle / coarsest iterations
   const double2* tv_extra = nullptr;
@@ -185,6 +193,15 @@ struct Hierarchy {
   // every system keeps its own Krylov scalars and stopping test, so the
   // result for each equals that of a solve on its own.
   template <typename T> void cycle(int l, const C<T>* b, C<T>* z, int nb = 1);
+  // the part of the cycle below level l: work<T>(l+1).bin -> work<T>(l+1).z
+  template <typename T> void coarse_correction(int l, int nb);
+  // the level-0 cycle and its pieces on FP16 fine spinors with site scales
+  // (b, bs: right-hand side; z, zs: result), FP32 arithmetic on FP16
+  // operator data; the coarse levels run as in cycle<float>
+  void cycle_hs(const __half2* b, const float* bs, __half2* z, float* zs, int nb);
+  void sap_hs(const __half2* b, const float* bs, __half2* z, float* zs, int nsweeps, int nb);
+  void restrict_hs(const __half2* fine, const float* fs, C<float>* coarse, int nb);
+  void prolong_hs(const C<float>* coarse, __half2* fine, float* fs, int nb);   // fine = P coarse
   // Coarsest solve (odd-even reduced GMRES) with the GMRES scalars on the
   // device: with poll > 0 the host reads the device's liveness flag (a
   // round trip each) first after max(poll, pred_steps) steps, then every

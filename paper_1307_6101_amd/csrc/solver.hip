@@ -714,6 +714,14 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
   } else {
     restrict_to<T>(l, b, Wc.bin.p, nb);
   }
+  coarse_correction<T>(l, nb);
+  prolong_add<T>(l, Wc.z.p, z, nb);
+  if (p.nu > 0) sap<T>(l, b, z, p.nu, nb);
+  lt_pop();
+}
+
+template <typename T> void Hierarchy::coarse_correction(int l, int nb) {
+  Work<T>& Wc = work<T>(l + 1);
   if (l + 1 == L - 1) {
     // under graph capture the fixed launch sequence, else with the host
     // reading the device's liveness flag
@@ -746,8 +754,54 @@ template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int n
     for (int r = 0; r < nb; ++r)
       if (visit[r]) vcopy<T, T>(Wc.z.p + r * nc, Wc.rec.p + r * nc, nc, s);
   }
-  prolong_add<T>(l, Wc.z.p, z, nb);
-  if (p.nu > 0) sap<T>(l, b, z, p.nu, nb);
+}
+
+// ---------------------------------------------------------------------------
+// the level-0 cycle on FP16 fine spinors (mu = 0: restriction of b, the
+// coarse correction, z = P e, then the post-smoothing SAP sweeps)
+// ---------------------------------------------------------------------------
+void Hierarchy::ensure_hs(int nb) {
+  if (hcap >= nb) return;
+  const size_t n0 = (size_t)lv[0].n * nb, v0 = (size_t)lv[0].V * nb;
+  h16a.alloc(n0);
+  h16b.alloc(n0);
+  h16as.alloc(v0);
+  h16bs.alloc(v0);
+  hcap = nb;
+}
+
+void Hierarchy::restrict_hs(const __half2* fine, const float* fsc, C<float>* coarse, int nb) {
+  const LevelStore& L_ = lv[0];
+  // FP16 P and fine field (plus a scale per site), FP32 coarse field
+  meter(L_.N * (double)L_.n * 4.0 + ((double)L_.n * 4.0 + L_.V * 4.0 + 2.0 * L_.N * lv[1].V * 8.0) * nb,
+        8.0 * L_.N * (double)L_.n * nb);
+  restrict_fine_hs(ctx->g, L_.at, L_.ad(), L_.N, L_.P16.p, fine, fsc, coarse, s, nb);
+}
+
+void Hierarchy::prolong_hs(const C<float>* coarse, __half2* fine, float* fsc, int nb) {
+  const LevelStore& L_ = lv[0];
+  meter(L_.N * (double)L_.n * 4.0 + ((double)L_.n * 4.0 + L_.V * 4.0 + 2.0 * L_.N * lv[1].V * 8.0) * nb,
+        8.0 * L_.N * (double)L_.n * nb);
+  prolong_fine_hs(ctx->g, L_.at, L_.ad(), L_.N, L_.P16.p, coarse, fine, fsc, s, nb);
+}
+
+void Hierarchy::sap_hs(const __half2* b, const float* bs, __half2* z, float* zs, int nsweeps, int nb) {
+  // per sweep: b, z in, z out (36 FP16 complex and 3 scales per site and
+  // field), FP16 links and clover (72 complex)
+  const double V = (double)lv[0].V;
+  meter(nsweeps * V * ((36 * 4.0 + 12.0) * nb + 72 * 4.0), nsweeps * (1870.0 + p.mr_iters * 2280.0) * V * nb);
+  for (int it = 0; it < nsweeps; ++it)
+    for (int col = 0; col < 2; ++col) sap_colour_hs(ctx->view16(), ctx->cblk.p, col, p.mr_iters, b, bs, z, zs, s, nb);
+}
+
+void Hierarchy::cycle_hs(const __half2* b, const float* bs, __half2* z, float* zs, int nb) {
+  lt_push(0);
+  Work<float>& Wc = work<float>(1);
+  DD_REQUIRE(nb <= Wc.cap && nb <= hcap, "batch larger than the work buffers");
+  restrict_hs(b, bs, Wc.bin.p, nb);
+  coarse_correction<float>(0, nb);
+  prolong_hs(Wc.z.p, z, zs, nb);
+  if (p.nu > 0) sap_hs(b, bs, z, zs, p.nu, nb);
   lt_pop();
 }
 
@@ -773,7 +827,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
   double2* V = oV.p;
   C<T>* Z = outerZ<T>(*this).p;
   // FP16 directions with per-site scales (FP16 storage, FP32 cycle)
-  const bool zh = std::is_same<T, float>::value && p.half_directions == 1;
+  const bool zh = std::is_same<T, float>::value && (p.half_directions == 1 || hs);
   gm_reset(gm(), nb, s);
   double2* w = ow.p;
   std::vector<double> bnorm, beta, target(nb), scale(nb);
@@ -842,6 +896,14 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       } else if constexpr (std::is_same<T, double>::value) {
         cycle<double>(0, Vj, Zj, nb);
         applyD64(Zj, w);
+      } else if (hs) {
+        // FP16 fine spinors: the cycle writes the stored direction itself
+        __half2* zj = oZ16.p + (size_t)j * vs;
+        float* zjs = oZs.p + (size_t)j * nb * ctx->g.V;
+        encode_h<double>(ctx->g, Vj, h16a.p, h16as.p, nb, s);
+        cycle_hs(h16a.p, h16as.p, zj, zjs, nb);
+        decode_h<double>(ctx->g, zj, zjs, ot.p, nb, s);
+        applyD64(ot.p, w);
       } else if (zh) {
         vcopy<double, T>(Vj, W0.bin.p, vs, s);
         cycle<T>(0, W0.bin.p, W0.x.p, nb);
@@ -982,7 +1044,8 @@ template <typename T> void Hierarchy::ensure_batch(int nb) {
   ox.alloc(n0);
   if (std::is_same<T, float>::value) {
     // FP16 preconditioned directions with one FP32 scale per site
-    if (p.half_directions == 1) {
+    if (hs) ensure_hs(nb);
+    if (p.half_directions == 1 || hs) {
       oZ16.alloc((size_t)p.nkv * n0);
       oZs.alloc((size_t)p.nkv * nb * ctx->g.V);
     } else {
@@ -1178,6 +1241,11 @@ void validate_params(const Context& ctx, const ddamg_params& p) {
   DD_REQUIRE(p.galerkin_cols == 0 || p.galerkin_cols == 1 || p.galerkin_cols == 4,
              "galerkin_cols must be 0, 1 or 4");
   DD_REQUIRE(p.profile_levels == 0 || p.profile_levels == 1, "profile_levels must be 0 or 1");
+  DD_REQUIRE(p.half_spinors == 0 || p.half_spinors == 1, "half_spinors must be 0 or 1");
+  DD_REQUIRE(p.half_spinors == 0 || (p.precond_prec == DDAMG_F32 && p.half_storage == 1),
+             "FP16 spinors need the FP32 preconditioner with FP16 operator storage (half_storage = 1)");
+  DD_REQUIRE(p.half_spinors == 0 || (p.mu == 0 && p.graph == 0),
+             "FP16 spinors need mu = 0 and graph = 0");
   DD_REQUIRE(p.graph == 0 || p.levels == 2 || p.cycle != DDAMG_KCYCLE,
              "a graph-captured preconditioner needs the V- or W-cycle (levels >= 3)");
   DD_REQUIRE(p.mu >= 0 && p.nu >= 0 && p.mr_iters >= 0 && p.n_inv >= 0, "negative iteration count");
@@ -1359,6 +1427,7 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
   H->s = s;
   H->tv_extra = tv_extra;
   H->half = pp->half_storage == 1;
+  H->hs = pp->half_spinors == 1;
   if (H->half) ctx->make_half(s);
   const WorkspaceScope scope(H->ws.get());
   H->layout();
@@ -1402,6 +1471,7 @@ void workspace_bytes(const ddamg_lattice* lat, const ddamg_params* pp, int nrhs_
     H.p = *pp;
     H.L = pp->levels;
     H.half = half;
+    H.hs = pp->half_spinors == 1;
     H.layout();
     H.reserve(nrhs_max);
   }

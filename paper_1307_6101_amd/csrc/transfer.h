@@ -43,6 +43,13 @@ void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int 
 template <typename T, typename S>
 void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
                   const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
+// the same with FP16 fine spinors with one FP32 scale per site (the form of
+// encode_sites) and FP16 interpolation: restriction reads them, prolongation
+// writes out = P in (it does not add) with new site scales
+void restrict_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
+                      const __half2* in, const float* ins, float2* out, hipStream_t s, int nb);
+void prolong_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
+                     const float2* in, __half2* out, float* outs, hipStream_t s, int nb);
 template <typename T, typename S>
 void restrict_coarse(const AggTables& a, const AggDev& ad, int d, int N, long long V,
                      const S* P, const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);

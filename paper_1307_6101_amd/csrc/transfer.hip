@@ -101,19 +101,23 @@ __device__ inline C<T> collect(const T* red, int N, int sigma, int k) {
 // each column of P is loaded once and applied to all of them.  Fine fields
 // of the batch are fstride apart, coarse fields cstride apart.
 // ---------------------------------------------------------------------------
-template <typename T, typename S, int RB>
+// the fine fields in spinor storage V (ins: their site scales for FP16)
+template <typename T, typename S, int RB, typename V = C<T>>
 __global__ void __launch_bounds__(256) k_restrict_fine(const int* __restrict__ members, int nbpa, int N, long long fstride,
-                                const S* __restrict__ P, const C<T>* __restrict__ in,
+                                const S* __restrict__ P, const V* __restrict__ in, const float* __restrict__ ins,
                                 C<T>* __restrict__ out, long long cstride) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);
   const int A = blockIdx.x, t = threadIdx.x;
   const int blk = members[A * nbpa + (t >> 4)], loc = t & 15;
+  const long long sstride = fstride / 12;
   in += (long long)blockIdx.y * RB * fstride;
+  if constexpr (std::is_same<V, __half2>::value) ins += (long long)blockIdx.y * RB * sstride;
   out += (long long)blockIdx.y * RB * cstride;
   C<T> v[RB][12];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) load_spinor<T>(in + r * fstride, blk, loc, v[r]);
+  for (int r = 0; r < RB; ++r)
+    load_site<T, V>(in + r * fstride, std::is_same<V, __half2>::value ? ins + r * sstride : nullptr, blk, loc, v[r]);
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
     load_spinor<T, S>(P + k * fstride, blk, loc, w);
@@ -143,24 +147,48 @@ void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int 
     constexpr int RB = decltype(rb)::value;
     const size_t sm = (size_t)((a.asz + 63) / 64) * RB * N * 4 * sizeof(T);
     k_restrict_fine<T, S, RB><<<dim3(a.nagg, nch), a.asz, sm, s>>>(ad.members, a.asz / 16, N, fs, P,
-                                                                   in + first * fs, out + first * cs, cs);
+                                                                   in + first * fs, nullptr, out + first * cs, cs);
   });
   DD_LAUNCH_CHECK();
 }
 
-template <typename T, typename S, int RB>
+void restrict_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
+                      const __half2* in, const float* ins, float2* out, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N, ss = (long long)g.nblk * 16;
+  rhs_chunks<float>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    const size_t sm = (size_t)((a.asz + 63) / 64) * RB * N * 4 * sizeof(float);
+    k_restrict_fine<float, __half2, RB, __half2><<<dim3(a.nagg, nch), a.asz, sm, s>>>(
+        ad.members, a.asz / 16, N, fs, P, in + first * fs, ins + first * ss, out + first * cs, cs);
+  });
+  DD_LAUNCH_CHECK();
+}
+
+// out += P in for V = C<T>; out = P in, encoded with new site scales
+// (outs), for FP16 spinors
+template <typename T, typename S, int RB, typename V = C<T>>
 __global__ void __launch_bounds__(256) k_prolong_fine(const int* __restrict__ blk_agg, int nblk, int N, long long fstride,
                                const S* __restrict__ P, const C<T>* __restrict__ in,
-                               C<T>* __restrict__ out, long long cstride) {
+                               V* __restrict__ out, float* __restrict__ outs, long long cstride) {
+  constexpr bool HS = std::is_same<V, __half2>::value;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= nblk) return;
+  const long long sstride = fstride / 12;
   in += (long long)blockIdx.y * RB * cstride;
   out += (long long)blockIdx.y * RB * fstride;
+  if constexpr (HS) outs += (long long)blockIdx.y * RB * sstride;
   const int A = blk_agg[blk];
   C<T> acc[RB][12];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) load_spinor<T>(out + r * fstride, blk, loc, acc[r]);
+  for (int r = 0; r < RB; ++r) {
+    if constexpr (HS) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[r][c] = czero<T>();
+    } else {
+      load_spinor<T>(out + r * fstride, blk, loc, acc[r]);
+    }
+  }
   for (int k = 0; k < N; ++k) {
     C<T> w[12];
     load_spinor<T, S>(P + k * fstride, blk, loc, w);
@@ -176,11 +204,7 @@ __global__ void __launch_bounds__(256) k_prolong_fine(const int* __restrict__ bl
     }
   }
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    C<T>* o = out + r * fstride + (long long)blk * 192 + loc;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) o[c * 16] = acc[r][c];
-  }
+  for (int r = 0; r < RB; ++r) store_site<T, V>(out + r * fstride, HS ? outs + r * sstride : nullptr, blk, loc, acc[r]);
 }
 
 template <typename T, typename S>
@@ -190,7 +214,18 @@ void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N
   rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
     constexpr int RB = decltype(rb)::value;
     k_prolong_fine<T, S, RB><<<dim3(nblocks((size_t)g.nblk * 16, 256), nch), 256, 0, s>>>(
-        ad.member_agg, g.nblk, N, fs, P, in + first * cs, out + first * fs, cs);
+        ad.member_agg, g.nblk, N, fs, P, in + first * cs, out + first * fs, nullptr, cs);
+  });
+  DD_LAUNCH_CHECK();
+}
+
+void prolong_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
+                     const float2* in, __half2* out, float* outs, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N, ss = (long long)g.nblk * 16;
+  rhs_chunks<float>(nb, [&](auto rb, int first, int nch) {
+    constexpr int RB = decltype(rb)::value;
+    k_prolong_fine<float, __half2, RB, __half2><<<dim3(nblocks((size_t)g.nblk * 16, 256), nch), 256, 0, s>>>(
+        ad.member_agg, g.nblk, N, fs, P, in + first * cs, out + first * fs, outs + first * ss, cs);
   });
   DD_LAUNCH_CHECK();
 }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddamg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-F64, F32, F16 = 0, 1, 2
+F64, F32, F16, F16S = 0, 1, 2, 3
 CANONICAL, NATIVE = 0, 1
 KCYCLE, VCYCLE, WCYCLE = 0, 1, 2
 
@@ -60,6 +60,7 @@ class Params(ctypes.Structure):
         ("coarse_dense", ctypes.c_int),
         ("galerkin_cols", ctypes.c_int),
         ("profile_levels", ctypes.c_int),
+        ("half_spinors", ctypes.c_int),
     ]
 
 

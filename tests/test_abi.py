@@ -54,8 +54,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(ddamg_params, half_storage), offsetof(ddamg_params, batch),
          offsetof(ddamg_params, sap_block_l), offsetof(ddamg_params, half_directions),
          offsetof(ddamg_params, graph));
-  printf("%zu %zu %zu\n", offsetof(ddamg_params, coarse_dense), offsetof(ddamg_params, galerkin_cols),
-         offsetof(ddamg_params, profile_levels));
+  printf("%zu %zu %zu %zu\n", offsetof(ddamg_params, coarse_dense), offsetof(ddamg_params, galerkin_cols),
+         offsetof(ddamg_params, profile_levels), offsetof(ddamg_params, half_spinors));
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(ddamg_solve_stats, err_vs_ref), offsetof(ddamg_solve_stats, t_setup_s),
          offsetof(ddamg_solve_stats, t_level_s), offsetof(ddamg_solve_stats, bytes),
          offsetof(ddamg_solve_stats, flops), offsetof(ddamg_solve_stats, coarsest_dense));
@@ -88,7 +88,8 @@ int main(void) {
     assert vals[18] == dd.Params.coarse_dense.offset
     assert vals[19] == dd.Params.galerkin_cols.offset
     assert vals[20] == dd.Params.profile_levels.offset
-    assert vals[21:27] == [dd.SolveStats.err_vs_ref.offset, dd.SolveStats.t_setup_s.offset,
+    assert vals[21] == dd.Params.half_spinors.offset
+    assert vals[22:28] == [dd.SolveStats.err_vs_ref.offset, dd.SolveStats.t_setup_s.offset,
                            dd.SolveStats.t_level_s.offset, dd.SolveStats.bytes.offset,
                            dd.SolveStats.flops.offset, dd.SolveStats.coarsest_dense.offset]
 
@@ -106,7 +107,7 @@ def test_params_default_is_table1(dd):
     assert p.half_storage == 0 and p.batch == 16 and p.half_directions == 0
     # beyond Tab. 1: host-driven coarsest GMRES, dense Schur product where small
     assert p.graph == 0 and p.coarse_dense == 1
-    assert p.galerkin_cols == 0 and p.profile_levels == 0
+    assert p.galerkin_cols == 0 and p.profile_levels == 0 and p.half_spinors == 0
 
 
 def test_host_validation_rejects_bad_lattice(dd):

@@ -44,6 +44,8 @@ DSLASH_F32_TRAFFIC_BYTES = 128.25e6
 # clover on the 48^3x96 lattice, from the FETCH_SIZE / WRITE_SIZE counter
 # runs summarised in profiles/ (None until taken for the current kernel)
 SAP_F16_PASS_TRAFFIC_BYTES = 6.241e9
+# the same for the pass on FP16 spinors (b, z with one FP32 scale per site)
+SAP_F16S_PASS_TRAFFIC_BYTES = None
 WORKLOAD = "clover16x32_3lvl"
 HEADLINE = "clover48x96_4lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
@@ -68,6 +70,9 @@ DPSI_SPINOR_REALS_PER_SITE = 48
 # clover (144 reals)
 SAP_REALS_PER_SITE = 216
 SAP_SPINOR_REALS_PER_SITE = 72
+# with FP16 spinors each of the three spinor reads / writes of a site also
+# moves its FP32 scale
+SAP_SCALE_BYTES_PER_SITE = 12
 
 
 def parse():
@@ -92,6 +97,10 @@ def parse():
                          "holds nothing but solves)")
     ap.add_argument("--no-levels", action="store_true",
                     help="skip the two- and three-level comparison on the headline lattice")
+    ap.add_argument("--fp32-spinors", action="store_true",
+                    help="FP32 fine-level spinors in the headline preconditioner (default: FP16 with site scales)")
+    ap.add_argument("--no-other-spinors", action="store_true",
+                    help="skip the solve with the other fine-spinor storage (and its per-level times)")
     ap.add_argument("--no-scan", action="store_true",
                     help="skip the short bare-mass scan (16^3x32, two and three levels against CGNR) "
                          "reported next to the default line")
@@ -458,9 +467,10 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def fill_params(dd, cfg, prec, half=False, batch=None, levels=None):
+def fill_params(dd, cfg, prec, half=False, batch=None, levels=None, spinors16=False, profile=False):
     """ddamg_params of a workload (Tab. 1 defaults otherwise); `levels` keeps
-    only the first levels of its hierarchy."""
+    only the first levels of its hierarchy; spinors16: FP16 fine-level
+    spinors in the preconditioner; profile: per-level GPU times."""
     L = cfg["levels"] if levels is None else levels
     p = dd.params_default(L)
     for l, a in enumerate(cfg["agg"][:L - 1]):
@@ -474,6 +484,8 @@ def fill_params(dd, cfg, prec, half=False, batch=None, levels=None):
     p.nu = cfg["nu"]
     p.precond_prec = prec
     p.half_storage = 1 if half else 0
+    p.half_spinors = 1 if spinors16 else 0
+    p.profile_levels = 1 if profile else 0
     if batch is not None:
         p.batch = batch
     return p
@@ -542,11 +554,12 @@ def headline_workload(args, dd, W, np, torch):
     z = torch.zeros_like(bd)
     log(f"[bench] inputs in {time.time() - t0:.1f}s")
 
-    def build(prec, half, levels=None):
+    def build(prec, half, levels=None, spinors16=False, profile=False):
         torch.cuda.synchronize()
         t = time.time()
-        H = dd.build_hierarchy(ctx, fill_params(dd, cfg, prec, half, batch=8, levels=levels), tvd,
-                               extra if (levels or cfg["levels"]) == 4 else None)
+        H = dd.build_hierarchy(ctx, fill_params(dd, cfg, prec, half, batch=8, levels=levels, spinors16=spinors16,
+                                                profile=profile),
+                               tvd, extra if (levels or cfg["levels"]) == 4 else None)
         torch.cuda.synchronize()
         return H, time.time() - t
 
@@ -557,8 +570,9 @@ def headline_workload(args, dd, W, np, torch):
             raise RuntimeError(f"solve failed rc={rc} {st}")
         return st[0]
 
-    H, t_setup = build(dd.F32, True)
-    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
+    spinors16 = not args.fp32_spinors
+    H, t_setup = build(dd.F32, True, spinors16=spinors16)
+    log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s (FP16 fine spinors: {spinors16})")
     for i in range(args.warmup):
         st = one_solve(H)
         log(f"[bench] warmup {i}: {st['outer_iters']} its, {st['seconds']:.3f}s")
@@ -609,6 +623,18 @@ def headline_workload(args, dd, W, np, torch):
     sweep_bytes = (SAP_SPINOR_REALS_PER_SITE * 4 + (SAP_REALS_PER_SITE - SAP_SPINOR_REALS_PER_SITE) * 2) * V
     kern["sap_colour_pass_f16store"] = dict(seconds=t_sap / 2, algorithmic_bytes=sweep_bytes / 2,
                                             gbs=sweep_bytes / t_sap / 1e9)
+    if spinors16:
+        # the pass the solve runs: b, z as FP16 with site scales (native form:
+        # entries, then scales, in one buffer)
+        hb = torch.empty(V * 12 + V, dtype=torch.float32, device=dev)
+        hz = torch.empty_like(hb)
+        dd.to_native(ctx, None, 0, bd, hb, prec=dd.F16S)
+        hz.zero_()
+        t_sh = time_launches(torch, lambda: dd.sap_smooth(H, 0, hb, hz, 1, prec=dd.F16S, layout=dd.NATIVE), reps)
+        sw16 = (SAP_REALS_PER_SITE * 2 + SAP_SCALE_BYTES_PER_SITE) * V
+        kern["sap_colour_pass_f16spinors"] = dict(seconds=t_sh / 2, algorithmic_bytes=sw16 / 2,
+                                                  gbs=sw16 / t_sh / 1e9)
+        del hb, hz
     t_d16 = time_launches(torch, lambda: dd.apply_Dc(H, 0, nat32, out32, prec=dd.F32, layout=dd.NATIVE), reps)
     d16 = (DPSI_SPINOR_REALS_PER_SITE * 4 + (DPSI_REALS_PER_SITE - DPSI_SPINOR_REALS_PER_SITE) * 2) * V
     kern["dslash_f16store"] = dict(seconds=t_d16, algorithmic_bytes=d16, gbs=d16 / t_d16 / 1e9)
@@ -649,13 +675,33 @@ def headline_workload(args, dd, W, np, torch):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
+    # the other spinor storage on the same lattice (FP16 operators), with the
+    # per-level GPU times of its solve (event marks where the work changes
+    # level: the consumed time per level of the paper's Tab. 4)
+    other = None
+    if not args.no_other_spinors:
+        Ho, t_o = build(dd.F32, True, spinors16=not spinors16, profile=True)
+        one_solve(Ho)
+        torch.cuda.synchronize()
+        to = time.time()
+        sto = one_solve(Ho)
+        torch.cuda.synchronize()
+        to = time.time() - to
+        other = dict(spinors="fp32" if spinors16 else "fp16", setup_s=round(t_o, 3), solve_s=round(to, 4),
+                     outer_iters=sto["outer_iters"], true_relres=sto["true_relres"],
+                     t_level_s=[round(x, 4) for x in sto["t_level_s"]])
+        log(f"[bench] {other['spinors']} spinors: solve {to:.3f}s, {sto['outer_iters']} its, "
+            f"per-level {other['t_level_s']}")
+        del Ho
+        torch.cuda.empty_cache()
+
     # fewer levels on the same lattice (mixed, FP16 storage), one solve each
     levels_cmp = None
     if not args.no_levels:
         levels_cmp = {"4": dict(setup_s=round(t_setup, 3), solve_s=round(ms / 1000.0, 4),
                                 outer_iters=mixed["outer_iters"])}
         for L in (3, 2):
-            Hl, t_l = build(dd.F32, True, levels=L)
+            Hl, t_l = build(dd.F32, True, levels=L, spinors16=spinors16)
             one_solve(Hl)
             torch.cuda.synchronize()
             tl = time.time()
@@ -702,11 +748,18 @@ def headline_workload(args, dd, W, np, torch):
                           ((3, None, "3lvl"), (2, None, "2lvl")), 1)
         scan = {"lattice": "16^3x32, eps=0.5, c_sw=1, tol 1e-10, b = D z*", "rows": rows}
 
-    dom = kern["sap_colour_pass_f16store"]
+    if spinors16:
+        dom = kern["sap_colour_pass_f16spinors"]
+        traffic = SAP_F16S_PASS_TRAFFIC_BYTES
+        kname = ("k_sap_colour<float, __half2, __half2> (one SAP colour pass, FP32 arithmetic on FP16 "
+                 "links, clover and spinors)")
+    else:
+        dom = kern["sap_colour_pass_f16store"]
+        traffic = SAP_F16_PASS_TRAFFIC_BYTES
+        kname = ("k_sap_colour<float, __half2, float2> (one SAP colour pass, FP32 arithmetic on FP16 "
+                 "links and clover)")
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": SAP_F16_PASS_TRAFFIC_BYTES,
-                "kernel": "k_sap_colour<float, __half2> (one SAP colour pass, FP32 arithmetic on FP16 "
-                          "links and clover)",
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
                 "us_per_launch": round(dom["seconds"] * 1e6, 2)}
 
@@ -726,7 +779,8 @@ def headline_workload(args, dd, W, np, torch):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 preconditioner on f16-stored operators, f64 outer",
+        "dtype": ("f32 preconditioner on f16-stored operators and fine spinors, f64 outer" if spinors16 else
+                  "f32 preconditioner on f16-stored operators, f64 outer"),
         "data": "synthetic (seeded SU(3) links exp(i eps H), one complex Gaussian rhs)",
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-clover, {cfg['levels']} levels "
                                f"(aggregates {aggs}, N={cfg['ntv']}, level-2 SAP blocks 3^4), c_sw={cfg['csw']}, "
@@ -739,6 +793,7 @@ def headline_workload(args, dd, W, np, torch):
         "oracle_sampled_max_site_relres": oracle_max,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (round(plain["time_to_solution_s"] / (ms / 1000.0), 3) if plain else None),
+        "other_spinor_storage": other,
         "levels_2_3_4": levels_cmp,
         "m0_scan_16x32": scan,
         "kernels": {k: dict({"us": round(v["seconds"] * 1e6, 2), "GB/s": round(v["gbs"], 1)},
@@ -899,7 +954,8 @@ def big_workload(args, name, cfg, dd, W, np, torch):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 preconditioner on f16-stored operators, f64 outer",
+        "dtype": ("f32 preconditioner on f16-stored operators and fine spinors, f64 outer" if spinors16 else
+                  "f32 preconditioner on f16-stored operators, f64 outer"),
         "data": "synthetic (seeded SU(3) links exp(i eps H), " + src + ")",
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-clover, {cfg['levels']} levels "
                                f"(aggregates {aggs}, N={cfg['ntv']}), c_sw={cfg['csw']}, eps={cfg['eps']}, "
@@ -918,7 +974,8 @@ def big_workload(args, name, cfg, dd, W, np, torch):
 def kernels_only(args, cfg, dd, W, np, torch):
     """The fine kernels alone, for hardware-counter runs: the Wilson-clover
     stencil in FP32 and FP64, one SAP sweep (two colour passes) on FP16-stored
-    links and clover and one in FP32, each from a cheap two-level hierarchy
+    links and clover, one in FP32 and one on FP16 links, clover and spinors,
+    each from a cheap two-level hierarchy
     (the fine smoother reads only the fine operator), and a 1 GiB device copy
     (the reference for scaling FETCH_SIZE / WRITE_SIZE counters)."""
     dims = tuple(int(x) for x in args.lattice.split(",")) if args.lattice else cfg["dims"]
@@ -960,6 +1017,24 @@ def kernels_only(args, cfg, dd, W, np, torch):
         out[name] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
         log(f"[bench] {name}: {t * 1e6:.1f} us per colour pass, {nbytes / t / 1e9:.0f} GB/s")
         del H
+    # the pass on FP16 spinors (native form: entries, then site scales)
+    p = dd.params_default(2)
+    p.ntv[0] = 2
+    p.n_inv = 0
+    p.precond_prec = dd.F32
+    p.half_storage = 1
+    p.half_spinors = 1
+    H = dd.build_hierarchy(ctx, p, tv)
+    hb = torch.empty(V * 13, dtype=torch.float32, device=dev)
+    hz = torch.zeros_like(hb)
+    dd.to_native(ctx, None, 0, bd, hb, prec=dd.F16S)
+    t = time_launches(torch, lambda: dd.sap_smooth(H, 0, hb, hz, 1, prec=dd.F16S, layout=dd.NATIVE),
+                      args.kernel_reps) / 2
+    nbytes = (SAP_REALS_PER_SITE * 2 + SAP_SCALE_BYTES_PER_SITE) * V / 2
+    out["sap_colour_pass_f16spinors"] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1),
+                                         "algorithmic_bytes": nbytes}
+    log(f"[bench] sap_colour_pass_f16spinors: {t * 1e6:.1f} us per colour pass, {nbytes / t / 1e9:.0f} GB/s")
+    del H, hb, hz
     # reference copy of known size: 1 GiB read + 1 GiB written
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)

@@ -79,10 +79,16 @@ enum {
  * preconditioner in single precision; the half-precision storage is this
  * library's); on a hierarchy it needs half_storage = 1. */
 /* F16S: F16 with the fine-level spinors too in binary16, one FP32 scale per
- * site (the storage of params.half_spinors); for ddamg_sap_smooth,
- * ddamg_restrict and ddamg_prolong on level 0 and ddamg_precondition, in
- * the canonical layout (the FP16 form exists only inside the library), on a
- * hierarchy built with half_spinors = 1. */
+ * site (the storage of params.half_spinors), for level 0 only: in
+ * ddamg_to_native / ddamg_from_native (canonical complex128 <-> the native
+ * FP16 form), and in ddamg_sap_smooth, ddamg_restrict (canonical or native
+ * layout) and ddamg_prolong (canonical layout; fine += the FP16-encoded
+ * P coarse) on a hierarchy built with half_spinors = 1.  The native FP16
+ * form of nrhs fine fields is one buffer: the entries of all fields
+ * ([nrhs][V/16][12][16] binary16 pairs (re, im), each site's 12 components
+ * divided by their largest |re|, |im|) followed by the site scales
+ * ([nrhs][V/16][16] float, that largest value); a restriction's coarse
+ * output is native FP32. */
 enum { DDAMG_F64 = 0, DDAMG_F32 = 1, DDAMG_F16 = 2, DDAMG_F16S = 3 };
 enum { DDAMG_CANONICAL = 0, DDAMG_NATIVE = 1 };   /* vector layout */
 enum { DDAMG_KCYCLE = 0, DDAMG_VCYCLE = 1, DDAMG_WCYCLE = 2 };  /* Alg. 2 / Alg. 1 / Alg. 1 with

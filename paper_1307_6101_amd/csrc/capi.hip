@@ -43,12 +43,13 @@ void check_prec(int prec, bool f16s = false) {
              f16s ? "prec must be DDAMG_F64, DDAMG_F32, DDAMG_F16 or DDAMG_F16S"
                   : "prec must be DDAMG_F64, DDAMG_F32 or DDAMG_F16");
 }
-// DDAMG_F16S: level 0, canonical layout, a hierarchy with FP16 spinors
-void check_f16s(const Hierarchy& H, int prec, int level, int layout) {
+// DDAMG_F16S: level 0 of a hierarchy with FP16 spinors; the native layout
+// where the call reads and writes only FP16 fine fields
+void check_f16s(const Hierarchy& H, int prec, int level, int layout, bool native_ok) {
   if (prec != DDAMG_F16S) return;
   DD_REQUIRE(H.hs, "DDAMG_F16S needs a hierarchy built with half_spinors = 1");
   DD_REQUIRE(level == 0, "DDAMG_F16S applies to level 0");
-  DD_REQUIRE(layout == DDAMG_CANONICAL, "DDAMG_F16S takes the canonical layout");
+  DD_REQUIRE(native_ok || layout == DDAMG_CANONICAL, "this DDAMG_F16S call takes the canonical layout");
 }
 // DDAMG_F16 on a hierarchy: its FP32 level operations read the FP16 copies
 // of the operator data, which exist when it was built with half_storage
@@ -175,6 +176,18 @@ void sap_impl(Hierarchy& H, int level, const void* b, void* z, int nsweeps, int 
   }
 }
 
+// The native form of nrhs FP16 fine fields (DDAMG_F16S, DDAMG_NATIVE): the
+// FP16 entries of all fields ([nrhs][V/16][12][16] __half2) followed by their
+// site scales ([nrhs][V] float), in one buffer.
+struct HsPacked {
+  __half2* h;
+  float* s;
+};
+HsPacked hs_packed(const void* p, long long n0, int nrhs) {
+  __half2* h = static_cast<__half2*>(const_cast<void*>(p));
+  return HsPacked{h, reinterpret_cast<float*>(h + n0 * nrhs)};
+}
+
 // Level calls on FP16 fine spinors (DDAMG_F16S): the canonical FP64 fields
 // are converted to native FP64 and encoded into the hierarchy's FP16
 // buffers, and the results decoded back, a batch of at most params.batch
@@ -189,9 +202,14 @@ template <typename F> void f16s_chunks(Hierarchy& H, int nrhs, F&& f) {
   for (int r0 = 0; r0 < nrhs; r0 += cap) f(r0, std::min(cap, nrhs - r0), a, c);
 }
 
-void sap_f16s(Hierarchy& H, const void* b, void* z, int nsweeps, int nrhs) {
+void sap_f16s(Hierarchy& H, const void* b, void* z, int nsweeps, int nrhs, int layout) {
   const FineGeom& g = H.ctx->g;
   const long long n = H.lv[0].n;
+  if (layout == DDAMG_NATIVE) {
+    const HsPacked pb = hs_packed(b, n, nrhs), pz = hs_packed(z, n, nrhs);
+    H.sap_hs(pb.h, pb.s, pz.h, pz.s, nsweeps, nrhs);
+    return;
+  }
   f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2*) {
     fine_to_native<double>(g, static_cast<const double2*>(b) + r0 * n, a, nb, H.s);
     encode_h<double>(g, a, H.h16a.p, H.h16as.p, nb, H.s);
@@ -203,9 +221,14 @@ void sap_f16s(Hierarchy& H, const void* b, void* z, int nsweeps, int nrhs) {
   });
 }
 
-void restrict_f16s(Hierarchy& H, const void* fine, void* coarse, int nrhs) {
+void restrict_f16s(Hierarchy& H, const void* fine, void* coarse, int nrhs, int layout) {
   const FineGeom& g = H.ctx->g;
   const long long n = H.lv[0].n, nc = H.lv[1].n;
+  if (layout == DDAMG_NATIVE) {
+    const HsPacked pf = hs_packed(fine, n, nrhs);
+    H.restrict_hs(pf.h, pf.s, static_cast<float2*>(coarse), nrhs);
+    return;
+  }
   f16s_chunks(H, nrhs, [&](int r0, int nb, double2* a, double2* c) {
     fine_to_native<double>(g, static_cast<const double2*>(fine) + r0 * n, a, nb, H.s);
     encode_h<double>(g, a, H.h16a.p, H.h16as.p, nb, H.s);
@@ -384,10 +407,18 @@ int ddamg_to_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in, v
                     int prec, void* stream) {
   return guarded([&] {
     DD_REQUIRE(ctx && ctx->c && in && out && nrhs >= 1, "bad argument");
-    check_prec(prec);
+    check_prec(prec, true);
+    DD_REQUIRE(prec != DDAMG_F16S || level == 0, "DDAMG_F16S applies to level 0");
     hipStream_t s = as_stream(stream);
     Context& c = *ctx->c;
-    if (level == 0) {
+    const WorkspaceScope wsc(c.ws.get());
+    if (prec == DDAMG_F16S) {
+      const long long n = c.g.V * 12;
+      double2* a = ctx_scratch<double>(c, 0, n * nrhs);
+      fine_to_native<double>(c.g, static_cast<const double2*>(in), a, nrhs, s);
+      const HsPacked po = hs_packed(out, n, nrhs);
+      encode_h<double>(c.g, a, po.h, po.s, nrhs, s);
+    } else if (level == 0) {
       if (prec == DDAMG_F64) fine_to_native<double>(c.g, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, s);
       else fine_to_native<float>(c.g, static_cast<const double2*>(in), static_cast<float2*>(out), nrhs, s);
     } else {
@@ -404,9 +435,19 @@ int ddamg_from_native(ddamg_ctx ctx, ddamg_hier hier, int level, const void* in,
                       int prec, void* stream) {
   return guarded([&] {
     DD_REQUIRE(ctx && ctx->c && in && out && nrhs >= 1, "bad argument");
-    check_prec(prec);
+    check_prec(prec, true);
+    DD_REQUIRE(prec != DDAMG_F16S || level == 0, "DDAMG_F16S applies to level 0");
     hipStream_t s = as_stream(stream);
     Context& c = *ctx->c;
+    const WorkspaceScope wsc(c.ws.get());
+    if (prec == DDAMG_F16S) {
+      const long long n = c.g.V * 12;
+      double2* a = ctx_scratch<double>(c, 0, n * nrhs);
+      const HsPacked pi = hs_packed(in, n, nrhs);
+      decode_h<double>(c.g, pi.h, pi.s, a, nrhs, s);
+      fine_from_native<double>(c.g, a, static_cast<double2*>(out), nrhs, s);
+      return;
+    }
     if (level == 0) {
       if (prec == DDAMG_F64) fine_from_native<double>(c.g, static_cast<const double2*>(in), static_cast<double2*>(out), nrhs, s);
       else fine_from_native<float>(c.g, static_cast<const float2*>(in), static_cast<double2*>(out), nrhs, s);
@@ -495,8 +536,8 @@ int ddamg_restrict(ddamg_hier hier, int level, const void* fine, void* coarse, i
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    check_f16s(H, prec, level, layout);
-    if (prec == DDAMG_F16S) restrict_f16s(H, fine, coarse, nrhs);
+    check_f16s(H, prec, level, layout, true);
+    if (prec == DDAMG_F16S) restrict_f16s(H, fine, coarse, nrhs, layout);
     else if (prec == DDAMG_F64) restrict_impl<double>(H, level, fine, coarse, nrhs, layout);
     else restrict_impl<float>(H, level, fine, coarse, nrhs, layout);
   });
@@ -513,7 +554,7 @@ int ddamg_prolong(ddamg_hier hier, int level, const void* coarse, void* fine, in
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    check_f16s(H, prec, level, layout);
+    check_f16s(H, prec, level, layout, false);
     if (prec == DDAMG_F16S) prolong_f16s(H, coarse, fine, nrhs);
     else if (prec == DDAMG_F64) prolong_impl<double>(H, level, coarse, fine, nrhs, layout);
     else prolong_impl<float>(H, level, coarse, fine, nrhs, layout);
@@ -531,8 +572,8 @@ int ddamg_sap_smooth(ddamg_hier hier, int level, const void* b, void* z, int nsw
     check_layout(layout);
     H.s = as_stream(stream);
     check_half(H, prec);
-    check_f16s(H, prec, level, layout);
-    if (prec == DDAMG_F16S) sap_f16s(H, b, z, nsweeps, nrhs);
+    check_f16s(H, prec, level, layout, true);
+    if (prec == DDAMG_F16S) sap_f16s(H, b, z, nsweeps, nrhs, layout);
     else if (prec == DDAMG_F64) sap_impl<double>(H, level, b, z, nsweeps, nrhs, layout);
     else sap_impl<float>(H, level, b, z, nsweeps, nrhs, layout);
   });

@@ -155,9 +155,40 @@ def test_f16s_validation(dd, two_s):
     with pytest.raises(dd.DDAMGError) as e:
         dd.sap_smooth(H32, 0, dev(v), empty(v.shape), 1, prec=dd.F16S)
     assert e.value.status == dd.EINVAL and "half_spinors" in str(e.value)
+    c = W.gaussian_field((2, 2, 2, 2), 8, 178)
     with pytest.raises(dd.DDAMGError) as e:
-        dd.sap_smooth(two_s.H, 0, dev(v), empty(v.shape), 1, prec=dd.F16S, layout=dd.NATIVE)
-    assert e.value.status == dd.EINVAL
+        dd.prolong(two_s.H, 0, dev(c), dev(v), prec=dd.F16S, layout=dd.NATIVE)
+    assert e.value.status == dd.EINVAL and "canonical" in str(e.value)
     with pytest.raises(dd.DDAMGError) as e:
         dd.apply_Dc(two_s.H, 0, dev(v), empty(v.shape), prec=dd.F16S)
     assert e.value.status == dd.EINVAL
+
+
+def test_f16s_native_form(dd, two_s):
+    """The native FP16 form (entries, then site scales, in one buffer): a
+    round trip through it is the FP16 rounding of the field, and SAP and
+    restriction on it give the canonical-layout calls' results exactly."""
+    import torch
+    n0, V = 12 * 8 ** 4, 8 ** 4
+    b = W.gaussian_spinor(two_s.dims, 176, nrhs=2)
+    z0 = W.gaussian_spinor(two_s.dims, 177, nrhs=2)
+    nb = torch.empty(2 * (n0 + V), dtype=torch.float32, device="cuda")
+    nz = torch.empty_like(nb)
+    dd.to_native(two_s.ctx, None, 0, dev(b), nb, nrhs=2, prec=dd.F16S)
+    dd.to_native(two_s.ctx, None, 0, dev(z0), nz, nrhs=2, prec=dd.F16S)
+    back = empty(b.shape)
+    dd.from_native(two_s.ctx, None, 0, nb, back, nrhs=2, prec=dd.F16S)
+    e = relerr(host(back), b)
+    say(f"  FP16 form round trip relerr {e:.2e}")
+    assert 1e-6 < e < U16
+    dd.sap_smooth(two_s.H, 0, nb, nz, 1, nrhs=2, prec=dd.F16S, layout=dd.NATIVE)
+    zn = empty(b.shape)
+    dd.from_native(two_s.ctx, None, 0, nz, zn, nrhs=2, prec=dd.F16S)
+    zc = dev(z0)
+    dd.sap_smooth(two_s.H, 0, dev(b), zc, 1, nrhs=2, prec=dd.F16S)
+    assert np.array_equal(host(zn), host(zc))
+    cc = empty((2, 2, 2, 2, 2, 8))
+    c32 = torch.empty(2 * 16 * 8, dtype=torch.complex64, device="cuda")
+    dd.restrict(two_s.H, 0, nb, c32, nrhs=2, prec=dd.F16S, layout=dd.NATIVE)
+    dd.restrict(two_s.H, 0, dev(b), cc, nrhs=2, prec=dd.F16S)
+    assert np.array_equal(c32.cpu().numpy().astype(np.complex128), host(cc).reshape(-1))

@@ -45,7 +45,7 @@ DSLASH_F32_TRAFFIC_BYTES = 128.25e6
 # runs summarised in profiles/ (None until taken for the current kernel)
 SAP_F16_PASS_TRAFFIC_BYTES = 6.241e9
 # the same for the pass on FP16 spinors (b, z with one FP32 scale per site)
-SAP_F16S_PASS_TRAFFIC_BYTES = None
+SAP_F16S_PASS_TRAFFIC_BYTES = 4.624e9
 WORKLOAD = "clover16x32_3lvl"
 HEADLINE = "clover48x96_4lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"

@@ -2,7 +2,9 @@
 
 namespace ddamg {
 
-constexpr int GMAX = 256;      // max workgroups of the first reduction pass
+// max workgroups of the first reduction pass: eight per compute unit, so
+// that enough wavefronts stream the vectors to keep HBM busy
+constexpr int GMAX = 2048;
 constexpr int RED_BS = 256;
 constexpr int RED_BS_ONE = 512;               // single-workgroup reduction
 constexpr long long RED_ONE_MAX = 32768;      // longest vector reduced by one workgroup
@@ -139,7 +141,7 @@ void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, 
               hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
   long long g = (n + 255) / 256;
-  if (g > 1024) g = 1024;
+  if (g > 4096) g = 4096;
   k_blincomb<T, TZ><<<dim3((unsigned)g, nb), 256, 0, s>>>(a, k, Z, zstride, y, n, dst);
   DD_LAUNCH_CHECK();
 }
@@ -236,7 +238,8 @@ __global__ void __launch_bounds__(256) k_bdots_pass2(const double* __restrict__ 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r = blockIdx.x;
   const double* pr = partial + (long long)r * g * 2 * (KMAX + 1);
   for (int j = 0; j < nv; ++j) {
-    const double v = t < g ? pr[(long long)t * 2 * (KMAX + 1) + j] : 0.0;
+    double v = 0.0;
+    for (int q = t; q < g; q += 256) v += pr[(long long)q * 2 * (KMAX + 1) + j];
     const double sv = wsum(v);
     if (lane == 0) lds[wave][j] = sv;
   }

@@ -425,6 +425,29 @@ int ddamg_solve_ex(ddamg_hier hier, const void* b, void* z, int nrhs, const void
 int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void* const* z, const int* nrhs,
                      ddamg_solve_stats* stats, void* stream);
 
+/* The uneven batch as one graph (the per-system solve of ddamg_solve, Sec. 1
+ * eq. (1) and Sec. 3, with Alg. 1's V-cycle or the W-cycle as
+ * preconditioner): n systems on their own lattices and hierarchies, one
+ * canonical complex128 right-hand side b[i] and initial guess / solution
+ * z[i] (device) each.  Every system's outer FGMRES keeps its Krylov scalars
+ * (Hessenberg matrix, Givens rotations, stopping test) on the device, so one
+ * outer step -- preconditioner, D, Gram-Schmidt -- is a fixed launch
+ * sequence; the steps of all n systems are captured into one HIP graph per
+ * step index (the systems side by side on the hierarchies' own streams), and
+ * the end of a restart cycle (solution update, recomputed FP64 residual,
+ * restart decision) into one more.  The host replays them, reading after
+ * each step the systems' device-written convergence flags: a system that has
+ * converged keeps running with zero coefficients and zero basis vectors,
+ * and the cycle ends when none is live.  Accepts only the recomputed
+ * residual ||b - D z|| <= tol ||b|| (as ddamg_solve).  Needs every hierarchy
+ * built with graph = 1 (V- or W-cycle for levels >= 3), precond_prec =
+ * DDAMG_F32, half_spinors = half_directions = 0 and one n_kv for all.  The
+ * graphs are captured on the first call for a list of hierarchies and kept
+ * (by hiers[0]) for the next calls with the same list.  stats (host, may be
+ * NULL) receives n records.  Synchronous.  Returns as ddamg_solve_many. */
+int ddamg_solve_batch(int n, const ddamg_hier* hiers, const void* const* b, void* const* z,
+                      ddamg_solve_stats* stats, void* stream);
+
 /* Change the SAP block shape of coarse level `level` (1 .. levels-2, the
  * coarse levels smoothed by SAP; Tab. 1's default is 2^4 blocks on every
  * level, Sec. 2 only requires a red-black block decomposition)

@@ -765,6 +765,179 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
   return report_worst(w);
 }
 
+}  // extern "C"
+
+namespace {
+
+// One graph over several hierarchies: from stream S the work forks to each
+// hierarchy's own stream, f(H) is captured there, and the branches join
+// back into S.  The branches have no dependencies between them, so the
+// replay runs the systems side by side.
+template <typename F>
+hipGraphExec_t capture_all(const std::vector<Hierarchy*>& hs, hipStream_t S, F&& f) {
+  struct Events {
+    std::vector<hipEvent_t> e;
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  ev.e.assign(hs.size() + 1, nullptr);
+  for (auto& x : ev.e) DD_CHECK_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  hipGraph_t g = nullptr;
+  DD_CHECK_HIP(hipStreamBeginCapture(S, hipStreamCaptureModeThreadLocal));
+  try {
+    DD_CHECK_HIP(hipEventRecord(ev.e[0], S));
+    for (size_t i = 0; i < hs.size(); ++i) {
+      Hierarchy& H = *hs[i];
+      DD_CHECK_HIP(hipStreamWaitEvent(H.own_s, ev.e[0], 0));
+      H.s = H.own_s;
+      const WorkspaceScope wsc(H.ws.get());
+      f(H);
+      DD_CHECK_HIP(hipEventRecord(ev.e[i + 1], H.own_s));
+      DD_CHECK_HIP(hipStreamWaitEvent(S, ev.e[i + 1], 0));
+    }
+  } catch (...) {
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(S, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    (void)hipGetLastError();
+    throw;
+  }
+  DD_CHECK_HIP(hipStreamEndCapture(S, &g));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  DD_CHECK_HIP(e);
+  return exec;
+}
+
+bool flag_of(const Hierarchy& H) { return *static_cast<volatile int*>(H.go_flag_host) != 0; }
+
+}  // namespace
+
+extern "C" {
+
+int ddamg_solve_batch(int n, const ddamg_hier* hiers, const void* const* b, void* const* z,
+                      ddamg_solve_stats* stats, void* stream) {
+  int worst = DDAMG_OK;
+  int rc = guarded([&] {
+    DD_REQUIRE(n >= 1 && n <= DDAMG_MAX_SYSTEMS, "n must be 1..DDAMG_MAX_SYSTEMS");
+    DD_REQUIRE(hiers && b && z, "null argument");
+    std::vector<Hierarchy*> hs(n);
+    for (int i = 0; i < n; ++i) {
+      DD_REQUIRE(hiers[i] != nullptr, "null hierarchy");
+      DD_REQUIRE(b[i] && z[i] && b[i] != z[i], "bad argument for system " + std::to_string(i));
+      hs[i] = &H_(hiers[i]);
+      for (int k = 0; k < i; ++k) DD_REQUIRE(hs[k] != hs[i], "a hierarchy appears twice (its solves would share buffers)");
+      DD_REQUIRE(hs[i]->p.nkv == hs[0]->p.nkv, "every hierarchy of the batch needs the same n_kv");
+    }
+    const int m = hs[0]->p.nkv;
+    for (Hierarchy* H : hs)
+      if (!H->own_s) DD_CHECK_HIP(hipStreamCreateWithFlags(&H->own_s, hipStreamNonBlocking));
+    // everything runs on the first hierarchy's own stream (a capture cannot
+    // start on the caller's stream, which may be the null stream), after
+    // the work already enqueued on the caller's
+    hipStream_t S = hs[0]->own_s;
+    {
+      struct Ev {
+        hipEvent_t e = nullptr;
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+      } ready;
+      DD_CHECK_HIP(hipEventCreateWithFlags(&ready.e, hipEventDisableTiming));
+      DD_CHECK_HIP(hipEventRecord(ready.e, as_stream(stream)));
+      DD_CHECK_HIP(hipStreamWaitEvent(S, ready.e, 0));
+    }
+    int max_restarts = 0;
+    for (Hierarchy* H : hs) {
+      const WorkspaceScope wsc(H->ws.get());
+      H->s = S;
+      H->outer_dev_prepare();
+      max_restarts = std::max(max_restarts, H->p.max_restarts);
+    }
+    // the step and tail graphs of this list of hierarchies, kept by the first
+    Hierarchy& H0 = *hs[0];
+    std::vector<long long> uids(n), gens(n);
+    for (int i = 0; i < n; ++i) uids[i] = hs[i]->uid, gens[i] = hs[i]->gen;
+    if (!H0.bgraphs || H0.bgraphs->uids != uids || H0.bgraphs->gens != gens) {
+      H0.bgraphs.reset();
+      std::unique_ptr<Hierarchy::BatchGraphs> bg(new Hierarchy::BatchGraphs);
+      bg->uids = uids;
+      bg->gens = gens;
+      for (int j = 0; j < m; ++j)
+        bg->step.push_back(capture_all(hs, S, [&](Hierarchy& H) { H.outer_dev_step(j); }));
+      bg->tail = capture_all(hs, S, [&](Hierarchy& H) { H.outer_dev_tail(); });
+      H0.bgraphs = std::move(bg);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    // inputs after the work already on S; targets, r_0 and V_0 eagerly
+    for (int i = 0; i < n; ++i) {
+      Hierarchy& H = *hs[i];
+      const WorkspaceScope wsc(H.ws.get());
+      H.s = S;
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(b[i]), H.ob.p, 1, S);
+      fine_to_native<double>(H.ctx->g, static_cast<const double2*>(z[i]), H.ox.p, 1, S);
+      H.outer_dev_begin();
+    }
+    DD_CHECK_HIP(hipStreamSynchronize(S));
+    std::vector<int> restarts(n, 0);
+    std::vector<char> active(n);
+    for (int i = 0; i < n; ++i) active[i] = flag_of(*hs[i]);
+    for (int c = 0; c < max_restarts; ++c) {
+      bool any = false;
+      for (int i = 0; i < n; ++i) {
+        any = any || active[i];
+        restarts[i] += active[i];
+      }
+      if (!any) break;
+      // one graph per outer step of every system; the host reads the
+      // systems' liveness flags after each and stops the cycle when none
+      // is left
+      for (int j = 0; j < m; ++j) {
+        DD_CHECK_HIP(hipGraphLaunch(H0.bgraphs->step[j], S));
+        DD_CHECK_HIP(hipStreamSynchronize(S));
+        bool live = false;
+        for (int i = 0; i < n; ++i) live = live || flag_of(*hs[i]);
+        if (!live) break;
+      }
+      DD_CHECK_HIP(hipGraphLaunch(H0.bgraphs->tail, S));
+      DD_CHECK_HIP(hipStreamSynchronize(S));
+      for (int i = 0; i < n; ++i) active[i] = flag_of(*hs[i]);
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // certification and results, system by system
+    for (int i = 0; i < n; ++i) {
+      Hierarchy& H = *hs[i];
+      const WorkspaceScope wsc(H.ws.get());
+      const long long nn = H.lv[0].n;
+      H.s = S;
+      std::vector<double> bn, rn;
+      bnorms<double>(*H.red, H.ob.p, nn, 1, bn, S);
+      dslash<double>(H.ctx->view<double>(), H.ox.p, H.ow.p, S, 1);
+      vbmy<double>(H.ob.p, H.ow.p, nn, S);
+      bnorms<double>(*H.red, H.ow.p, nn, 1, rn, S);
+      long long its = 0;
+      DD_CHECK_HIP(hipMemcpyAsync(&its, H.go_iters.p, sizeof(its), hipMemcpyDeviceToHost, S));
+      fine_from_native<double>(H.ctx->g, H.ox.p, static_cast<double2*>(z[i]), 1, S);
+      DD_CHECK_HIP(hipStreamSynchronize(S));
+      ddamg_solve_stats st{};
+      st.outer_iters = (int)its;
+      st.restarts = restarts[i];
+      st.true_relres = bn[0] > 0 ? rn[0] / bn[0] : 0.0;
+      st.seconds = secs;
+      st.err_vs_ref = -1;
+      st.t_setup_s = H.t_setup;
+      if (!std::isfinite(rn[0])) st.status = DDAMG_ENONFINITE;
+      else if (rn[0] <= H.p.tol * bn[0]) st.status = DDAMG_OK;
+      else st.status = DDAMG_ENOCONV;
+      if (st.status != DDAMG_OK && worst == DDAMG_OK) worst = st.status;
+      if (stats) stats[i] = st;
+    }
+  });
+  if (rc != DDAMG_OK) return rc;
+  return report_worst(worst);
+}
+
 int ddamg_set_sap_block(ddamg_hier hier, int level, const int block[4]) {
   return guarded([&] {
     Hierarchy& H = H_(hier);

@@ -45,8 +45,11 @@ struct DevGmres {
 
 // iters[r] = 0
 void gm_reset(const DevGmres& d, int nb, hipStream_t s);
-// start of a restart cycle from the norms ||r_r||^2 in res[r][0]: first
-// cycle sets the targets tol * ||b_r||; scale[r] = 1 / ||r_r|| (0 for
+// start of a restart cycle from the norms ||r_r||^2 in res[r][0]: first = 1
+// (first cycle) sets the targets tol * ||b_r||; first = 0 continues the
+// systems whose Arnoldi estimate has not met the target; first = 2 decides
+// by the recomputed residual instead: a system continues while that
+// residual is finite and above its target.  scale[r] = 1 / ||r_r|| (0 for
 // systems that are done); flag = some system is active
 void gm_begin(const DevGmres& d, int m, int nb, double tol, int first, hipStream_t s);
 // after the first Gram-Schmidt pass of step j (res = <V_i, w>, <w, w>):

@@ -31,9 +31,11 @@ __device__ inline void set_flag(int* flag, bool pred) {
 __device__ inline bool gm_begin_body(DevGmres& d, int r, int m, double tol, int first) {
   GmSys& S = d.sys[r];
   const double beta = sqrt(fmax(d.res[(size_t)r * (KMAX + 1)].x, 0.0));
-  if (first) {
+  if (first == 1) {
     S.target = tol * beta;
     S.active = beta > 0.0;
+  } else if (first == 2) {
+    S.active = S.active && isfinite(beta) && beta > S.target;
   } else {
     S.active = S.active && !S.conv && beta > 0.0;
   }

@@ -172,6 +172,32 @@ struct Hierarchy {
   std::vector<PreGraph> graphs;
   DevGmres gm();
   void drop_graphs();
+  // outer FGMRES of one right-hand side with its scalars on the device
+  // (ddamg_solve_batch): its own GMRES record and liveness flag, the
+  // preconditioner, D and the Gram-Schmidt step as a fixed launch sequence
+  // (capturable), fields in ob (b), ox (x, native FP64)
+  DevArray<GmSys> go_sys;
+  DevArray<double2> go_res, go_coef;
+  DevArray<double> go_scale;
+  DevArray<long long> go_iters;
+  int* go_flag_host = nullptr;
+  int* go_flag_dev = nullptr;
+  long long go_zeroed = -1;        // gen at which the outer bases were cleared
+  DevGmres gmo();
+  void outer_dev_prepare();        // buffers, warm-up of lazy allocations (eager)
+  void outer_dev_begin();          // targets, r_0 = b - D x_0, V_0 (eager)
+  void outer_dev_step(int j);      // step j: Z_j = M V_j, w = D Z_j, Gram-Schmidt, V_{j+1}
+  void outer_dev_tail();           // x += Z y, r = b - D x, restart decision, V_0
+  long long uid = 0;               // unique per hierarchy (graph caches key on it)
+  // graphs of ddamg_solve_batch over a list of hierarchies (kept by the
+  // first one): one per outer step, one for the cycle's tail
+  struct BatchGraphs {
+    std::vector<long long> uids, gens;
+    std::vector<hipGraphExec_t> step;
+    hipGraphExec_t tail = nullptr;
+    ~BatchGraphs();
+  };
+  std::unique_ptr<BatchGraphs> bgraphs;
 
   template <typename T> Work<T>& work(int l);
   template <typename T> const C<T>* P(int l) const;
@@ -259,8 +285,10 @@ struct Hierarchy {
     for (auto& m : lt_marks) lt_pool.push_back(m.first);
     for (hipEvent_t e : lt_pool) (void)hipEventDestroy(e);
     drop_graphs();
+    bgraphs.reset();
     if (own_s) (void)hipStreamDestroy(own_s);
     if (gm_flag_host) (void)hipHostFree(gm_flag_host);
+    if (go_flag_host) (void)hipHostFree(go_flag_host);
   }
 };
 

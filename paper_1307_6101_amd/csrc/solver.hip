@@ -15,6 +15,8 @@
 //    odd-even reduced (Schur) system, solved by GMRES from zero.
 #include "solver.h"
 
+#include <atomic>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -557,6 +559,138 @@ DevGmres Hierarchy::gm() {
   d.iters = gm_iters.p;
   d.flag = gm_flag_dev;
   return d;
+}
+
+// ---------------------------------------------------------------------------
+// outer FGMRES of one right-hand side with the scalars on the device: the
+// host-driven outer() above as a fixed launch sequence per step, so that the
+// steps of several hierarchies can be captured into one graph
+// (ddamg_solve_batch).  Right preconditioning by the level-0 cycle at FP32
+// (fixed launch sequence: V- or W-cycle, coarsest GMRES with device scalars),
+// FP64 basis V and residuals, FP32 directions Z.  A system whose estimate has
+// met the target runs the remaining steps with zero coefficients and zero
+// basis vectors; at the end of a cycle the recomputed FP64 residual decides
+// whether it continues (gm_begin mode 2), as the host-driven solver's
+// certification does.
+// ---------------------------------------------------------------------------
+DevGmres Hierarchy::gmo() {
+  if (!go_sys.p) {
+    go_sys.alloc(NBMAX);
+    go_res.alloc((size_t)NBMAX * (KMAX + 1));
+    go_coef.alloc((size_t)NBMAX * KMAX);
+    go_scale.alloc(NBMAX);
+    go_iters.alloc(NBMAX);
+    ++gen;
+  }
+  if (!go_flag_host && !counting_only()) {
+    DD_CHECK_HIP(hipHostMalloc(&go_flag_host, sizeof(int), hipHostMallocCoherent));
+    DD_CHECK_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&go_flag_dev), go_flag_host, 0));
+  }
+  DevGmres d;
+  d.sys = go_sys.p;
+  d.res = go_res.p;
+  d.coef = go_coef.p;
+  d.scale = go_scale.p;
+  d.iters = go_iters.p;
+  d.flag = go_flag_dev;
+  return d;
+}
+
+void Hierarchy::outer_dev_prepare() {
+  DD_REQUIRE(p.precond_prec == DDAMG_F32 && !hs && p.half_directions == 0,
+             "the batched graph solve needs the FP32 preconditioner with FP32 spinors and directions");
+  DD_REQUIRE(p.graph == 1, "the batched graph solve needs hierarchies built with graph = 1");
+  ensure_batch<float>(1);
+  gmo();
+  gm();
+  const long long n = lv[0].n;
+  if (go_zeroed != gen) {
+    // the tail combines all n_kv directions (zero coefficients past the
+    // last step): every slot must hold finite values from the start
+    vzero<double>(oV.p, (long long)(p.nkv + 1) * n, s);
+    vzero<float>(oZ32.p, (long long)p.nkv * n, s);
+  }
+  // one eager cycle makes the lazily allocated scratch exist before capture
+  Work<float>& W0 = work<float>(0);
+  vzero<float>(W0.bin.p, n, s);
+  dev_scalars = true;
+  try {
+    cycle<float>(0, W0.bin.p, oZ32.p, 1);
+  } catch (...) {
+    dev_scalars = false;
+    throw;
+  }
+  dev_scalars = false;
+  DD_CHECK_HIP(hipStreamSynchronize(s));
+  go_zeroed = gen;
+}
+
+void Hierarchy::outer_dev_begin() {
+  const long long n = lv[0].n;
+  const DevGmres d = gmo();
+  const BArg a = d.arg();
+  const FineOpView<double> D = ctx->view<double>();
+  gm_reset(d, 1, s);
+  // targets tol * ||b||
+  red->bdots<double>(nullptr, ob.p, 0, 0, ob.p, n, 1, s, d.res);
+  gm_begin(d, p.nkv, 1, p.tol, 1, s);
+  // r_0 = b - D x_0 decides whether the system starts at all
+  dslash<double>(D, ox.p, ow.p, s, 1);
+  vbmy<double>(ob.p, ow.p, n, s);
+  red->bdots<double>(nullptr, ow.p, 0, 0, ow.p, n, 1, s, d.res);
+  gm_begin(d, p.nkv, 1, p.tol, 2, s);
+  bscale<double>(a, ow.p, oV.p, n, 1, s);
+}
+
+void Hierarchy::outer_dev_step(int j) {
+  const long long n = lv[0].n;
+  const int m = p.nkv;
+  const DevGmres d = gmo();
+  const BArg a = d.arg();
+  const FineOpView<double> D = ctx->view<double>();
+  Work<float>& W0 = work<float>(0);
+  double2* Vj = oV.p + (size_t)j * n;
+  float2* Zj = oZ32.p + (size_t)j * n;
+  vcopy<double, float>(Vj, W0.bin.p, n, s);
+  const bool ds = dev_scalars;
+  dev_scalars = true;
+  try {
+    cycle<float>(0, W0.bin.p, Zj, 1);
+  } catch (...) {
+    dev_scalars = ds;
+    throw;
+  }
+  dev_scalars = ds;
+  vcopy<float, double>(Zj, ot.p, n, s);
+  meter((double)ctx->g.V * (24 * 16.0 + 72 * 16.0), 1870.0 * ctx->g.V);
+  dslash<double>(D, ot.p, ow.p, s, 1);
+  meter((2.0 * (j + 2) + 1) * n * 16.0, 16.0 * (j + 2) * n);
+  red->bdots<double>(nullptr, oV.p, n, j + 1, ow.p, n, 1, s, d.res);
+  gm_cgs1(d, j, 1, s);
+  red->bdots<double>(&a, oV.p, n, j + 1, ow.p, n, 1, s, d.res);
+  gm_step(d, j, m, 1, s);
+  if (j + 1 < m) blincomb<double, double>(a, j + 1, oV.p, n, ow.p, n, 1, oV.p + (size_t)(j + 1) * n, s);
+}
+
+void Hierarchy::outer_dev_tail() {
+  const long long n = lv[0].n;
+  const int m = p.nkv;
+  const DevGmres d = gmo();
+  const BArg a = d.arg();
+  const FineOpView<double> D = ctx->view<double>();
+  gm_solve(d, m, 1, s);
+  blincomb<double, float>(a, m, oZ32.p, n, ox.p, n, 1, nullptr, s);
+  dslash<double>(D, ox.p, ow.p, s, 1);
+  vbmy<double>(ob.p, ow.p, n, s);
+  red->bdots<double>(nullptr, ow.p, 0, 0, ow.p, n, 1, s, d.res);
+  gm_begin(d, m, 1, p.tol, 2, s);
+  bscale<double>(a, ow.p, oV.p, n, 1, s);
+}
+
+Hierarchy::BatchGraphs::~BatchGraphs() {
+  for (hipGraphExec_t e : step)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (tail) (void)hipGraphExecDestroy(tail);
 }
 
 template <typename T, typename Op>
@@ -1419,7 +1553,9 @@ Hierarchy* create_hierarchy(Context* ctx, const ddamg_params* pp, const double2*
                             int nrhs_max) {
   DD_REQUIRE(ctx && pp && tvc, "null argument");
   validate_params(*ctx, *pp);
+  static std::atomic<long long> next_uid{1};
   std::unique_ptr<Hierarchy> H(new Hierarchy);
+  H->uid = next_uid++;
   H->ws = std::move(ws);
   H->ctx = ctx;
   H->p = *pp;

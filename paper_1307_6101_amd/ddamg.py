@@ -126,6 +126,8 @@ _SIGS = {
     "ddamg_solve_ex": (_I, [_P, _P, _P, _I, _P, ctypes.POINTER(SolveStats), _P]),
     "ddamg_solve_many": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                               ctypes.POINTER(_I), ctypes.POINTER(SolveStats), _P]),
+    "ddamg_solve_batch": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                               ctypes.POINTER(SolveStats), _P]),
     "ddamg_set_sap_block": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int * 4)]),
     "ddamg_set_batch": (_I, [_P, _I]),
     "ddamg_tune": (_I, [_P, _P, _I, ctypes.c_char_p, ctypes.POINTER(TuneResult), _P]),
@@ -362,6 +364,23 @@ def solve_many(hiers, bs, zs, nrhs=None):
     if rc not in (OK, ENOCONV, ENONFINITE):
         _check(rc)
     return rc, [s.as_dict() for s in stats[:sum(nrhs)]]
+
+
+def solve_batch(hiers, bs, zs):
+    """The uneven batch as one graph per outer step (ddamg_solve_batch): one
+    right-hand side per hierarchy; returns (status, [stats dict per system]).
+    ENOCONV / ENONFINITE are returned, other failures raise."""
+    n = len(hiers)
+    if len(bs) != n or len(zs) != n:
+        raise ValueError("one b and one z per hierarchy")
+    hv = (_P * n)(*[h.handle for h in hiers])
+    bv = (_P * n)(*[_ptr(b) for b in bs])
+    zv = (_P * n)(*[_ptr(z) for z in zs])
+    stats = (SolveStats * n)()
+    rc = load_library().ddamg_solve_batch(n, hv, bv, zv, stats, _stream())
+    if rc not in (OK, ENOCONV, ENONFINITE):
+        _check(rc)
+    return rc, [s.as_dict() for s in stats]
 
 
 def set_sap_block(hier, level, block):

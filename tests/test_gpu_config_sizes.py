@@ -178,6 +178,44 @@ def test_c4_uneven_batch_of_eight(dd):
         assert mx <= 1e-10 * norm(b) and est <= 1e-9 * norm(b)
 
 
+@pytest.mark.timeout(900)
+def test_c4_uneven_batch_one_graph(dd):
+    """The same eight lattices with graph-capturable V-cycle hierarchies
+    solved by ddamg_solve_batch (one graph per outer step over all eight,
+    device convergence flags), each certified by the oracle's sampled
+    residual."""
+    hs, bs, zs, keep = [], [], [], []
+    for j in range(len(W.UNEVEN_BATCH)):
+        cfg = W.uneven_batch_config(j)
+        dims = cfg["dims"]
+        U = W.links(dims, cfg["eps"], cfg["seed_links"])
+        ctx = dd.create(dims, cfg["m0"], cfg["csw"], dev(U))
+        tv = fields_on_device(dims, 12, cfg["ntv"][0], cfg["seed_tv"])
+        P = to_params(dd, cfg, dd.F32, cycle="V")
+        P.graph = 1
+        P.coarse_restart, P.coarse_max_restarts = 8, 1
+        hs.append(dd.build_hierarchy(ctx, P, tv))
+        del tv
+        b = W.gaussian_spinor(dims, cfg["seed_rhs"])
+        bs.append(dev(b))
+        zs.append(empty(b.shape))
+        zs[-1].zero_()
+        keep.append((cfg, U, b, ctx))
+    rc, st = dd.solve_batch(hs, bs, zs)
+    say(f"  solve_batch rc={rc} its={[x['outer_iters'] for x in st]}")
+    assert rc == dd.OK
+    for j, (cfg, U, b, _) in enumerate(keep):
+        dims = cfg["dims"]
+        assert st[j]["true_relres"] <= 1e-10
+        zz = host(zs[j])
+        sites = sample_sites(dims, 24, 4200 + j)
+        est, mx = sampled_residual(U, cfg["m0"], cfg["csw"],
+                                   lambda s: b[tuple(v % e for v, e in zip(s, dims))[::-1]], zz, sites)
+        say(f"  lattice {j}: gpu relres {st[j]['true_relres']:.2e}, oracle sampled estimate "
+            f"{est / norm(b):.2e}")
+        assert mx <= 1e-10 * norm(b) and est <= 1e-9 * norm(b)
+
+
 # ---------------------------------------------------------------------------
 # 48^3 x 96, four levels
 # ---------------------------------------------------------------------------

@@ -1137,10 +1137,10 @@ def uneven_workload(args, dd, W, np, torch):
             z.zero_()
         torch.cuda.synchronize()
 
-    def together(hs):
+    def together(hs, one_graph=False):
         zero_all()
         t = time.time()
-        rc, st = dd.solve_many(hs, bs, zs)
+        rc, st = (dd.solve_batch if one_graph else dd.solve_many)(hs, bs, zs)
         torch.cuda.synchronize()
         return time.time() - t, rc, st
 
@@ -1160,7 +1160,7 @@ def uneven_workload(args, dd, W, np, torch):
                     coarsest_iters=[x["coarsest_iters"] for x in st],
                     max_true_relres=max(x["true_relres"] for x in st))
 
-    def run_set(name, prec, cycle, graph, reps, tune=False):
+    def run_set(name, prec, cycle, graph, reps, tune=False, one_graph=False):
         hs, su = build_set(prec, cycle, graph)
         log(f"[bench] {name}: setup {su}")
         tuned = None
@@ -1174,7 +1174,7 @@ def uneven_workload(args, dd, W, np, torch):
             log(f"[bench] {name}: tuned in {tuned['search_s']}s, level-1 SAP blocks {tuned['sap_block_level1']}")
         times, st = [], None
         for i in range(reps):
-            tt, rc, st = together(hs)
+            tt, rc, st = together(hs, one_graph)
             times.append(tt)
             log(f"[bench] {name}, together #{i}: {tt:.3f}s rc={rc} its {[x['outer_iters'] for x in st]} "
                 f"coarsest {[x['coarsest_iters'] for x in st]}")
@@ -1196,6 +1196,11 @@ def uneven_workload(args, dd, W, np, torch):
     vres, _ = run_set("mixed V-cycle", dd.F32, "V", False, 2)
     gres, _ = run_set("mixed V-cycle, graph-captured", dd.F32, "V", True, 3)
     gres["coarsest_budget"] = {"restart": GRAPH_COARSE[0], "cycles": GRAPH_COARSE[1]}
+    # the same hierarchies through ddamg_solve_batch: one graph per outer
+    # step over all eight systems, the outer scalars and convergence flags
+    # on the device
+    bres, _ = run_set("mixed V-cycle, one graph over all systems", dd.F32, "V", True, 3, one_graph=True)
+    bres["coarsest_budget"] = gres["coarsest_budget"]
     plain = None
     if not args.no_plain:
         per, its, su, stat = [], [], [], []
@@ -1249,6 +1254,7 @@ def uneven_workload(args, dd, W, np, torch):
         "kcycle": kres,
         "vcycle": vres,
         "vcycle_graph_captured": gres,
+        "vcycle_one_graph_all_systems": bres,
         "plain_fp64": plain,
         "cgnr_fp64": cgn,
         "speedup_vs_plain_fp64": round(plain["total_s"] / (ms / 1000.0), 3) if plain else None,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -769,47 +770,112 @@ int ddamg_solve_many(int n, const ddamg_hier* hiers, const void* const* b, void*
 
 namespace {
 
-// One graph over several hierarchies: from stream S the work forks to each
-// hierarchy's own stream, f(H) is captured there, and the branches join
-// back into S.  The branches have no dependencies between them, so the
-// replay runs the systems side by side.
+// One graph over several hierarchies.  f(H) is captured for each hierarchy
+// on its own stream into a graph of its own; their kernel nodes are then
+// copied into one graph, each system's nodes with their own dependencies
+// and none between systems, so the replay runs the systems side by side.
+// The node lists per system let the host disable a system's nodes once it
+// has converged (disabled nodes do nothing).
 template <typename F>
-hipGraphExec_t capture_all(const std::vector<Hierarchy*>& hs, hipStream_t S, F&& f) {
-  struct Events {
-    std::vector<hipEvent_t> e;
-    ~Events() {
-      for (hipEvent_t x : e)
-        if (x) (void)hipEventDestroy(x);
+Hierarchy::BatchGraph capture_all(const std::vector<Hierarchy*>& hs, F&& f) {
+  Hierarchy::BatchGraph bg;
+  const size_t n = hs.size();
+  struct Graphs {
+    std::vector<hipGraph_t> g;
+    ~Graphs() {
+      for (hipGraph_t x : g)
+        if (x) (void)hipGraphDestroy(x);
     }
-  } ev;
-  ev.e.assign(hs.size() + 1, nullptr);
-  for (auto& x : ev.e) DD_CHECK_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
-  hipGraph_t g = nullptr;
-  DD_CHECK_HIP(hipStreamBeginCapture(S, hipStreamCaptureModeThreadLocal));
-  try {
-    DD_CHECK_HIP(hipEventRecord(ev.e[0], S));
-    for (size_t i = 0; i < hs.size(); ++i) {
-      Hierarchy& H = *hs[i];
-      DD_CHECK_HIP(hipStreamWaitEvent(H.own_s, ev.e[0], 0));
-      H.s = H.own_s;
-      const WorkspaceScope wsc(H.ws.get());
+  } parts;
+  parts.g.assign(n, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    Hierarchy& H = *hs[i];
+    H.s = H.own_s;
+    const WorkspaceScope wsc(H.ws.get());
+    DD_CHECK_HIP(hipStreamBeginCapture(H.own_s, hipStreamCaptureModeThreadLocal));
+    try {
       f(H);
-      DD_CHECK_HIP(hipEventRecord(ev.e[i + 1], H.own_s));
-      DD_CHECK_HIP(hipStreamWaitEvent(S, ev.e[i + 1], 0));
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(H.own_s, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      (void)hipGetLastError();
+      throw;
     }
+    DD_CHECK_HIP(hipStreamEndCapture(H.own_s, &parts.g[i]));
+  }
+  DD_CHECK_HIP(hipGraphCreate(&bg.g, 0));
+  try {
+    bg.nodes.resize(n);
+    bg.on.assign(n, 1);
+    for (size_t i = 0; i < n; ++i) {
+      size_t cnt = 0;
+      DD_CHECK_HIP(hipGraphGetNodes(parts.g[i], nullptr, &cnt));
+      std::vector<hipGraphNode_t> src(cnt);
+      if (cnt) DD_CHECK_HIP(hipGraphGetNodes(parts.g[i], src.data(), &cnt));
+      // copy in dependency order (each node after the nodes it waits for)
+      std::map<hipGraphNode_t, hipGraphNode_t> dst;
+      std::vector<std::vector<hipGraphNode_t>> deps(cnt);
+      for (size_t k = 0; k < cnt; ++k) {
+        size_t nd = 0;
+        DD_CHECK_HIP(hipGraphNodeGetDependencies(src[k], nullptr, &nd));
+        deps[k].resize(nd);
+        if (nd) DD_CHECK_HIP(hipGraphNodeGetDependencies(src[k], deps[k].data(), &nd));
+      }
+      size_t done = 0;
+      std::vector<char> copied(cnt, 0);
+      while (done < cnt) {
+        bool progress = false;
+        for (size_t k = 0; k < cnt; ++k) {
+          if (copied[k]) continue;
+          std::vector<hipGraphNode_t> dd;
+          bool ready = true;
+          for (hipGraphNode_t d : deps[k]) {
+            auto it = dst.find(d);
+            if (it == dst.end()) {
+              ready = false;
+              break;
+            }
+            dd.push_back(it->second);
+          }
+          if (!ready) continue;
+          hipGraphNodeType type;
+          DD_CHECK_HIP(hipGraphNodeGetType(src[k], &type));
+          hipGraphNode_t nn = nullptr;
+          if (type == hipGraphNodeTypeKernel) {
+            hipKernelNodeParams kp{};
+            DD_CHECK_HIP(hipGraphKernelNodeGetParams(src[k], &kp));
+            DD_CHECK_HIP(hipGraphAddKernelNode(&nn, bg.g, dd.data(), dd.size(), &kp));
+            bg.nodes[i].push_back(nn);
+          } else if (type == hipGraphNodeTypeEmpty) {
+            DD_CHECK_HIP(hipGraphAddEmptyNode(&nn, bg.g, dd.data(), dd.size()));
+          } else {
+            throw Error(DDAMG_EHIP, "a captured outer step holds a graph node other than a kernel");
+          }
+          dst[src[k]] = nn;
+          copied[k] = 1;
+          ++done;
+          progress = true;
+        }
+        DD_REQUIRE(progress, "cyclic dependencies in a captured graph");
+      }
+    }
+    DD_CHECK_HIP(hipGraphInstantiate(&bg.exec, bg.g, nullptr, nullptr, 0));
   } catch (...) {
-    hipGraph_t junk = nullptr;
-    (void)hipStreamEndCapture(S, &junk);
-    if (junk) (void)hipGraphDestroy(junk);
-    (void)hipGetLastError();
+    if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
+    if (bg.g) (void)hipGraphDestroy(bg.g);
     throw;
   }
-  DD_CHECK_HIP(hipStreamEndCapture(S, &g));
-  hipGraphExec_t exec = nullptr;
-  const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  DD_CHECK_HIP(e);
-  return exec;
+  return bg;
+}
+
+// enable the nodes of exactly the systems in `want`
+void set_systems(Hierarchy::BatchGraph& bg, const std::vector<char>& want) {
+  for (size_t i = 0; i < want.size(); ++i) {
+    if (bg.on[i] == want[i]) continue;
+    for (hipGraphNode_t nd : bg.nodes[i]) DD_CHECK_HIP(hipGraphNodeSetEnabled(bg.exec, nd, want[i] ? 1u : 0u));
+    bg.on[i] = want[i];
+  }
 }
 
 bool flag_of(const Hierarchy& H) { return *static_cast<volatile int*>(H.go_flag_host) != 0; }
@@ -864,9 +930,8 @@ int ddamg_solve_batch(int n, const ddamg_hier* hiers, const void* const* b, void
       std::unique_ptr<Hierarchy::BatchGraphs> bg(new Hierarchy::BatchGraphs);
       bg->uids = uids;
       bg->gens = gens;
-      for (int j = 0; j < m; ++j)
-        bg->step.push_back(capture_all(hs, S, [&](Hierarchy& H) { H.outer_dev_step(j); }));
-      bg->tail = capture_all(hs, S, [&](Hierarchy& H) { H.outer_dev_tail(); });
+      for (int j = 0; j < m; ++j) bg->step.push_back(capture_all(hs, [&](Hierarchy& H) { H.outer_dev_step(j); }));
+      bg->tail = capture_all(hs, [&](Hierarchy& H) { H.outer_dev_tail(); });
       H0.bgraphs = std::move(bg);
     }
     const auto t0 = std::chrono::steady_clock::now();
@@ -891,16 +956,24 @@ int ddamg_solve_batch(int n, const ddamg_hier* hiers, const void* const* b, void
       }
       if (!any) break;
       // one graph per outer step of every system; the host reads the
-      // systems' liveness flags after each and stops the cycle when none
-      // is left
+      // systems' device-written liveness flags after each, disables the
+      // nodes of the systems that have stopped in the graphs still to run,
+      // and ends the cycle when none is left
+      std::vector<char> live = active;
       for (int j = 0; j < m; ++j) {
-        DD_CHECK_HIP(hipGraphLaunch(H0.bgraphs->step[j], S));
+        Hierarchy::BatchGraph& G = H0.bgraphs->step[j];
+        set_systems(G, live);
+        DD_CHECK_HIP(hipGraphLaunch(G.exec, S));
         DD_CHECK_HIP(hipStreamSynchronize(S));
-        bool live = false;
-        for (int i = 0; i < n; ++i) live = live || flag_of(*hs[i]);
-        if (!live) break;
+        bool anylive = false;
+        for (int i = 0; i < n; ++i) {
+          live[i] = live[i] && flag_of(*hs[i]);
+          anylive = anylive || live[i];
+        }
+        if (!anylive) break;
       }
-      DD_CHECK_HIP(hipGraphLaunch(H0.bgraphs->tail, S));
+      set_systems(H0.bgraphs->tail, active);
+      DD_CHECK_HIP(hipGraphLaunch(H0.bgraphs->tail.exec, S));
       DD_CHECK_HIP(hipStreamSynchronize(S));
       for (int i = 0; i < n; ++i) active[i] = flag_of(*hs[i]);
     }

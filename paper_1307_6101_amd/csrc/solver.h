@@ -191,10 +191,16 @@ struct Hierarchy {
   long long uid = 0;               // unique per hierarchy (graph caches key on it)
   // graphs of ddamg_solve_batch over a list of hierarchies (kept by the
   // first one): one per outer step, one for the cycle's tail
+  struct BatchGraph {
+    hipGraph_t g = nullptr;        // kept: its nodes name the ones to disable
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::vector<hipGraphNode_t>> nodes;   // kernel nodes per system
+    std::vector<char> on;                             // per system: enabled
+  };
   struct BatchGraphs {
     std::vector<long long> uids, gens;
-    std::vector<hipGraphExec_t> step;
-    hipGraphExec_t tail = nullptr;
+    std::vector<BatchGraph> step;  // one per outer step index
+    BatchGraph tail;
     ~BatchGraphs();
   };
   std::unique_ptr<BatchGraphs> bgraphs;

@@ -688,9 +688,12 @@ void Hierarchy::outer_dev_tail() {
 }
 
 Hierarchy::BatchGraphs::~BatchGraphs() {
-  for (hipGraphExec_t e : step)
-    if (e) (void)hipGraphExecDestroy(e);
-  if (tail) (void)hipGraphExecDestroy(tail);
+  auto drop = [](BatchGraph& b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.g) (void)hipGraphDestroy(b.g);
+  };
+  for (auto& b : step) drop(b);
+  drop(tail);
 }
 
 template <typename T, typename Op>

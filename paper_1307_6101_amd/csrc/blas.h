@@ -44,8 +44,10 @@ struct BArg {
   __device__ double scale(int r) const { return inl ? isc[r] : sc[r]; }
 };
 
-// y_r += sum_j c[r][j] Z_{j,r} (j < k), then, if dst != nullptr,
-// dst_r = sc[r] * y_r (dst_r = 0 where sc[r] == 0)
+// y_r += sum_j c[r][j] Z_{j,r} (j < k); with dst != nullptr instead
+// dst_r = sc[r] * (y_r + sum_j c[r][j] Z_{j,r}) (0 where sc[r] == 0) and y
+// is left as it was (the Gram-Schmidt update of the next basis vector, whose
+// intermediate is not needed)
 template <typename T, typename TZ>
 void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, long long n, int nb, C<T>* dst,
               hipStream_t s);

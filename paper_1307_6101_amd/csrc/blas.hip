@@ -131,8 +131,9 @@ __global__ void k_blincomb(const BArg a, int k, const C<TZ>* __restrict__ Z, lon
     double2 acc = ccast<double>(y[i]);
     for (int j = 0; j < k; ++j) cfma(acc, a.coef(r, j), ccast<double>(Z[j * zstride + i]));
     const C<T> v = ccast<T>(acc);
-    y[i] = v;
+    // with dst the updated y is only an intermediate: not written back
     if (dst) dst[i] = sc == 0.0 ? czero<T>() : ccast<T>(cscale(ccast<double>(v), sc));
+    else y[i] = v;
   }
 }
 
@@ -141,7 +142,7 @@ void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, 
               hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
   long long g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > 1024) g = 1024;
   k_blincomb<T, TZ><<<dim3((unsigned)g, nb), 256, 0, s>>>(a, k, Z, zstride, y, n, dst);
   DD_LAUNCH_CHECK();
 }

@@ -125,6 +125,11 @@ void clover_build(const FineGeom& g, const double2* links, double m0, double csw
 template <typename T, typename S>
 void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb = 1);
 
+// out = D in in FP64 for nb fields stored in FP16 with site scales (the form
+// of encode_sites): D applied to exactly the values the FP16 field stands for
+void dslash_hs(const FineOpView<double>& op, const __half2* in, const float* ins, double2* out, hipStream_t s,
+               int nb = 1);
+
 // one SAP colour pass: z += MR-block-solve(b - D z) on blocks of colour c,
 // for nb right-hand sides (fields as for dslash)
 template <typename T, typename S>

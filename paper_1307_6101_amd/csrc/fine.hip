@@ -307,41 +307,42 @@ __device__ inline Nbr8 load_nbr8(const int* __restrict__ nbr, int blk) {
   return Nbr8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
 }
 
-template <typename T, typename S, int MU>
-__device__ inline void hops_mu(const FineOpView<T, S>& op, const C<T>* __restrict__ in, int blk, int loc,
-                               const Nbr8& nb8, C<T> acc[12]) {
+// (the input field in spinor storage V: C<T>, or FP16 with site scales ins)
+template <typename T, typename S, typename V, int MU>
+__device__ inline void hops_mu(const FineOpView<T, S>& op, const V* __restrict__ in, const float* __restrict__ ins,
+                               int blk, int loc, const Nbr8& nb8, C<T> acc[12]) {
   constexpr int bit = 1 << MU;
   C<T> psi[12], u[9];
   // forward: psi(x+mu), U_mu(x)
   {
     const int nb = (loc & bit) ? nb8.v[2 * MU] : blk;
-    load_spinor<T>(in, nb, loc ^ bit, psi);
+    load_site<T, V>(in, ins, nb, loc ^ bit, psi);
     load_link<T, S>(op.U, blk, loc, MU, u);
     hop_apply<T, MU, true>(psi, u, acc);
   }
   // backward: psi(x-mu), U_mu(x-mu)^H
   {
     const int nb = (loc & bit) ? blk : nb8.v[2 * MU + 1];
-    load_spinor<T>(in, nb, loc ^ bit, psi);
+    load_site<T, V>(in, ins, nb, loc ^ bit, psi);
     load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
     hop_apply<T, MU, false>(psi, u, acc);
   }
 }
 
 // out(x) = (D in)(x) for one site
-template <typename T, typename S>
-__device__ inline void dslash_site(const FineOpView<T, S>& op, const C<T>* __restrict__ in, int blk,
-                                   int loc, C<T> out[12]) {
+template <typename T, typename S, typename V = C<T>>
+__device__ inline void dslash_site(const FineOpView<T, S>& op, const V* __restrict__ in,
+                                   const float* __restrict__ ins, int blk, int loc, C<T> out[12]) {
   const Nbr8 nb8 = load_nbr8(op.nbr, blk);
   C<T> acc[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-  hops_mu<T, S, 0>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, S, 1>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, S, 2>(op, in, blk, loc, nb8, acc);
-  hops_mu<T, S, 3>(op, in, blk, loc, nb8, acc);
+  hops_mu<T, S, V, 0>(op, in, ins, blk, loc, nb8, acc);
+  hops_mu<T, S, V, 1>(op, in, ins, blk, loc, nb8, acc);
+  hops_mu<T, S, V, 2>(op, in, ins, blk, loc, nb8, acc);
+  hops_mu<T, S, V, 3>(op, in, ins, blk, loc, nb8, acc);
   C<T> psi[12];
-  load_spinor<T>(in, blk, loc, psi);
+  load_site<T, V>(in, ins, blk, loc, psi);
   clover_apply<T, S>(op.A, blk, loc, psi, out);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
@@ -352,18 +353,20 @@ __device__ inline void dslash_site(const FineOpView<T, S>& op, const C<T>* __res
 
 // One site per thread.  A batch of nb fields runs over a one-dimensional
 // grid of gx * nb workgroups with the XCD-aware batch mapping.
-template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_dslash(FineOpView<T, S> op, const C<T>* __restrict__ in,
-                                                C<T>* __restrict__ out, long long fs, int gx, int nb) {
+template <typename T, typename S, typename V = C<T>>
+__global__ void __launch_bounds__(256) k_dslash(FineOpView<T, S> op, const V* __restrict__ in,
+                                                const float* __restrict__ ins, C<T>* __restrict__ out,
+                                                long long fs, int gx, int nb) {
   int x, r;
   xcd_slab_rhs(blockIdx.x, gx, nb, x, r);
   const int tid = x * blockDim.x + threadIdx.x;
   const int blk = tid >> 4, loc = tid & 15;
   if (blk >= op.nblk) return;
   in += (long long)r * fs;
+  if constexpr (std::is_same<V, __half2>::value) ins += (long long)r * (fs / 12);
   out += (long long)r * fs;
   C<T> o[12];
-  dslash_site<T, S>(op, in, blk, loc, o);
+  dslash_site<T, S, V>(op, in, ins, blk, loc, o);
   C<T>* p = out + (long long)blk * 192 + loc;
 #pragma unroll
   for (int c = 0; c < 12; ++c) p[c * 16] = o[c];
@@ -373,7 +376,15 @@ template <typename T, typename S>
 void dslash(const FineOpView<T, S>& op, const C<T>* in, C<T>* out, hipStream_t s, int nb) {
   const long long fs = (long long)op.nblk * 192;
   const unsigned gx = nblocks((size_t)op.nblk * 16, 256);
-  k_dslash<T, S><<<gx * nb, 256, 0, s>>>(op, in, out, fs, (int)gx, nb);
+  k_dslash<T, S><<<gx * nb, 256, 0, s>>>(op, in, nullptr, out, fs, (int)gx, nb);
+  DD_LAUNCH_CHECK();
+}
+
+void dslash_hs(const FineOpView<double>& op, const __half2* in, const float* ins, double2* out, hipStream_t s,
+               int nb) {
+  const long long fs = (long long)op.nblk * 192;
+  const unsigned gx = nblocks((size_t)op.nblk * 16, 256);
+  k_dslash<double, double2, __half2><<<gx * nb, 256, 0, s>>>(op, in, ins, out, fs, (int)gx, nb);
   DD_LAUNCH_CHECK();
 }
 

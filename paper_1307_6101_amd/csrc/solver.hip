@@ -1039,8 +1039,10 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
         float* zjs = oZs.p + (size_t)j * nb * ctx->g.V;
         encode_h<double>(ctx->g, Vj, h16a.p, h16as.p, nb, s);
         cycle_hs(h16a.p, h16as.p, zj, zjs, nb);
-        decode_h<double>(ctx->g, zj, zjs, ot.p, nb, s);
-        applyD64(ot.p, w);
+        // D in FP64 on exactly the stored FP16 direction
+        // (FP16 spinor and its scale in, FP64 spinor out, FP64 links and clover)
+        meter((double)ctx->g.V * ((52.0 + 192.0) * nb + 72 * 16.0), 1870.0 * ctx->g.V * nb);
+        dslash_hs(D, zj, zjs, w, s, nb);
       } else if (zh) {
         vcopy<double, T>(Vj, W0.bin.p, vs, s);
         cycle<T>(0, W0.bin.p, W0.x.p, nb);

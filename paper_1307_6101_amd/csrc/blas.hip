@@ -75,8 +75,41 @@ __device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C
   double nrm = 0;
 #pragma unroll
   for (int j = 0; j < 2 * KK + 1; ++j) acc[j] = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  const long long S = (long long)gridDim.x * blockDim.x;
+  long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if constexpr (KK <= 12) {
+    // two elements per trip, all their loads issued before the arithmetic
+    // (more memory requests in flight per wavefront)
+    for (; i0 + S < n; i0 += 2 * S) {
+      const long long i1 = i0 + S;
+      double2 w0 = ccast<double>(w[i0]), w1 = ccast<double>(w[i1]);
+      double2 v0[KK > 0 ? KK : 1], v1[KK > 0 ? KK : 1];
+#pragma unroll
+      for (int j = 0; j < KK; ++j) {
+        v0[j] = ccast<double>(V[j * stride + i0]);
+        v1[j] = ccast<double>(V[j * stride + i1]);
+      }
+      if (upd) {
+#pragma unroll
+        for (int j = 0; j < KK; ++j) {
+          cfma(w0, c.c[j], v0[j]);
+          cfma(w1, c.c[j], v1[j]);
+        }
+        const C<T> t0 = ccast<T>(w0), t1 = ccast<T>(w1);
+        w[i0] = t0;
+        w[i1] = t1;
+        w0 = ccast<double>(t0);
+        w1 = ccast<double>(t1);
+      }
+#pragma unroll
+      for (int j = 0; j < KK; ++j) {
+        acc[2 * j] += v0[j].x * w0.x + v0[j].y * w0.y + v1[j].x * w1.x + v1[j].y * w1.y;
+        acc[2 * j + 1] += v0[j].x * w0.y - v0[j].y * w0.x + v1[j].x * w1.y - v1[j].y * w1.x;
+      }
+      nrm += w0.x * w0.x + w0.y * w0.y + w1.x * w1.x + w1.y * w1.y;
+    }
+  }
+  for (long long i = i0; i < n; i += S) {
     double2 wi = ccast<double>(w[i]);
     if (upd) {
 #pragma unroll
@@ -126,8 +159,26 @@ __global__ void k_blincomb(const BArg a, int k, const C<TZ>* __restrict__ Z, lon
   y += (long long)r * n;
   const double sc = dst ? a.scale(r) : 0.0;
   if (dst) dst += (long long)r * n;
+  const long long S = (long long)gridDim.x * blockDim.x;
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+  // two elements per trip (two independent load streams per vector)
+  for (; i + S < n; i += 2 * S) {
+    double2 acc0 = ccast<double>(y[i]), acc1 = ccast<double>(y[i + S]);
+    for (int j = 0; j < k; ++j) {
+      const double2 cj = a.coef(r, j);
+      cfma(acc0, cj, ccast<double>(Z[j * zstride + i]));
+      cfma(acc1, cj, ccast<double>(Z[j * zstride + i + S]));
+    }
+    const C<T> v0 = ccast<T>(acc0), v1 = ccast<T>(acc1);
+    if (dst) {
+      dst[i] = sc == 0.0 ? czero<T>() : ccast<T>(cscale(ccast<double>(v0), sc));
+      dst[i + S] = sc == 0.0 ? czero<T>() : ccast<T>(cscale(ccast<double>(v1), sc));
+    } else {
+      y[i] = v0;
+      y[i + S] = v1;
+    }
+  }
+  for (; i < n; i += S) {
     double2 acc = ccast<double>(y[i]);
     for (int j = 0; j < k; ++j) cfma(acc, a.coef(r, j), ccast<double>(Z[j * zstride + i]));
     const C<T> v = ccast<T>(acc);

@@ -851,7 +851,8 @@ def cpu_baseline_headline(cfg, U, b, outer_iters, V, gpu_solve_s):
 
 def big_workload(args, name, cfg, dd, W, np, torch):
     """The larger lattices, run on request: a step is one solve with the
-    FP32 preconditioner on FP16-stored operator data.  On the 32^3x64
+    FP32 preconditioner on FP16-stored operator data and FP16 fine spinors
+    (FP32 spinors with --fp32-spinors).  On the 32^3x64
     lattice the 12 spin-colour point sources go through in one batch (the
     coarse operator on the matrix cores); on the 48^3x96 lattice (four
     levels) one Gaussian right-hand side.  The plain FP64 method solves
@@ -900,6 +901,7 @@ def big_workload(args, name, cfg, dd, W, np, torch):
         p.nu = cfg["nu"]
         p.precond_prec = prec
         p.half_storage = 1 if half else 0
+        p.half_spinors = 1 if half and spinors16 else 0
         p.batch = batch
         return p
 
@@ -909,6 +911,8 @@ def big_workload(args, name, cfg, dd, W, np, torch):
         H = dd.build_hierarchy(ctx, params(prec, half, batch), tvd, extra)
         torch.cuda.synchronize()
         return H, time.time() - t
+
+    spinors16 = not args.fp32_spinors
 
     def solve(Hh, nb):
         z.zero_()

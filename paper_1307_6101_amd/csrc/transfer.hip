@@ -139,9 +139,194 @@ __global__ void __launch_bounds__(256) k_restrict_fine(const int* __restrict__ m
   }
 }
 
+// ---------------------------------------------------------------------------
+// Restriction and prolongation of a batch on the matrix cores (FP32
+// arithmetic, 8..16 fields per launch chunk, N <= 32).  Per aggregate and
+// chirality half the restriction is the complex GEMM
+//   out (nb x N) = V^T (nb x 96 per block, summed over the blocks) conj(P),
+// the prolongation out (96 x nb per block) = P (96 x N) c (N x nb).  One
+// workgroup per aggregate stages a 2^4 block of every field (and of every
+// P_k for the restriction) in LDS at a time with contiguous loads, decoded
+// to FP32 (FP16 fields times their site scales, FP16 P widened), and feeds
+// 16x16x4 FP32 MFMA tiles from there: four real products per complex step.
+// Operand layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result register v of lane l is D[4 (l / 16) + v][l % 16].
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int TMF_NB = 16;     // fields per launch chunk
+constexpr int TMF_PAD = 196;   // LDS row stride (complex) of a staged block
+
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <typename S, typename V>
+__global__ void __launch_bounds__(256) k_restrict_fine_mfma(const int* __restrict__ members, int nbpa, int N,
+                                                             long long fstride, const S* __restrict__ P,
+                                                             const V* __restrict__ in, const float* __restrict__ ins,
+                                                             float2* __restrict__ out, long long cstride, int nb) {
+  constexpr bool HS = std::is_same<V, __half2>::value;
+  __shared__ float2 vl[TMF_NB][TMF_PAD];
+  __shared__ float2 pl[32][TMF_PAD];
+  const int A = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int r0 = blockIdx.y * TMF_NB, nr = min(TMF_NB, nb - r0);
+  const long long sstride = fstride / 12;
+  const int sg = w & 1, kt = w >> 1, rr = lane & 15, kk = lane >> 4;
+  f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+  constexpr int NVE = TMF_NB * 192 / 256, NPE = 32 * 192 / 256;   // staged elements per thread
+  for (int bi = 0; bi < nbpa; ++bi) {
+    const int blk = members[A * nbpa + bi];
+    // every load of the block first, then the LDS stores (a load consumed
+    // at once would stall each of them in turn)
+    V va[NVE];
+    float vm[NVE];
+    S pa[NPE];
+#pragma unroll
+    for (int i = 0; i < NVE; ++i) {
+      const int e = t + 256 * i, r = e / 192, q = e - r * 192;
+      va[i] = szero<V>();
+      vm[i] = 1.f;
+      if (r < nr) {
+        va[i] = in[(long long)(r0 + r) * fstride + (long long)blk * 192 + q];
+        if constexpr (HS) vm[i] = ins[(long long)(r0 + r) * sstride + (long long)blk * 16 + (q & 15)];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPE; ++i) {
+      const int e = t + 256 * i, k = e / 192, q = e - k * 192;
+      pa[i] = k < N ? P[(long long)k * fstride + (long long)blk * 192 + q] : szero<S>();
+    }
+#pragma unroll
+    for (int i = 0; i < NVE; ++i) {
+      const int e = t + 256 * i, r = e / 192, q = e - r * 192;
+      float2 v = ldc<float, V>(va[i]);
+      v.x *= vm[i];
+      v.y *= vm[i];
+      vl[r][q] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NPE; ++i) {
+      const int e = t + 256 * i, k = e / 192, q = e - k * 192;
+      pl[k][q] = ldc<float, S>(pa[i]);
+    }
+    __syncthreads();
+    // the 96 components of chirality half sg: 6 spin-colour rows x 16 sites,
+    // summed per block and then over the blocks (shorter chains of FP32
+    // additions than one running sum over the aggregate)
+    f32x4 br = {0.f, 0.f, 0.f, 0.f}, bi_ = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int s4 = 0; s4 < 96; s4 += 4) {
+      const int q = sg * 96 + s4 + kk;
+      const float2 a = vl[rr][q];
+      const float2 b = pl[kt * 16 + rr][q];
+      // conj(P) v: re = vr pr + vi pi, im = vi pr - vr pi
+      br = mfma4(a.x, b.x, br);
+      br = mfma4(a.y, b.y, br);
+      bi_ = mfma4(a.y, b.x, bi_);
+      bi_ = mfma4(-a.x, b.y, bi_);
+    }
+    cr += br;
+    ci += bi_;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * kk + v, k = kt * 16 + rr;
+    if (r < nr && k < N) out[(long long)(r0 + r) * cstride + (long long)A * 2 * N + sg * N + k] = make_float2(cr[v], ci[v]);
+  }
+}
+
+template <typename S, typename V>
+__global__ void __launch_bounds__(256) k_prolong_fine_mfma(const int* __restrict__ members, int nbpa, int N,
+                                                            long long fstride, const S* __restrict__ P,
+                                                            const float2* __restrict__ in, V* __restrict__ out,
+                                                            float* __restrict__ outs, long long cstride, int nb) {
+  constexpr bool HS = std::is_same<V, __half2>::value;
+  __shared__ float2 cl[TMF_NB][65];
+  __shared__ float2 ol[TMF_NB][TMF_PAD];
+  const int A = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int r0 = blockIdx.y * TMF_NB, nr = min(TMF_NB, nb - r0);
+  const long long sstride = fstride / 12;
+  const int rl = lane & 15, kk = lane >> 4;
+  for (int e = t; e < TMF_NB * 2 * N; e += 256) {
+    const int r = e / (2 * N), q = e - r * 2 * N;
+    cl[r][q] = r < nr ? in[(long long)(r0 + r) * cstride + (long long)A * 2 * N + q] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int bi = 0; bi < nbpa; ++bi) {
+    const int blk = members[A * nbpa + bi];
+    // twelve 16-site row tiles (one per spin-colour component), three per wavefront
+    for (int c = w; c < 12; c += 4) {
+      const int sg = c / 6;
+      f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      // the tile's P entries for every k step, loaded before the products
+      S pa[8];
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        const int k = 4 * st + kk;
+        pa[st] = k < N ? P[(long long)k * fstride + (long long)blk * 192 + c * 16 + rl] : szero<S>();
+      }
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        const int k0 = 4 * st;
+        if (k0 >= N) break;
+        const int k = k0 + kk;
+        const float2 a = ldc<float, S>(pa[st]);
+        const float2 b = k < N ? cl[rl][sg * N + k] : make_float2(0.f, 0.f);
+        // P c: re = pr cr - pi ci, im = pr ci + pi cr
+        cr = mfma4(a.x, b.x, cr);
+        cr = mfma4(-a.y, b.y, cr);
+        ci = mfma4(a.x, b.y, ci);
+        ci = mfma4(a.y, b.x, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ol[rl][c * 16 + 4 * kk + v] = make_float2(cr[v], ci[v]);
+    }
+    __syncthreads();
+    // one thread per (field, site) of the block writes the site
+    const int r = t >> 4, loc = t & 15;
+    if (r < nr) {
+      float2 v[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = ol[r][c * 16 + loc];
+      V* o = out + (long long)(r0 + r) * fstride;
+      if constexpr (!HS) {
+        float2 old[12];
+        load_spinor<float, V>(o, blk, loc, old);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = cadd(v[c], old[c]);
+      }
+      store_site<float, V>(o, HS ? outs + (long long)(r0 + r) * sstride : nullptr, blk, loc, v);
+    }
+    __syncthreads();
+  }
+}
+
+// whether the matrix-core transfer takes a batch of nb with N test vectors
+inline bool use_transfer_mfma(int nb, int N, int asz) { return nb >= 8 && N <= 32 && asz <= 1024; }
+
+template <typename S, typename V>
+void restrict_fine_mfma(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P, const V* in,
+                        const float* ins, float2* out, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
+  k_restrict_fine_mfma<S, V><<<dim3(a.nagg, (nb + TMF_NB - 1) / TMF_NB), 256, 0, s>>>(ad.members, a.asz / 16, N, fs,
+                                                                                     P, in, ins, out, cs, nb);
+  DD_LAUNCH_CHECK();
+}
+
+template <typename S, typename V>
+void prolong_fine_mfma(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P, const float2* in,
+                       V* out, float* outs, hipStream_t s, int nb) {
+  const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
+  k_prolong_fine_mfma<S, V><<<dim3(a.nagg, (nb + TMF_NB - 1) / TMF_NB), 256, 0, s>>>(ad.members, a.asz / 16, N, fs,
+                                                                                    P, in, out, outs, cs, nb);
+  DD_LAUNCH_CHECK();
+}
+
 template <typename T, typename S>
 void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
                    const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_transfer_mfma(nb, N, a.asz)) return restrict_fine_mfma<S, float2>(g, a, ad, N, P, in, nullptr, out, s, nb);
+  }
   const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
   rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
     constexpr int RB = decltype(rb)::value;
@@ -154,6 +339,7 @@ void restrict_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int 
 
 void restrict_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
                       const __half2* in, const float* ins, float2* out, hipStream_t s, int nb) {
+  if (use_transfer_mfma(nb, N, a.asz)) return restrict_fine_mfma<__half2, __half2>(g, a, ad, N, P, in, ins, out, s, nb);
   const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N, ss = (long long)g.nblk * 16;
   rhs_chunks<float>(nb, [&](auto rb, int first, int nch) {
     constexpr int RB = decltype(rb)::value;
@@ -210,6 +396,9 @@ __global__ void __launch_bounds__(256) k_prolong_fine(const int* __restrict__ bl
 template <typename T, typename S>
 void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const S* P,
                   const C<T>* in, C<T>* out, hipStream_t s, int nb) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_transfer_mfma(nb, N, a.asz)) return prolong_fine_mfma<S, float2>(g, a, ad, N, P, in, out, nullptr, s, nb);
+  }
   const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N;
   rhs_chunks<T>(nb, [&](auto rb, int first, int nch) {
     constexpr int RB = decltype(rb)::value;
@@ -221,6 +410,7 @@ void prolong_fine(const FineGeom& g, const AggTables& a, const AggDev& ad, int N
 
 void prolong_fine_hs(const FineGeom& g, const AggTables& a, const AggDev& ad, int N, const __half2* P,
                      const float2* in, __half2* out, float* outs, hipStream_t s, int nb) {
+  if (use_transfer_mfma(nb, N, a.asz)) return prolong_fine_mfma<__half2, __half2>(g, a, ad, N, P, in, out, outs, s, nb);
   const long long fs = (long long)g.nblk * 192, cs = (long long)a.nagg * 2 * N, ss = (long long)g.nblk * 16;
   rhs_chunks<float>(nb, [&](auto rb, int first, int nch) {
     constexpr int RB = decltype(rb)::value;

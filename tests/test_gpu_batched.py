@@ -17,7 +17,7 @@ import workloads as W
 from oracle.aggregation import Aggregation
 from oracle.dirac import WilsonClover
 from oracle.sap import sap_sweep
-from tests.gpu_util import dev, empty, export_P, host, oracle_from_gpu, relerr, say
+from tests.gpu_util import dev, empty, export_P, host, oracle_from_gpu, relerr, say, to_params
 from tests.test_gpu_hierarchy import Setup, _p
 
 pytestmark = pytest.mark.gpu
@@ -160,3 +160,37 @@ def test_batched_smoothers(dd, three):
         z = dev(z0)
         dd.sap_smooth(three.H, 1, dev(b), z, 1, nrhs=nrhs, prec=prec)
         _check(host(z), ref, tol, f"coarse SAP prec={prec}")
+
+
+@pytest.mark.parametrize("nrhs", [12, 20])
+def test_batched_transfers_matrix_cores(dd, nrhs):
+    """Batches of 8 or more fields take the matrix-core restriction and
+    prolongation (16 fields per launch chunk, here one full chunk and one of
+    4 after it): against the oracle at FP32 accuracy, with N = 20 test
+    vectors (two 16-column tiles, the second partly empty).  Tolerance: each
+    coarse entry of the restriction sums 96 FP32 products per 2^4 block and
+    then 16 block sums, so its rounding error is typically
+    (sqrt(96) + sqrt(16)) u ~ 8e-7 (u = 2^-24), at most a few times that:
+    4e-6."""
+    S = Setup(dd, (8, 8, 8, 16), _p(2, [(4, 4, 4, 4)], [20]), prec=dd.F32)
+    agg = Aggregation(S.dims, (4, 4, 4, 4), export_P(dd, S.H, 0, 20))
+    v = W.gaussian_spinor(S.dims, 511, nrhs=nrhs)
+    c = W.gaussian_field(agg.cdims, 40, 512, nrhs=nrhs)
+    rref = np.stack([agg.restrict(x) for x in v])
+    pref = np.stack([v[r] + agg.prolong(c[r]) for r in range(nrhs)])
+    out = empty(c.shape)
+    dd.restrict(S.H, 0, dev(v), out, nrhs=nrhs, prec=dd.F32)
+    _check(host(out), rref, 4e-6, f"restrict fine on the matrix cores, nrhs={nrhs}")
+    f = dev(v)
+    dd.prolong(S.H, 0, dev(c), f, nrhs=nrhs, prec=dd.F32)
+    _check(host(f), pref, 4e-6, f"prolong fine on the matrix cores, nrhs={nrhs}")
+    # FP16 interpolation (FP32 arithmetic): within the FP16-storage band
+    P16 = to_params(dd, S.p, dd.F32, half=True)
+    H16 = dd.build_hierarchy(S.ctx, P16, dev(S.tv))
+    a16 = Aggregation(S.dims, (4, 4, 4, 4), export_P(dd, H16, 0, 20))
+    out = empty(c.shape)
+    dd.restrict(H16, 0, dev(v), out, nrhs=nrhs, prec=dd.F16)
+    e = max(np.linalg.norm(host(out)[r] - a16.restrict(v[r])) / np.linalg.norm(a16.restrict(v[r]))
+            for r in range(nrhs))
+    say(f"  FP16 P, matrix cores: restrict relerr {e:.2e}")
+    assert 1e-5 < e < 4 * 2.0 ** -11

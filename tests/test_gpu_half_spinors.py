@@ -83,21 +83,23 @@ def test_f16s_sap_sweep(dd, three_s):
     assert _in_band(e, SMOOTH_TOL)
 
 
-def test_f16s_restrict_prolong(dd, two_s):
+@pytest.mark.parametrize("nrhs", [2, 12])
+def test_f16s_restrict_prolong(dd, two_s, nrhs):
+    """(12 fields: the matrix-core kernels)"""
     agg = Aggregation(two_s.dims, (4, 4, 4, 4), export_P(dd, two_s.H, 0, 4))
-    v = W.gaussian_spinor(two_s.dims, 172, nrhs=2)
-    c = W.gaussian_field(agg.cdims, 8, 173, nrhs=2)
+    v = W.gaussian_spinor(two_s.dims, 172, nrhs=nrhs)
+    c = W.gaussian_field(agg.cdims, 8, 173, nrhs=nrhs)
     out = empty(c.shape)
-    dd.restrict(two_s.H, 0, dev(v), out, nrhs=2, prec=dd.F16S)
-    for r in range(2):
+    dd.restrict(two_s.H, 0, dev(v), out, nrhs=nrhs, prec=dd.F16S)
+    for r in range(nrhs):
         e = relerr(host(out)[r], agg.restrict(v[r]))
         say(f"  FP16-spinor restrict relerr {e:.2e}")
         assert _in_band(e, APPLY_TOL)
     # prolongation adds the decoded FP16 field P c to the canonical one
-    f0 = W.gaussian_spinor(two_s.dims, 174, nrhs=2)
+    f0 = W.gaussian_spinor(two_s.dims, 174, nrhs=nrhs)
     f = dev(f0)
-    dd.prolong(two_s.H, 0, dev(c), f, nrhs=2, prec=dd.F16S)
-    for r in range(2):
+    dd.prolong(two_s.H, 0, dev(c), f, nrhs=nrhs, prec=dd.F16S)
+    for r in range(nrhs):
         pc = agg.prolong(c[r])
         e = norm(host(f)[r] - f0[r] - pc) / norm(pc)
         say(f"  FP16-spinor prolong relerr {e:.2e}")

@@ -76,10 +76,27 @@ def test_solves_dense_and_sparse(case):
         for r in range(3):
             res = norm(b[r] - op.apply(zz[r])) / norm(b[r])
             assert res <= 1e-10 and st[r]["true_relres"] <= 1e-10
+        # the path taken: the 640-unknown dense Schur matrix, or none
+        assert all(s["coarsest_dense"] == (640 if dense else 0) for s in st)
         its[dense] = [s["outer_iters"] for s in st]
         say(f"  coarse_dense={dense}: outer iterations {its[dense]}, "
             f"coarsest {[s['coarsest_iters'] for s in st]}")
     assert all(abs(a - c) <= 1 for a, c in zip(its[1], its[0]))
+
+
+def test_fp32_cycle_dense_against_sparse(case):
+    """The FP32 dense Schur product (the matrix copy the FP32 and FP16
+    preconditioners use) against the sparse FP32 product, one cycle on the
+    same hierarchy data: equal up to FP32 rounding (1e-5)."""
+    dd, p, op, ctx, tv = case
+    b = W.gaussian_spinor(DIMS, 73, nrhs=2)
+    zd, zs = empty(b.shape), empty(b.shape)
+    dd.precondition(_hier(case, dd.F32, 1), dev(b), zd, nrhs=2)
+    dd.precondition(_hier(case, dd.F32, 0), dev(b), zs, nrhs=2)
+    for r in range(2):
+        e = relerr(host(zd)[r], host(zs)[r])
+        say(f"  FP32 cycle, dense against sparse Schur product: relerr {e:.2e}")
+        assert e < 1e-5
 
 
 def test_coarse_dense_validation(case):

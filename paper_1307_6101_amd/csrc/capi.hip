@@ -888,6 +888,7 @@ int ddamg_solve_batch(int n, const ddamg_hier* hiers, const void* const* b, void
                       ddamg_solve_stats* stats, void* stream) {
   int worst = DDAMG_OK;
   int rc = guarded([&] {
+    const TraceRange range("ddamg solve batch");
     DD_REQUIRE(n >= 1 && n <= DDAMG_MAX_SYSTEMS, "n must be 1..DDAMG_MAX_SYSTEMS");
     DD_REQUIRE(hiers && b && z, "null argument");
     std::vector<Hierarchy*> hs(n);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -150,5 +151,15 @@ inline void rhs_chunks(int nb, F&& f) {
 }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// A named range on the host timeline for tracing tools (ROCTx: rocprofv3
+// --marker-trace shows each range with the kernels launched inside it);
+// nearly free when no tool listens.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 }  // namespace ddamg

@@ -751,6 +751,7 @@ void Hierarchy::gmres_dev(int l, Op op, const C<T>* b, C<T>* x, int m, int cycle
 }
 
 template <typename T> void Hierarchy::coarsest_solve(const C<T>* b, C<T>* z, int nb, int poll) {
+  const TraceRange range("ddamg coarsest solve");
   const int c = L - 1;
   const LevelStore& L_ = lv[c];
   Work<T>& W = work<T>(c);
@@ -836,7 +837,11 @@ template <typename T> void Hierarchy::apply_pre_graph(int nb) {
 // ---------------------------------------------------------------------------
 // the level-l cycle (Alg. 1; Alg. 2 replaces the recursive call by FGMRES)
 // ---------------------------------------------------------------------------
+static const char* const CYCLE_RANGE[4] = {"ddamg cycle level 0", "ddamg cycle level 1", "ddamg cycle level 2",
+                                            "ddamg cycle level 3"};
+
 template <typename T> void Hierarchy::cycle(int l, const C<T>* b, C<T>* z, int nb) {
+  const TraceRange range(CYCLE_RANGE[l]);
   lt_push(l);
   Work<T>& W = work<T>(l);
   Work<T>& Wc = work<T>(l + 1);
@@ -952,6 +957,7 @@ template <> DevArray<C<double>>& outerZ<double>(Hierarchy& H) { return H.oZ64; }
 template <> DevArray<C<float>>& outerZ<float>(Hierarchy& H) { return H.oZ32; }
 
 template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_solve_stats* st, int nb) {
+  const TraceRange range("ddamg outer FGMRES");
   const long long n = lv[0].n, vs = (long long)nb * n;
   const int m = p.nkv;
   ensure_batch<T>(nb);
@@ -1198,6 +1204,7 @@ template <typename T> void Hierarchy::ensure_batch(int nb) {
 }
 
 void Hierarchy::build_level(int l, bool from32) {
+  const TraceRange range("ddamg P and Galerkin operator");
   ++gen;
   LevelStore& F = lv[l];
   LevelStore& Cc = lv[l + 1];
@@ -1270,6 +1277,7 @@ void Hierarchy::build_dense_schur(int c) {
 // done, so the N updates are independent and run together (in chunks of
 // the work capacity).
 template <typename T> void Hierarchy::initial_setup(int l) {
+  const TraceRange range("ddamg initial setup (Alg. 3)");
   LevelStore& F = lv[l];
   const long long n = F.n;
   const int N = F.N;
@@ -1301,6 +1309,7 @@ template <typename T> void Hierarchy::initial_setup(int l) {
 }
 
 template <typename T> void Hierarchy::iterative_setup(int l, int i) {
+  const TraceRange range("ddamg iterative setup (Alg. 4)");
   if (l >= L - 1) return;
   const int N = lv[l].N;
   const int cap = work<T>(l).cap;

@@ -390,8 +390,12 @@ int ddamg_precondition(ddamg_hier hier, const void* b, void* z, int nrhs, int la
  * stopping tests and restarts (at every level), so each result is the one
  * a solve of that system alone gives, up to rounding.  stats (host, may be
  * NULL) receives one record per right-hand side; `seconds` is the wall
- * time of its batch.  Returns DDAMG_ENOCONV / DDAMG_ENONFINITE if any
- * right-hand side did (a non-finite inner residual fails the whole batch). */
+ * time of its batch.  A restart cycle that reduces a system's recomputed
+ * residual by less than 0.1 % ends that system (stagnation: a tolerance
+ * below what FP64 reaches, or a preconditioner that does not help) with
+ * DDAMG_ENOCONV instead of running out its restarts.  Returns DDAMG_ENOCONV
+ * / DDAMG_ENONFINITE if any right-hand side did (a non-finite inner
+ * residual fails the whole batch). */
 int ddamg_solve(ddamg_hier hier, const void* b, void* z, int nrhs, ddamg_solve_stats* stats,
                 void* stream);
 

@@ -71,6 +71,10 @@ static inline double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
 // launches), then one read per step
 constexpr int COARSE_POLL = 1;
 
+// the outer FGMRES stops a system whose recomputed residual a restart cycle
+// has reduced by less than this factor (stagnation)
+constexpr double OUTER_STAGNATION = 0.999;
+
 // largest coarsest Schur system (unknowns) stored as a dense matrix: 2048^2
 // complex entries are 64 MiB in FP64 and 32 MiB in FP32
 constexpr long long DENSE_SCHUR_MAX = 2048;
@@ -1012,6 +1016,7 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       any = any || active[r];
     }
     if (!any) break;
+    const std::vector<double> beta_start = beta;
     bscale_host<double>(*red, scale, w, V, n, nb, s);
     std::fill(H.begin(), H.end(), cd(0));
     std::fill(g.begin(), g.end(), cd(0));
@@ -1112,6 +1117,12 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
         active[r] = 0;
       } else if (beta[r] <= target[r]) {
         status[r] = DDAMG_OK;
+        active[r] = 0;
+      } else if (beta[r] > OUTER_STAGNATION * beta_start[r]) {
+        // a whole restart cycle left the recomputed residual where it was
+        // (a tolerance below what the arithmetic reaches, or a useless
+        // preconditioner): more cycles would not change it
+        status[r] = DDAMG_ENOCONV;
         active[r] = 0;
       }
     }

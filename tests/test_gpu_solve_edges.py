@@ -84,3 +84,20 @@ def test_parameter_validation(dd, two, field, value):
     with pytest.raises(dd.DDAMGError) as ei:
         dd.build_hierarchy(two.ctx, P, dev(two.tv))
     assert ei.value.status == dd.EINVAL
+
+
+def test_stagnation_ends_the_solve(dd, two):
+    """A tolerance below what FP64 reaches: once a restart cycle no longer
+    reduces the recomputed residual, the solve stops with ENOCONV instead of
+    running out its 100 restarts, and the iterate it returns is the
+    converged one."""
+    p = dict(two.p, tol=1e-18, max_restarts=100)
+    H = dd.build_hierarchy(two.ctx, to_params(dd, p, dd.F32), dev(two.tv))
+    b = W.gaussian_spinor(two.dims, 1006)
+    z = empty(b.shape)
+    rc, st = dd.solve(H, dev(b), z)
+    say(f"  stagnation: rc={rc} {st[0]}")
+    assert rc == dd.ENOCONV and st[0]["status"] == dd.ENOCONV
+    assert st[0]["restarts"] < 20
+    zz = host(z)
+    assert norm(b - two.op.apply(zz)) / norm(b) < 1e-13

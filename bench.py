@@ -924,7 +924,9 @@ def big_workload(args, name, cfg, dd, W, np, torch):
             raise RuntimeError(f"solve failed rc={rc}")
         return time.time() - t, st
 
-    H, t_setup = build(dd.F32, True, min(BATCH_RHS, 8 if cfg["levels"] == 4 else BATCH_RHS))
+    # batch: the 20 setup test vectors in one batch (and the 12 sources in
+    # one batched solve) on 32^3x64; 8 on the four-level lattice
+    H, t_setup = build(dd.F32, True, 8 if cfg["levels"] == 4 else max(BATCH_RHS, cfg["ntv"][0]))
     log(f"[bench] mixed FP16-storage setup {t_setup:.2f}s")
     for i in range(args.warmup):
         tw, st = solve(H, nsrc)

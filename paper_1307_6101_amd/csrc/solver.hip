@@ -1557,6 +1557,8 @@ void Hierarchy::reserve(int nrhs) {
   if (p.precond_prec == DDAMG_F32) at(0.f);
   else at(0.0);
   gm();
+  // the outer solver's device records of the batch graph solve
+  if (p.graph == 1) gmo();
   setup_flags.alloc(2);
   // canonical-layout level calls and the preconditioner call: two fields of
   // the finest level per right-hand side at the hierarchy's precision

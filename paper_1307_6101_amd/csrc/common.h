@@ -59,13 +59,24 @@ template <typename V> __host__ __device__ inline V cjmul(V a, V b) {
   V c; c.x = a.x * b.x + a.y * b.y; c.y = a.x * b.y - a.y * b.x; return c;
 }
 template <typename V> __host__ __device__ inline V cconj(V a) { a.y = -a.y; return a; }
-// acc += a * b
+// fused multiply-add of one real type (host and device)
+__host__ __device__ inline double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ inline float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// acc += a * b, as four fused multiply-adds into the accumulator (written
+// as acc + (a.x b.x - a.y b.y) the compiler may only fuse the inner
+// difference, leaving a multiply and an add besides)
 template <typename V> __host__ __device__ inline void cfma(V& acc, V a, V b) {
-  acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+  acc.x = rfma(a.x, b.x, acc.x);
+  acc.x = rfma(-a.y, b.y, acc.x);
+  acc.y = rfma(a.x, b.y, acc.y);
+  acc.y = rfma(a.y, b.x, acc.y);
 }
 // acc += conj(a) * b
 template <typename V> __host__ __device__ inline void cjfma(V& acc, V a, V b) {
-  acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+  acc.x = rfma(a.x, b.x, acc.x);
+  acc.x = rfma(a.y, b.y, acc.x);
+  acc.y = rfma(a.x, b.y, acc.y);
+  acc.y = rfma(-a.y, b.x, acc.y);
 }
 template <typename V, typename S> __host__ __device__ inline V cscale(V a, S s) {
   a.x *= s; a.y *= s; return a;

@@ -34,6 +34,7 @@ struct CoarseGeom {
   std::vector<int> site_blk;   // [V] block id
   std::vector<int> site_pos;   // [V] block id * bs + index in the block
   std::vector<unsigned> inmask;  // [V] bit k: nbr9[k] lies in the site's block
+  int kmax = 9;                // most set bits of any inmask (blocks one MR step reads per site)
   // parity (odd-even)
   bool bipartite;
   std::vector<int> even, odd;
@@ -73,6 +74,7 @@ struct SapTables {
   const int* site_pos;         // [V]
   const unsigned* inmask;      // [V]
   int nblk, bs;
+  int kmax;                    // most operator blocks an MR step reads for one site
 };
 
 // one SAP colour pass z <- z + MR_blocks(b - D z) on the blocks of colour

@@ -76,6 +76,8 @@ CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]) {
         if (g.site_blk[g.nbr9[s * 9 + k]] == g.site_blk[s]) m |= 1u << k;
       g.inmask[s] = m;
     }
+    g.kmax = 0;
+    for (int s = 0; s < g.V; ++s) g.kmax = std::max(g.kmax, __builtin_popcount(g.inmask[s]));
   }
   return g;
 }
@@ -430,12 +432,17 @@ __device__ inline C<T> block_alpha_wave(const T* __restrict__ part, int blk, int
   return s2 > T(0) ? mk<T>(s0 / s2, s1 / s2) : czero<T>();
 }
 
+// The workgroup of the site at position pos0 + blockIdx.x of the block-major
+// order (blk_sites and site_pos are inverse tables) finds its block without a
+// table read; the inputs of the step are read before the step size of the
+// previous step is known, which is then applied to them in registers.
 template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const int* __restrict__ csites,
-                                                   SapTables tb, int step, const C<T>* __restrict__ rho_prev,
-                                                   const C<T>* __restrict__ q_prev, const T* __restrict__ part_prev,
-                                                   C<T>* __restrict__ rho_cur, C<T>* __restrict__ q_cur,
-                                                   T* __restrict__ part_cur, C<T>* __restrict__ z, long long n) {
+                                                   SapTables tb, int pos0, int step,
+                                                   const C<T>* __restrict__ rho_prev, const C<T>* __restrict__ q_prev,
+                                                   const T* __restrict__ part_prev, C<T>* __restrict__ rho_cur,
+                                                   C<T>* __restrict__ q_cur, T* __restrict__ part_cur,
+                                                   C<T>* __restrict__ z, long long n) {
   __shared__ C<T> vin[RB][9][64];
   __shared__ C<T> prow[SW][RB][64];
   __shared__ C<T> alpha_s[RB];
@@ -449,25 +456,54 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
   z += off;
   part_prev += poff;
   part_cur += poff;
-  const int pos = tb.site_pos[site], blk = pos / tb.bs;
-  const unsigned mask = tb.inmask[site];   // self and the in-block neighbours
-  const size_t bsz = (size_t)d * d;
-  SiteCols<T, S, NCH, RB> sc;
-  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, mask, w * NCH, lane, d);
+  const int pos = pos0 + blockIdx.x, blk = pos / tb.bs;
   if (step > 0 && w < RB) {
     const C<T> a = block_alpha_wave<T>(part_prev + w * pn, blk, tb.bs, lane);
     if (lane == 0) alpha_s[w] = a;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < RB * 9 * d; e += blockDim.x) {
-    const int r = e / (9 * d), kj = e % (9 * d), k = kj / d, j = kj % d;
-    if ((mask >> k) & 1u) {
-      const size_t o = r * n + (size_t)op.nbr9[site * 9 + k] * d + j;
-      C<T> v = rho_prev[o];
-      if (step > 0) v = csub(v, cmul(alpha_s[r], q_prev[o]));
-      vin[r][k][j] = v;
+  const unsigned mask = tb.inmask[site];   // self and the in-block neighbours
+  const size_t bsz = (size_t)d * d;
+  SiteCols<T, S, NCH, RB> sc;
+  sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, mask, w * NCH, lane, d);
+  // this thread's share of the in-block inputs, and the site's own z and
+  // previous residual for the update of z
+  constexpr int EPT = (RB * 9 * 64 + 64 * SW - 1) / (64 * SW);
+  C<T> rv[EPT], qv[EPT];
+  int slot[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 64 * SW;
+    slot[i] = -1;
+    rv[i] = qv[i] = czero<T>();
+    if (e < RB * 9 * d) {
+      const int r = e / (9 * d), k = (e % (9 * d)) / d, j = e % d;
+      if ((mask >> k) & 1u) {
+        const size_t o = r * n + (size_t)op.nbr9[site * 9 + k] * d + j;
+        rv[i] = rho_prev[o];
+        if (step > 0) qv[i] = q_prev[o];
+        slot[i] = e;
+      }
     }
   }
+  C<T> zown[RB], rown[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    zown[r] = rown[r] = czero<T>();
+    if (step > 0 && w == 0 && lane < d) {
+      const size_t o = r * n + (size_t)site * d + lane;
+      zown[r] = z[o];
+      rown[r] = rho_prev[o];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (slot[i] >= 0) {
+      const int e = slot[i], r = e / (9 * d), k = (e % (9 * d)) / d, j = e % d;
+      C<T> v = rv[i];
+      if (step > 0) v = csub(v, cmul(alpha_s[r], qv[i]));
+      vin[r][k][j] = v;
+    }
   __syncthreads();
   C<T> q[RB];
   sc.apply(vin, q);
@@ -482,9 +518,8 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
         rho_cur[o] = rho;
         q_cur[o] = q[r];
         if (step > 0) {
-          C<T> zz = z[o];
-          cfma(zz, alpha_s[r], rho_prev[o]);
-          z[o] = zz;
+          cfma(zown[r], alpha_s[r], rown[r]);
+          z[o] = zown[r];
         }
       }
       const C<T> qq = lane < d ? q[r] : czero<T>();
@@ -502,12 +537,167 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
   }
 }
 
+// The MR step of one field in FP32 arithmetic for blocks in which no site
+// has more than KM of its nine operator blocks inside (2^4 blocks: itself and
+// four neighbours).  Four wavefronts per site, wavefront w owning columns
+// w*NCH .. w*NCH+NCH-1, lane i the row i; the prefetch registers hold only
+// the blocks the site reads (the mask's set bits in order), so that per
+// register twice the operator bytes of k_sap_q's nine-block layout are in
+// flight: the step is bound by the loads a compute unit keeps outstanding.
+constexpr int SW4 = 4;
+template <typename S, int NCH, int KM>
+__global__ void __launch_bounds__(64 * SW4) k_sap_q1(CoarseOpView<float, S> op, const int* __restrict__ csites,
+                                                     SapTables tb, int pos0, int step,
+                                                     const float2* __restrict__ rho_prev,
+                                                     const float2* __restrict__ q_prev,
+                                                     const float* __restrict__ part_prev, float2* __restrict__ rho_cur,
+                                                     float2* __restrict__ q_cur, float* __restrict__ part_cur,
+                                                     float2* __restrict__ z, long long n) {
+  __shared__ float2 vin[9][64];
+  __shared__ float2 prow[SW4][64];
+  __shared__ float2 alpha_s;
+  const int site = csites[blockIdx.x], w = threadIdx.x >> 6, lane = threadIdx.x & 63, d = op.d;
+  const long long off = (long long)blockIdx.y * n, poff = (long long)blockIdx.y * op.V * 4;
+  rho_prev += off;
+  q_prev += off;
+  rho_cur += off;
+  q_cur += off;
+  z += off;
+  part_prev += poff;
+  part_cur += poff;
+  const int pos = pos0 + blockIdx.x, blk = pos / tb.bs;
+  if (step > 0 && w == 0) {
+    const float2 a = block_alpha_wave<float>(part_prev, blk, tb.bs, lane);
+    if (lane == 0) alpha_s = a;
+  }
+  const unsigned mask = tb.inmask[site];
+  int kb[KM];
+  {
+    unsigned mm = mask;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+      kb[kk] = mm ? __builtin_ctz(mm) : -1;
+      mm &= mm - 1u;
+    }
+  }
+  const size_t bsz = (size_t)d * d;
+  const S* Kx = op.K + (size_t)site * 9 * bsz;
+  const int j0 = w * NCH, row = lane < d ? lane : 0;
+  S m[KM][NCH];
+#pragma unroll
+  for (int kk = 0; kk < KM; ++kk)
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int j = j0 + u < d ? j0 + u : 0;
+      m[kk][u] = kb[kk] >= 0 ? Kx[kb[kk] * bsz + (size_t)j * d + row] : szero<S>();
+    }
+  constexpr int EPT = (9 * 64 + 64 * SW4 - 1) / (64 * SW4);
+  float2 rv[EPT], qv[EPT];
+  int slot[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 64 * SW4;
+    slot[i] = -1;
+    rv[i] = qv[i] = czero<float>();
+    if (e < 9 * d) {
+      const int k = e / d, j = e % d;
+      if ((mask >> k) & 1u) {
+        const size_t o = (size_t)op.nbr9[site * 9 + k] * d + j;
+        rv[i] = rho_prev[o];
+        if (step > 0) qv[i] = q_prev[o];
+        slot[i] = e;
+      }
+    }
+  }
+  float2 zown = czero<float>(), rown = czero<float>();
+  const size_t own = (size_t)site * d + lane;
+  if (step > 0 && w == 0 && lane < d) {
+    zown = z[own];
+    rown = rho_prev[own];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (slot[i] >= 0) {
+      const int e = slot[i];
+      float2 v = rv[i];
+      if (step > 0) v = csub(v, cmul(alpha_s, qv[i]));
+      vin[e / d][e % d] = v;
+    }
+  __syncthreads();
+  float2 acc = czero<float>();
+#pragma unroll
+  for (int kk = 0; kk < KM; ++kk)
+    if (kb[kk] >= 0)
+#pragma unroll
+      for (int u = 0; u < NCH; ++u)
+        if (j0 + u < d) cfma(acc, ldc<float, S>(m[kk][u]), vin[kb[kk]][j0 + u]);
+  if (lane >= d) acc = czero<float>();
+  prow[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) {
+    float2 q = czero<float>(), rho = czero<float>();
+#pragma unroll
+    for (int v = 0; v < SW4; ++v) q = cadd(q, prow[v][lane]);
+    if (lane < d) {
+      rho = vin[0][lane];
+      rho_cur[own] = rho;
+      q_cur[own] = q;
+      if (step > 0) {
+        cfma(zown, alpha_s, rown);
+        z[own] = zown;
+      }
+    } else {
+      q = czero<float>();
+    }
+    float a0 = q.x * rho.x + q.y * rho.y, a1 = q.x * rho.y - q.y * rho.x, a2 = q.x * q.x + q.y * q.y;
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      float* p = part_cur + (size_t)pos * 4;
+      p[0] = a0;
+      p[1] = a1;
+      p[2] = a2;
+    }
+  }
+}
+
+// columns per wavefront of k_sap_q1 for d components: an even number
+template <typename F>
+inline void with_nch4(int d, F&& f) {
+  switch ((d + 7) / 8) {
+    case 1: f(std::integral_constant<int, 2>{}); break;
+    case 2: f(std::integral_constant<int, 4>{}); break;
+    case 3: f(std::integral_constant<int, 6>{}); break;
+    case 4: f(std::integral_constant<int, 8>{}); break;
+    case 5: f(std::integral_constant<int, 10>{}); break;
+    case 6: f(std::integral_constant<int, 12>{}); break;
+    case 7: f(std::integral_constant<int, 14>{}); break;
+    case 8: f(std::integral_constant<int, 16>{}); break;
+    default: throw Error(-1, "coarse levels support at most 64 components per site");
+  }
+}
+// k_sap_q1 takes the step when the arithmetic is FP32, the field is one,
+// every site reads at most five blocks and their prefetch fits 80 registers
+constexpr int Q1_KM = 5;
+template <typename T, typename S>
+inline bool use_sap_q1(const SapTables& tb, int d) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    const int nch4 = 2 * ((d + 7) / 8);
+    return tb.kmax <= Q1_KM && Q1_KM * nch4 * (int)(sizeof(S) / 4) <= 80;
+  }
+}
+
 template <typename T>
-__global__ void k_sap_fin(int d, const int* __restrict__ csites, SapTables tb, const C<T>* __restrict__ rho,
-                          const T* __restrict__ part, C<T>* __restrict__ z, long long n, long long pn) {
+__global__ void k_sap_fin(int d, const int* __restrict__ csites, SapTables tb, int pos0,
+                          const C<T>* __restrict__ rho, const T* __restrict__ part, C<T>* __restrict__ z, long long n,
+                          long long pn) {
   __shared__ C<T> alpha_s;
   const int site = csites[blockIdx.x];
-  const int blk = tb.site_pos[site] / tb.bs;
+  const int blk = (pos0 + blockIdx.x) / tb.bs;
   rho += blockIdx.y * n;
   z += blockIdx.y * n;
   part += blockIdx.y * pn;
@@ -515,12 +705,16 @@ __global__ void k_sap_fin(int d, const int* __restrict__ csites, SapTables tb, c
     const C<T> a = block_alpha_wave<T>(part, blk, tb.bs, threadIdx.x);
     if (threadIdx.x == 0) alpha_s = a;
   }
-  __syncthreads();
   const int i = threadIdx.x;
+  C<T> zz = czero<T>(), rr = czero<T>();
+  const size_t o = (size_t)site * d + i;
   if (i < d) {
-    const size_t o = (size_t)site * d + i;
-    C<T> zz = z[o];
-    cfma(zz, alpha_s, rho[o]);
+    zz = z[o];
+    rr = rho[o];
+  }
+  __syncthreads();
+  if (i < d) {
+    cfma(zz, alpha_s, rr);
     z[o] = zz;
   }
 }
@@ -531,7 +725,8 @@ void coarse_sap_colour(const CoarseOpView<T, S>& op, const SapTables& tb, int co
   if (mr_iters <= 0) return;
   DD_REQUIRE(op.d <= 64, "coarse levels support at most 64 components per site");
   const int nsites = (tb.nblk / 2) * tb.bs;
-  const int* csites = tb.blk_sites + (size_t)colour * (tb.nblk / 2) * tb.bs;   // blocks are colour-major
+  const int pos0 = colour * (tb.nblk / 2) * tb.bs;   // blocks are colour-major
+  const int* csites = tb.blk_sites + pos0;
   const long long n = (long long)op.V * op.d, pn = (long long)op.V * 4;
   with_nch(op.d, [&](auto nch) {
     constexpr int NCH = decltype(nch)::value;
@@ -542,14 +737,27 @@ void coarse_sap_colour(const CoarseOpView<T, S>& op, const SapTables& tb, int co
       k_sap_res<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(op, csites, b + o, z + o, ws.rho[1] + o, n);
       for (int t = 0; t < mr_iters; ++t) {
         const int pp = (t + 1) & 1, cc = t & 1;   // previous / current buffers
+        if constexpr (RB == 1 && std::is_same<T, float>::value) {
+          if (use_sap_q1<T, S>(tb, op.d)) {
+            with_nch4(op.d, [&](auto nch4) {
+              constexpr int NC4 = decltype(nch4)::value;
+              if constexpr (Q1_KM * NC4 * (int)(sizeof(S) / 4) <= 80) {
+                k_sap_q1<S, NC4, Q1_KM><<<dim3(nsites, nc), 64 * SW4, 0, s>>>(
+                    op, csites, tb, pos0, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po, ws.rho[cc] + o,
+                    ws.q[cc] + o, ws.part[cc] + po, z + o, n);
+              }
+            });
+            continue;
+          }
+        }
         k_sap_q<T, S, NCH, RB><<<dim3(nsites, nc), 64 * SW, 0, s>>>(
-            op, csites, tb, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po, ws.rho[cc] + o, ws.q[cc] + o,
+            op, csites, tb, pos0, t, ws.rho[pp] + o, ws.q[pp] + o, ws.part[pp] + po, ws.rho[cc] + o, ws.q[cc] + o,
             ws.part[cc] + po, z + o, n);
       }
     });
   });
   const int last = (mr_iters - 1) & 1;
-  k_sap_fin<T><<<dim3(nsites, nb), 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, tb, ws.rho[last],
+  k_sap_fin<T><<<dim3(nsites, nb), 64 * ((op.d + 63) / 64), 0, s>>>(op.d, csites, tb, pos0, ws.rho[last],
                                                                    ws.part[last], z, n, pn);
   DD_LAUNCH_CHECK();
 }

@@ -57,7 +57,7 @@ struct LevelStore {
   CoarseGeom cg;
   DevArray<int> c_nbr9, c_blk_sites, c_site_blk, c_site_pos, c_even, c_odd;
   DevArray<unsigned> c_inmask;
-  SapTables sap_tables() const { return SapTables{c_blk_sites.p, c_site_pos.p, c_inmask.p, cg.nblk, cg.bs}; }
+  SapTables sap_tables() const { return SapTables{c_blk_sites.p, c_site_pos.p, c_inmask.p, cg.nblk, cg.bs, cg.kmax}; }
   DevArray<double2> D64;           // Galerkin output: self + forward blocks, row-major
   DevArray<double2> K64, Einv64;   // nine-block column-major apply copies
   DevArray<float2> K32, Einv32;

@@ -36,16 +36,27 @@ T_START = time.time()
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 BATCH_RHS = 12          # batch size of the batched-kernel timings (the 12 spin-colour sources)
-# HBM traffic per launch of the FP32 stencil on the bench lattice, from the
-# FETCH_SIZE / WRITE_SIZE counter runs summarised in
-# profiles/dslash_clover16x32_counters.md (null once the kernel changes)
-DSLASH_F32_TRAFFIC_BYTES = 128.25e6
+# HBM traffic per launch of the FP32 stencil on the 16^3x32 lattice: None,
+# the kernel's arithmetic has changed since the FETCH_SIZE / WRITE_SIZE runs
+# of profiles/dslash_clover16x32_counters.md
+DSLASH_F32_TRAFFIC_BYTES = None
 # HBM traffic per launch of the SAP colour pass on FP16-stored links and
 # clover on the 48^3x96 lattice, from the FETCH_SIZE / WRITE_SIZE counter
 # runs summarised in profiles/ (None until taken for the current kernel)
-SAP_F16_PASS_TRAFFIC_BYTES = 6.241e9
+SAP_F16_PASS_TRAFFIC_BYTES = 6.228e9
 # the same for the pass on FP16 spinors (b, z with one FP32 scale per site)
-SAP_F16S_PASS_TRAFFIC_BYTES = 4.624e9
+SAP_F16S_PASS_TRAFFIC_BYTES = 4.616e9
+# FP32 vector peak without packed FP32 instructions (which the library does
+# not emit): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = 78.6
+# flops of one SAP update of a site (a complex multiply 6, a complex add 2,
+# real times complex 2): the residual b - D z (8 spin-projected hops of 168
+# flops: 12 for the projection, 132 for U times two half spinors, 24 to
+# rebuild and add; the two Hermitian 6x6 clover blocks 504; combining 72)
+# = 1920, then per MR step the block operator (4 hops, clover, combining:
+# 1224), the inner products (144) and the two updates (192) = 1560, three
+# steps 4680, and z += x (24): 6624
+SAP_FLOPS_PER_UPDATED_SITE = 6624
 WORKLOAD = "clover16x32_3lvl"
 HEADLINE = "clover48x96_4lvl"
 METRIC = "Dψ HBM GB/s + time-to-1e-10 solve, mixed/batched vs FP64 plain, 1 GPU"
@@ -758,10 +769,17 @@ def headline_workload(args, dd, W, np, torch):
         traffic = SAP_F16_PASS_TRAFFIC_BYTES
         kname = ("k_sap_colour<float, __half2, float2> (one SAP colour pass, FP32 arithmetic on FP16 "
                  "links and clover)")
+    sap_flops = SAP_FLOPS_PER_UPDATED_SITE * V / 2
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
-                "us_per_launch": round(dom["seconds"] * 1e6, 2)}
+                "us_per_launch": round(dom["seconds"] * 1e6, 2),
+                # the same launch against the FP32 vector units: its arithmetic
+                # intensity (6624 flop per 444 B) lies above their balance point
+                "alu": {"achieved": round(sap_flops / dom["seconds"] / 1e12, 2), "peak": VALU_F32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s",
+                        "frac": round(sap_flops / dom["seconds"] / 1e12 / VALU_F32_PEAK_TFLOPS, 4),
+                        "flops_per_launch": sap_flops}}
 
     cpu = None
     if not args.no_cpu_baseline:

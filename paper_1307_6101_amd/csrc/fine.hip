@@ -406,19 +406,16 @@ void dslash_hs(const FineOpView<double>& op, const __half2* in, const float* ins
 // link U) or backward (the upper site, U^H), with the link passed as the site
 // applies it; the backward hop's projection phases are the forward ones times
 // -1 (sg), so every lane runs the same instructions.
-template <typename T, typename S, int MU>
-__device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, const C<T> (&u)[9],
-                                   C<T> acc[12]) {
+template <typename T, int MU, typename G>
+__device__ inline void oriented_hop(G&& get, T sg, const C<T> (&u)[9], C<T> acc[12]) {
   using P = Proj<MU>;
-  constexpr int bit = 1 << MU;
   constexpr int c0 = (4 - P::K0) & 3, c1 = (4 - P::K1) & 3;
-  const T sg = (loc & bit) ? T(-1) : T(1);
   C<T> h[6];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const C<T> p0 = rs[a * 256 + (t ^ bit)], p1 = rs[(3 + a) * 256 + (t ^ bit)];
-    const C<T> q0 = mul_ik<P::K0>(rs[(P::J0 * 3 + a) * 256 + (t ^ bit)]);
-    const C<T> q1 = mul_ik<P::K1>(rs[(P::J1 * 3 + a) * 256 + (t ^ bit)]);
+    const C<T> p0 = get(a), p1 = get(3 + a);
+    const C<T> q0 = mul_ik<P::K0>(get(P::J0 * 3 + a));
+    const C<T> q1 = mul_ik<P::K1>(get(P::J1 * 3 + a));
     h[a] = mk<T>(fma(sg, q0.x, p0.x), fma(sg, q0.y, p0.y));
     h[3 + a] = mk<T>(fma(sg, q1.x, p1.x), fma(sg, q1.y, p1.y));
   }
@@ -436,9 +433,20 @@ __device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, 
     }
 }
 
-// The site's in-block links: kept in registers across the MR steps (FP32
-// and FP16 storage) or read again at every step (FP64, where registers do
-// not suffice).  The clover is read at every step: keeping it too (144 more
+// The in-block hop of direction MU, the neighbour's spinor in LDS (rs,
+// [12][256], the site at column t): forward for the lower site of the pair,
+// backward for the upper one
+template <typename T, typename S, int MU>
+__device__ inline void inblock_hop(const C<T>* __restrict__ rs, int t, int loc, const C<T> (&u)[9],
+                                   C<T> acc[12]) {
+  constexpr int bit = 1 << MU;
+  const T sg = (loc & bit) ? T(-1) : T(1);
+  oriented_hop<T, MU>([&](int c) { return rs[c * 256 + (t ^ bit)]; }, sg, u, acc);
+}
+
+// The site's in-block links: loaded into registers once per pass for the
+// residual's in-block hops and the MR steps (FP32 and FP16 storage) or read
+// again at every use (FP64, where registers do not suffice).  The clover is read at every step: keeping it too (144 more
 // registers in FP32) leaves one wavefront per SIMD and was measured slower.
 // The link of in-block direction mu as the site applies it: the link
 // joining loc and loc ^ (1 << mu) belongs to the lower site, which applies
@@ -507,35 +515,42 @@ template <typename T> __device__ inline void pin12(C<T> (&acc)[12]) {
   for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[c].x), "+v"(acc[c].y));
 }
 
-// The hops of direction MU in the residual of a SAP block site, whose
-// block's current z is staged in LDS (rs, [12][256], the site at column t):
-// of the two neighbours in direction MU one lies in the block and is read
-// from LDS, the other from memory.
+// The out-of-block hop of direction MU in the residual of a SAP block site:
+// the neighbour outside the block is x+mu for the upper site of the pair
+// (link U_mu(x), the site's own) and x-mu for the lower one (link
+// U_mu(x-mu) of the neighbour block's site, applied as U^H).  The link is
+// loaded oriented, so both kinds of site run the same instructions.
 template <typename T, typename S, typename V, int MU>
-__device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const V* __restrict__ in, const float* __restrict__ ins,
-                                   const C<T>* rs, int t, int blk, int loc, const Nbr8& nb8, C<T> (&acc)[12]) {
+__device__ inline void sap_outer_hop(const FineOpView<T, S>& op, const V* __restrict__ in,
+                                     const float* __restrict__ ins, int blk, int loc, const Nbr8& nb8,
+                                     C<T> (&acc)[12]) {
   constexpr int bit = 1 << MU;
-  const bool up = loc & bit;   // the forward neighbour is outside the block
+  const bool up = loc & bit;
+  const int nbb = up ? nb8.v[2 * MU] : nb8.v[2 * MU + 1];
   C<T> psi[12], u[9];
-  // forward: psi(x+mu), U_mu(x)
-  if (up) {
-    load_site<T, V>(in, ins, nb8.v[2 * MU], loc ^ bit, psi);
-  } else {
+  load_site<T, V>(in, ins, nbb, loc ^ bit, psi);
+  const S* p = op.U + (long long)(up ? blk : nbb) * 576 + MU * 144 + (up ? loc : loc ^ bit);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
-  }
-  load_link<T, S>(op.U, blk, loc, MU, u);
-  hop_apply<T, MU, true>(psi, u, acc);
-  // backward: psi(x-mu), U_mu(x-mu)^H
-  const int nb = up ? blk : nb8.v[2 * MU + 1];
-  if (up) {
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = rs[c * 256 + (t ^ bit)];
-  } else {
-    load_site<T, V>(in, ins, nb, loc ^ bit, psi);
-  }
-  load_link<T, S>(op.U, nb, loc ^ bit, MU, u);
-  hop_apply<T, MU, false>(psi, u, acc);
+    for (int b = 0; b < 3; ++b) {
+      const C<T> v = ldc<T, S>(p[(up ? a * 3 + b : b * 3 + a) * 16]);
+      u[a * 3 + b] = up ? v : cconj(v);
+    }
+  oriented_hop<T, MU>([&](int c) { return psi[c]; }, up ? T(1) : T(-1), u, acc);
+}
+
+// Both hops of direction MU in the residual: the out-of-block one from
+// memory, the in-block one from the staged z (rs) with the link the site
+// keeps for its MR steps
+template <typename T, typename S, typename V, int MU, typename B>
+__device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const V* __restrict__ in, const float* __restrict__ ins,
+                                   const C<T>* rs, int t, int blk, int loc, const Nbr8& nb8, const B& bop,
+                                   C<T> (&acc)[12]) {
+  sap_outer_hop<T, S, V, MU>(op, in, ins, blk, loc, nb8, acc);
+  C<T> u[9];
+  bop.link(op, blk, loc, MU, u);
+  inblock_hop<T, S, MU>(rs, t, loc, u, acc);
   pin12<T>(acc);
 }
 
@@ -584,16 +599,18 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
 #pragma unroll
       for (int c = 0; c < 12; ++c) rs[c * 256 + t] = zz[c];
     }
+    // the in-block links, for the residual's in-block hops and the MR steps
+    bop.load(op, blk, loc, valid);
     __syncthreads();
     if (valid) {
       const Nbr8 nb8 = load_nbr8(op.nbr, blk);
       C<T> acc[12], zz[12], dz[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = czero<T>();
-      sap_hops_mu<T, S, V, 0>(op, z, zs, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, V, 1>(op, z, zs, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, V, 2>(op, z, zs, rs, t, blk, loc, nb8, acc);
-      sap_hops_mu<T, S, V, 3>(op, z, zs, rs, t, blk, loc, nb8, acc);
+      sap_hops_mu<T, S, V, 0>(op, z, zs, rs, t, blk, loc, nb8, bop, acc);
+      sap_hops_mu<T, S, V, 1>(op, z, zs, rs, t, blk, loc, nb8, bop, acc);
+      sap_hops_mu<T, S, V, 2>(op, z, zs, rs, t, blk, loc, nb8, bop, acc);
+      sap_hops_mu<T, S, V, 3>(op, z, zs, rs, t, blk, loc, nb8, bop, acc);
 #pragma unroll
       for (int c = 0; c < 12; ++c) zz[c] = rs[c * 256 + t];
       if constexpr (CL) clover_mul<T>([&](int e) { return ldc<T, S>(cl[e * 256 + t]); }, zz, dz);
@@ -610,8 +627,6 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       for (int c = 0; c < 12; ++c) rho[c] = czero<T>();
     }
     __syncthreads();   // rs is rewritten by the first MR step
-    // the block operator is read after the residual, which needs the registers
-    bop.load(op, blk, loc, valid);
 #pragma unroll
     for (int c = 0; c < 12; ++c) x[c] = czero<T>();
 
@@ -638,11 +653,14 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       T qr_re = 0, qr_im = 0, qq = 0;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        q[c].x -= T(0.5) * acc[c].x;
-        q[c].y -= T(0.5) * acc[c].y;
-        qr_re += q[c].x * rho[c].x + q[c].y * rho[c].y;
-        qr_im += q[c].x * rho[c].y - q[c].y * rho[c].x;
-        qq += q[c].x * q[c].x + q[c].y * q[c].y;
+        q[c].x = rfma(T(-0.5), acc[c].x, q[c].x);
+        q[c].y = rfma(T(-0.5), acc[c].y, q[c].y);
+        qr_re = rfma(q[c].x, rho[c].x, qr_re);
+        qr_re = rfma(q[c].y, rho[c].y, qr_re);
+        qr_im = rfma(q[c].x, rho[c].y, qr_im);
+        qr_im = rfma(-q[c].y, rho[c].x, qr_im);
+        qq = rfma(q[c].x, q[c].x, qq);
+        qq = rfma(q[c].y, q[c].y, qq);
       }
       qr_re = sum16<T>(qr_re);
       qr_im = sum16<T>(qr_im);
@@ -652,8 +670,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         cfma(x[c], alpha, rho[c]);
-        C<T> aq = cmul(alpha, q[c]);
-        rho[c] = csub(rho[c], aq);
+        cfma(rho[c], mk<T>(-alpha.x, -alpha.y), q[c]);
       }
       __syncthreads();
     }

@@ -43,9 +43,9 @@ DSLASH_F32_TRAFFIC_BYTES = None
 # HBM traffic per launch of the SAP colour pass on FP16-stored links and
 # clover on the 48^3x96 lattice, from the FETCH_SIZE / WRITE_SIZE counter
 # runs summarised in profiles/ (None until taken for the current kernel)
-SAP_F16_PASS_TRAFFIC_BYTES = 6.228e9
+SAP_F16_PASS_TRAFFIC_BYTES = 5.572e9
 # the same for the pass on FP16 spinors (b, z with one FP32 scale per site)
-SAP_F16S_PASS_TRAFFIC_BYTES = 4.616e9
+SAP_F16S_PASS_TRAFFIC_BYTES = 4.122e9
 # FP32 vector peak without packed FP32 instructions (which the library does
 # not emit): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 78.6

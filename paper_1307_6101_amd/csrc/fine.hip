@@ -554,6 +554,19 @@ __device__ inline void sap_hops_mu(const FineOpView<T, S>& op, const V* __restri
   pin12<T>(acc);
 }
 
+// a site's spinor from its stored components (and FP16 scale m), as load_site
+template <typename T, typename V>
+__device__ inline void decode_kept(const V (&raw)[12], float m, C<T> v[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    v[c] = ldc<T, V>(raw[c]);
+    if constexpr (std::is_same<V, __half2>::value) {
+      v[c].x *= T(m);
+      v[c].y *= T(m);
+    }
+  }
+}
+
 // one workgroup per (chunk of 16 blocks, field of the batch), gx chunks;
 // b and z in spinor storage V (bs, zs: their site scales for FP16)
 template <typename T, typename S, typename V>
@@ -589,13 +602,27 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       for (int e = 0; e < 36; ++e) cl[e * 256 + t] = pa[e * 16];
     }
     // the block's z in LDS: in-block neighbours and the site itself come
-    // from there, the other neighbours from memory
+    // from there, the other neighbours from memory.  In FP32 arithmetic the
+    // site's z also stays in registers as stored (and its scale) for the
+    // final z += x
+    constexpr bool KZ = !std::is_same<T, double>::value;
+    V zkeep[KZ ? 12 : 1];
+    float zsk = 1.f;
     {
       C<T> zz[12];
-      if (valid) load_site<T, V>(z, zs, blk, loc, zz);
-      else
 #pragma unroll
-        for (int c = 0; c < 12; ++c) zz[c] = czero<T>();
+      for (int c = 0; c < 12; ++c) zz[c] = czero<T>();
+      if (valid) {
+        if constexpr (KZ) {
+          const V* pz = z + (long long)blk * 192 + loc;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) zkeep[c] = pz[c * 16];
+          if constexpr (HS) zsk = zs[(long long)blk * 16 + loc];
+          decode_kept<T, V>(zkeep, zsk, zz);
+        } else {
+          load_site<T, V>(z, zs, blk, loc, zz);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c) rs[c * 256 + t] = zz[c];
     }
@@ -675,18 +702,13 @@ __global__ void __launch_bounds__(256) k_sap_colour(FineOpView<T, S> op, const i
       __syncthreads();
     }
     if (valid) {
-      if constexpr (HS) {
-        // z + x re-encoded with the site's new scale
-        C<T> zz[12];
-        load_site<T, V>(z, zs, blk, loc, zz);
+      // z + x (for FP16 spinors re-encoded with the site's new scale)
+      C<T> zz[12];
+      if constexpr (KZ) decode_kept<T, V>(zkeep, zsk, zz);
+      else load_site<T, V>(z, zs, blk, loc, zz);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) zz[c] = cadd(zz[c], x[c]);
-        store_site<T, V>(z, zs, blk, loc, zz);
-      } else {
-        C<T>* p = z + (long long)blk * 192 + loc;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) p[c * 16] = cadd(p[c * 16], x[c]);
-      }
+      for (int c = 0; c < 12; ++c) zz[c] = cadd(zz[c], x[c]);
+      store_site<T, V>(z, zs, blk, loc, zz);
     }
   }
 }

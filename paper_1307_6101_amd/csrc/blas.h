@@ -68,12 +68,13 @@ class Reducer {
   Reducer();
   ~Reducer();
   // batched: a == nullptr for plain inner products, else the update
-  // w_r += sum_j c[r][j] V_{j,r} first
+  // w_r += sum_j c[r][j] V_{j,r} first, written back to w unless store_w is
+  // false (then the products are those of the updated w, which stays as it was)
   // (results to `out` in device memory, same layout, when it is given;
   // no host access then, so the call can be captured into a graph)
   template <typename T>
   void bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
-             hipStream_t s, double2* out = nullptr);
+             hipStream_t s, double2* out = nullptr, bool store_w = true);
   // results of the last batched call, out[r * (k+1) + j] (synchronises)
   void bfetch(int k1, int nb, std::complex<double>* out, hipStream_t s);
   // the coefficients (row r: system r, KMAX per row; missing entries 0) and

@@ -68,7 +68,7 @@ __device__ inline double wsum(double v) {
 
 template <typename T, int BS, int KK>
 __device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C<T>* __restrict__ w,
-                                 long long n, bool upd, const Coefs& c, double* __restrict__ dst) {
+                                 long long n, bool upd, bool store, const Coefs& c, double* __restrict__ dst) {
   constexpr int k = KK;
   __shared__ double lds[BS / 64][2 * (KMAX + 1)];
   double acc[2 * KK + 1];
@@ -96,8 +96,10 @@ __device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C
           cfma(w1, c.c[j], v1[j]);
         }
         const C<T> t0 = ccast<T>(w0), t1 = ccast<T>(w1);
-        w[i0] = t0;
-        w[i1] = t1;
+        if (store) {
+          w[i0] = t0;
+          w[i1] = t1;
+        }
         w0 = ccast<double>(t0);
         w1 = ccast<double>(t1);
       }
@@ -115,7 +117,7 @@ __device__ inline void dots_body(const C<T>* __restrict__ V, long long stride, C
 #pragma unroll
       for (int j = 0; j < KK; ++j) cfma(wi, c.c[j], ccast<double>(V[j * stride + i]));
       const C<T> wt = ccast<T>(wi);
-      w[i] = wt;
+      if (store) w[i] = wt;
       wi = ccast<double>(wt);
     }
 #pragma unroll
@@ -259,7 +261,7 @@ __global__ void __launch_bounds__(BS) k_bdots_pass1(const BArg a, int upd, const
 #pragma unroll
     for (int j = 0; j < KK; ++j) cc.c[j] = a.coef(r, j);
   }
-  dots_body<T, BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, upd != 0, cc,
+  dots_body<T, BS, KK>(V + (long long)r * n, vstride, w + (long long)r * n, n, upd != 0, upd == 1, cc,
                        partial + ((long long)r * g + blockIdx.x) * 2 * (KMAX + 1));
 }
 
@@ -301,7 +303,7 @@ __global__ void __launch_bounds__(256) k_bdots_pass2(const double* __restrict__ 
 
 template <typename T>
 void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>* w, long long n, int nb,
-                    hipStream_t s, double2* dev_out) {
+                    hipStream_t s, double2* dev_out, bool store_w) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched inner products");
   // short vectors (the coarse levels): one workgroup of RED_BS_ONE threads
   // per system writes the result directly, no second pass
@@ -311,7 +313,8 @@ void Reducer::bdots(const BArg* a, const C<T>* V, long long vstride, int k, C<T>
   if (g < 1) g = 1;
   double* out = reinterpret_cast<double*>(dev_out ? dev_out : result_);
   static const BArg none{};
-  BDotsLaunch<T, 0>::go(k, (unsigned)g, one ? RED_BS_ONE : RED_BS, nb, s, a ? *a : none, a ? 1 : 0, V, vstride,
+  BDotsLaunch<T, 0>::go(k, (unsigned)g, one ? RED_BS_ONE : RED_BS, nb, s, a ? *a : none, a ? (store_w ? 1 : 2) : 0,
+                        V, vstride,
                         w, n, g == 1 ? out : partial_.p);
   DD_LAUNCH_CHECK();
   if (g > 1) {
@@ -393,7 +396,7 @@ Reducer::~Reducer() {
   template void vbmy<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
   template void vadd<T>(const C<T>*, C<T>*, long long, hipStream_t);                         \
   template void Reducer::bdots<T>(const BArg*, const C<T>*, long long, int, C<T>*, long long, int, \
-                                  hipStream_t, double2*);                                      \
+                                  hipStream_t, double2*, bool);                                \
   template void blincomb<T, T>(const BArg&, int, const C<T>*, long long, C<T>*, long long, int, C<T>*, \
                                hipStream_t);                                               \
   template void bscale<T>(const BArg&, const C<T>*, C<T>*, long long, int, hipStream_t);

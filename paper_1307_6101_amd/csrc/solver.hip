@@ -321,7 +321,9 @@ void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, i
                         std::vector<cd>& cf) {
   const int k1 = j + 2;
   // the inner products read V_0..V_j and w; the update reads them again and
-  // writes the next basis vector
+  // writes the next basis vector.  The second pass takes the products of
+  // w - V h1 without storing it: the basis vector is then formed from w with
+  // the summed coefficients -(h1 + h2)
   meter((2.0 * k1 + 1) * n * sizeof(C<T>) * nb, 16.0 * k1 * n * nb);
   std::vector<cd> h1((size_t)nb * k1), h2((size_t)nb * k1), c1((size_t)nb * KMAX, cd(0));
   red->bdots<T>(nullptr, V, vstride, j + 1, w, n, nb, s);
@@ -349,7 +351,7 @@ void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, i
   }
   if (!any) return;
   const BArg a = red->upload(c1, std::vector<double>(), nb, s);
-  red->bdots<T>(&a, V, vstride, j + 1, w, n, nb, s);
+  red->bdots<T>(&a, V, vstride, j + 1, w, n, nb, s, nullptr, false);
   red->bfetch(k1, nb, h2.data(), s);
   for (int r = 0; r < nb; ++r) {
     if (!again[r]) continue;
@@ -358,7 +360,7 @@ void Hierarchy::arnoldi(const C<T>* V, long long vstride, long long n, int nb, i
     for (int i = 0; i <= j; ++i) {
       nn -= std::norm(hr[i]);
       h[(size_t)r * (KMAX + 1) + i] += hr[i];
-      cf[(size_t)r * KMAX + i] = -hr[i];
+      cf[(size_t)r * KMAX + i] = -h[(size_t)r * (KMAX + 1) + i];
     }
     hn[r] = std::sqrt(std::max(nn, 0.0));
   }

@@ -52,6 +52,13 @@ template <typename T, typename TZ>
 void blincomb(const BArg& a, int k, const C<TZ>* Z, long long zstride, C<T>* y, long long n, int nb, C<T>* dst,
               hipStream_t s);
 
+// dst_r = sc[r] * (y_r + sum_j c[r][j] Z_{j,r}) for native fine fields
+// (systems nblk*192 apart) and, in the same pass, its FP16 form with one FP32
+// scale per site (half [nb][nblk*192], hscale [nb][nblk*16]), as encode_h
+// would make it from dst
+void blincomb_encode(const BArg& a, int k, const double2* Z, long long zstride, const double2* y, double2* dst,
+                     __half2* half, float* hscale, int nblk, int nb, hipStream_t s);
+
 // y_r += sum_j c[r][j] Z_{j,r} for fine fields stored in FP16 with one FP32
 // scale per site (half [k][nb][nblk*192], scale [k][nb][nblk*16])
 void blincomb_sites(const BArg& a, int k, const __half2* Z, const float* scale, double2* y, int nblk, int nb,

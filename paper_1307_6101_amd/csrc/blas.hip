@@ -1,4 +1,5 @@
 #include "blas.h"
+#include "fine_dev.h"
 
 namespace ddamg {
 
@@ -228,6 +229,42 @@ void blincomb_sites(const BArg& a, int k, const __half2* Z, const float* scale, 
                     hipStream_t s) {
   DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
   k_blincomb_sites<<<dim3(nblocks((size_t)nblk * 16, 256), nb), 256, 0, s>>>(a, k, Z, scale, y, nblk, nb);
+  DD_LAUNCH_CHECK();
+}
+
+// The next basis vector of the outer FGMRES and its FP16 form in one pass:
+// per site, dst = sc (y + sum_j c_j Z_j) as k_blincomb forms it, written in
+// FP64 and encoded with the site's scale as encode_h would from dst
+__global__ void k_blincomb_encode(const BArg a, int k, const double2* __restrict__ Z, long long zstride,
+                                  const double2* __restrict__ y, double2* __restrict__ dst, __half2* __restrict__ half,
+                                  float* __restrict__ hscale, int nblk) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = tid >> 4, loc = tid & 15, r = blockIdx.y;
+  if (blk >= nblk) return;
+  const long long fs = (long long)nblk * 192, ss = (long long)nblk * 16;
+  const long long off = (long long)r * fs + (long long)blk * 192 + loc;
+  double2 acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = y[off + c * 16];
+  for (int j = 0; j < k; ++j) {
+    const double2 cj = a.coef(r, j);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) cfma(acc[c], cj, Z[j * zstride + off + c * 16]);
+  }
+  const double sc = a.scale(r);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    acc[c] = sc == 0.0 ? czero<double>() : cscale(acc[c], sc);
+    dst[off + c * 16] = acc[c];
+  }
+  store_site<double, __half2>(half + (long long)r * fs, hscale + (long long)r * ss, blk, loc, acc);
+}
+
+void blincomb_encode(const BArg& a, int k, const double2* Z, long long zstride, const double2* y, double2* dst,
+                     __half2* half, float* hscale, int nblk, int nb, hipStream_t s) {
+  DD_REQUIRE(k >= 0 && k <= KMAX && nb >= 1 && nb <= NBMAX, "bad batched linear combination");
+  k_blincomb_encode<<<dim3(nblocks((size_t)nblk * 16, 256), nb), 256, 0, s>>>(a, k, Z, zstride, y, dst, half,
+                                                                             hscale, nblk);
   DD_LAUNCH_CHECK();
 }
 

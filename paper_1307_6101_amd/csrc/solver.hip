@@ -1025,6 +1025,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
     for (int r = 0; r < nb; ++r) g[(size_t)r * (m + 1)] = active[r] ? beta[r] : 0.0;
     std::vector<int> jend(nb, 0);
     std::vector<char> live = active;
+    // FP16 spinors: the FP16 form of V_j, made by the previous step's update
+    bool vj_encoded = false;
     for (int j = 0; j < m; ++j) {
       double2* Vj = V + (size_t)j * vs;
       C<T>* Zj = Z + (size_t)j * vs;
@@ -1050,7 +1052,8 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
         // FP16 fine spinors: the cycle writes the stored direction itself
         __half2* zj = oZ16.p + (size_t)j * vs;
         float* zjs = oZs.p + (size_t)j * nb * ctx->g.V;
-        encode_h<double>(ctx->g, Vj, h16a.p, h16as.p, nb, s);
+        if (!vj_encoded) encode_h<double>(ctx->g, Vj, h16a.p, h16as.p, nb, s);
+        vj_encoded = false;
         cycle_hs(h16a.p, h16as.p, zj, zjs, nb);
         // D in FP64 on exactly the stored FP16 direction
         // (FP16 spinor and its scale in, FP64 spinor out, FP64 links and clover)
@@ -1091,7 +1094,13 @@ template <typename T> void Hierarchy::outer(const double2* b, double2* x, ddamg_
       if (j + 1 < m) {
         for (int r = 0; r < nb; ++r) scale[r] = live[r] ? 1.0 / hn[r] : 0.0;
         const BArg a = red->upload(cf, scale, nb, s);
-        blincomb<double, double>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+        if (hs && !p.graph && !std::is_same<T, double>::value) {
+          // the next basis vector and its FP16 form for the next cycle
+          blincomb_encode(a, j + 1, V, vs, w, V + (size_t)(j + 1) * vs, h16a.p, h16as.p, ctx->g.nblk, nb, s);
+          vj_encoded = true;
+        } else {
+          blincomb<double, double>(a, j + 1, V, vs, w, n, nb, V + (size_t)(j + 1) * vs, s);
+        }
       }
     }
     int kmax = 0;
@@ -1465,6 +1474,7 @@ void Hierarchy::set_sap_block(int l, const int blk[4]) {
   S.cg.site_blk = std::move(g.site_blk);
   S.cg.site_pos = std::move(g.site_pos);
   S.cg.inmask = std::move(g.inmask);
+  S.cg.kmax = g.kmax;
   S.c_blk_sites.upload(S.cg.blk_sites, s);
   S.c_site_blk.upload(S.cg.site_blk, s);
   S.c_site_pos.upload(S.cg.site_pos, s);

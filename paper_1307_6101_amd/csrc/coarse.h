@@ -33,7 +33,7 @@ struct CoarseGeom {
   std::vector<int> blk_sites;  // [nblk][bs], blocks colour-major (colour 0 first)
   std::vector<int> site_blk;   // [V] block id
   std::vector<int> site_pos;   // [V] block id * bs + index in the block
-  std::vector<unsigned> inmask;  // [V] bit k: nbr9[k] lies in the site's block
+  std::vector<unsigned> inmask;  // [nblk*bs] by block-major position: bit k, nbr9[k] lies in the site's block
   int kmax = 9;                // most set bits of any inmask (blocks one MR step reads per site)
   // parity (odd-even)
   bool bipartite;
@@ -72,7 +72,7 @@ struct SapScratch {
 struct SapTables {
   const int* blk_sites;        // [nblk][bs], blocks colour-major
   const int* site_pos;         // [V]
-  const unsigned* inmask;      // [V]
+  const unsigned* inmask;      // [nblk*bs], by block-major position
   int nblk, bs;
   int kmax;                    // most operator blocks an MR step reads for one site
 };

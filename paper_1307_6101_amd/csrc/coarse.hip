@@ -70,11 +70,13 @@ CoarseGeom make_coarse_geom(const int dims[4], int d, const int sap[4]) {
         }
         ++nbk;
       }
+    // indexed by block-major position, which a site kernel knows without a
+    // table read
     for (int s = 0; s < g.V; ++s) {
       unsigned m = 1u;
       for (int k = 1; k < 9; ++k)
         if (g.site_blk[g.nbr9[s * 9 + k]] == g.site_blk[s]) m |= 1u << k;
-      g.inmask[s] = m;
+      g.inmask[g.site_pos[s]] = m;
     }
     g.kmax = 0;
     for (int s = 0; s < g.V; ++s) g.kmax = std::max(g.kmax, __builtin_popcount(g.inmask[s]));
@@ -433,9 +435,10 @@ __device__ inline C<T> block_alpha_wave(const T* __restrict__ part, int blk, int
 }
 
 // The workgroup of the site at position pos0 + blockIdx.x of the block-major
-// order (blk_sites and site_pos are inverse tables) finds its block without a
-// table read; the inputs of the step are read before the step size of the
-// previous step is known, which is then applied to them in registers.
+// order (blk_sites and site_pos are inverse tables) finds its block and its
+// in-block mask without chasing the site index; the inputs of the step are
+// read before the step size of the previous step is known, which is then
+// applied to them in registers.
 template <typename T, typename S, int NCH, int RB>
 __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const int* __restrict__ csites,
                                                    SapTables tb, int pos0, int step,
@@ -461,7 +464,7 @@ __global__ void __launch_bounds__(64 * SW) k_sap_q(CoarseOpView<T, S> op, const 
     const C<T> a = block_alpha_wave<T>(part_prev + w * pn, blk, tb.bs, lane);
     if (lane == 0) alpha_s[w] = a;
   }
-  const unsigned mask = tb.inmask[site];   // self and the in-block neighbours
+  const unsigned mask = tb.inmask[pos];   // self and the in-block neighbours
   const size_t bsz = (size_t)d * d;
   SiteCols<T, S, NCH, RB> sc;
   sc.prefetch(op.K + (size_t)site * 9 * bsz, bsz, mask, w * NCH, lane, d);
@@ -570,7 +573,7 @@ __global__ void __launch_bounds__(64 * SW4) k_sap_q1(CoarseOpView<float, S> op, 
     const float2 a = block_alpha_wave<float>(part_prev, blk, tb.bs, lane);
     if (lane == 0) alpha_s = a;
   }
-  const unsigned mask = tb.inmask[site];
+  const unsigned mask = tb.inmask[pos];
   int kb[KM];
   {
     unsigned mm = mask;
